@@ -1,0 +1,21 @@
+"""ORACLE — test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product (``paper_1606_03255_amd``)
+never imports it and shares no code with it.
+
+Contents
+--------
+``direct``   plain FP64 definition of the sums (C + OpenMP, ``direct.c``):
+             forward f_j = sum_k c_k w_j^k (eq. 4.1 with xi_k = k),
+             adjoint h_k = sum_j g_j conj(w_j)^k (the C^* of Sect. 4),
+             derivative f'_j = sum_k 2 pi i k c_k w_j^k,
+             and a compensated-Horner cross-check.
+``brute``    independent brute force: every power w^k formed on its own in
+             80-bit extended precision (numpy longdouble) or with mpmath.
+``method``   the paper's Algorithm 2 (Sect. 4) step by step in numpy FP64,
+             with the Laplace-side factorisation of Def. 3.2 / Lemma A.2 and
+             the Fourier "black box" either exact (dense NDFT) or a
+             Kaiser-Bessel NFFT.
+"""
+from .direct import forward, adjoint, derivative, horner, num_threads, load  # noqa: F401
