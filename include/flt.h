@@ -1,0 +1,139 @@
+/*
+ * flt.h -- fast Fourier-Laplace transform on AMD MI355X (gfx950).
+ *
+ * Evaluates the exponential sums of Kunis & Melzer, "Fast evaluation of real
+ * and complex exponential sums", Sect. 4, eq. 4.1 with integer exponents:
+ *
+ *     f(z_j) = sum_{k=0}^{N-1} c_k e^{2 pi i k z_j},   Im z_j >= 0,   j < M,
+ *
+ * i.e. a polynomial with monomial coefficients c_k at w_j = e^{2 pi i z_j} in
+ * the closed unit disk, by the paper's Algorithm 2: dyadic bands of
+ * y = 2 pi Im z (Def. 3.2), rank-q Chebyshev interpolation of every admissible
+ * Laplace block (Lemma A.1/A.2), the Hadamard-product identity of Lemma 4.2,
+ * and one oversampled Kaiser-Bessel NFFT per band column as the Fourier black
+ * box.  The result satisfies max_j |f~_j - f_j| <= eps * sum_k |c_k|
+ * (Thm 4.3).  All work after plan creation runs in HIP kernels on the GPU.
+ *
+ * Conventions for every entry point
+ *   - Complex arrays are interleaved (re, im): complex64 = 2 x float,
+ *     complex128 = 2 x double, contiguous, element stride 1.
+ *   - "device" pointers are HIP device (or managed) memory of the device that
+ *     was current when the plan was created; "host" pointers are ordinary host
+ *     memory.  The caller owns every pointer it passes; the library never
+ *     frees caller memory and keeps no pointer to caller memory after a call
+ *     returns, except the workspace registered with flt_plan_set_workspace.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Transform
+ *     calls only enqueue work on it and return; results are ready when the
+ *     stream reaches that point.  Inputs are read-only.
+ *   - Every call returns FLT_OK (0) or a negative FLT_E* code; no exception
+ *     crosses the boundary and nothing aborts.  Argument checks happen before
+ *     any device work, so a failed call enqueues nothing.
+ *   - A plan is immutable after creation apart from its workspace binding and
+ *     may be used from one stream at a time.
+ */
+#ifndef FLT_H
+#define FLT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct flt_plan flt_plan;
+
+/* dtype: the arithmetic form of a plan */
+#define FLT_C64  1 /* c, f complex64; FP32 bulk arithmetic, FP64 phase reduction and final per-node sums */
+#define FLT_C128 2 /* c, f complex128; FP64 throughout */
+
+/* flags for flt_plan_create */
+#define FLT_FLAG_HOST_ONLY (1u << 0) /* plan on the host only (parameters, partition, byte model); no device */
+
+/* return codes */
+#define FLT_OK            0
+#define FLT_EINVAL       -1 /* null pointer, N < 1, M < 1, unknown dtype/flags, band index out of range */
+#define FLT_EDOMAIN      -2 /* eps outside (0,1); Im z < 0 (|w| > 1) or NaN/inf in Re z, NaN in Im z */
+#define FLT_EPRECISION   -3 /* eps below what the dtype can deliver (c64: 1e-6, c128: 1e-14) */
+#define FLT_ENOWORKSPACE -4 /* no workspace registered, or the one given is too small */
+#define FLT_EHIP         -5 /* a HIP runtime call failed; see flt_last_hip_error() */
+#define FLT_ESTATE       -6 /* plan created with FLT_FLAG_HOST_ONLY used for device work */
+#define FLT_ENOMEM       -7 /* host allocation failed */
+#define FLT_ERANGE       -8 /* N beyond the largest supported size (2^21 + 1 coefficients) */
+
+/* Plan-wide figures (Def. 3.2, Alg. 2, Lemma 4.1). */
+typedef struct flt_info {
+    int64_t N, M;            /* coefficients, nodes */
+    int32_t dtype;           /* FLT_C64 or FLT_C128 */
+    int32_t q;               /* Chebyshev rank, ceil(1/2 + log4(1/eps_K)) */
+    int32_t D;               /* dyadic levels (the paper's M), ceil(log2(y1 xi1 / eps_K)) + 1 */
+    int32_t n_xi;            /* xi_1 = 2^n_xi >= N - 1 */
+    int32_t mw;              /* Kaiser-Bessel window half-width (2 mw taps) */
+    int32_t num_bands;       /* occupied bands, Y_D included, Z^0 excluded */
+    double eps, eps_K, eps_A;/* target accuracy and its Laplace / Fourier shares */
+    double y1;               /* ln(1/eps_K): nodes with y = 2 pi Im z > y1 form Z^0 */
+    int64_t nodes_z0;        /* nodes in Z^0 (f = c_0 there) */
+    size_t workspace_bytes;  /* device workspace a transform call needs */
+    double bytes_forward;    /* algorithmic HBM bytes of one forward call */
+    double flops_forward;    /* algorithmic flops of one forward call */
+} flt_info;
+
+/* One occupied band (Def. 3.2 Y_m, or Y_D). */
+typedef struct flt_band_info {
+    int32_t m;               /* 1..D-1 for Y_m, D for Y_D */
+    int32_t q;               /* columns: the rank q, or 1 for Y_D */
+    int32_t ell_lo, ell_hi;  /* interpolated frequency blocks Omega_l, l_m <= l <= L_m (none for Y_D) */
+    int64_t K;               /* support: frequencies 1..min(K, N-1) */
+    int64_t n;               /* NFFT grid length (2K, at least 16) */
+    int64_t k0;              /* centre of the support, floor(K/2) */
+    int64_t nodes;           /* nodes in the band */
+    int32_t passes;          /* FFT passes through HBM (1 or 2) */
+    int32_t pad;
+} flt_band_info;
+
+/* Build a plan for N coefficients and M nodes z (host, 2*M doubles,
+ * complex128 layout; copied, the caller keeps ownership).  Host work in FP64:
+ * parameters, node classification and sorting, interpolation and window
+ * tables; then an upload to the current device (unless FLT_FLAG_HOST_ONLY).
+ * Im z = +inf is accepted (w = 0, f = c_0).  *out receives the plan or NULL. */
+int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z,
+                    double eps, int dtype, uint32_t flags);
+
+/* Release the plan's device and host memory; NULL is a no-op.  The caller
+ * must ensure no enqueued work of the plan is still pending. */
+void flt_plan_destroy(flt_plan* plan);
+
+/* Host queries (valid for every plan). */
+int flt_plan_info(const flt_plan* plan, flt_info* out);
+int flt_plan_band(const flt_plan* plan, int32_t i, flt_band_info* out);   /* 0 <= i < num_bands */
+/* out (host, M int32): band of each node in caller order: 0 = Z^0, m = Y_m, D = Y_D */
+int flt_plan_node_bands(const flt_plan* plan, int32_t* out);
+
+/* Device workspace: the caller allocates at least flt_plan_workspace_size()
+ * bytes of device memory (256-byte aligned) and registers it; it must stay
+ * valid while transforms that use it are pending.  The plan does not own it. */
+int flt_plan_workspace_size(const flt_plan* plan, size_t* bytes);
+int flt_plan_set_workspace(flt_plan* plan, void* dev, size_t bytes);
+
+/* Forward (Alg. 2): f[j] ~ sum_{k<N} c_k w_j^k.
+ * c: device complex[N] of the plan's dtype; f: device complex[M], overwritten.
+ * Error <= eps * sum|c_k| (Thm 4.3). */
+int flt_forward(flt_plan* plan, const void* c, void* f, void* stream);
+
+/* Derivative: fp[j] ~ f'(z_j) = sum_{k<N} 2 pi i k c_k w_j^k, i.e. Alg. 2
+ * applied to c'_k = 2 pi i k c_k; error <= eps * sum_k |2 pi k c_k|. */
+int flt_derivative(flt_plan* plan, const void* c, void* fp, void* stream);
+
+/* Adjoint (Sect. 4, closing remarks: C^* by the adjoints of the K and A
+ * factors): c_out[k] ~ sum_{j<M} g_j conj(w_j)^k, k < N.
+ * g: device complex[M]; c_out: device complex[N], overwritten.
+ * Error <= eps * sum|g_j|. */
+int flt_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream);
+
+const char* flt_strerror(int code);
+int flt_last_hip_error(void); /* hipError_t of the last failing HIP call in this thread */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLT_H */

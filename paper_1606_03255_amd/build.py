@@ -1,0 +1,65 @@
+"""Build the gfx950 library ``libflt.so`` (and, for tests, the CPU build of
+the same kernel bodies, ``libflt_emu.so``) in-tree.
+
+    python -m paper_1606_03255_amd.build            # library
+    python -m paper_1606_03255_amd.build --emu      # library + CPU test build
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INC = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libflt.so")
+EMU = os.path.join(HERE, "libflt_emu.so")
+ARCH = os.environ.get("FLT_OFFLOAD_ARCH", "gfx950")
+
+HIP_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
+    # no packed FP32 instructions anywhere in the device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I" + INC, "-I" + CSRC,
+]
+
+
+def _run(cmd):
+    print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+
+
+def build_lib(jobs=3):
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = ["kernels.hip", "api.cpp", "plan_host.cpp"]
+    objs = []
+    procs = []
+    for s in srcs:
+        o = os.path.join(objdir, s + ".o")
+        lang = ["-x", "hip"] if s.endswith(".hip") else []
+        cmd = ["hipcc"] + HIP_FLAGS + lang + ["-c", os.path.join(CSRC, s), "-o", o]
+        print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+        objs.append(o)
+    rcs = [p.wait() for p in procs]
+    if any(rcs):
+        raise RuntimeError("compilation failed")
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+def build_emu():
+    tmp = EMU + ".tmp%d" % os.getpid()
+    _run(["g++", "-O2", "-g", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-I" + INC, "-I" + CSRC,
+          os.path.join(CSRC, "emu.cpp"), os.path.join(CSRC, "plan_host.cpp"), "-o", tmp])
+    os.replace(tmp, EMU)
+    return EMU
+
+
+if __name__ == "__main__":
+    build_lib()
+    if "--emu" in sys.argv:
+        build_emu()

@@ -1,0 +1,280 @@
+// C-ABI of the fast Fourier-Laplace transform (see include/flt.h).
+#include <hip/hip_runtime_api.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "flt.h"
+#include "launch.h"
+#include "plan_host.h"
+
+using namespace flt;
+
+static thread_local int g_last_hip = 0;
+
+struct flt_plan {
+    HostPlan hp;
+    bool host_only = true;
+    int device = -1;
+    void* dev = nullptr;     // one allocation holding every table and list
+    PlanView<float> pv32{};
+    PlanView<double> pv64{};
+    DevLists lists{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+static int hip_fail(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return FLT_EHIP;
+}
+
+namespace {
+struct Packer {
+    std::vector<char> buf;
+    size_t add(const void* p, size_t bytes)
+    {
+        size_t off = (buf.size() + 255) & ~(size_t)255;
+        buf.resize(off + (bytes ? bytes : 1));
+        if (bytes) memcpy(buf.data() + off, p, bytes);
+        return off;
+    }
+    template <typename T> size_t add_cast(const std::vector<double>& v)
+    {
+        std::vector<T> t(v.begin(), v.end());
+        return add(t.data(), t.size() * sizeof(T));
+    }
+};
+}  // namespace
+
+template <typename T> static PlanView<T> make_view(const HostPlan& hp, char* base, size_t o_bands, size_t o_coef,
+                                                   size_t o_deconv, size_t o_ycheb, size_t o_tws, size_t o_twl,
+                                                   size_t o_twh, size_t o_nx, size_t o_ny, size_t o_perm)
+{
+    PlanView<T> pv;
+    pv.bands = (const BandDesc*)(base + o_bands);
+    pv.coef = (const T*)(base + o_coef);
+    pv.deconv = (const T*)(base + o_deconv);
+    pv.ycheb = (const double*)(base + o_ycheb);
+    pv.tw_stage = (const cplx<T>*)(base + o_tws);
+    pv.tw_lo = (const cplx<T>*)(base + o_twl);
+    pv.tw_hi = (const cplx<T>*)(base + o_twh);
+    pv.nx = (const double*)(base + o_nx);
+    pv.ny = (const double*)(base + o_ny);
+    pv.perm = (const int32_t*)(base + o_perm);
+    pv.mw = hp.mw;
+    pv.kb_b = (T)hp.kb_b;
+    return pv;
+}
+
+static int upload(flt_plan* p)
+{
+    const HostPlan& hp = p->hp;
+    const bool f32 = hp.dtype == FLT_C64;
+    Packer pk;
+    const size_t o_bands = pk.add(hp.bands.data(), hp.bands.size() * sizeof(BandDesc));
+    const size_t o_coef = f32 ? pk.add_cast<float>(hp.coef) : pk.add_cast<double>(hp.coef);
+    const size_t o_deconv = f32 ? pk.add_cast<float>(hp.deconv) : pk.add_cast<double>(hp.deconv);
+    const size_t o_ycheb = pk.add(hp.ycheb.data(), hp.ycheb.size() * sizeof(double));
+    const size_t o_tws = f32 ? pk.add_cast<float>(hp.tw_stage) : pk.add_cast<double>(hp.tw_stage);
+    const size_t o_twl = f32 ? pk.add_cast<float>(hp.tw_lo) : pk.add_cast<double>(hp.tw_lo);
+    const size_t o_twh = f32 ? pk.add_cast<float>(hp.tw_hi) : pk.add_cast<double>(hp.tw_hi);
+    const size_t o_nx = pk.add(hp.nx.data(), hp.nx.size() * sizeof(double));
+    const size_t o_ny = pk.add(hp.ny.data(), hp.ny.size() * sizeof(double));
+    const size_t o_perm = pk.add(hp.perm.data(), hp.perm.size() * sizeof(int32_t));
+    const size_t o_l0 = pk.add(hp.onepass_fwd.data(), hp.onepass_fwd.size() * sizeof(FftItem));
+    const size_t o_l1 = pk.add(hp.passA_fwd.data(), hp.passA_fwd.size() * sizeof(FftItem));
+    const size_t o_l2 = pk.add(hp.passB.data(), hp.passB.size() * sizeof(FftItem));
+    const size_t o_l3 = pk.add(hp.onepass_adj.data(), hp.onepass_adj.size() * sizeof(FftItem));
+    const size_t o_l4 = pk.add(hp.passA_adj.data(), hp.passA_adj.size() * sizeof(FftItem));
+    const size_t o_l5 = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
+
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipMalloc(&p->dev, pk.buf.size());
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipMemcpy(p->dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    char* base = (char*)p->dev;
+    p->pv32 = make_view<float>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm);
+    p->pv64 = make_view<double>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm);
+    DevLists& L = p->lists;
+    L.onepass_fwd = (const FftItem*)(base + o_l0);
+    L.passA_fwd = (const FftItem*)(base + o_l1);
+    L.passB = (const FftItem*)(base + o_l2);
+    L.onepass_adj = (const FftItem*)(base + o_l3);
+    L.passA_adj = (const FftItem*)(base + o_l4);
+    L.nodes = (const NodeItem*)(base + o_l5);
+    L.n_onepass_fwd = (int)hp.onepass_fwd.size();
+    L.n_passA_fwd = (int)hp.passA_fwd.size();
+    L.n_passB = (int)hp.passB.size();
+    L.n_onepass_adj = (int)hp.onepass_adj.size();
+    L.n_passA_adj = (int)hp.passA_adj.size();
+    L.n_nodes = (int)hp.nodes.size();
+    return FLT_OK;
+}
+
+extern "C" {
+
+int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+{
+    if (!out) return FLT_EINVAL;
+    *out = nullptr;
+    if (flags & ~(uint32_t)FLT_FLAG_HOST_ONLY) return FLT_EINVAL;
+    flt_plan* p = new (std::nothrow) flt_plan();
+    if (!p) return FLT_ENOMEM;
+    int rc;
+    try {
+        rc = build_host_plan(p->hp, N, M, z, eps, dtype);
+    } catch (const std::bad_alloc&) {
+        rc = FLT_ENOMEM;
+    }
+    if (rc == FLT_OK && !(flags & FLT_FLAG_HOST_ONLY)) {
+        p->host_only = false;
+        rc = upload(p);
+    }
+    if (rc != FLT_OK) {
+        flt_plan_destroy(p);
+        return rc;
+    }
+    *out = p;
+    return FLT_OK;
+}
+
+void flt_plan_destroy(flt_plan* p)
+{
+    if (!p) return;
+    if (p->dev) hipFree(p->dev);
+    delete p;
+}
+
+int flt_plan_info(const flt_plan* p, flt_info* o)
+{
+    if (!p || !o) return FLT_EINVAL;
+    const HostPlan& hp = p->hp;
+    memset(o, 0, sizeof(*o));
+    o->N = hp.N;
+    o->M = hp.M;
+    o->dtype = hp.dtype;
+    o->q = hp.q;
+    o->D = hp.D;
+    o->n_xi = hp.n_xi;
+    o->mw = hp.mw;
+    int nb = 0;
+    for (const BandDesc& B : hp.bands) nb += B.q > 0;
+    o->num_bands = nb;
+    o->eps = hp.eps;
+    o->eps_K = hp.eps_K;
+    o->eps_A = hp.eps_A;
+    o->y1 = hp.y1;
+    o->nodes_z0 = hp.nodes_z0;
+    o->workspace_bytes = hp.ws_bytes;
+    o->bytes_forward = hp.bytes_forward;
+    o->flops_forward = hp.flops_forward;
+    return FLT_OK;
+}
+
+int flt_plan_band(const flt_plan* p, int32_t i, flt_band_info* o)
+{
+    if (!p || !o) return FLT_EINVAL;
+    int seen = 0;
+    for (size_t b = 0; b < p->hp.bands.size(); ++b) {
+        const BandDesc& B = p->hp.bands[b];
+        if (B.q == 0) continue;
+        if (seen++ != i) continue;
+        memset(o, 0, sizeof(*o));
+        o->m = p->hp.band_m[b];
+        o->q = B.q;
+        o->ell_lo = B.ell_lo;
+        o->ell_hi = B.ell_hi;
+        o->K = B.k0 * 2 > 0 ? B.k0 * 2 : 1;
+        o->n = (int64_t)1 << B.log2n;
+        o->k0 = B.k0;
+        o->nodes = B.node_count;
+        o->passes = B.log2n2 > 0 ? 2 : 1;
+        return FLT_OK;
+    }
+    return FLT_EINVAL;
+}
+
+int flt_plan_node_bands(const flt_plan* p, int32_t* out)
+{
+    if (!p || !out) return FLT_EINVAL;
+    memcpy(out, p->hp.node_band.data(), p->hp.node_band.size() * sizeof(int32_t));
+    return FLT_OK;
+}
+
+int flt_plan_workspace_size(const flt_plan* p, size_t* bytes)
+{
+    if (!p || !bytes) return FLT_EINVAL;
+    *bytes = p->hp.ws_bytes;
+    return FLT_OK;
+}
+
+int flt_plan_set_workspace(flt_plan* p, void* dev, size_t bytes)
+{
+    if (!p || !dev) return FLT_EINVAL;
+    if (p->host_only) return FLT_ESTATE;
+    if (bytes < p->hp.ws_bytes || ((uintptr_t)dev & 255)) return FLT_ENOWORKSPACE;
+    p->ws = (char*)dev;
+    p->ws_bytes = bytes;
+    return FLT_OK;
+}
+
+static int check_call(const flt_plan* p, const void* a, const void* b)
+{
+    if (!p || !a || !b) return FLT_EINVAL;
+    if (p->host_only) return FLT_ESTATE;
+    if (!p->ws) return FLT_ENOWORKSPACE;
+    return FLT_OK;
+}
+
+static int run_forward(flt_plan* p, const void* c, void* f, int deriv, void* stream)
+{
+    int rc = check_call(p, c, f);
+    if (rc != FLT_OK) return rc;
+    const HostPlan& hp = p->hp;
+    hipError_t e = hp.dtype == FLT_C64
+        ? launch_forward<float>(p->lists, p->pv32, c, f, p->ws, hp.off_grid, hp.off_scratch, deriv, (hipStream_t)stream)
+        : launch_forward<double>(p->lists, p->pv64, c, f, p->ws, hp.off_grid, hp.off_scratch, deriv, (hipStream_t)stream);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+
+int flt_forward(flt_plan* p, const void* c, void* f, void* stream) { return run_forward(p, c, f, 0, stream); }
+
+int flt_derivative(flt_plan* p, const void* c, void* fp, void* stream) { return run_forward(p, c, fp, 1, stream); }
+
+int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream)
+{
+    int rc = check_call(p, g, c_out);
+    if (rc != FLT_OK) return rc;
+    const HostPlan& hp = p->hp;
+    hipError_t e = hp.dtype == FLT_C64
+        ? launch_adjoint<float>(p->lists, p->pv32, hp.N, hp.grid_elems, g, c_out, p->ws, hp.off_grid, hp.off_scratch,
+                                hp.off_acc, (hipStream_t)stream)
+        : launch_adjoint<double>(p->lists, p->pv64, hp.N, hp.grid_elems, g, c_out, p->ws, hp.off_grid,
+                                 hp.off_scratch, hp.off_acc, (hipStream_t)stream);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+
+const char* flt_strerror(int code)
+{
+    switch (code) {
+        case FLT_OK: return "ok";
+        case FLT_EINVAL: return "invalid argument";
+        case FLT_EDOMAIN: return "argument outside the method's domain (eps not in (0,1), Im z < 0, NaN or inf)";
+        case FLT_EPRECISION: return "accuracy below what the dtype can deliver";
+        case FLT_ENOWORKSPACE: return "workspace missing or too small";
+        case FLT_EHIP: return "HIP runtime error";
+        case FLT_ESTATE: return "plan has no device state (host-only plan)";
+        case FLT_ENOMEM: return "host allocation failed";
+        case FLT_ERANGE: return "size beyond the supported range";
+        default: return "unknown error";
+    }
+}
+
+int flt_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// CPU build of the kernel bodies, for tests only: every workgroup runs as an
+// OpenMP team of FFT_THREADS / GATHER_THREADS threads with real barriers, on
+// host copies of the plan tables.  It exercises exactly the index arithmetic
+// and synchronisation of the GPU kernels, so tests can check it (optionally
+// under AddressSanitizer) before anything is launched on a GPU.  Nothing in
+// the library or its Python binding loads this file's build.
+#define _GNU_SOURCE 1
+#include <math.h>
+#include <omp.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <vector>
+
+#include "flt.h"
+#include "kernels_impl.h"
+#include "plan_host.h"
+
+namespace flt {
+
+struct HostCtx {
+    int t, nt, b;
+    int tid() const { return t; }
+    int ntid() const { return nt; }
+    int bid() const { return b; }
+    void sync() const {
+#pragma omp barrier
+    }
+    void atomic_add(double* p, double v) const {
+#pragma omp atomic
+        *p += v;
+    }
+    void atomic_add(float* p, float v) const {
+#pragma omp atomic
+        *p += v;
+    }
+};
+
+template <typename T> static std::vector<T> cast(const std::vector<double>& v)
+{
+    return std::vector<T>(v.begin(), v.end());
+}
+
+template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body)
+{
+    for (size_t b = 0; b < nblocks; ++b) {
+#pragma omp parallel num_threads(nthreads)
+        {
+            HostCtx ctx{omp_get_thread_num(), omp_get_num_threads(), (int)b};
+            body(ctx);
+        }
+    }
+}
+
+template <typename T, int MW>
+static void gather_mw(const PlanView<T>& pv, const HostPlan& hp, const cplx<T>* c, const cplx<T>* grids,
+                      cplx<T>* f, int with_c0)
+{
+    run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0);
+    });
+}
+
+template <typename T, int MW>
+static void spread_mw(const PlanView<T>& pv, const HostPlan& hp, const cplx<T>* g, cplx<T>* grids, double* acc)
+{
+    std::vector<double> red(2 * GATHER_THREADS);
+    run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_spread<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), g, grids, acc, red.data());
+    });
+}
+
+template <typename T>
+static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
+{
+    constexpr int ITEMS = (1 << Sizes<T>::LOG2P) / FFT_THREADS;
+    const std::vector<T> coef = cast<T>(hp.coef), deconv = cast<T>(hp.deconv);
+    const std::vector<T> tws = cast<T>(hp.tw_stage), twl = cast<T>(hp.tw_lo), twh = cast<T>(hp.tw_hi);
+    PlanView<T> pv;
+    pv.bands = hp.bands.data();
+    pv.coef = coef.data();
+    pv.deconv = deconv.data();
+    pv.ycheb = hp.ycheb.data();
+    pv.tw_stage = (const cplx<T>*)tws.data();
+    pv.tw_lo = (const cplx<T>*)twl.data();
+    pv.tw_hi = (const cplx<T>*)twh.data();
+    pv.nx = hp.nx.data();
+    pv.ny = hp.ny.data();
+    pv.perm = hp.perm.data();
+    pv.mw = hp.mw;
+    pv.kb_b = (T)hp.kb_b;
+
+    std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems, 1));
+    std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems, 1));
+    std::vector<cplx<T>> lds(1 << Sizes<T>::LOG2P);
+    memset(grids.data(), 0, grids.size() * sizeof(cplx<T>));
+    memset(scratch.data(), 0, scratch.size() * sizeof(cplx<T>));
+    if (op == 0 || op == 1) {
+        const cplx<T>* c = (const cplx<T>*)in;
+        cplx<T>* f = (cplx<T>*)out;
+        const int deriv = op == 1;
+        run_blocks(hp.onepass_fwd.size(), FFT_THREADS, [&](const HostCtx& ctx) {
+            body_onepass_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_fwd.data(), c, grids.data(), deriv, lds.data());
+        });
+        run_blocks(hp.passA_fwd.size(), FFT_THREADS, [&](const HostCtx& ctx) {
+            body_passA_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.passA_fwd.data(), c, scratch.data(), deriv, lds.data());
+        });
+        run_blocks(hp.passB.size(), FFT_THREADS, [&](const HostCtx& ctx) {
+            body_passB<HostCtx, T, ITEMS>(ctx, pv, hp.passB.data(), scratch.data(), 0, grids.data(), +1, lds.data());
+        });
+        switch (hp.mw) {
+#define G(MWV) case MWV: gather_mw<T, MWV>(pv, hp, c, grids.data(), f, !deriv); break;
+            G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
+#undef G
+            default: return FLT_EINVAL;
+        }
+        return FLT_OK;
+    }
+    if (op == 2) {
+        const cplx<T>* g = (const cplx<T>*)in;
+        cplx<T>* co = (cplx<T>*)out;
+        std::vector<double> acc(2 * hp.N, 0.0);
+        switch (hp.mw) {
+#define S(MWV) case MWV: spread_mw<T, MWV>(pv, hp, g, grids.data(), acc.data()); break;
+            S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
+#undef S
+            default: return FLT_EINVAL;
+        }
+        run_blocks(hp.passB.size(), FFT_THREADS, [&](const HostCtx& ctx) {
+            body_passB<HostCtx, T, ITEMS>(ctx, pv, hp.passB.data(), grids.data(), 1, scratch.data(), -1, lds.data());
+        });
+        run_blocks(hp.passA_adj.size(), FFT_THREADS, [&](const HostCtx& ctx) {
+            body_passA_adj<HostCtx, T, ITEMS>(ctx, pv, hp.passA_adj.data(), scratch.data(), acc.data(), lds.data());
+        });
+        run_blocks(hp.onepass_adj.size(), FFT_THREADS, [&](const HostCtx& ctx) {
+            body_onepass_adj<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_adj.data(), grids.data(), acc.data(), lds.data());
+        });
+        for (int64_t k = 0; k < hp.N; ++k) co[k] = mk<T>((T)acc[2 * k], (T)acc[2 * k + 1]);
+        return FLT_OK;
+    }
+    return FLT_EINVAL;
+}
+
+}  // namespace flt
+
+extern "C" int flt_emu_run(int64_t N, int64_t M, const double* z, double eps, int dtype, int op,
+                           const void* in, void* out)
+{
+    flt::HostPlan hp;
+    int rc = flt::build_host_plan(hp, N, M, z, eps, dtype);
+    if (rc != FLT_OK) return rc;
+    return dtype == FLT_C64 ? flt::emu_run<float>(hp, op, in, out) : flt::emu_run<double>(hp, op, in, out);
+}

@@ -1,0 +1,106 @@
+// Types shared by the host planner and the kernels.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIP__)
+#include <hip/hip_runtime.h>
+#else  // host-only translation units (planner, CPU build of the kernel bodies)
+#ifndef __host__
+#define __host__
+#endif
+#ifndef __device__
+#define __device__
+#endif
+#ifndef __forceinline__
+#define __forceinline__ inline
+#endif
+#endif
+
+#define FLT_HD __host__ __device__ __forceinline__
+
+namespace flt {
+
+template <typename T> struct alignas(2 * sizeof(T)) cplx { T x, y; };
+
+template <typename T> FLT_HD cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
+template <typename T> FLT_HD cplx<T> add(cplx<T> a, cplx<T> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename T> FLT_HD cplx<T> sub(cplx<T> a, cplx<T> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename T> FLT_HD cplx<T> mul(cplx<T> a, cplx<T> b)
+{
+    return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T> FLT_HD cplx<T> scale(cplx<T> a, T s) { return mk(a.x * s, a.y * s); }
+// multiply by i*sign (sign = +1 or -1)
+template <typename T> FLT_HD cplx<T> mul_isign(cplx<T> a, int sign)
+{
+    return sign > 0 ? mk(-a.y, a.x) : mk(a.y, -a.x);
+}
+
+// Sizes fixed at compile time.
+constexpr int FFT_THREADS = 512;          // threads of every FFT workgroup
+constexpr int TW_STAGE_LOG2 = 13;         // stage twiddle table: e^{-2 pi i t / 2^13}
+constexpr int TW2_LOG2 = 22;              // two-level table resolution 2^22 (largest grid)
+constexpr int TW2_HALF = 11;              // lo/hi tables of 2^11 entries each
+constexpr int GATHER_THREADS = 256;       // nodes per gather/spread workgroup
+constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
+constexpr int MAX_MW = 10;                // largest window half-width supported
+
+template <typename T> struct Sizes;
+template <> struct Sizes<float>  { static constexpr int LOG2P = 13; };   // 8192 complex64 = 64 KB of LDS
+template <> struct Sizes<double> { static constexpr int LOG2P = 12; };   // 4096 complex128 = 64 KB of LDS
+
+// One occupied band of the node partition (Def. 3.2 Y_m, or Y_D), or the
+// constant band (q = 0) that holds the Z^0 nodes.
+struct BandDesc {
+    int32_t q;           // columns; 0 for the constant band
+    int32_t log2n;       // NFFT grid length n = 2^log2n
+    int32_t log2n1;      // first FFT factor (log2n for a one-pass band)
+    int32_t log2n2;      // second factor, log2n - log2n1 (0 for one pass)
+    int32_t log2b;       // pass A: sub-transforms per workgroup
+    int32_t log2B;       // pass B: sub-transforms per workgroup = width of the blocked layout
+    int32_t ell_lo;      // interpolated frequency blocks ell_lo..ell_hi (ell_hi < ell_lo: none)
+    int32_t ell_hi;
+    int32_t n_xi;        // xi_1 = 2^n_xi
+    int32_t coef_off;    // first coefficient of block ell_lo in the Chebyshev table (q*q per block)
+    int32_t deconv_off;  // deconvolution table of this n: entries |k'| = 0..n/4
+    int32_t ycheb_off;   // q (node, weight) pairs of the y interpolation in the ycheb table
+    int64_t k0;          // centre of the frequency support
+    int64_t kmax;        // support is k = 1..kmax
+    int64_t grid_off;    // complex offset of the band's q grids (column-major, n each)
+    int64_t scratch_off; // complex offset of the band's pass-A output (two-pass bands)
+    int64_t node_start;  // first node of the band in the sorted node arrays
+    int64_t node_count;
+};
+
+// Work item of an FFT kernel: band, first column, and a block index.
+struct FftItem {
+    int32_t band;
+    int32_t s0;          // first column
+    int32_t ns;          // columns in this item (one-pass kernel) / unused
+    int32_t blk;         // j2-block (pass A) or l1-block (pass B)
+};
+
+// Work item of the node kernels: up to GATHER_THREADS consecutive sorted nodes of one band.
+struct NodeItem {
+    int32_t band;
+    int32_t count;
+    int64_t start;
+};
+
+// Everything a kernel needs to read from the plan (device or host pointers).
+template <typename T> struct PlanView {
+    const BandDesc* bands;
+    const T* coef;           // Chebyshev coefficients a[s][i] per (band, block)
+    const T* deconv;         // 1 / (n phi_hat(k')) per distinct n
+    const double* ycheb;     // per band: q pairs (y_s, lambda_s)
+    const cplx<T>* tw_stage; // e^{-2 pi i t / 2^13}
+    const cplx<T>* tw_lo;    // e^{-2 pi i t / 2^22},        t < 2^11
+    const cplx<T>* tw_hi;    // e^{-2 pi i t 2^11 / 2^22},   t < 2^11
+    const double* nx;        // sorted nodes: x in [0,1)
+    const double* ny;        //               y = 2 pi Im z
+    const int32_t* perm;     //               caller index
+    int32_t mw;              // window half-width
+    T kb_b;                  // Kaiser-Bessel shape b = pi (2 - 1/sigma)
+};
+
+}  // namespace flt

@@ -1,0 +1,185 @@
+// gfx950 kernels of the fast Fourier-Laplace transform and their launch
+// sequences.  The bodies live in kernels_impl.h; this file binds them to the
+// HIP execution model (workgroup = one work item of a precomputed list, LDS
+// tiles of 64 KB for the FFT kernels) and orders them on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include "kernels_impl.h"
+#include "launch.h"
+
+namespace flt {
+
+struct DevCtx {
+    __device__ __forceinline__ int tid() const { return (int)threadIdx.x; }
+    __device__ __forceinline__ int ntid() const { return (int)blockDim.x; }
+    __device__ __forceinline__ int bid() const { return (int)blockIdx.x; }
+    __device__ __forceinline__ void sync() const { __syncthreads(); }
+    __device__ __forceinline__ void atomic_add(double* p, double v) const { unsafeAtomicAdd(p, v); }
+    __device__ __forceinline__ void atomic_add(float* p, float v) const { unsafeAtomicAdd(p, v); }
+};
+
+template <typename T> constexpr int fft_items() { return (1 << Sizes<T>::LOG2P) / FFT_THREADS; }
+
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void k_onepass_fwd(PlanView<T> pv, const FftItem* items,
+                                                             const cplx<T>* c, cplx<T>* grids, int deriv)
+{
+    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    body_onepass_fwd<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, c, grids, deriv, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
+                                                           const cplx<T>* c, cplx<T>* scratch, int deriv)
+{
+    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    body_passA_fwd<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, c, scratch, deriv, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void k_passB(PlanView<T> pv, const FftItem* items, const cplx<T>* src,
+                                                       int64_t sel, cplx<T>* dst, int sign)
+{
+    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    body_passB<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, src, sel, dst, sign, lds);
+}
+
+template <typename T, int MW>
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PlanView<T> pv, const NodeItem* items, const cplx<T>* c,
+                                                           const cplx<T>* grids, cplx<T>* f, int with_c0)
+{
+    body_gather<DevCtx, T, MW>(DevCtx(), pv, items, c, grids, f, with_c0);
+}
+
+template <typename T, int MW>
+__global__ __launch_bounds__(GATHER_THREADS) void k_spread(PlanView<T> pv, const NodeItem* items, const cplx<T>* g,
+                                                           cplx<T>* grids, double* acc)
+{
+    __shared__ double red[2 * GATHER_THREADS];
+    body_spread<DevCtx, T, MW>(DevCtx(), pv, items, g, grids, acc, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void k_onepass_adj(PlanView<T> pv, const FftItem* items,
+                                                             const cplx<T>* grids, double* acc)
+{
+    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    body_onepass_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, grids, acc, lds);
+}
+
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void k_passA_adj(PlanView<T> pv, const FftItem* items,
+                                                           const cplx<T>* scratch, double* acc)
+{
+    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    body_passA_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, scratch, acc, lds);
+}
+
+// Clear `n` 16-byte words (a fill kernel, so the sequence stays capturable).
+__global__ __launch_bounds__(256) void k_zero16(double2* p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = make_double2(0.0, 0.0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_finalize_adj(const double* acc, cplx<T>* out, int64_t N)
+{
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = mk<T>((T)acc[2 * k], (T)acc[2 * k + 1]);
+}
+
+static int grid_for(int64_t work, int per_block)
+{
+    int64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;
+    return (int)g;
+}
+
+template <typename T, int MW>
+static void launch_gather_mw(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, const cplx<T>* grids,
+                             cplx<T>* f, int with_c0, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_gather<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, c, grids, f,
+                       with_c0);
+}
+
+template <typename T, int MW>
+static void launch_spread_mw(const DevLists& L, const PlanView<T>& pv, const cplx<T>* g, cplx<T>* grids,
+                             double* acc, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_spread<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, g, grids, acc);
+}
+
+template <typename T>
+hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* cv, void* fv, char* ws,
+                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st)
+{
+    const cplx<T>* c = (const cplx<T>*)cv;
+    cplx<T>* f = (cplx<T>*)fv;
+    cplx<T>* grids = (cplx<T>*)(ws + off_grid);
+    cplx<T>* scratch = (cplx<T>*)(ws + off_scratch);
+    if (L.n_onepass_fwd)
+        hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(L.n_onepass_fwd), dim3(FFT_THREADS), 0, st, pv, L.onepass_fwd, c,
+                           grids, deriv);
+    if (L.n_passA_fwd)
+        hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
+                           scratch, deriv);
+    if (L.n_passB)
+        hipLaunchKernelGGL(k_passB<T>, dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
+                           (const cplx<T>*)scratch, (int64_t)0, grids, +1);
+    if (L.n_nodes) {
+        switch (pv.mw) {
+#define G(MWV) case MWV: launch_gather_mw<T, MWV>(L, pv, c, grids, f, !deriv, st); break;
+            G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
+#undef G
+            default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, int64_t N, int64_t grid_elems, const void* gv,
+                          void* outv, char* ws, size_t off_grid, size_t off_scratch, size_t off_acc, hipStream_t st)
+{
+    const cplx<T>* g = (const cplx<T>*)gv;
+    cplx<T>* out = (cplx<T>*)outv;
+    cplx<T>* grids = (cplx<T>*)(ws + off_grid);
+    cplx<T>* scratch = (cplx<T>*)(ws + off_scratch);
+    double* acc = (double*)(ws + off_acc);
+    const int64_t gwords = (grid_elems * (int64_t)sizeof(cplx<T>) + 15) / 16;
+    if (gwords) hipLaunchKernelGGL(k_zero16, dim3(grid_for(gwords, 256 * 8)), dim3(256), 0, st, (double2*)grids, gwords);
+    hipLaunchKernelGGL(k_zero16, dim3(grid_for(N, 256 * 8)), dim3(256), 0, st, (double2*)acc, N);
+    if (L.n_nodes) {
+        switch (pv.mw) {
+#define S(MWV) case MWV: launch_spread_mw<T, MWV>(L, pv, g, grids, acc, st); break;
+            S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
+#undef S
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (L.n_passB)
+        hipLaunchKernelGGL(k_passB<T>, dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
+                           (const cplx<T>*)grids, (int64_t)1, scratch, -1);
+    if (L.n_passA_adj)
+        hipLaunchKernelGGL(k_passA_adj<T>, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
+                           (const cplx<T>*)scratch, acc);
+    if (L.n_onepass_adj)
+        hipLaunchKernelGGL(k_onepass_adj<T>, dim3(L.n_onepass_adj), dim3(FFT_THREADS), 0, st, pv, L.onepass_adj,
+                           (const cplx<T>*)grids, acc);
+    hipLaunchKernelGGL(k_finalize_adj<T>, dim3(grid_for(N, 256 * 4)), dim3(256), 0, st, acc, out, N);
+    return hipGetLastError();
+}
+
+template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const void*, void*, char*, size_t,
+                                          size_t, int, hipStream_t);
+template hipError_t launch_forward<double>(const DevLists&, const PlanView<double>&, const void*, void*, char*, size_t,
+                                           size_t, int, hipStream_t);
+template hipError_t launch_adjoint<float>(const DevLists&, const PlanView<float>&, int64_t, int64_t, const void*,
+                                          void*, char*, size_t, size_t, size_t, hipStream_t);
+template hipError_t launch_adjoint<double>(const DevLists&, const PlanView<double>&, int64_t, int64_t, const void*,
+                                           void*, char*, size_t, size_t, size_t, hipStream_t);
+
+}  // namespace flt

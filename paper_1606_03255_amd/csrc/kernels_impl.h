@@ -1,0 +1,537 @@
+// Kernel bodies of the fast Fourier-Laplace transform (Kunis & Melzer,
+// Algorithm 2).  Every body is a template over an execution context `Ctx`
+// that supplies the workgroup geometry, the barrier and atomics, so one
+// source serves the gfx950 kernels (kernels.hip) and a CPU build used by the
+// tests to check indexing and bounds before anything runs on the GPU.
+//
+// Per band m the forward transform is, for each column s < q:
+//   a2/a3  G[k, s] = c_k * t_k[s],  t_k[s] = sum_r L_r^{Omega_l}(k) K^{Y_m,Omega_l}[s, r]
+//          (the frequency side of the tensor interpolant, Lemma 4.2 / Alg. 2),
+//          t_k[s] = 1 on blocks l > L_m (Lemma A.2 iv), deconvolved by
+//          1/(n phi_hat(k - k0)) and placed at (k - k0) mod n;
+//   a4     g_s[l] = sum_k' Ghat[k', s] e^{2 pi i k' l / n}  (oversampled FFT);
+//   a5     F_s(x_j) = sum_{|n x_j - l| < mw} g_s[l] phi(x_j - l/n)  (window gather);
+//   a6     f_j = c_0 + e^{2 pi i k0 x_j} sum_s L_s^{Y_m}(y_j) F_s(x_j)   (FP64 sum).
+// The adjoint runs the transposes in reverse order.
+#pragma once
+#include <math.h>
+#include <stdint.h>
+
+#include "flt_types.h"
+
+namespace flt {
+
+FLT_HD int ceil_log2_u64(int64_t k)  // k >= 1
+{
+    return k <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(k - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Frequency side: t_k[s], the interpolant of xi -> e^{-y_s xi} on the block
+// Omega_l that holds k, evaluated from its Chebyshev coefficients (the same
+// polynomial as sum_r K[s,r] L_r(k); coefficients built by the planner).
+// ---------------------------------------------------------------------------
+template <typename T>
+FLT_HD T laplace_row(const PlanView<T>& pv, const BandDesc& B, int s, int64_t k)
+{
+    const int cl = ceil_log2_u64(k);           // Omega_l = (2^(cl-1), 2^cl] holds k
+    const int ell = B.n_xi + 1 - cl;
+    if (ell > B.ell_hi) return T(1);           // kernel ~ 1 on l > L_m (Lemma A.2 iv)
+    const int q = B.q;
+    const T* a = pv.coef + B.coef_off + ((ell - B.ell_lo) * q + s) * q;
+    // u = (k - centre) / half-width = k 2^(2-cl) - 3, exact in T for k < 2^24
+    const T u = (T)ldexp((double)k, 2 - cl) - T(3);
+    const T u2 = u + u;
+    T b1 = 0, b2 = 0;
+    for (int i = q - 1; i >= 1; --i) {         // Clenshaw
+        T b0 = a[i] + u2 * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return a[0] + u * b1 - b2;
+}
+
+// Value of column s of band B's FFT input at natural grid index j.
+template <typename T>
+FLT_HD cplx<T> grid_input(const PlanView<T>& pv, const BandDesc& B, const cplx<T>* c,
+                          int s, int64_t j, int deriv)
+{
+    const int64_t n = (int64_t)1 << B.log2n;
+    const int64_t kp = j < (n >> 1) ? j : j - n;
+    const int64_t k = kp + B.k0;
+    if (k < 1 || k > B.kmax) return mk<T>(0, 0);
+    T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+    cplx<T> v = c[k];
+    if (deriv) {                                // c'_k = 2 pi i k c_k
+        w *= (T)(6.283185307179586476925286766559 * (double)k);
+        v = mk(-v.y, v.x);
+    }
+    return scale(v, w);
+}
+
+// ---------------------------------------------------------------------------
+// Radix-2/4/8 butterflies: X[a] = sum_b v[b] e^{sign 2 pi i a b / R}
+// ---------------------------------------------------------------------------
+template <typename T> FLT_HD void dft2(cplx<T>* v)
+{
+    cplx<T> a = v[0], b = v[1];
+    v[0] = add(a, b);
+    v[1] = sub(a, b);
+}
+template <typename T> FLT_HD void dft4(cplx<T>* v, int sign)
+{
+    cplx<T> s02 = add(v[0], v[2]), d02 = sub(v[0], v[2]);
+    cplx<T> s13 = add(v[1], v[3]), d13 = mul_isign(sub(v[1], v[3]), sign);
+    v[0] = add(s02, s13);
+    v[2] = sub(s02, s13);
+    v[1] = add(d02, d13);
+    v[3] = sub(d02, d13);
+}
+template <typename T> FLT_HD void dft8(cplx<T>* v, int sign)
+{
+    cplx<T> a[4] = {v[0], v[2], v[4], v[6]};
+    cplx<T> b[4] = {v[1], v[3], v[5], v[7]};
+    dft4(a, sign);
+    dft4(b, sign);
+    const T h = T(0.70710678118654752440084436210485);
+    const T sh = sign > 0 ? h : -h;
+    cplx<T> w1 = mul(b[1], mk(h, sh));
+    cplx<T> w2 = mul_isign(b[2], sign);
+    cplx<T> w3 = mul(b[3], mk(-h, sh));
+    v[0] = add(a[0], b[0]); v[4] = sub(a[0], b[0]);
+    v[1] = add(a[1], w1);   v[5] = sub(a[1], w1);
+    v[2] = add(a[2], w2);   v[6] = sub(a[2], w2);
+    v[3] = add(a[3], w3);   v[7] = sub(a[3], w3);
+}
+
+template <typename T, int R> FLT_HD void dft(cplx<T>* v, int sign)
+{
+    if (R == 2) dft2(v);
+    else if (R == 4) dft4(v, sign);
+    else dft8(v, sign);
+}
+
+// e^{sign 2 pi i t / 2^TW_STAGE_LOG2}
+template <typename T> FLT_HD cplx<T> tw_stage_at(const cplx<T>* tw, int t, int sign)
+{
+    cplx<T> w = tw[t];
+    if (sign > 0) w.y = -w.y;
+    return w;
+}
+
+// e^{sign 2 pi i e / n}, n = 2^log2n <= 2^22, from the two-level table
+template <typename T> FLT_HD cplx<T> tw_grid_at(const PlanView<T>& pv, int64_t e, int log2n, int sign)
+{
+    const int64_t ee = (e & (((int64_t)1 << log2n) - 1)) << (TW2_LOG2 - log2n);
+    cplx<T> w = mul(pv.tw_hi[ee >> TW2_HALF], pv.tw_lo[ee & ((1 << TW2_HALF) - 1)]);
+    if (sign > 0) w.y = -w.y;
+    return w;
+}
+
+// One Stockham autosort radix-R stage over `nsub` contiguous transforms of
+// length 2^log2L held in `buf` (in place: reads, barrier, writes, barrier).
+template <class Ctx, typename T, int R, int ITEMS>
+FLT_HD void fft_stage(const Ctx& ctx, cplx<T>* buf, int log2L, int P, int log2Ns, int sign,
+                      const cplx<T>* tw)
+{
+    constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : 3);
+    constexpr int NB = ITEMS / R > 0 ? ITEMS / R : 1;
+    const int nbut = P >> LR;
+    const int log2Lq = log2L - LR;
+    const int Nsm = (1 << log2Ns) - 1;
+    cplx<T> v[NB][R];
+    int dst[NB];
+    for (int i = 0; i < NB; ++i) {
+        const int u = ctx.tid() + i * ctx.ntid();
+        dst[i] = -1;
+        if (u < nbut) {
+            const int sub = u >> log2Lq;
+            const int j = u & ((1 << log2Lq) - 1);
+            const cplx<T>* src = buf + (sub << log2L) + j;
+            for (int r = 0; r < R; ++r) v[i][r] = src[r << log2Lq];
+            const int k = j & Nsm;
+            if (log2Ns > 0) {
+                const int sh = TW_STAGE_LOG2 - log2Ns - LR;
+                for (int r = 1; r < R; ++r) v[i][r] = mul(v[i][r], tw_stage_at(tw, (k * r) << sh, sign));
+            }
+            dft<T, R>(v[i], sign);
+            dst[i] = (sub << log2L) + ((j >> log2Ns) << (log2Ns + LR)) + k;
+        }
+    }
+    ctx.sync();
+    for (int i = 0; i < NB; ++i)
+        if (dst[i] >= 0)
+            for (int r = 0; r < R; ++r) buf[dst[i] + (r << log2Ns)] = v[i][r];
+    ctx.sync();
+}
+
+// In-place DFTs X[l] = sum_j x[j] e^{sign 2 pi i j l / L} of `nsub` transforms
+// of length L = 2^log2L stored contiguously in LDS; nsub*L <= ITEMS*ntid.
+template <class Ctx, typename T, int ITEMS>
+FLT_HD void lds_fft(const Ctx& ctx, cplx<T>* buf, int log2L, int nsub, int sign, const cplx<T>* tw)
+{
+    const int P = nsub << log2L;
+    int log2Ns = 0, rem = log2L;
+    while (rem > 0) {
+        const int r = (rem % 3 == 0) ? 3 : ((rem % 3 == 2) ? 2 : (rem >= 4 ? 2 : 1));
+        if (r == 3) fft_stage<Ctx, T, 8, ITEMS>(ctx, buf, log2L, P, log2Ns, sign, tw);
+        else if (r == 2) fft_stage<Ctx, T, 4, ITEMS>(ctx, buf, log2L, P, log2Ns, sign, tw);
+        else fft_stage<Ctx, T, 2, ITEMS>(ctx, buf, log2L, P, log2Ns, sign, tw);
+        log2Ns += r;
+        rem -= r;
+    }
+}
+
+// Address of natural grid index l in a band's blocked layout
+// [l1 / B][l2][l1 mod B], l = l1 + n1 l2  (one-pass bands: address = l).
+FLT_HD int64_t grid_addr(const BandDesc& B, int64_t l)
+{
+    const int64_t l1 = l & (((int64_t)1 << B.log2n1) - 1);
+    const int64_t l2 = l >> B.log2n1;
+    return ((l1 >> B.log2B) << (B.log2n2 + B.log2B)) + (l2 << B.log2B) + (l1 & (((int64_t)1 << B.log2B) - 1));
+}
+
+// ---------------------------------------------------------------------------
+// a2-a4, one-pass bands: generate `ns` columns, FFT them in LDS, store.
+// ---------------------------------------------------------------------------
+template <class Ctx, typename T, int ITEMS>
+FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                             const cplx<T>* c, cplx<T>* grids, int deriv, cplx<T>* lds)
+{
+    const FftItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int log2n = B.log2n;
+    const int P = it.ns << log2n;
+    for (int p = ctx.tid(); p < P; p += ctx.ntid())
+        lds[p] = grid_input(pv, B, c, it.s0 + (p >> log2n), (int64_t)(p & ((1 << log2n) - 1)), deriv);
+    ctx.sync();
+    lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n, it.ns, +1, pv.tw_stage);
+    cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << log2n);
+    for (int p = ctx.tid(); p < P; p += ctx.ntid()) out[p] = lds[p];
+}
+
+// ---------------------------------------------------------------------------
+// a2-a4, two-pass bands, pass A: for b = 2^log2b consecutive j2, the length-n1
+// DFTs over j1 of x[j2 + n2 j1] (generated from c), times e^{2 pi i j2 l1 / n},
+// stored as Y[l1 / B][j2][l1 mod B].
+// ---------------------------------------------------------------------------
+template <class Ctx, typename T, int ITEMS>
+FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                           const cplx<T>* c, cplx<T>* scratch, int deriv, cplx<T>* lds)
+{
+    const FftItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int s = it.s0;
+    const int log2n1 = B.log2n1, log2n2 = B.log2n2, log2b = B.log2b, log2B = B.log2B;
+    const int P = 1 << (log2b + log2n1);
+    const int64_t j2_0 = (int64_t)it.blk << log2b;
+    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+        const int jj = p & ((1 << log2b) - 1);
+        const int j1 = p >> log2b;
+        const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
+        lds[(jj << log2n1) + j1] = grid_input(pv, B, c, s, j, deriv);
+    }
+    ctx.sync();
+    lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, +1, pv.tw_stage);
+    cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
+    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+        const int l1lo = p & ((1 << log2B) - 1);
+        const int jj = (p >> log2B) & ((1 << log2b) - 1);
+        const int l1hi = p >> (log2B + log2b);
+        const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
+        const int64_t j2 = j2_0 + jj;
+        cplx<T> v = mul(lds[(jj << log2n1) + l1], tw_grid_at(pv, j2 * l1, B.log2n, +1));
+        Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
+    }
+}
+
+// pass B: for B = 2^log2B consecutive l1, the length-n2 DFTs over j2 of
+// Y[j2][l1]; X[l1 + n1 l2] stored blocked as [l1 / B][l2][l1 mod B].
+template <class Ctx, typename T, int ITEMS>
+FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                       const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base,
+                       int sign, cplx<T>* lds)
+{
+    // src_band_off_sel: 0 -> source at scratch_off, destination at grid_off (forward);
+    //                   1 -> source at grid_off, destination at scratch_off (adjoint)
+    const FftItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int log2n2 = B.log2n2, log2B = B.log2B;
+    const int P = 1 << (log2B + log2n2);
+    const int64_t so = src_band_off_sel ? B.grid_off : B.scratch_off;
+    const int64_t dso = src_band_off_sel ? B.scratch_off : B.grid_off;
+    const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << (log2n2 + log2B));
+    const cplx<T>* src = src_base + so + blk_off;
+    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+        const int j2 = p >> log2B;
+        const int lo = p & ((1 << log2B) - 1);
+        lds[(lo << log2n2) + j2] = src[p];
+    }
+    ctx.sync();
+    lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n2, 1 << log2B, sign, pv.tw_stage);
+    cplx<T>* dst = dst_base + dso + blk_off;
+    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+        const int l2 = p >> log2B;
+        const int lo = p & ((1 << log2B) - 1);
+        dst[p] = lds[(lo << log2n2) + l2];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Window and node weights
+// ---------------------------------------------------------------------------
+// Kaiser-Bessel window at grid offsets u_t = delta + mw - 1 - t, t < 2 mw:
+// phi = sinh(b v) / (pi v), v = sqrt(mw^2 - u^2).
+template <typename T, int MW>
+FLT_HD void kb_weights(T delta, T b, T* phi)
+{
+    const T inv_pi = T(0.31830988618379067153776752674503);
+    for (int t = 0; t < 2 * MW; ++t) {
+        const T u = delta + T(MW - 1 - t);
+        const T v2 = T(MW * MW) - u * u;
+        const T v = v2 > T(0) ? (T)sqrt(v2) : T(0);
+        phi[t] = v > T(0) ? (T)sinh(b * v) / v * inv_pi : b * inv_pi;
+    }
+}
+
+// Barycentric weights on the band's q Chebyshev nodes (Sect. 2), FP64:
+// L_s(y) = (lambda_s / (y - y_s)) / sum_r lambda_r / (y - y_r); a node hit gives
+// the Kronecker delta.  bary_setup returns 1/sum (or 0 with *hit set).
+struct BaryY {
+    double inv;
+    int hit;
+};
+FLT_HD BaryY bary_setup(const double* yc, int q, double y)
+{
+    BaryY r;
+    r.hit = -1;
+    double sum = 0;
+    for (int s = 0; s < q; ++s) {
+        const double d = y - yc[2 * s];
+        if (d == 0.0) r.hit = s;
+        else sum += yc[2 * s + 1] / d;
+    }
+    r.inv = r.hit >= 0 ? 0.0 : 1.0 / sum;
+    return r;
+}
+FLT_HD double bary_at(const double* yc, const BaryY& b, int s, double y)
+{
+    if (b.hit >= 0) return s == b.hit ? 1.0 : 0.0;
+    return yc[2 * s + 1] / (y - yc[2 * s]) * b.inv;
+}
+
+// ---------------------------------------------------------------------------
+// a5 + a6: per node, gather the window from the q grids, weight by L_s(y),
+// sum in FP64, modulate by e^{2 pi i k0 x} and add c0.
+// ---------------------------------------------------------------------------
+template <class Ctx, typename T, int MW>
+FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items,
+                        const cplx<T>* c, const cplx<T>* grids, cplx<T>* f, int with_c0)
+{
+    const NodeItem it = items[ctx.bid()];
+    const int i = ctx.tid();
+    if (i >= it.count) return;
+    const int64_t jj = it.start + i;
+    const BandDesc& B = pv.bands[it.band];
+    const int32_t dst = pv.perm[jj];
+    const double c0r = with_c0 ? (double)c[0].x : 0.0;
+    const double c0i = with_c0 ? (double)c[0].y : 0.0;
+    if (B.q == 0) {
+        f[dst] = mk<T>((T)c0r, (T)c0i);
+        return;
+    }
+    const double x = pv.nx[jj], y = pv.ny[jj];
+    const int log2n = B.log2n;
+    const int64_t nmask = ((int64_t)1 << log2n) - 1;
+    const double nxv = ldexp(x, log2n);
+    const double fl = floor(nxv);
+    const int64_t l0 = (int64_t)fl;
+    T phi[2 * MW];
+    kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
+    const double* yc = pv.ycheb + 2 * B.ycheb_off;
+    const BaryY by = bary_setup(yc, B.q, y);
+    int64_t addr[2 * MW];
+    for (int t = 0; t < 2 * MW; ++t) addr[t] = grid_addr(B, (l0 - MW + 1 + t) & nmask);
+    const cplx<T>* g = grids + B.grid_off;
+    double ar = 0, ai = 0;
+    for (int s = 0; s < B.q; ++s) {
+        const cplx<T>* gs = g + ((int64_t)s << log2n);
+        T fr = 0, fi = 0;
+        for (int t = 0; t < 2 * MW; ++t) {
+            const cplx<T> v = gs[addr[t]];
+            fr += v.x * phi[t];
+            fi += v.y * phi[t];
+        }
+        const double Ls = bary_at(yc, by, s, y);
+        ar += Ls * (double)fr;
+        ai += Ls * (double)fi;
+    }
+    // e^{2 pi i k0 x}: k0 is 0 or a power of two, so k0 x and its fraction are exact
+    double ph = (double)B.k0 * x;
+    ph -= floor(ph);
+    double sn, cs;
+    sincos(6.283185307179586476925286766559 * ph, &sn, &cs);
+    f[dst] = mk<T>((T)(c0r + ar * cs - ai * sn), (T)(c0i + ar * sn + ai * cs));
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint a7.  Spread: grid_s[l] += g_j e^{-2 pi i k0 x_j} L_s(y_j) phi(x_j - l/n);
+// also accumulates sum_j g_j (the k = 0 coefficient) into acc[0].
+// ---------------------------------------------------------------------------
+template <class Ctx, typename T, int MW>
+FLT_HD void body_spread(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items,
+                        const cplx<T>* gin, cplx<T>* grids, double* acc, double* red)
+{
+    const NodeItem it = items[ctx.bid()];
+    const int i = ctx.tid();
+    const BandDesc& B = pv.bands[it.band];
+    double gr = 0, gi = 0;
+    int64_t jj = it.start + i;
+    if (i < it.count) {
+        const cplx<T> gv = gin[pv.perm[jj]];
+        gr = (double)gv.x;
+        gi = (double)gv.y;
+    }
+    // workgroup sum of g for the k = 0 coefficient
+    red[2 * i] = gr;
+    red[2 * i + 1] = gi;
+    ctx.sync();
+    for (int h = ctx.ntid() >> 1; h > 0; h >>= 1) {
+        if (i < h) {
+            red[2 * i] += red[2 * (i + h)];
+            red[2 * i + 1] += red[2 * (i + h) + 1];
+        }
+        ctx.sync();
+    }
+    if (i == 0) {
+        ctx.atomic_add(acc, red[0]);
+        ctx.atomic_add(acc + 1, red[1]);
+    }
+    if (i >= it.count || B.q == 0) return;
+    const double x = pv.nx[jj], y = pv.ny[jj];
+    const int log2n = B.log2n;
+    const int64_t nmask = ((int64_t)1 << log2n) - 1;
+    const double nxv = ldexp(x, log2n);
+    const double fl = floor(nxv);
+    const int64_t l0 = (int64_t)fl;
+    T phi[2 * MW];
+    kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
+    const double* yc = pv.ycheb + 2 * B.ycheb_off;
+    const BaryY by = bary_setup(yc, B.q, y);
+    double ph = (double)B.k0 * x;
+    ph -= floor(ph);
+    double sn, cs;
+    sincos(6.283185307179586476925286766559 * ph, &sn, &cs);
+    const double ur = gr * cs + gi * sn;   // g e^{-2 pi i k0 x}
+    const double ui = gi * cs - gr * sn;
+    T* g = (T*)(grids + B.grid_off);
+    for (int s = 0; s < B.q; ++s) {
+        const double Ls = bary_at(yc, by, s, y);
+        const T vr = (T)(ur * Ls), vi = (T)(ui * Ls);
+        T* gs = g + ((int64_t)s << (log2n + 1));
+        for (int t = 0; t < 2 * MW; ++t) {
+            const int64_t a = grid_addr(B, (l0 - MW + 1 + t) & nmask);
+            ctx.atomic_add(gs + 2 * a, vr * phi[t]);
+            ctx.atomic_add(gs + 2 * a + 1, vi * phi[t]);
+        }
+    }
+}
+
+// Adjoint of one-pass bands: per column, inverse-sign FFT in LDS, deconvolve,
+// transposed contraction acc_k += sum_s t_k[s] Ghat_s[k - k0] (FP64, atomics).
+template <class Ctx, typename T, int ITEMS>
+FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                             const cplx<T>* grids, double* acc, cplx<T>* lds)
+{
+    const FftItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int log2n = B.log2n;
+    const int n = 1 << log2n;
+    double accr[ITEMS], acci[ITEMS];
+    for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
+    for (int s = 0; s < B.q; ++s) {
+        const cplx<T>* src = grids + B.grid_off + ((int64_t)s << log2n);
+        for (int p = ctx.tid(); p < n; p += ctx.ntid()) lds[p] = src[p];
+        ctx.sync();
+        lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n, 1, -1, pv.tw_stage);
+        for (int i = 0; i < ITEMS; ++i) {
+            const int p = ctx.tid() + i * ctx.ntid();
+            if (p >= n) break;
+            const int64_t kp = p < (n >> 1) ? p : p - n;
+            const int64_t k = kp + B.k0;
+            if (k < 1 || k > B.kmax) continue;
+            const T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+            accr[i] += (double)(lds[p].x * w);
+            acci[i] += (double)(lds[p].y * w);
+        }
+        ctx.sync();
+    }
+    for (int i = 0; i < ITEMS; ++i) {
+        const int p = ctx.tid() + i * ctx.ntid();
+        if (p >= n) break;
+        const int64_t kp = p < (n >> 1) ? p : p - n;
+        const int64_t k = kp + B.k0;
+        if (k < 1 || k > B.kmax) continue;
+        ctx.atomic_add(acc + 2 * k, accr[i]);
+        ctx.atomic_add(acc + 2 * k + 1, acci[i]);
+    }
+}
+
+// Adjoint pass A: for b consecutive j2, all columns s: Y[j2][l1] e^{-2 pi i j2 l1 / n},
+// inverse-sign DFT over l1 -> j1, deconvolve, transposed contraction into acc.
+template <class Ctx, typename T, int ITEMS>
+FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                           const cplx<T>* scratch, double* acc, cplx<T>* lds)
+{
+    const FftItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int log2n1 = B.log2n1, log2n2 = B.log2n2, log2b = B.log2b, log2B = B.log2B;
+    const int P = 1 << (log2b + log2n1);
+    const int64_t n = (int64_t)1 << B.log2n;
+    const int64_t j2_0 = (int64_t)it.blk << log2b;
+    double accr[ITEMS], acci[ITEMS];
+    for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
+    for (int s = 0; s < B.q; ++s) {
+        const cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
+        for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+            const int l1lo = p & ((1 << log2B) - 1);
+            const int jj = (p >> log2B) & ((1 << log2b) - 1);
+            const int l1hi = p >> (log2B + log2b);
+            const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
+            const int64_t j2 = j2_0 + jj;
+            const cplx<T> v = Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
+            lds[(jj << log2n1) + l1] = mul(v, tw_grid_at(pv, j2 * l1, B.log2n, -1));
+        }
+        ctx.sync();
+        lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, -1, pv.tw_stage);
+        for (int i = 0; i < ITEMS; ++i) {
+            const int p = ctx.tid() + i * ctx.ntid();
+            if (p >= P) break;
+            const int jj = p & ((1 << log2b) - 1);
+            const int j1 = p >> log2b;
+            const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
+            const int64_t kp = j < (n >> 1) ? j : j - n;
+            const int64_t k = kp + B.k0;
+            if (k < 1 || k > B.kmax) continue;
+            const T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+            const cplx<T> v = lds[(jj << log2n1) + j1];
+            accr[i] += (double)(v.x * w);
+            acci[i] += (double)(v.y * w);
+        }
+        ctx.sync();
+    }
+    for (int i = 0; i < ITEMS; ++i) {
+        const int p = ctx.tid() + i * ctx.ntid();
+        if (p >= P) break;
+        const int jj = p & ((1 << log2b) - 1);
+        const int j1 = p >> log2b;
+        const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
+        const int64_t kp = j < (n >> 1) ? j : j - n;
+        const int64_t k = kp + B.k0;
+        if (k < 1 || k > B.kmax) continue;
+        ctx.atomic_add(acc + 2 * k, accr[i]);
+        ctx.atomic_add(acc + 2 * k + 1, acci[i]);
+    }
+}
+
+}  // namespace flt

@@ -1,0 +1,310 @@
+// Host planner for the fast Fourier-Laplace transform (Kunis & Melzer,
+// Algorithm 2).  FP64 throughout; see plan_host.h.
+#include "plan_host.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+
+#include "flt.h"
+
+namespace flt {
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+double bessel_i0(double x)
+{
+    // sum_j ((x/2)^2)^j / (j!)^2: all terms positive, no cancellation
+    const double h = 0.25 * x * x;
+    double t = 1.0, s = 1.0;
+    for (int j = 1; j < 1000; ++j) {
+        t *= h / ((double)j * (double)j);
+        s += t;
+        if (t < s * 1e-17) break;
+    }
+    return s;
+}
+
+// Kaiser-Bessel NFFT error bound relative to the coefficient 1-norm, oversampling 2
+// (Potts & Steidl): 4 pi (sqrt(m) + m) (1 - 1/sigma)^(1/4) e^{-2 pi m sqrt(1 - 1/sigma)}.
+static double kb_error_bound(int m)
+{
+    const double s = sqrt(0.5);
+    return 4.0 * PI * (sqrt((double)m) + m) * sqrt(s) * exp(-2.0 * PI * m * s);
+}
+
+static int log2_exact(int64_t v)
+{
+    int r = 0;
+    while (((int64_t)1 << r) < v) ++r;
+    return r;
+}
+
+int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype)
+{
+    if (!z || N < 1 || M < 1 || (dtype != FLT_C64 && dtype != FLT_C128)) return FLT_EINVAL;
+    if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
+    if (eps < (dtype == FLT_C64 ? 1e-6 : 1e-14)) return FLT_EPRECISION;
+    if (N - 1 > ((int64_t)1 << 21)) return FLT_ERANGE;
+    if (M > (int64_t)INT32_MAX) return FLT_ERANGE;
+    for (int64_t j = 0; j < M; ++j) {
+        const double re = z[2 * j], im = z[2 * j + 1];
+        if (!isfinite(re) || isnan(im) || im < 0.0) return FLT_EDOMAIN;
+    }
+
+    hp = HostPlan();
+    hp.N = N;
+    hp.M = M;
+    hp.dtype = dtype;
+    hp.eps = eps;
+    // Lemma 4.1: split the target between the Laplace and Fourier factors
+    hp.eps_K = eps / 3.0;
+    hp.eps_A = eps / 3.0;
+    // Def. 3.2 / Alg. 2 with y_1 = ln(1/eps_K) and xi_1 = 2^n_xi >= N - 1
+    hp.q = (int)ceil(0.5 + log(1.0 / hp.eps_K) / log(4.0));
+    if (hp.q > MAX_Q) return FLT_EPRECISION;
+    hp.y1 = log(1.0 / hp.eps_K);
+    hp.n_xi = log2_exact(std::max<int64_t>(N - 1, 1));
+    const double xi1 = ldexp(1.0, hp.n_xi);
+    hp.D = (int)ceil(log2(hp.y1 * xi1 / hp.eps_K)) + 1;
+    hp.mw = 2;
+    while (kb_error_bound(hp.mw) > hp.eps_A) ++hp.mw;
+    if (hp.mw > MAX_MW) return FLT_EPRECISION;
+    hp.kb_b = PI * (2.0 - 1.0 / 2.0);
+    const int q = hp.q, D = hp.D;
+
+    // ---- node partition: Z^0 (y > y_1), Y_m = (y_1 2^-m, y_1 2^(1-m)], Y_D = [0, y_1 2^(1-D)]
+    std::vector<double> xs(M), ys(M);
+    hp.node_band.resize(M);
+    std::vector<int64_t> count(D + 1, 0);
+    for (int64_t j = 0; j < M; ++j) {
+        const double re = z[2 * j], im = z[2 * j + 1];
+        double x = re - floor(re);
+        if (x >= 1.0) x = 0.0;
+        const double y = isinf(im) ? INFINITY : 2.0 * PI * im;
+        xs[j] = x;
+        ys[j] = y;
+        int m;
+        if (y > hp.y1) m = 0;
+        else if (y == 0.0) m = D;
+        else {
+            m = (int)floor(log2(hp.y1 / y)) + 1;
+            m = std::min(std::max(m, 1), D);
+            while (m < D && !(y > ldexp(hp.y1, -m))) ++m;
+            while (m > 1 && y > ldexp(hp.y1, 1 - m)) --m;
+        }
+        hp.node_band[j] = m;
+        count[m]++;
+    }
+    hp.nodes_z0 = count[0];
+
+    // ---- bands
+    const int LOG2P = dtype == FLT_C64 ? Sizes<float>::LOG2P : Sizes<double>::LOG2P;
+    std::vector<int> band_of_m(D + 1, -1);
+    int64_t n_const = count[0];
+    for (int m = 1; m <= D; ++m) {
+        if (count[m] == 0) continue;
+        if (N == 1) { n_const += count[m]; continue; }      // only c_0: every node is constant
+        BandDesc B{};
+        const int64_t K = (int64_t)1 << (m < D ? std::min(m, hp.n_xi) : hp.n_xi);
+        B.q = m < D ? q : 1;
+        B.ell_lo = m < D ? std::max(1, hp.n_xi - m + 1) : 1;
+        B.ell_hi = m < D ? D - m : 0;
+        B.n_xi = hp.n_xi;
+        B.kmax = std::min<int64_t>(K, N - 1);
+        B.k0 = K / 2;
+        B.log2n = std::max(log2_exact(2 * K), 4);
+        if (B.log2n <= LOG2P) {
+            B.log2n1 = B.log2n;
+            B.log2n2 = B.log2b = B.log2B = 0;
+        } else {
+            B.log2n1 = (B.log2n + 1) / 2;
+            B.log2n2 = B.log2n - B.log2n1;
+            B.log2b = std::min(LOG2P - B.log2n1, B.log2n2);
+            B.log2B = std::min(LOG2P - B.log2n2, B.log2n1);
+        }
+        band_of_m[m] = (int)hp.bands.size();
+        hp.bands.push_back(B);
+        hp.band_m.push_back(m);
+    }
+    int const_band = -1;
+    if (n_const > 0) {
+        BandDesc B{};
+        B.q = 0;
+        const_band = (int)hp.bands.size();
+        hp.bands.push_back(B);
+        hp.band_m.push_back(0);
+    }
+    const int nb = (int)hp.bands.size();
+
+    // ---- sort nodes by (band, grid cell)
+    std::vector<int> nb_of(M);
+    std::vector<int64_t> cell(M);
+    for (int64_t j = 0; j < M; ++j) {
+        const int m = hp.node_band[j];
+        const int b = (m == 0 || band_of_m[m] < 0) ? const_band : band_of_m[m];
+        nb_of[j] = b;
+        cell[j] = hp.bands[b].q ? (int64_t)floor(ldexp(xs[j], hp.bands[b].log2n)) : 0;
+    }
+    std::vector<int32_t> idx(M);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t a, int32_t b) {
+        if (nb_of[a] != nb_of[b]) return nb_of[a] < nb_of[b];
+        return cell[a] < cell[b];
+    });
+    hp.perm = idx;
+    hp.nx.resize(M);
+    hp.ny.resize(M);
+    for (int64_t i = 0; i < M; ++i) {
+        hp.nx[i] = xs[idx[i]];
+        hp.ny[i] = ys[idx[i]];
+    }
+    {
+        int64_t pos = 0;
+        for (int b = 0; b < nb; ++b) {
+            int64_t cnt = 0;
+            while (pos + cnt < M && nb_of[idx[pos + cnt]] == b) ++cnt;
+            hp.bands[b].node_start = pos;
+            hp.bands[b].node_count = cnt;
+            pos += cnt;
+        }
+    }
+
+    // ---- tables
+    std::vector<double> t(q), lam(q), theta(q);
+    for (int s = 0; s < q; ++s) {
+        theta[s] = (2.0 * s + 1.0) * PI / (2.0 * q);
+        t[s] = cos(theta[s]);                                   // Sect. 2: zeros of T_q
+        lam[s] = ((s & 1) ? -1.0 : 1.0) * sin(theta[s]);        // barycentric weights
+    }
+    std::map<int, int> deconv_of;
+    for (int b = 0; b < nb; ++b) {
+        BandDesc& B = hp.bands[b];
+        const int m = hp.band_m[b];
+        if (B.q == 0) continue;
+        // y interpolation nodes (Y_m) and weights
+        B.ycheb_off = (int32_t)(hp.ycheb.size() / 2);
+        if (m < D) {
+            const double lo = ldexp(hp.y1, -m), hi = ldexp(hp.y1, 1 - m);
+            for (int s = 0; s < q; ++s) {
+                hp.ycheb.push_back(0.5 * (lo + hi) + 0.5 * (hi - lo) * t[s]);
+                hp.ycheb.push_back(lam[s]);
+            }
+        } else {
+            hp.ycheb.push_back(0.5 * ldexp(hp.y1, 1 - D));
+            hp.ycheb.push_back(1.0);
+        }
+        // Chebyshev coefficients of xi -> sum_r K[s,r] L_r^{Omega_l}(xi) per block l
+        B.coef_off = (int32_t)hp.coef.size();
+        if (m < D) {
+            const double ylo = ldexp(hp.y1, -m), yhi = ldexp(hp.y1, 1 - m);
+            for (int ell = B.ell_lo; ell <= B.ell_hi; ++ell) {
+                const double xlo = ldexp(xi1, -ell), xhi = ldexp(xi1, 1 - ell);
+                for (int s = 0; s < q; ++s) {
+                    const double ysn = 0.5 * (ylo + yhi) + 0.5 * (yhi - ylo) * t[s];
+                    for (int i = 0; i < q; ++i) {
+                        double a = 0.0;
+                        for (int r = 0; r < q; ++r) {
+                            const double xr = 0.5 * (xlo + xhi) + 0.5 * (xhi - xlo) * t[r];
+                            a += exp(-ysn * xr) * cos(i * theta[r]);   // K[s,r] T_i(t_r)
+                        }
+                        hp.coef.push_back(a * (i == 0 ? 1.0 : 2.0) / q);
+                    }
+                }
+            }
+        }
+        // deconvolution 1 / (n phi_hat(k')) = 1 / I_0(mw sqrt(b^2 - (2 pi k'/n)^2)), |k'| <= n/4
+        auto it = deconv_of.find(B.log2n);
+        if (it == deconv_of.end()) {
+            const int off = (int)hp.deconv.size();
+            const int64_t n = (int64_t)1 << B.log2n;
+            for (int64_t kp = 0; kp <= n / 4; ++kp) {
+                const double w = 2.0 * PI * (double)kp / (double)n;
+                hp.deconv.push_back(1.0 / bessel_i0(hp.mw * sqrt(hp.kb_b * hp.kb_b - w * w)));
+            }
+            it = deconv_of.emplace(B.log2n, off).first;
+        }
+        B.deconv_off = it->second;
+    }
+    if (hp.coef.empty()) hp.coef.push_back(0.0);
+    if (hp.deconv.empty()) hp.deconv.push_back(0.0);
+    if (hp.ycheb.empty()) { hp.ycheb.push_back(0.0); hp.ycheb.push_back(0.0); }
+    const int TWN = 1 << TW_STAGE_LOG2;
+    hp.tw_stage.resize(2 * TWN);
+    for (int i = 0; i < TWN; ++i) {
+        const double a = 2.0 * PI * (double)i / TWN;
+        hp.tw_stage[2 * i] = cos(a);
+        hp.tw_stage[2 * i + 1] = -sin(a);
+    }
+    const int H = 1 << TW2_HALF;
+    hp.tw_lo.resize(2 * H);
+    hp.tw_hi.resize(2 * H);
+    for (int i = 0; i < H; ++i) {
+        const double a = 2.0 * PI * (double)i / ldexp(1.0, TW2_LOG2);
+        const double bb = 2.0 * PI * (double)i / ldexp(1.0, TW2_LOG2 - TW2_HALF);
+        hp.tw_lo[2 * i] = cos(a);
+        hp.tw_lo[2 * i + 1] = -sin(a);
+        hp.tw_hi[2 * i] = cos(bb);
+        hp.tw_hi[2 * i + 1] = -sin(bb);
+    }
+
+    // ---- workspace layout and work lists
+    int64_t goff = 0, soff = 0;
+    for (int b = 0; b < nb; ++b) {
+        BandDesc& B = hp.bands[b];
+        if (B.q == 0) continue;
+        const int64_t n = (int64_t)1 << B.log2n;
+        B.grid_off = goff;
+        goff += (int64_t)B.q * n;
+        if (B.log2n2 > 0) {
+            B.scratch_off = soff;
+            soff += (int64_t)B.q * n;
+        }
+        if (B.log2n2 == 0) {
+            const int ns = std::max(1, std::min(B.q, 1 << (LOG2P - B.log2n)));
+            for (int s0 = 0; s0 < B.q; s0 += ns) hp.onepass_fwd.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
+            hp.onepass_adj.push_back(FftItem{b, 0, B.q, 0});
+        } else {
+            const int nA = 1 << (B.log2n2 - B.log2b), nB = 1 << (B.log2n1 - B.log2B);
+            for (int s = 0; s < B.q; ++s) {
+                for (int k = 0; k < nA; ++k) hp.passA_fwd.push_back(FftItem{b, s, 1, k});
+                for (int k = 0; k < nB; ++k) hp.passB.push_back(FftItem{b, s, 1, k});
+            }
+            for (int k = 0; k < nA; ++k) hp.passA_adj.push_back(FftItem{b, 0, B.q, k});
+        }
+    }
+    for (int b = 0; b < nb; ++b) {
+        const BandDesc& B = hp.bands[b];
+        for (int64_t s = 0; s < B.node_count; s += GATHER_THREADS)
+            hp.nodes.push_back(NodeItem{b, (int32_t)std::min<int64_t>(GATHER_THREADS, B.node_count - s), B.node_start + s});
+    }
+    hp.grid_elems = goff;
+    hp.scratch_elems = soff;
+    const size_t S = hp.elem_bytes();
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    hp.off_grid = 0;
+    hp.off_scratch = al(hp.off_grid + (size_t)goff * S);
+    hp.off_acc = al(hp.off_scratch + (size_t)soff * S);
+    hp.ws_bytes = al(hp.off_acc + (size_t)N * 16);
+
+    // ---- algorithmic model of one forward: every band grid written once and
+    // read once, c read once per band, node records and results once
+    double bytes = (double)M * (16.0 + 4.0 + S);
+    double flops = 0;
+    for (int b = 0; b < nb; ++b) {
+        const BandDesc& B = hp.bands[b];
+        if (B.q == 0) continue;
+        const double n = ldexp(1.0, B.log2n);
+        bytes += 2.0 * B.q * n * S + (double)B.kmax * S;
+        flops += 2.0 * B.q * B.q * (double)B.kmax + 8.0 * B.q * (double)B.kmax;   // contraction, scaling
+        flops += 5.0 * B.q * n * B.log2n;                                          // FFT
+        flops += (double)B.node_count * (8.0 * B.q * 2 * hp.mw + 4.0 * B.q);       // gather, weighting
+    }
+    hp.bytes_forward = bytes;
+    hp.flops_forward = flops;
+    return FLT_OK;
+}
+
+}  // namespace flt

@@ -1,0 +1,56 @@
+// Host planner: parameters (Def. 3.2, Lemma 4.1), node partition and sort,
+// interpolation / window / twiddle tables, work lists and workspace layout.
+// Pure C++ (FP64); the HIP library uploads what it builds.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "flt_types.h"
+
+namespace flt {
+
+struct HostPlan {
+    // parameters
+    int64_t N = 0, M = 0;
+    int dtype = 0;
+    double eps = 0, eps_K = 0, eps_A = 0, y1 = 0;
+    int q = 0, D = 0, n_xi = 0, mw = 0;
+    double kb_b = 0;
+    int64_t nodes_z0 = 0;
+
+    // bands: occupied Y_m / Y_D first (ascending m), then the constant band (Z^0) if any
+    std::vector<BandDesc> bands;
+    std::vector<int32_t> band_m;      // paper index m of each band (D for Y_D, 0 for Z^0)
+    std::vector<int32_t> node_band;   // caller order: 0 = Z^0, m, D
+
+    // sorted nodes
+    std::vector<double> nx, ny;
+    std::vector<int32_t> perm;
+
+    // tables in FP64 (rounded to the working type on upload)
+    std::vector<double> coef, deconv, ycheb;
+    std::vector<double> tw_stage, tw_lo, tw_hi;   // interleaved complex
+
+    // work lists
+    std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj;
+    std::vector<NodeItem> nodes;
+
+    // workspace layout (bytes)
+    int64_t grid_elems = 0, scratch_elems = 0;
+    size_t off_grid = 0, off_scratch = 0, off_acc = 0, ws_bytes = 0;
+
+    // algorithmic model
+    double bytes_forward = 0, flops_forward = 0;
+
+    size_t elem_bytes() const { return dtype == 1 ? 8 : 16; }   // complex element
+};
+
+// Returns FLT_OK or a negative FLT_E* code (see flt.h).
+int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype);
+
+// Modified Bessel function I_0 by its power series (host, FP64).
+double bessel_i0(double x);
+
+}  // namespace flt

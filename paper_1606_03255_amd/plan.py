@@ -1,0 +1,205 @@
+"""Python face of the fast Fourier-Laplace transform.
+
+``Plan`` wraps one ``flt_plan`` of the C ABI: torch supplies the device
+memory (workspace, outputs) and the stream; every step of the transform runs
+in the library's kernels.  ``FourierLaplace`` is the autograd Function that
+pairs the forward with its hand-written backward (adjoint for dL/dc, the
+derivative transform for dL/dz).
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _as_host_z(z):
+    try:
+        import torch
+        if isinstance(z, torch.Tensor):
+            z = z.detach().to("cpu", torch.complex128).numpy()
+    except ImportError:  # pragma: no cover
+        pass
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).reshape(-1))
+    return z
+
+
+def _dtype_code(dtype):
+    if dtype in ("c64", "complex64", L.FLT_C64):
+        return L.FLT_C64
+    if dtype in ("c128", "complex128", L.FLT_C128):
+        return L.FLT_C128
+    try:
+        import torch
+        if dtype == torch.complex64:
+            return L.FLT_C64
+        if dtype == torch.complex128:
+            return L.FLT_C128
+    except ImportError:  # pragma: no cover
+        pass
+    raise ValueError("dtype must be complex64 or complex128")
+
+
+class Plan:
+    """Plan for N coefficients at the nodes z (Im z >= 0) with accuracy eps.
+
+    dtype ``complex64`` selects the FP32 form (FP32 bulk arithmetic, FP64
+    phase reduction and per-node sums); ``complex128`` the plain FP64 form.
+    With ``host_only=True`` only the host-side plan is built (parameters,
+    partition, byte model) and no GPU is touched.
+    """
+
+    def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False):
+        self._lib = L.load()
+        self._ptr = ctypes.c_void_p()
+        self.N = int(N)
+        zh = _as_host_z(z)
+        self.M = int(zh.shape[0])
+        self.dtype_code = _dtype_code(dtype)
+        self.host_only = bool(host_only)
+        flags = L.FLT_FLAG_HOST_ONLY if host_only else 0
+        self._ws = None
+        if host_only:
+            rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M,
+                                           zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           float(eps), self.dtype_code, flags)
+            L.check(rc, "flt_plan_create")
+            self.device = None
+            return
+        import torch
+        self.device = torch.device(device if device is not None else "cuda", )
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M,
+                                           zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           float(eps), self.dtype_code, flags)
+            L.check(rc, "flt_plan_create")
+            nbytes = ctypes.c_size_t()
+            L.check(self._lib.flt_plan_workspace_size(self._ptr, ctypes.byref(nbytes)), "flt_plan_workspace_size")
+            self._ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+            L.check(self._lib.flt_plan_set_workspace(self._ptr, ctypes.c_void_p(self._ws.data_ptr()),
+                                                     self._ws.numel()), "flt_plan_set_workspace")
+
+    # ---------------------------------------------------------------- queries
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex64 if self.dtype_code == L.FLT_C64 else torch.complex128
+
+    def info(self):
+        inf = L.FltInfo()
+        L.check(self._lib.flt_plan_info(self._ptr, ctypes.byref(inf)), "flt_plan_info")
+        return {name: getattr(inf, name) for name, _ in L.FltInfo._fields_}
+
+    def bands(self):
+        out = []
+        for i in range(self.info()["num_bands"]):
+            b = L.FltBandInfo()
+            L.check(self._lib.flt_plan_band(self._ptr, i, ctypes.byref(b)), "flt_plan_band")
+            out.append({name: getattr(b, name) for name, _ in L.FltBandInfo._fields_ if name != "pad"})
+        return out
+
+    def node_bands(self):
+        out = np.empty(self.M, np.int32)
+        L.check(self._lib.flt_plan_node_bands(self._ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+                "flt_plan_node_bands")
+        return out
+
+    # ------------------------------------------------------------- transforms
+    def _prep(self, t, n, name):
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError("%s must be a torch tensor on the plan's device" % name)
+        if t.dtype != self.torch_dtype:
+            raise TypeError("%s has dtype %s, the plan computes in %s" % (name, t.dtype, self.torch_dtype))
+        if t.device != self.device:
+            raise ValueError("%s is on %s, the plan lives on %s" % (name, t.device, self.device))
+        if t.numel() != n:
+            raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+        return t.contiguous()
+
+    def _run(self, fn, x, nin, nout, out, name):
+        import torch
+        if self.host_only:
+            raise RuntimeError("host-only plan")
+        x = self._prep(x, nin, name)
+        if out is None:
+            out = torch.empty(nout, dtype=self.torch_dtype, device=self.device)
+        else:
+            out = self._prep(out, nout, "out")
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(fn(self._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                   ctypes.c_void_p(stream)), fn.__name__)
+        return out
+
+    def forward(self, c, out=None):
+        """f_j ~ sum_k c_k exp(2 pi i k z_j); c: complex[N] on the device."""
+        return self._run(self._lib.flt_forward, c, self.N, self.M, out, "c")
+
+    def derivative(self, c, out=None):
+        """f'(z_j) ~ sum_k 2 pi i k c_k exp(2 pi i k z_j)."""
+        return self._run(self._lib.flt_derivative, c, self.N, self.M, out, "c")
+
+    def adjoint(self, g, out=None):
+        """h_k ~ sum_j g_j conj(exp(2 pi i k z_j)), k < N."""
+        return self._run(self._lib.flt_adjoint, g, self.M, self.N, out, "g")
+
+    def close(self):
+        if getattr(self, "_ptr", None) and self._ptr.value:
+            if self.device is not None:
+                import torch
+                torch.cuda.synchronize(self.device)
+            self._lib.flt_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_function():
+    import torch
+
+    class FourierLaplace(torch.autograd.Function):
+        """f = C(z) c with C_jk = exp(2 pi i k z_j), through ``plan``.
+
+        Backward (PyTorch's conjugate-Wirtinger convention):
+            dL/dc = C^H grad_f                      (plan.adjoint)
+            dL/dz = grad_f * conj(f'(z))            (plan.derivative)
+        ``z`` must hold the values the plan was built from."""
+
+        @staticmethod
+        def forward(ctx, c, z, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(c)
+            ctx.z_dtype = z.dtype
+            return plan.forward(c)
+
+        @staticmethod
+        def backward(ctx, grad_f):
+            (c,) = ctx.saved_tensors
+            plan = ctx.plan
+            grad_f = grad_f.to(plan.torch_dtype).contiguous()
+            gc = plan.adjoint(grad_f) if ctx.needs_input_grad[0] else None
+            gz = None
+            if ctx.needs_input_grad[1]:
+                fp = plan.derivative(c.detach())
+                gz = (grad_f * fp.conj()).to(ctx.z_dtype)
+            return gc, gz, None
+
+    return FourierLaplace
+
+
+_FL = None
+
+
+def fourier_laplace(c, z, plan):
+    """Differentiable f = C(z) c evaluated by ``plan`` (see FourierLaplace)."""
+    global _FL
+    if _FL is None:
+        _FL = _make_function()
+    return _FL.apply(c, z, plan)

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every
+symbol the header declares; host-only plans report the parameters of
+Def. 3.2 / Lemma 4.1 and the partition the oracle computes; invalid input is
+rejected with the documented codes before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1606_03255_amd as flt
+from paper_1606_03255_amd import _lib as L
+from paper_1606_03255_amd import inputs
+from oracle import method as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.load()
+    hdr = open(os.path.join(ROOT, "include", "flt.h")).read()
+    declared = set(re.findall(r"\b(flt_[a-z_]+)\s*\(", hdr))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("N,eps,dt", [(256, 1e-10, "complex128"), (1 << 14, 1e-6, "complex64"),
+                                      (1 << 20, 1e-11, "complex128"), (3, 1e-4, "complex64"), (1, 1e-6, "complex64")])
+def test_host_plan_parameters_and_partition(N, eps, dt):
+    rng = np.random.default_rng(N)
+    z = np.concatenate([inputs.nodes_disk(rng, 500), inputs.nodes_annulus(rng, 500)])
+    z[0] = complex(0.1, np.inf)
+    z[1] = 0.5 + 0j
+    p = flt.Plan(N, z, eps, dt, host_only=True)
+    info = p.info()
+    P = O.Params(N, eps)
+    assert (info["q"], info["D"], info["n_xi"], info["mw"]) == (P.q, P.D, P.n, P.mw)
+    assert info["eps_K"] == pytest.approx(eps / 3) and info["eps_A"] == pytest.approx(eps / 3)
+    x, y = O.polar(z)
+    assert np.array_equal(p.node_bands(), O.node_band(P, y))
+    bands = p.bands()
+    assert sum(b["nodes"] for b in bands) + info["nodes_z0"] == len(z) or N == 1
+    for b in bands:
+        m = b["m"]
+        if m < P.D:
+            assert (b["ell_lo"], b["ell_hi"]) == (P.ell(m), P.L(m))
+            assert b["q"] == P.q
+            assert (b["n"], b["k0"]) == P.grid(m)
+        else:
+            assert b["q"] == 1 and (b["n"], b["k0"]) == P.grid(P.D)
+    p.close()
+
+
+def _create(N, M, z, eps, dtype, flags=L.FLT_FLAG_HOST_ONLY):
+    lib = L.load()
+    ptr = ctypes.c_void_p()
+    zz = np.ascontiguousarray(z, np.complex128)
+    rc = lib.flt_plan_create(ctypes.byref(ptr), N, M, zz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                             eps, dtype, flags)
+    if rc == 0:
+        lib.flt_plan_destroy(ptr)
+    return rc
+
+
+def test_error_codes():
+    z = np.array([0.1 + 0.1j, 0.2 + 0.0j])
+    assert _create(10, 2, z, 1e-6, 1) == 0
+    assert _create(0, 2, z, 1e-6, 1) == -1                               # N < 1: EINVAL
+    assert _create(10, 0, z, 1e-6, 1) == -1                               # M < 1
+    assert _create(10, 2, z, 1e-6, 3) == -1                               # dtype
+    assert _create(10, 2, z, 1e-6, 1, flags=1 << 7) == -1                 # flags
+    assert _create(10, 2, z, 1.5, 1) == -2                                # eps not in (0,1)
+    assert _create(10, 2, z, 0.0, 1) == -2
+    assert _create(10, 2, np.array([0.1 - 1e-9j, 0.2]), 1e-6, 1) == -2    # Im z < 0
+    assert _create(10, 2, np.array([complex(np.nan, 0.1), 0.2]), 1e-6, 1) == -2
+    assert _create(10, 2, np.array([complex(np.inf, 0.1), 0.2]), 1e-6, 1) == -2
+    assert _create(10, 2, np.array([complex(0.1, np.nan), 0.2]), 1e-6, 1) == -2
+    assert _create(10, 2, np.array([complex(0.1, np.inf), 0.2]), 1e-6, 1) == 0   # w = 0 is fine
+    assert _create(10, 2, z, 1e-7, 1) == -3                               # below the FP32 floor
+    assert _create(10, 2, z, 1e-15, 2) == -3                              # below the FP64 floor
+    assert _create((1 << 21) + 2, 2, z, 1e-6, 1) == -8                    # beyond the largest grid
+
+
+def test_host_only_plan_refuses_device_work():
+    lib = L.load()
+    ptr = ctypes.c_void_p()
+    z = np.ascontiguousarray(np.array([0.1 + 0.1j, 0.2 + 0.0j]))
+    assert lib.flt_plan_create(ctypes.byref(ptr), 10, 2, z.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               1e-6, 1, L.FLT_FLAG_HOST_ONLY) == 0
+    dummy = ctypes.c_void_p(16)
+    assert lib.flt_forward(ptr, dummy, dummy, None) == -6
+    assert lib.flt_adjoint(ptr, dummy, dummy, None) == -6
+    assert lib.flt_plan_set_workspace(ptr, dummy, 1 << 30) == -6
+    assert lib.flt_forward(None, dummy, dummy, None) == -1
+    size = ctypes.c_size_t()
+    assert lib.flt_plan_workspace_size(ptr, ctypes.byref(size)) == 0 and size.value > 0
+    assert lib.flt_strerror(-4) == b"workspace missing or too small"
+    lib.flt_plan_destroy(ptr)
+    lib.flt_plan_destroy(None)
+
+
+def test_byte_model_large_workload():
+    w = inputs.workload("large")
+    p = flt.Plan(w["N"], w["z"], 1e-6, "complex64", host_only=True)
+    info = p.info()
+    bands = p.bands()
+    S = 8
+    expect = w["M"] * (16 + 4 + S) + sum(2 * b["q"] * b["n"] * S + min(b["K"], w["N"] - 1) * S for b in bands)
+    assert info["bytes_forward"] == pytest.approx(expect, rel=1e-12)
+    assert (info["q"], info["D"]) == (12, 47)

@@ -1,0 +1,190 @@
+"""GPU parity of the HIP path (through the C ABI) against the oracle.
+
+Bars (all relative to the 1-norm of the input, the paper's E of eq. 5.1):
+* against the FP64 direct sums: E <= eps (Thm 4.3) for the FP64 form, and
+  E <= eps for the FP32 form with eps >= 1e-6;
+* against Algorithm 2 step by step with the same Kaiser-Bessel box (FP64):
+  <= 1e-13, i.e. the same approximation up to rounding.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import method as O
+from paper_1606_03255_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _run(torch, c, z, eps, dtype, op="forward", N=None):
+    from paper_1606_03255_amd import Plan
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    N = len(c) if N is None else N
+    plan = Plan(N, z, eps, tdt)
+    x = torch.from_numpy(np.ascontiguousarray(c)).to("cuda", tdt)
+    out = getattr(plan, op)(x)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy().astype(np.complex128)
+    plan.close()
+    return res
+
+
+def _nodes(rng, M, kind):
+    if kind == "disk":
+        return inputs.nodes_disk(rng, M)
+    if kind == "annulus":
+        return inputs.nodes_annulus(rng, M)
+    return np.concatenate([inputs.nodes_annulus(rng, M // 2), inputs.nodes_disk(rng, M - M // 2)])
+
+
+CASES = [
+    # N, M, eps, dtype, nodes      (one-pass only / two-pass FFT bands / ragged sizes)
+    (256, 256, 1e-10, "c128", "disk"),
+    (256, 256, 1e-6, "c64", "mixed"),
+    (1000, 777, 1e-8, "c128", "mixed"),
+    (5000, 900, 1e-11, "c128", "mixed"),
+    (9000, 1500, 1e-6, "c64", "mixed"),
+    (1 << 14, 1 << 14, 1e-11, "c128", "disk"),
+    (1 << 14, 1 << 14, 1e-6, "c64", "disk"),
+    (70000, 3000, 1e-6, "c64", "annulus"),
+    (70000, 3000, 1e-12, "c128", "annulus"),
+]
+
+
+@pytest.mark.parametrize("N,M,eps,dtype,kind", CASES)
+def test_forward_vs_direct(torch, N, M, eps, dtype, kind):
+    _say("forward", N, M, eps, dtype, kind)
+    rng = np.random.default_rng(N + M)
+    c = inputs.coefficients(rng, N)
+    if dtype == "c64":
+        c = c.astype(np.complex64).astype(np.complex128)
+    z = _nodes(rng, M, kind)
+    f = _run(torch, c, z, eps, dtype)
+    E = np.abs(f - oracle.forward(c, z)).max() / np.abs(c).sum()
+    _say("   E =", E)
+    assert E <= eps
+
+
+@pytest.mark.parametrize("N,M,eps,dtype,kind", [c for c in CASES if c[0] * c[1] <= 2e7])
+def test_adjoint_and_derivative_vs_direct(torch, N, M, eps, dtype, kind):
+    _say("adjoint/derivative", N, M, eps, dtype, kind)
+    rng = np.random.default_rng(N + 2 * M)
+    z = _nodes(rng, M, kind)
+    g = inputs.coefficients(rng, M)
+    c = inputs.coefficients(rng, N)
+    if dtype == "c64":
+        g = g.astype(np.complex64).astype(np.complex128)
+        c = c.astype(np.complex64).astype(np.complex128)
+    h = _run(torch, g, z, eps, dtype, "adjoint", N=N)
+    Eh = np.abs(h - oracle.adjoint(g, z, N)).max() / np.abs(g).sum()
+    fp = _run(torch, c, z, eps, dtype, "derivative")
+    Ed = np.abs(fp - oracle.derivative(c, z)).max() / np.abs(2 * np.pi * np.arange(N) * c).sum()
+    _say("   E adjoint =", Eh, " E derivative =", Ed)
+    assert Eh <= eps
+    assert Ed <= eps
+
+
+@pytest.mark.parametrize("N,M,eps", [(256, 256, 1e-10), (3000, 500, 1e-8), (300, 200, 1e-6)])
+def test_fp64_matches_algorithm2_step_by_step(torch, N, M, eps):
+    """Same readings, same Kaiser-Bessel box: agreement to rounding."""
+    _say("alg2 parity", N, M, eps)
+    rng = np.random.default_rng(7 * N + M)
+    c = inputs.coefficients(rng, N)
+    z = _nodes(rng, M, "mixed")
+    n1 = np.abs(c).sum()
+    f = _run(torch, c, z, eps, "c128")
+    assert np.abs(f - O.alg2_forward(c, z, eps, "nfft")).max() <= 1e-13 * n1
+    g = inputs.coefficients(rng, M)
+    h = _run(torch, g, z, eps, "c128", "adjoint", N=N)
+    assert np.abs(h - O.alg2_adjoint(g, z, N, eps, "nfft")).max() <= 1e-13 * np.abs(g).sum()
+
+
+def test_edge_cases(torch):
+    rng = np.random.default_rng(99)
+    # N = 1: f = c_0 everywhere; N = 2: a single frequency
+    for N in (1, 2, 3, 17):
+        _say("edge N", N)
+        c = inputs.coefficients(rng, N)
+        z = _nodes(rng, 50, "mixed")
+        z[0] = complex(0.25, np.inf)   # w = 0
+        z[1] = 0.999999999999 + 0j     # on the circle, x -> 1
+        z[2] = 3.5 + 0j                # Re z outside [0, 1)
+        z[3] = -0.25 + 1e-9j
+        for dt, eps in (("c128", 1e-12), ("c64", 1e-6)):
+            cc = c.astype(np.complex64).astype(np.complex128) if dt == "c64" else c
+            f = _run(torch, cc, z, eps, dt)
+            assert np.abs(f - oracle.forward(cc, z)).max() <= eps * np.abs(cc).sum()
+    # M = 1; nodes exactly on band boundaries y = y_1 2^-m
+    N = 600
+    c = inputs.coefficients(rng, N)
+    P = O.Params(N, 1e-9)
+    ys = np.array([P.y1 * 2.0 ** -m for m in range(1, 30)] + [P.y1, 0.0])
+    z = rng.random(len(ys)) + 1j * ys / (2 * np.pi)
+    for zz in (z[:1], z):
+        _say("edge boundaries", len(zz))
+        f = _run(torch, c, zz, 1e-9, "c128")
+        assert np.abs(f - oracle.forward(c, zz)).max() <= 1e-9 * np.abs(c).sum()
+    # adversarial coefficients: every phase aligned at one node
+    z = _nodes(rng, 64, "annulus")
+    w = np.exp(2j * np.pi * z[5])
+    k = np.arange(3000)
+    c = np.conj(w ** k) / np.maximum(np.abs(w ** k), 1e-300)
+    f = _run(torch, c, z, 1e-10, "c128")
+    assert np.abs(f - oracle.forward(c, z)).max() <= 1e-10 * np.abs(c).sum()
+
+
+def test_dot_identity(torch):
+    """<C c, g> = <c, C^H g> for the realised operator (to rounding)."""
+    rng = np.random.default_rng(5)
+    N, M = 5000, 2000
+    z = _nodes(rng, M, "mixed")
+    c = inputs.coefficients(rng, N)
+    g = inputs.coefficients(rng, M)
+    f = _run(torch, c, z, 1e-9, "c128")
+    h = _run(torch, g, z, 1e-9, "c128", "adjoint", N=N)
+    lhs = np.vdot(g, f)
+    rhs = np.vdot(h, c)
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(c).sum() * np.abs(g).sum()
+
+
+def _sample_nodes(plan_bands, z, rng, k=1500):
+    """Every node of each band with < 64 nodes plus a random sample."""
+    idx = set(rng.choice(len(z), size=min(k, len(z)), replace=False).tolist())
+    for b in np.unique(plan_bands):
+        sel = np.nonzero(plan_bands == b)[0]
+        if len(sel) < 64:
+            idx.update(sel.tolist())
+    return np.array(sorted(idx))
+
+
+@pytest.mark.parametrize("dtype,eps", [("c64", 1e-6), ("c128", 1e-11)])
+def test_large_workload_sampled(torch, dtype, eps):
+    """N = M = 2^20, half annulus / half disk, in the launch configuration the
+    benchmark times; checked against the direct sums on sampled nodes."""
+    from paper_1606_03255_amd import Plan
+    _say("large", dtype, eps)
+    w = inputs.workload("large")
+    c = w["c"].astype(np.complex128)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    plan = Plan(w["N"], w["z"], eps, tdt)
+    f = plan.forward(torch.from_numpy(c).to("cuda", tdt)).cpu().numpy().astype(np.complex128)
+    sel = _sample_nodes(plan.node_bands(), w["z"], np.random.default_rng(0))
+    plan.close()
+    ref = oracle.forward(c, w["z"][sel])
+    E = np.abs(f[sel] - ref).max() / np.abs(c).sum()
+    _say("   sampled nodes", len(sel), "E =", E)
+    assert E <= eps
