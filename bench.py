@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast Fourier-Laplace transform on one MI355X.
+
+Workload: N = M = 2^20, c_k complex64 with Re/Im ~ N(0,1); the first M/2 nodes
+uniform by area in the annulus 1-1e-3 < |w| <= 1, the rest uniform by area in
+the unit disk (seed 3, see paper_1606_03255_amd/inputs.py).
+
+value      node evaluations per second of the FP32 form (eps = 1e-6): M times
+           the number of timed forward calls over their wall time, inputs
+           resident in HBM, plan built beforehand (plan time reported apart).
+fwd_bwd    forward + adjoint (dL/dc) + derivative (dL/dz) per step, for the
+           FP32 form and for the plain FP64 path (eps = 1e-11) on the same
+           inputs; speedup = t(FP64) / t(FP32).
+roofline   the dominant kernel's algorithmic bytes per launch over its launch
+           duration (HIP events recorded between the launches on the stream
+           the kernels run on), against the 8 TB/s HBM peak.
+cpu_baseline  the FP64 direct-sum oracle on a random sample of the nodes, on
+           the host cores; the same sample (plus every node of sparsely filled
+           bands) gives the error E of both GPU forms against it.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node evals/s at N=M=2^20, err<=1e-6 vs FP64 direct; fwd+bwd speedup vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+STAGES = ("onepass_fft", "passA_fft", "passB_fft", "gather")
+KERNEL_NAMES = {"onepass_fft": "k_onepass_fwd", "passA_fft": "k_passA_fwd", "passB_fft": "k_passB",
+                "gather": "k_gather"}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels_impl.h", "kernels.hip", "flt_types.h"):
+        with open(os.path.join(ROOT, "paper_1606_03255_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stage_bytes(plan, S):
+    """Algorithmic HBM bytes per launch of each forward stage.
+    FFT stages: each band grid written once by the stage that produces it and
+    read once by the stage that consumes it; c read once per band.  Gather:
+    node records (x, y: 16 B, index 4 B) and the result, plus the band grid
+    cells its nodes touch (at most the whole grid, at most 2 mw cells per
+    column and node)."""
+    info = plan.info()
+    mw = info["mw"]
+    b = {k: 0.0 for k in STAGES}
+    for band in plan.bands():
+        q, n, nodes = band["q"], band["n"], band["nodes"]
+        kmax = min(band["K"], plan.N - 1)
+        grid = q * n * S
+        if band["passes"] == 1:
+            b["onepass_fft"] += grid + kmax * S
+        else:
+            b["passA_fft"] += grid + kmax * S
+            b["passB_fft"] += 2 * grid
+        b["gather"] += min(grid, nodes * q * 2 * mw * S)
+    b["gather"] += plan.M * (16 + 4 + S)
+    return b
+
+
+def time_steps(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return t0.elapsed_time(t1) / steps, wall
+
+
+def traffic_for(kernel):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, or
+    None if it was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_large_fp32.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    v = rec.get("kernels", {}).get(KERNEL_NAMES[kernel])
+    return None if v is None else v.get("bytes_per_launch")
+
+
+def cpu_baseline(w, f32, f64, plan_bands, target_s=12.0):
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(12345)
+    c = w["c"].astype(np.complex128)
+    z = w["z"]
+    M = len(z)
+    oracle.load()
+    cal = rng.choice(M, size=256, replace=False)
+    t = time.perf_counter()
+    oracle.forward(c, z[cal])
+    tc = time.perf_counter() - t
+    S = int(min(M, max(256, 256 * target_s / max(tc, 1e-3))))
+    sel = rng.choice(M, size=S, replace=False)
+    t = time.perf_counter()
+    ref = oracle.forward(c, z[sel])
+    dt = time.perf_counter() - t
+    # error check: the timed sample plus every node of bands holding < 64 nodes
+    extra = []
+    for bnd in np.unique(plan_bands):
+        idx = np.nonzero(plan_bands == bnd)[0]
+        if len(idx) < 64:
+            extra.extend(idx.tolist())
+    extra = np.setdiff1d(np.array(extra, dtype=np.int64), sel)
+    ref_x = oracle.forward(c, z[extra]) if len(extra) else np.zeros(0, np.complex128)
+    allsel = np.concatenate([sel, extra])
+    allref = np.concatenate([ref, ref_x])
+    n1 = np.abs(c).sum()
+    E32 = float(np.abs(f32[allsel] - allref).max() / n1)
+    E64 = float(np.abs(f64[allsel] - allref).max() / n1)
+    return {"value": S / dt, "unit": "node evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d of the %d nodes drawn uniformly at random (seed 12345), all N=%d coefficients; "
+                      "FP64 direct sum, %.1f s" % (S, M, len(c), dt)}, E32, E64, int(len(allsel))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--forward-only", action="store_true", help="skip the fwd+bwd and FP64 legs")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this transform runs on one GPU; --gpus %d is not supported (use --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1606_03255_amd import Plan, inputs
+
+    def log(*a):
+        print("[bench]", *a, file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    w = inputs.workload("large")
+    N, M = w["N"], w["M"]
+    t = time.perf_counter()
+    p32 = Plan(N, w["z"], 1e-6, torch.complex64, device=dev)
+    plan32_ms = (time.perf_counter() - t) * 1e3
+    log("FP32 plan built in %.0f ms" % plan32_ms)
+    c32 = torch.from_numpy(w["c"]).to(dev)
+    rng = np.random.default_rng(7)
+    g = (rng.standard_normal(M) + 1j * rng.standard_normal(M)) * np.sqrt(0.5)
+    g32 = torch.from_numpy(g.astype(np.complex64)).to(dev)
+    f32_out = torch.empty(M, dtype=torch.complex64, device=dev)
+
+    ms_fwd, wall = time_steps(torch, lambda: p32.forward(c32, out=f32_out), args.steps, args.warmup)
+    value = M / (ms_fwd * 1e-3)
+    log("FP32 forward %.3f ms/step -> %.3e node evals/s" % (ms_fwd, value))
+    f32 = f32_out.cpu().numpy().astype(np.complex128)
+
+    # per-kernel durations (HIP events between the launches on the current stream)
+    reps = max(3, min(args.steps, 10))
+    acc = [0.0] * 4
+    for _ in range(reps):
+        _, ms = p32.profile_forward(c32)
+        acc = [a + b for a, b in zip(acc, ms)]
+    stage_ms = {k: v / reps for k, v in zip(STAGES, acc)}
+    sb = stage_bytes(p32, 8)
+    dom = max(STAGES, key=lambda k: stage_ms[k])
+    achieved = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    traffic = traffic_for(dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": KERNEL_NAMES[dom],
+                "bytes_per_launch": sb[dom], "ms_per_launch": round(stage_ms[dom], 4)}
+    log("stages ms", {k: round(v, 4) for k, v in stage_ms.items()})
+
+    fwd_bwd = None
+    f64 = None
+    E64 = None
+    if not args.forward_only:
+        def step32():
+            p32.forward(c32, out=f32_out)
+            p32.adjoint(g32)
+            p32.derivative(c32)
+        ms32, _ = time_steps(torch, step32, max(3, args.steps // 2), 1)
+        p64 = Plan(N, w["z"], 1e-11, torch.complex128, device=dev)
+        c64 = c32.to(torch.complex128)
+        g64 = g32.to(torch.complex128)
+        f64_out = torch.empty(M, dtype=torch.complex128, device=dev)
+
+        def step64():
+            p64.forward(c64, out=f64_out)
+            p64.adjoint(g64)
+            p64.derivative(c64)
+        ms64, _ = time_steps(torch, step64, max(3, args.steps // 2), 1)
+        ms64_fwd, _ = time_steps(torch, lambda: p64.forward(c64, out=f64_out), max(3, args.steps // 2), 1)
+        f64 = f64_out.cpu().numpy()
+        p64.close()
+        fwd_bwd = {"ms_fp32_form": round(ms32, 4), "ms_fp64_path": round(ms64, 4),
+                   "speedup": round(ms64 / ms32, 3), "ms_fp64_forward": round(ms64_fwd, 4)}
+        log("fwd+bwd FP32 %.3f ms, FP64 %.3f ms, speedup %.2f" % (ms32, ms64, ms64 / ms32))
+
+    cpu = None
+    E32 = None
+    n_checked = 0
+    if not args.no_cpu_baseline:
+        cpu, E32, E64c, n_checked = cpu_baseline(w, f32, f64 if f64 is not None else f32, p32.node_bands())
+        E64 = E64c if f64 is not None else None
+        log("cpu baseline", cpu, "E32", E32, "E64", E64)
+
+    info = p32.info()
+    rec = {
+        "metric": METRIC, "value": value, "unit": "node evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_fwd, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "N=M=2^20, half annulus 1-1e-3<|w|<=1, half disk, complex64, eps=1e-6, FP32 form",
+                   "N": N, "M": M, "eps": 1e-6, "q": info["q"], "D": info["D"], "mw": info["mw"],
+                   "bands": info["num_bands"], "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "error": {"E_fp32_form": E32, "E_fp64_path": E64, "nodes_checked": n_checked},
+        "fwd_bwd": fwd_bwd,
+        "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+        "stage_bytes": sb,
+        "plan_ms": round(plan32_ms, 1),
+        "bytes_forward_model": info["bytes_forward"],
+        "wall_s_timed": round(wall, 3),
+    }
+    p32.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

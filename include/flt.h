@@ -130,6 +130,12 @@ int flt_derivative(flt_plan* plan, const void* c, void* fp, void* stream);
  * Error <= eps * sum|g_j|. */
 int flt_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream);
 
+/* Measurement: run one forward on `stream` with HIP events recorded between
+ * its four kernel launches and wait for it; stage_ms (host, 4 doubles)
+ * receives the durations of (one-pass band FFTs, pass A, pass B, window
+ * gather) in milliseconds.  Same arguments and results as flt_forward. */
+int flt_profile_forward(flt_plan* plan, const void* c, void* f, void* stream, double* stage_ms);
+
 const char* flt_strerror(int code);
 int flt_last_hip_error(void); /* hipError_t of the last failing HIP call in this thread */
 

@@ -146,7 +146,7 @@ int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, doubl
 void flt_plan_destroy(flt_plan* p)
 {
     if (!p) return;
-    if (p->dev) hipFree(p->dev);
+    if (p->dev) (void)hipFree(p->dev);
     delete p;
 }
 
@@ -256,6 +256,32 @@ int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream)
                                 hp.off_acc, (hipStream_t)stream)
         : launch_adjoint<double>(p->lists, p->pv64, hp.N, hp.grid_elems, g, c_out, p->ws, hp.off_grid,
                                  hp.off_scratch, hp.off_acc, (hipStream_t)stream);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+
+int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, double* stage_ms)
+{
+    int rc = check_call(p, c, f);
+    if (rc != FLT_OK) return rc;
+    if (!stage_ms) return FLT_EINVAL;
+    const HostPlan& hp = p->hp;
+    hipEvent_t ev[5] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    if (e == hipSuccess)
+        e = hp.dtype == FLT_C64
+            ? launch_forward<float>(p->lists, p->pv32, c, f, p->ws, hp.off_grid, hp.off_scratch, 0,
+                                    (hipStream_t)stream, ev)
+            : launch_forward<double>(p->lists, p->pv64, c, f, p->ws, hp.off_grid, hp.off_scratch, 0,
+                                     (hipStream_t)stream, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        float ms = 0;
+        e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+        stage_ms[i] = ms;
+    }
+    for (int i = 0; i < 5; ++i)
+        if (ev[i]) (void)hipEventDestroy(ev[i]);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
 

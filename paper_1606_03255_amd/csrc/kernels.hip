@@ -114,21 +114,25 @@ static void launch_spread_mw(const DevLists& L, const PlanView<T>& pv, const cpl
 
 template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* cv, void* fv, char* ws,
-                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st)
+                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st, hipEvent_t* ev)
 {
     const cplx<T>* c = (const cplx<T>*)cv;
     cplx<T>* f = (cplx<T>*)fv;
     cplx<T>* grids = (cplx<T>*)(ws + off_grid);
     cplx<T>* scratch = (cplx<T>*)(ws + off_scratch);
+    if (ev) (void)hipEventRecord(ev[0], st);
     if (L.n_onepass_fwd)
         hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(L.n_onepass_fwd), dim3(FFT_THREADS), 0, st, pv, L.onepass_fwd, c,
                            grids, deriv);
+    if (ev) (void)hipEventRecord(ev[1], st);
     if (L.n_passA_fwd)
         hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
                            scratch, deriv);
+    if (ev) (void)hipEventRecord(ev[2], st);
     if (L.n_passB)
         hipLaunchKernelGGL(k_passB<T>, dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
                            (const cplx<T>*)scratch, (int64_t)0, grids, +1);
+    if (ev) (void)hipEventRecord(ev[3], st);
     if (L.n_nodes) {
         switch (pv.mw) {
 #define G(MWV) case MWV: launch_gather_mw<T, MWV>(L, pv, c, grids, f, !deriv, st); break;
@@ -137,6 +141,7 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* 
             default: return hipErrorInvalidValue;
         }
     }
+    if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
 
@@ -174,9 +179,9 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, int64_t N, i
 }
 
 template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const void*, void*, char*, size_t,
-                                          size_t, int, hipStream_t);
+                                          size_t, int, hipStream_t, hipEvent_t*);
 template hipError_t launch_forward<double>(const DevLists&, const PlanView<double>&, const void*, void*, char*, size_t,
-                                           size_t, int, hipStream_t);
+                                           size_t, int, hipStream_t, hipEvent_t*);
 template hipError_t launch_adjoint<float>(const DevLists&, const PlanView<float>&, int64_t, int64_t, const void*,
                                           void*, char*, size_t, size_t, size_t, hipStream_t);
 template hipError_t launch_adjoint<double>(const DevLists&, const PlanView<double>&, int64_t, int64_t, const void*,

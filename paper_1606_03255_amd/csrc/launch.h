@@ -18,9 +18,12 @@ struct DevLists {
 };
 
 // a2-a6 (forward, or derivative when deriv != 0): c -> f on stream st.
+// If ev is not null, ev[0..4] are recorded on st before the first launch and
+// after each of the four stages (one-pass FFTs, pass A, pass B, gather).
 template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* c, void* f, char* ws,
-                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st);
+                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st,
+                          hipEvent_t* ev = nullptr);
 
 // a7 (adjoint): g -> c_out on stream st.
 template <typename T>

@@ -145,6 +145,19 @@ class Plan:
         """h_k ~ sum_j g_j conj(exp(2 pi i k z_j)), k < N."""
         return self._run(self._lib.flt_adjoint, g, self.M, self.N, out, "g")
 
+    def profile_forward(self, c, out=None):
+        """One forward with per-kernel HIP-event timing; returns (f, stage_ms)
+        with stage_ms for (one-pass FFTs, pass A, pass B, gather)."""
+        import torch
+        c = self._prep(c, self.N, "c")
+        out = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out is None else out
+        ms = (ctypes.c_double * 4)()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(self._lib.flt_profile_forward(self._ptr, ctypes.c_void_p(c.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream), ms),
+                "flt_profile_forward")
+        return out, list(ms)
+
     def close(self):
         if getattr(self, "_ptr", None) and self._ptr.value:
             if self.device is not None:
