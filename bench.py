@@ -30,9 +30,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "node evals/s at N=M=2^20, err<=1e-6 vs FP64 direct; fwd+bwd speedup vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-STAGES = ("onepass_fft", "passA_fft", "passB_fft", "gather")
+STAGES = ("onepass_fft", "passA_fft", "passB_fft", "gather", "direct")
 KERNEL_NAMES = {"onepass_fft": "k_onepass_fwd", "passA_fft": "k_passA_fwd", "passB_fft": "k_passB",
-                "gather": "k_gather"}
+                "gather": "k_gather", "direct": "k_direct_fwd"}
+DIRECT_NG = 8   # nodes per direct-sum workgroup (c is read once per group)
 
 
 def kernel_source_hash():
@@ -49,7 +50,8 @@ def stage_bytes(plan, S):
     read once by the stage that consumes it; c read once per band.  Gather:
     node records (x, y: 16 B, index 4 B) and the result, plus the band grid
     cells its nodes touch (at most the whole grid, at most 2 mw cells per
-    column and node)."""
+    column and node).  Direct bands: c read once per group of DIRECT_NG
+    nodes, node records and results."""
     info = plan.info()
     mw = info["mw"]
     b = {k: 0.0 for k in STAGES}
@@ -57,6 +59,9 @@ def stage_bytes(plan, S):
         q, n, nodes = band["q"], band["n"], band["nodes"]
         kmax = min(band["K"], plan.N - 1)
         grid = q * n * S
+        if band["direct"]:
+            b["direct"] += -(-nodes // DIRECT_NG) * plan.N * S + nodes * (16 + 4 + S)
+            continue
         if band["passes"] == 1:
             b["onepass_fft"] += grid + kmax * S
         else:
@@ -175,7 +180,7 @@ def main():
 
     # per-kernel durations (HIP events between the launches on the current stream)
     reps = max(3, min(args.steps, 10))
-    acc = [0.0] * 4
+    acc = [0.0] * 5
     for _ in range(reps):
         _, ms = p32.profile_forward(c32)
         acc = [a + b for a, b in zip(acc, ms)]

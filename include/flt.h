@@ -49,6 +49,8 @@ typedef struct flt_plan flt_plan;
 
 /* flags for flt_plan_create */
 #define FLT_FLAG_HOST_ONLY (1u << 0) /* plan on the host only (parameters, partition, byte model); no device */
+#define FLT_FLAG_NFFT_ONLY (1u << 1) /* every band by Alg. 2's NFFT path; by default a band whose grids would
+                                        cost more than summing its few nodes directly is summed exactly */
 
 /* return codes */
 #define FLT_OK            0
@@ -87,8 +89,8 @@ typedef struct flt_band_info {
     int64_t n;               /* NFFT grid length (2K, at least 16) */
     int64_t k0;              /* centre of the support, floor(K/2) */
     int64_t nodes;           /* nodes in the band */
-    int32_t passes;          /* FFT passes through HBM (1 or 2) */
-    int32_t pad;
+    int32_t passes;          /* FFT passes through HBM (1 or 2); 0 for a direct band */
+    int32_t direct;          /* 1: the band's nodes are summed directly (exact), not by NFFT */
 } flt_band_info;
 
 /* Build a plan for N coefficients and M nodes z (host, 2*M doubles,
@@ -131,9 +133,9 @@ int flt_derivative(flt_plan* plan, const void* c, void* fp, void* stream);
 int flt_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream);
 
 /* Measurement: run one forward on `stream` with HIP events recorded between
- * its four kernel launches and wait for it; stage_ms (host, 4 doubles)
- * receives the durations of (one-pass band FFTs, pass A, pass B, window
- * gather) in milliseconds.  Same arguments and results as flt_forward. */
+ * its stages and wait for it; stage_ms (host, 5 doubles) receives the
+ * durations of (one-pass band FFTs, pass A, pass B, window gather, direct-sum
+ * bands) in milliseconds.  Same arguments and results as flt_forward. */
 int flt_profile_forward(flt_plan* plan, const void* c, void* f, void* stream, double* stage_ms);
 
 const char* flt_strerror(int code);

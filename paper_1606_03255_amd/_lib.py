@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(HERE, "libflt.so")
 FLT_C64 = 1
 FLT_C128 = 2
 FLT_FLAG_HOST_ONLY = 1
+FLT_FLAG_NFFT_ONLY = 2
 
 ERRORS = {
     0: "FLT_OK", -1: "FLT_EINVAL", -2: "FLT_EDOMAIN", -3: "FLT_EPRECISION", -4: "FLT_ENOWORKSPACE",
@@ -41,7 +42,7 @@ class FltBandInfo(ctypes.Structure):
     _fields_ = [
         ("m", ctypes.c_int32), ("q", ctypes.c_int32), ("ell_lo", ctypes.c_int32), ("ell_hi", ctypes.c_int32),
         ("K", ctypes.c_int64), ("n", ctypes.c_int64), ("k0", ctypes.c_int64), ("nodes", ctypes.c_int64),
-        ("passes", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("passes", ctypes.c_int32), ("direct", ctypes.c_int32),
     ]
 
 

@@ -90,6 +90,12 @@ static int upload(flt_plan* p)
     const size_t o_l3 = pk.add(hp.onepass_adj.data(), hp.onepass_adj.size() * sizeof(FftItem));
     const size_t o_l4 = pk.add(hp.passA_adj.data(), hp.passA_adj.size() * sizeof(FftItem));
     const size_t o_l5 = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
+    const size_t o_l6 = pk.add(hp.owner.data(), hp.owner.size() * sizeof(FftItem));
+    const size_t o_l7 = pk.add(hp.nfft_nodes.data(), hp.nfft_nodes.size() * sizeof(NodeItem));
+    const size_t o_l8 = pk.add(hp.direct_fwd.data(), hp.direct_fwd.size() * sizeof(DirectItem));
+    const size_t o_l9 = pk.add(hp.direct_adj.data(), hp.direct_adj.size() * sizeof(DirectItem));
+    const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
+    const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return hip_fail(e);
@@ -107,12 +113,23 @@ static int upload(flt_plan* p)
     L.onepass_adj = (const FftItem*)(base + o_l3);
     L.passA_adj = (const FftItem*)(base + o_l4);
     L.nodes = (const NodeItem*)(base + o_l5);
+    L.owner = (const FftItem*)(base + o_l6);
+    L.nfft_nodes = (const NodeItem*)(base + o_l7);
+    L.direct_fwd = (const DirectItem*)(base + o_l8);
+    L.direct_adj = (const DirectItem*)(base + o_l9);
+    L.dlist = (const int32_t*)(base + o_dl);
+    L.cstart = (const int32_t*)(base + o_cs);
     L.n_onepass_fwd = (int)hp.onepass_fwd.size();
     L.n_passA_fwd = (int)hp.passA_fwd.size();
     L.n_passB = (int)hp.passB.size();
     L.n_onepass_adj = (int)hp.onepass_adj.size();
     L.n_passA_adj = (int)hp.passA_adj.size();
     L.n_nodes = (int)hp.nodes.size();
+    L.n_owner = (int)hp.owner.size();
+    L.n_nfft_nodes = (int)hp.nfft_nodes.size();
+    L.n_direct_fwd = (int)hp.direct_fwd.size();
+    L.n_direct_adj = (int)hp.direct_adj.size();
+    L.n_dlist = (int64_t)hp.dlist.size();
     return FLT_OK;
 }
 
@@ -122,12 +139,12 @@ int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, doubl
 {
     if (!out) return FLT_EINVAL;
     *out = nullptr;
-    if (flags & ~(uint32_t)FLT_FLAG_HOST_ONLY) return FLT_EINVAL;
+    if (flags & ~(uint32_t)(FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY)) return FLT_EINVAL;
     flt_plan* p = new (std::nothrow) flt_plan();
     if (!p) return FLT_ENOMEM;
     int rc;
     try {
-        rc = build_host_plan(p->hp, N, M, z, eps, dtype);
+        rc = build_host_plan(p->hp, N, M, z, eps, dtype, flags);
     } catch (const std::bad_alloc&) {
         rc = FLT_ENOMEM;
     }
@@ -193,7 +210,8 @@ int flt_plan_band(const flt_plan* p, int32_t i, flt_band_info* o)
         o->n = (int64_t)1 << B.log2n;
         o->k0 = B.k0;
         o->nodes = B.node_count;
-        o->passes = B.log2n2 > 0 ? 2 : 1;
+        o->passes = B.direct ? 0 : (B.log2n2 > 0 ? 2 : 1);
+        o->direct = B.direct;
         return FLT_OK;
     }
     return FLT_EINVAL;
@@ -223,6 +241,25 @@ int flt_plan_set_workspace(flt_plan* p, void* dev, size_t bytes)
     return FLT_OK;
 }
 
+static WsLayout layout(const flt_plan* p)
+{
+    const HostPlan& hp = p->hp;
+    WsLayout W;
+    W.ws = p->ws;
+    W.off_grid = hp.off_grid;
+    W.off_scratch = hp.off_scratch;
+    W.off_acc = hp.off_acc;
+    W.off_U = hp.off_U;
+    W.off_phi = hp.off_phi;
+    W.off_l0 = hp.off_l0;
+    W.off_dacc = hp.off_dacc;
+    W.qs = hp.qs;
+    W.N = hp.N;
+    W.M = hp.M;
+    W.grid_elems = hp.grid_elems;
+    return W;
+}
+
 static int check_call(const flt_plan* p, const void* a, const void* b)
 {
     if (!p || !a || !b) return FLT_EINVAL;
@@ -236,9 +273,10 @@ static int run_forward(flt_plan* p, const void* c, void* f, int deriv, void* str
     int rc = check_call(p, c, f);
     if (rc != FLT_OK) return rc;
     const HostPlan& hp = p->hp;
+    const WsLayout W = layout(p);
     hipError_t e = hp.dtype == FLT_C64
-        ? launch_forward<float>(p->lists, p->pv32, c, f, p->ws, hp.off_grid, hp.off_scratch, deriv, (hipStream_t)stream)
-        : launch_forward<double>(p->lists, p->pv64, c, f, p->ws, hp.off_grid, hp.off_scratch, deriv, (hipStream_t)stream);
+        ? launch_forward<float>(p->lists, p->pv32, W, c, f, deriv, (hipStream_t)stream)
+        : launch_forward<double>(p->lists, p->pv64, W, c, f, deriv, (hipStream_t)stream);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
 
@@ -251,11 +289,10 @@ int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream)
     int rc = check_call(p, g, c_out);
     if (rc != FLT_OK) return rc;
     const HostPlan& hp = p->hp;
+    const WsLayout W = layout(p);
     hipError_t e = hp.dtype == FLT_C64
-        ? launch_adjoint<float>(p->lists, p->pv32, hp.N, hp.grid_elems, g, c_out, p->ws, hp.off_grid, hp.off_scratch,
-                                hp.off_acc, (hipStream_t)stream)
-        : launch_adjoint<double>(p->lists, p->pv64, hp.N, hp.grid_elems, g, c_out, p->ws, hp.off_grid,
-                                 hp.off_scratch, hp.off_acc, (hipStream_t)stream);
+        ? launch_adjoint<float>(p->lists, p->pv32, W, g, c_out, (hipStream_t)stream)
+        : launch_adjoint<double>(p->lists, p->pv64, W, g, c_out, (hipStream_t)stream);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
 
@@ -265,22 +302,20 @@ int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, doubl
     if (rc != FLT_OK) return rc;
     if (!stage_ms) return FLT_EINVAL;
     const HostPlan& hp = p->hp;
-    hipEvent_t ev[5] = {};
+    hipEvent_t ev[6] = {};
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 5 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    const WsLayout W = layout(p);
     if (e == hipSuccess)
-        e = hp.dtype == FLT_C64
-            ? launch_forward<float>(p->lists, p->pv32, c, f, p->ws, hp.off_grid, hp.off_scratch, 0,
-                                    (hipStream_t)stream, ev)
-            : launch_forward<double>(p->lists, p->pv64, c, f, p->ws, hp.off_grid, hp.off_scratch, 0,
-                                     (hipStream_t)stream, ev);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        e = hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, c, f, 0, (hipStream_t)stream, ev)
+                                : launch_forward<double>(p->lists, p->pv64, W, c, f, 0, (hipStream_t)stream, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) {
         float ms = 0;
         e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
         stage_ms[i] = ms;
     }
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 6; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }

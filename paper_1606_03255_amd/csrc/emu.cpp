@@ -53,20 +53,20 @@ template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body
 }
 
 template <typename T, int MW>
-static void gather_mw(const PlanView<T>& pv, const HostPlan& hp, const cplx<T>* c, const cplx<T>* grids,
-                      cplx<T>* f, int with_c0)
+static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, const cplx<T>* c, cplx<T>* grids,
+                     cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0)
 {
-    run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-        body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0);
+    if (!adjoint) {
+        run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+            body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0);
+        });
+        return;
+    }
+    run_blocks(hp.nfft_nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_adj_prep<HostCtx, T, MW>(ctx, pv, hp.nfft_nodes.data(), c, hp.qs, U, Phi, L0);
     });
-}
-
-template <typename T, int MW>
-static void spread_mw(const PlanView<T>& pv, const HostPlan& hp, const cplx<T>* g, cplx<T>* grids, double* acc)
-{
-    std::vector<double> red(2 * GATHER_THREADS);
-    run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-        body_spread<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), g, grids, acc, red.data());
+    run_blocks(hp.owner.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_adj_owner<HostCtx, T, MW>(ctx, pv, hp.owner.data(), hp.qs, U, Phi, L0, hp.cstart.data(), grids);
     });
 }
 
@@ -90,11 +90,23 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     pv.mw = hp.mw;
     pv.kb_b = (T)hp.kb_b;
 
+    // exactly sized buffers, so AddressSanitizer sees any out-of-range access
     std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems, 1));
     std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems, 1));
+    std::vector<cplx<T>> U((size_t)hp.M * hp.qs);
+    std::vector<T> Phi((size_t)hp.M * 2 * hp.mw);
+    std::vector<int32_t> L0(hp.M);
+    std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
     std::vector<cplx<T>> lds(1 << Sizes<T>::LOG2P);
-    memset(grids.data(), 0, grids.size() * sizeof(cplx<T>));
-    memset(scratch.data(), 0, scratch.size() * sizeof(cplx<T>));
+    std::vector<T> lc(MAX_COEF_LDS);
+    const int64_t nd = (int64_t)hp.dlist.size();
+    auto mwsw = [&](int adjoint, const cplx<T>* c, cplx<T>* f, int with_c0) {
+        switch (hp.mw) {
+#define G(MWV) case MWV: nodes_mw<T, MWV>(pv, hp, adjoint, c, grids.data(), f, with_c0, U.data(), Phi.data(), L0.data()); break;
+            G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
+#undef G
+        }
+    };
     if (op == 0 || op == 1) {
         const cplx<T>* c = (const cplx<T>*)in;
         cplx<T>* f = (cplx<T>*)out;
@@ -103,16 +115,24 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             body_onepass_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_fwd.data(), c, grids.data(), deriv, lds.data());
         });
         run_blocks(hp.passA_fwd.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_passA_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.passA_fwd.data(), c, scratch.data(), deriv, lds.data());
+            body_passA_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.passA_fwd.data(), c, scratch.data(), deriv, lds.data(),
+                                              lc.data());
         });
         run_blocks(hp.passB.size(), FFT_THREADS, [&](const HostCtx& ctx) {
             body_passB<HostCtx, T, ITEMS>(ctx, pv, hp.passB.data(), scratch.data(), 0, grids.data(), +1, lds.data());
         });
-        switch (hp.mw) {
-#define G(MWV) case MWV: gather_mw<T, MWV>(pv, hp, c, grids.data(), f, !deriv); break;
-            G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
-#undef G
-            default: return FLT_EINVAL;
+        mwsw(0, c, f, !deriv);
+        if (nd) {
+            run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
+                body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 0);
+            });
+            run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
+                body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, hp.N, deriv,
+                                            dacc.data(), red.data());
+            });
+            run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
+                body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 1);
+            });
         }
         return FLT_OK;
     }
@@ -120,20 +140,22 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         const cplx<T>* g = (const cplx<T>*)in;
         cplx<T>* co = (cplx<T>*)out;
         std::vector<double> acc(2 * hp.N, 0.0);
-        switch (hp.mw) {
-#define S(MWV) case MWV: spread_mw<T, MWV>(pv, hp, g, grids.data(), acc.data()); break;
-            S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
-#undef S
-            default: return FLT_EINVAL;
-        }
+        const int64_t nsum = (hp.M + 256 * SUMG_PER_THREAD - 1) / (256 * SUMG_PER_THREAD);
+        run_blocks(nsum, 256, [&](const HostCtx& ctx) { body_sum_g<HostCtx, T>(ctx, g, hp.M, acc.data(), red.data()); });
+        mwsw(1, g, nullptr, 0);
         run_blocks(hp.passB.size(), FFT_THREADS, [&](const HostCtx& ctx) {
             body_passB<HostCtx, T, ITEMS>(ctx, pv, hp.passB.data(), grids.data(), 1, scratch.data(), -1, lds.data());
         });
         run_blocks(hp.passA_adj.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_passA_adj<HostCtx, T, ITEMS>(ctx, pv, hp.passA_adj.data(), scratch.data(), acc.data(), lds.data());
+            body_passA_adj<HostCtx, T, ITEMS>(ctx, pv, hp.passA_adj.data(), scratch.data(), acc.data(), lds.data(),
+                                              lc.data());
         });
         run_blocks(hp.onepass_adj.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_onepass_adj<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_adj.data(), grids.data(), acc.data(), lds.data());
+            body_onepass_adj<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_adj.data(), grids.data(), acc.data(), lds.data(),
+                                                lc.data());
+        });
+        run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
+            body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, hp.N, acc.data());
         });
         for (int64_t k = 0; k < hp.N; ++k) co[k] = mk<T>((T)acc[2 * k], (T)acc[2 * k + 1]);
         return FLT_OK;
@@ -143,11 +165,11 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
 
 }  // namespace flt
 
-extern "C" int flt_emu_run(int64_t N, int64_t M, const double* z, double eps, int dtype, int op,
+extern "C" int flt_emu_run(int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags, int op,
                            const void* in, void* out)
 {
     flt::HostPlan hp;
-    int rc = flt::build_host_plan(hp, N, M, z, eps, dtype);
+    int rc = flt::build_host_plan(hp, N, M, z, eps, dtype, flags);
     if (rc != FLT_OK) return rc;
     return dtype == FLT_C64 ? flt::emu_run<float>(hp, op, in, out) : flt::emu_run<double>(hp, op, in, out);
 }

@@ -44,6 +44,12 @@ constexpr int TW2_HALF = 11;              // lo/hi tables of 2^11 entries each
 constexpr int GATHER_THREADS = 256;       // nodes per gather/spread workgroup
 constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
 constexpr int MAX_MW = 10;                // largest window half-width supported
+constexpr int MAX_COEF_LDS = 2048;        // LDS slots for one column's Chebyshev coefficients
+constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread
+constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
+constexpr int DIRECT_ATPT = 8;            // direct adjoint: coefficients per thread
+constexpr int DIRECT_ANG = 256;           // direct adjoint: nodes per workgroup
+constexpr int SUMG_PER_THREAD = 16;       // sum of g: elements per thread
 
 template <typename T> struct Sizes;
 template <> struct Sizes<float>  { static constexpr int LOG2P = 13; };   // 8192 complex64 = 64 KB of LDS
@@ -64,12 +70,14 @@ struct BandDesc {
     int32_t coef_off;    // first coefficient of block ell_lo in the Chebyshev table (q*q per block)
     int32_t deconv_off;  // deconvolution table of this n: entries |k'| = 0..n/4
     int32_t ycheb_off;   // q (node, weight) pairs of the y interpolation in the ycheb table
+    int32_t direct;      // 1: the band's nodes are evaluated by the direct sum (no grids)
     int64_t k0;          // centre of the frequency support
     int64_t kmax;        // support is k = 1..kmax
     int64_t grid_off;    // complex offset of the band's q grids (column-major, n each)
     int64_t scratch_off; // complex offset of the band's pass-A output (two-pass bands)
     int64_t node_start;  // first node of the band in the sorted node arrays
     int64_t node_count;
+    int64_t cs_off;      // cell-start table of the band (n + 1 entries) for the adjoint
 };
 
 // Work item of an FFT kernel: band, first column, and a block index.
@@ -85,6 +93,14 @@ struct NodeItem {
     int32_t band;
     int32_t count;
     int64_t start;
+};
+
+// Work item of the direct-sum kernels: a run of the direct-node list and a chunk of k.
+struct DirectItem {
+    int32_t first;
+    int32_t count;
+    int32_t chunk;
+    int32_t pad;
 };
 
 // Everything a kernel needs to read from the plan (device or host pointers).

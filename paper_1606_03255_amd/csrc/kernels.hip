@@ -1,7 +1,7 @@
 // gfx950 kernels of the fast Fourier-Laplace transform and their launch
 // sequences.  The bodies live in kernels_impl.h; this file binds them to the
-// HIP execution model (workgroup = one work item of a precomputed list, LDS
-// tiles of 64 KB for the FFT kernels) and orders them on the caller's stream.
+// HIP execution model (one workgroup per item of a precomputed work list,
+// 64 KB LDS tiles for the FFT kernels) and orders them on the caller's stream.
 #include <hip/hip_runtime.h>
 
 #include "kernels_impl.h"
@@ -33,7 +33,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_passA_fwd(PlanView<T> pv, const
                                                            const cplx<T>* c, cplx<T>* scratch, int deriv)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_passA_fwd<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, c, scratch, deriv, lds);
+    __shared__ T lc[MAX_COEF_LDS];
+    body_passA_fwd<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, c, scratch, deriv, lds, lc);
 }
 
 template <typename T>
@@ -52,11 +53,26 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PlanView<T> pv, const
 }
 
 template <typename T, int MW>
-__global__ __launch_bounds__(GATHER_THREADS) void k_spread(PlanView<T> pv, const NodeItem* items, const cplx<T>* g,
-                                                           cplx<T>* grids, double* acc)
+__global__ __launch_bounds__(GATHER_THREADS) void k_adj_prep(PlanView<T> pv, const NodeItem* items,
+                                                             const cplx<T>* g, int qs, cplx<T>* U, T* Phi,
+                                                             int32_t* L0)
 {
-    __shared__ double red[2 * GATHER_THREADS];
-    body_spread<DevCtx, T, MW>(DevCtx(), pv, items, g, grids, acc, red);
+    body_adj_prep<DevCtx, T, MW>(DevCtx(), pv, items, g, qs, U, Phi, L0);
+}
+
+template <typename T, int MW>
+__global__ __launch_bounds__(GATHER_THREADS) void k_adj_owner(PlanView<T> pv, const FftItem* items, int qs,
+                                                              const cplx<T>* U, const T* Phi, const int32_t* L0,
+                                                              const int32_t* cstart, cplx<T>* grids)
+{
+    body_adj_owner<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, cstart, grids);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_g(const cplx<T>* g, int64_t M, double* acc)
+{
+    __shared__ double red[2 * 256];
+    body_sum_g<DevCtx, T>(DevCtx(), g, M, acc, red);
 }
 
 template <typename T>
@@ -64,7 +80,8 @@ __global__ __launch_bounds__(FFT_THREADS) void k_onepass_adj(PlanView<T> pv, con
                                                              const cplx<T>* grids, double* acc)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_onepass_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, grids, acc, lds);
+    __shared__ T lc[MAX_COEF_LDS];
+    body_onepass_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, grids, acc, lds, lc);
 }
 
 template <typename T>
@@ -72,7 +89,30 @@ __global__ __launch_bounds__(FFT_THREADS) void k_passA_adj(PlanView<T> pv, const
                                                            const cplx<T>* scratch, double* acc)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_passA_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, scratch, acc, lds);
+    __shared__ T lc[MAX_COEF_LDS];
+    body_passA_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, scratch, acc, lds, lc);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_direct_fwd(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
+                                                    const cplx<T>* c, int64_t N, int deriv, double* dacc)
+{
+    __shared__ double red[2 * DIRECT_NG * 256];
+    body_direct_fwd<DevCtx, T>(DevCtx(), pv, items, dlist, c, N, deriv, dacc, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_direct_io(PlanView<T> pv, const int32_t* dlist, int64_t nd, double* dacc,
+                                                   cplx<T>* f, int op)
+{
+    body_direct_io<DevCtx, T>(DevCtx(), pv, dlist, nd, dacc, f, op);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_direct_adj(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
+                                                    const cplx<T>* g, int64_t N, double* acc)
+{
+    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, N, acc);
 }
 
 // Clear `n` 16-byte words (a fill kernel, so the sequence stays capturable).
@@ -98,7 +138,7 @@ static int grid_for(int64_t work, int per_block)
 }
 
 template <typename T, int MW>
-static void launch_gather_mw(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, const cplx<T>* grids,
+static void mw_forward_nodes(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, const cplx<T>* grids,
                              cplx<T>* f, int with_c0, hipStream_t st)
 {
     hipLaunchKernelGGL((k_gather<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, c, grids, f,
@@ -106,20 +146,29 @@ static void launch_gather_mw(const DevLists& L, const PlanView<T>& pv, const cpl
 }
 
 template <typename T, int MW>
-static void launch_spread_mw(const DevLists& L, const PlanView<T>& pv, const cplx<T>* g, cplx<T>* grids,
-                             double* acc, hipStream_t st)
+static void mw_adjoint_nodes(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const cplx<T>* g,
+                             cplx<T>* grids, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_spread<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, g, grids, acc);
+    cplx<T>* U = (cplx<T>*)(W.ws + W.off_U);
+    T* Phi = (T*)(W.ws + W.off_phi);
+    int32_t* L0 = (int32_t*)(W.ws + W.off_l0);
+    if (L.n_nfft_nodes)
+        hipLaunchKernelGGL((k_adj_prep<T, MW>), dim3(L.n_nfft_nodes), dim3(GATHER_THREADS), 0, st, pv,
+                           L.nfft_nodes, g, W.qs, U, Phi, L0);
+    if (L.n_owner)
+        hipLaunchKernelGGL((k_adj_owner<T, MW>), dim3(L.n_owner), dim3(GATHER_THREADS), 0, st, pv, L.owner, W.qs,
+                           (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, L.cstart, grids);
 }
 
 template <typename T>
-hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* cv, void* fv, char* ws,
-                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st, hipEvent_t* ev)
+hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* cv, void* fv,
+                          int deriv, hipStream_t st, hipEvent_t* ev)
 {
     const cplx<T>* c = (const cplx<T>*)cv;
     cplx<T>* f = (cplx<T>*)fv;
-    cplx<T>* grids = (cplx<T>*)(ws + off_grid);
-    cplx<T>* scratch = (cplx<T>*)(ws + off_scratch);
+    cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
+    cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
+    double* dacc = (double*)(W.ws + W.off_dacc);
     if (ev) (void)hipEventRecord(ev[0], st);
     if (L.n_onepass_fwd)
         hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(L.n_onepass_fwd), dim3(FFT_THREADS), 0, st, pv, L.onepass_fwd, c,
@@ -135,35 +184,40 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* 
     if (ev) (void)hipEventRecord(ev[3], st);
     if (L.n_nodes) {
         switch (pv.mw) {
-#define G(MWV) case MWV: launch_gather_mw<T, MWV>(L, pv, c, grids, f, !deriv, st); break;
+#define G(MWV) case MWV: mw_forward_nodes<T, MWV>(L, pv, c, grids, f, !deriv, st); break;
             G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
 #undef G
             default: return hipErrorInvalidValue;
         }
     }
     if (ev) (void)hipEventRecord(ev[4], st);
+    if (L.n_dlist) {
+        const int gb = (int)((L.n_dlist + 255) / 256);
+        hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, f, 0);
+        hipLaunchKernelGGL(k_direct_fwd<T>, dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd, L.dlist, c,
+                           W.N, deriv, dacc);
+        hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, f, 1);
+    }
+    if (ev) (void)hipEventRecord(ev[5], st);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, int64_t N, int64_t grid_elems, const void* gv,
-                          void* outv, char* ws, size_t off_grid, size_t off_scratch, size_t off_acc, hipStream_t st)
+hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* gv, void* outv,
+                          hipStream_t st)
 {
     const cplx<T>* g = (const cplx<T>*)gv;
     cplx<T>* out = (cplx<T>*)outv;
-    cplx<T>* grids = (cplx<T>*)(ws + off_grid);
-    cplx<T>* scratch = (cplx<T>*)(ws + off_scratch);
-    double* acc = (double*)(ws + off_acc);
-    const int64_t gwords = (grid_elems * (int64_t)sizeof(cplx<T>) + 15) / 16;
-    if (gwords) hipLaunchKernelGGL(k_zero16, dim3(grid_for(gwords, 256 * 8)), dim3(256), 0, st, (double2*)grids, gwords);
-    hipLaunchKernelGGL(k_zero16, dim3(grid_for(N, 256 * 8)), dim3(256), 0, st, (double2*)acc, N);
-    if (L.n_nodes) {
-        switch (pv.mw) {
-#define S(MWV) case MWV: launch_spread_mw<T, MWV>(L, pv, g, grids, acc, st); break;
-            S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
+    cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
+    cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
+    double* acc = (double*)(W.ws + W.off_acc);
+    hipLaunchKernelGGL(k_zero16, dim3(grid_for(W.N, 256 * 8)), dim3(256), 0, st, (double2*)acc, W.N);
+    hipLaunchKernelGGL(k_sum_g<T>, dim3(grid_for(W.M, 256 * SUMG_PER_THREAD)), dim3(256), 0, st, g, W.M, acc);
+    switch (pv.mw) {
+#define S(MWV) case MWV: mw_adjoint_nodes<T, MWV>(L, pv, W, g, grids, st); break;
+        S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
 #undef S
-            default: return hipErrorInvalidValue;
-        }
+        default: return hipErrorInvalidValue;
     }
     if (L.n_passB)
         hipLaunchKernelGGL(k_passB<T>, dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
@@ -174,17 +228,20 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, int64_t N, i
     if (L.n_onepass_adj)
         hipLaunchKernelGGL(k_onepass_adj<T>, dim3(L.n_onepass_adj), dim3(FFT_THREADS), 0, st, pv, L.onepass_adj,
                            (const cplx<T>*)grids, acc);
-    hipLaunchKernelGGL(k_finalize_adj<T>, dim3(grid_for(N, 256 * 4)), dim3(256), 0, st, acc, out, N);
+    if (L.n_direct_adj)
+        hipLaunchKernelGGL(k_direct_adj<T>, dim3(L.n_direct_adj), dim3(256), 0, st, pv, L.direct_adj, L.dlist, g,
+                           W.N, acc);
+    hipLaunchKernelGGL(k_finalize_adj<T>, dim3(grid_for(W.N, 256 * 4)), dim3(256), 0, st, acc, out, W.N);
     return hipGetLastError();
 }
 
-template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const void*, void*, char*, size_t,
-                                          size_t, int, hipStream_t, hipEvent_t*);
-template hipError_t launch_forward<double>(const DevLists&, const PlanView<double>&, const void*, void*, char*, size_t,
-                                           size_t, int, hipStream_t, hipEvent_t*);
-template hipError_t launch_adjoint<float>(const DevLists&, const PlanView<float>&, int64_t, int64_t, const void*,
-                                          void*, char*, size_t, size_t, size_t, hipStream_t);
-template hipError_t launch_adjoint<double>(const DevLists&, const PlanView<double>&, int64_t, int64_t, const void*,
-                                           void*, char*, size_t, size_t, size_t, hipStream_t);
+template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,
+                                          void*, int, hipStream_t, hipEvent_t*);
+template hipError_t launch_forward<double>(const DevLists&, const PlanView<double>&, const WsLayout&, const void*,
+                                           void*, int, hipStream_t, hipEvent_t*);
+template hipError_t launch_adjoint<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,
+                                          void*, hipStream_t);
+template hipError_t launch_adjoint<double>(const DevLists&, const PlanView<double>&, const WsLayout&, const void*,
+                                           void*, hipStream_t);
 
 }  // namespace flt

@@ -182,6 +182,61 @@ FLT_HD void lds_fft(const Ctx& ctx, cplx<T>* buf, int log2L, int nsub, int sign,
     }
 }
 
+// Column s's Chebyshev coefficients of every interpolated block of band B,
+// staged into LDS as lc[(l - ell_lo) q + i].
+template <class Ctx, typename T>
+FLT_HD void stage_coef(const Ctx& ctx, const PlanView<T>& pv, const BandDesc& B, int s, T* lc)
+{
+    const int q = B.q;
+    const int nblk = B.ell_hi - B.ell_lo + 1;
+    for (int idx = ctx.tid(); idx < nblk * q; idx += ctx.ntid()) {
+        const int e = idx / q, i = idx - e * q;
+        lc[idx] = pv.coef[B.coef_off + (e * q + s) * q + i];
+    }
+}
+
+// t_k[s] from the staged coefficients of column s (see laplace_row).
+template <typename T>
+FLT_HD T laplace_row_lds(const T* lc, const BandDesc& B, int64_t k)
+{
+    const int cl = ceil_log2_u64(k);
+    const int ell = B.n_xi + 1 - cl;
+    if (ell > B.ell_hi) return T(1);
+    const int q = B.q;
+    const T* a = lc + (ell - B.ell_lo) * q;
+    const T u = ldexp((T)k, 2 - cl) - T(3);
+    const T u2 = u + u;
+    T b1 = 0, b2 = 0;
+    for (int i = q - 1; i >= 1; --i) {
+        T b0 = a[i] + u2 * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return a[0] + u * b1 - b2;
+}
+
+// c_k / (n phi_hat(k - k0)), times 2 pi i k for the derivative transform.
+template <typename T>
+FLT_HD cplx<T> point_base(const PlanView<T>& pv, const BandDesc& B, const cplx<T>* c, int64_t kp, int64_t k,
+                          int deriv)
+{
+    T w = pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+    cplx<T> v = c[k];
+    if (deriv) {
+        w *= (T)(6.283185307179586476925286766559 * (double)k);
+        v = mk(-v.y, v.x);
+    }
+    return scale(v, w);
+}
+
+// frac(k x) in [-1/2, 1/2] with the error-free product k x = p + e (FMA), FP64.
+FLT_HD double frac_kx(double k, double x)
+{
+    const double p = k * x;
+    const double e = fma(k, x, -p);
+    return (p - rint(p)) + e;
+}
+
 // Address of natural grid index l in a band's blocked layout
 // [l1 / B][l2][l1 mod B], l = l1 + n1 l2  (one-pass bands: address = l).
 FLT_HD int64_t grid_addr(const BandDesc& B, int64_t l)
@@ -217,31 +272,53 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // ---------------------------------------------------------------------------
 template <class Ctx, typename T, int ITEMS>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                           const cplx<T>* c, cplx<T>* scratch, int deriv, cplx<T>* lds)
+                           const cplx<T>* c, cplx<T>* scratch, int deriv, cplx<T>* lds, T* lc)
 {
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int s = it.s0;
     const int log2n1 = B.log2n1, log2n2 = B.log2n2, log2b = B.log2b, log2B = B.log2B;
     const int P = 1 << (log2b + log2n1);
+    const int64_t n = (int64_t)1 << B.log2n;
     const int64_t j2_0 = (int64_t)it.blk << log2b;
-    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
-        const int jj = p & ((1 << log2b) - 1);
-        const int j1 = p >> log2b;
-        const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
-        lds[(jj << log2n1) + j1] = grid_input(pv, B, c, s, j, deriv);
+    // c_k / (n phi_hat(k')) of this thread's points, shared by all q columns
+    cplx<T> base[ITEMS];
+    for (int i = 0; i < ITEMS; ++i) {
+        const int p = ctx.tid() + i * ctx.ntid();
+        base[i] = mk<T>(0, 0);
+        if (p < P) {
+            const int64_t j = j2_0 + (p & ((1 << log2b) - 1)) + ((int64_t)(p >> log2b) << log2n2);
+            const int64_t kp = j < (n >> 1) ? j : j - n;
+            const int64_t k = kp + B.k0;
+            if (k >= 1 && k <= B.kmax) base[i] = point_base(pv, B, c, kp, k, deriv);
+        }
     }
-    ctx.sync();
-    lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, +1, pv.tw_stage);
-    cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
-    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
-        const int l1lo = p & ((1 << log2B) - 1);
-        const int jj = (p >> log2B) & ((1 << log2b) - 1);
-        const int l1hi = p >> (log2B + log2b);
-        const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
-        const int64_t j2 = j2_0 + jj;
-        cplx<T> v = mul(lds[(jj << log2n1) + l1], tw_grid_at(pv, j2 * l1, B.log2n, +1));
-        Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
+    for (int s = 0; s < B.q; ++s) {
+        stage_coef(ctx, pv, B, s, lc);
+        ctx.sync();
+        for (int i = 0; i < ITEMS; ++i) {
+            const int p = ctx.tid() + i * ctx.ntid();
+            if (p >= P) break;
+            const int jj = p & ((1 << log2b) - 1);
+            const int j1 = p >> log2b;
+            const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
+            const int64_t k = (j < (n >> 1) ? j : j - n) + B.k0;
+            cplx<T> v = base[i];
+            if (k >= 1 && k <= B.kmax) v = scale(v, laplace_row_lds(lc, B, k));
+            lds[(jj << log2n1) + j1] = v;
+        }
+        ctx.sync();
+        lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, +1, pv.tw_stage);
+        cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
+        for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+            const int l1lo = p & ((1 << log2B) - 1);
+            const int jj = (p >> log2B) & ((1 << log2b) - 1);
+            const int l1hi = p >> (log2B + log2b);
+            const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
+            const int64_t j2 = j2_0 + jj;
+            cplx<T> v = mul(lds[(jj << log2n1) + l1], tw_grid_at(pv, j2 * l1, B.log2n, +1));
+            Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
+        }
+        ctx.sync();
     }
 }
 
@@ -375,64 +452,219 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
 }
 
 // ---------------------------------------------------------------------------
-// Adjoint a7.  Spread: grid_s[l] += g_j e^{-2 pi i k0 x_j} L_s(y_j) phi(x_j - l/n);
-// also accumulates sum_j g_j (the k = 0 coefficient) into acc[0].
+// Adjoint a7, node side: per node of an NFFT band, u_j^s = g_j e^{-2 pi i k0 x_j}
+// L_s(y_j) (FP64, rounded to T), the window weights of its 2 mw taps and its cell.
 // ---------------------------------------------------------------------------
 template <class Ctx, typename T, int MW>
-FLT_HD void body_spread(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items,
-                        const cplx<T>* gin, cplx<T>* grids, double* acc, double* red)
+FLT_HD void body_adj_prep(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items, const cplx<T>* gin,
+                          int qs, cplx<T>* U, T* Phi, int32_t* L0)
 {
     const NodeItem it = items[ctx.bid()];
     const int i = ctx.tid();
+    if (i >= it.count) return;
+    const int64_t j = it.start + i;
     const BandDesc& B = pv.bands[it.band];
-    double gr = 0, gi = 0;
-    int64_t jj = it.start + i;
-    if (i < it.count) {
-        const cplx<T> gv = gin[pv.perm[jj]];
-        gr = (double)gv.x;
-        gi = (double)gv.y;
-    }
-    // workgroup sum of g for the k = 0 coefficient
-    red[2 * i] = gr;
-    red[2 * i + 1] = gi;
-    ctx.sync();
-    for (int h = ctx.ntid() >> 1; h > 0; h >>= 1) {
-        if (i < h) {
-            red[2 * i] += red[2 * (i + h)];
-            red[2 * i + 1] += red[2 * (i + h) + 1];
-        }
-        ctx.sync();
-    }
-    if (i == 0) {
-        ctx.atomic_add(acc, red[0]);
-        ctx.atomic_add(acc + 1, red[1]);
-    }
-    if (i >= it.count || B.q == 0) return;
-    const double x = pv.nx[jj], y = pv.ny[jj];
-    const int log2n = B.log2n;
-    const int64_t nmask = ((int64_t)1 << log2n) - 1;
-    const double nxv = ldexp(x, log2n);
+    const double x = pv.nx[j], y = pv.ny[j];
+    const double nxv = ldexp(x, B.log2n);
     const double fl = floor(nxv);
-    const int64_t l0 = (int64_t)fl;
+    L0[j] = (int32_t)fl;
     T phi[2 * MW];
     kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
-    const double* yc = pv.ycheb + 2 * B.ycheb_off;
-    const BaryY by = bary_setup(yc, B.q, y);
+    for (int t = 0; t < 2 * MW; ++t) Phi[j * (2 * MW) + t] = phi[t];
+    const cplx<T> gv = gin[pv.perm[j]];
     double ph = (double)B.k0 * x;
     ph -= floor(ph);
     double sn, cs;
     sincos(6.283185307179586476925286766559 * ph, &sn, &cs);
-    const double ur = gr * cs + gi * sn;   // g e^{-2 pi i k0 x}
-    const double ui = gi * cs - gr * sn;
-    T* g = (T*)(grids + B.grid_off);
+    const double ur = (double)gv.x * cs + (double)gv.y * sn;   // g e^{-2 pi i k0 x}
+    const double ui = (double)gv.y * cs - (double)gv.x * sn;
+    const double* yc = pv.ycheb + 2 * B.ycheb_off;
+    const BaryY by = bary_setup(yc, B.q, y);
     for (int s = 0; s < B.q; ++s) {
         const double Ls = bary_at(yc, by, s, y);
-        const T vr = (T)(ur * Ls), vi = (T)(ui * Ls);
-        T* gs = g + ((int64_t)s << (log2n + 1));
-        for (int t = 0; t < 2 * MW; ++t) {
-            const int64_t a = grid_addr(B, (l0 - MW + 1 + t) & nmask);
-            ctx.atomic_add(gs + 2 * a, vr * phi[t]);
-            ctx.atomic_add(gs + 2 * a + 1, vi * phi[t]);
+        U[j * qs + s] = mk<T>((T)(ur * Ls), (T)(ui * Ls));
+    }
+}
+
+// Adjoint a7, grid side (owner computes, no atomics): cell l of each column of
+// band B receives sum_j u_j^s phi(n x_j - l) over the nodes whose window
+// covers l.  Nodes are sorted by cell l0 = floor(n x), and l is covered iff
+// l0 lies in [l - mw, l + mw) (mod n), so the contributors form at most two
+// runs of the sorted order, found in the band's cell-start table.
+template <class Ctx, typename T, int MW>
+FLT_HD void body_adj_owner(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items, int qs,
+                           const cplx<T>* U, const T* Phi, const int32_t* L0, const int32_t* cstart,
+                           cplx<T>* grids)
+{
+    const FftItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int64_t n = (int64_t)1 << B.log2n;
+    const int64_t l = (int64_t)it.blk * ctx.ntid() + ctx.tid();
+    if (l >= n) return;
+    const int32_t* c0 = cstart + B.cs_off;       // c0[c]: first sorted node of the band with cell >= c
+    const int64_t a = l - MW, b = l + MW;
+    int32_t r0s, r0e, r1s = 0, r1e = 0;
+    if (a < 0) { r0s = c0[a + n]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b]; }
+    else if (b > n) { r0s = c0[a]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b - n]; }
+    else { r0s = c0[a]; r0e = c0[b]; }
+    cplx<T>* g = grids + B.grid_off;
+    const int64_t addr = grid_addr(B, l);
+    for (int s = 0; s < B.q; ++s) {
+        T ar = 0, ai = 0;
+        for (int run = 0; run < 2; ++run) {
+            const int32_t js = run ? r1s : r0s, je = run ? r1e : r0e;
+            for (int32_t j = js; j < je; ++j) {
+                int64_t t = l - (int64_t)L0[j] + (MW - 1);   // tap index of l in node j's window
+                if (t < 0) t += n;
+                if (t >= n) t -= n;
+                const T w = Phi[(int64_t)j * (2 * MW) + t];
+                const cplx<T> u = U[(int64_t)j * qs + s];
+                ar += u.x * w;
+                ai += u.y * w;
+            }
+        }
+        g[((int64_t)s << B.log2n) + addr] = mk(ar, ai);
+    }
+}
+
+// sum_j g_j (the k = 0 coefficient of the adjoint), FP64, into acc[0..1].
+template <class Ctx, typename T>
+FLT_HD void body_sum_g(const Ctx& ctx, const cplx<T>* g, int64_t M, double* acc, double* red)
+{
+    const int tid = ctx.tid(), nt = ctx.ntid();
+    const int64_t base = (int64_t)ctx.bid() * nt * SUMG_PER_THREAD;
+    double sr = 0, si = 0;
+    for (int t = 0; t < SUMG_PER_THREAD; ++t) {
+        const int64_t i = base + (int64_t)t * nt + tid;
+        if (i < M) {
+            sr += (double)g[i].x;
+            si += (double)g[i].y;
+        }
+    }
+    red[2 * tid] = sr;
+    red[2 * tid + 1] = si;
+    ctx.sync();
+    for (int h = nt >> 1; h > 0; h >>= 1) {
+        if (tid < h) {
+            red[2 * tid] += red[2 * (tid + h)];
+            red[2 * tid + 1] += red[2 * (tid + h) + 1];
+        }
+        ctx.sync();
+    }
+    if (tid == 0) {
+        ctx.atomic_add(acc, red[0]);
+        ctx.atomic_add(acc + 1, red[1]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Bands the plan evaluates by the direct sum (few nodes, large grids): the
+// exact f_j = sum_{k<N} c_k w_j^k.  Every thread takes DIRECT_TPT consecutive
+// terms from an anchor w^{k0} formed in FP64 (exact phase reduction of k0 x),
+// then the recurrence p <- p w in T; partial sums are combined in FP64.
+// ---------------------------------------------------------------------------
+template <class Ctx, typename T>
+FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
+                            const cplx<T>* c, int64_t N, int deriv, double* dacc, double* red)
+{
+    const DirectItem it = items[ctx.bid()];
+    const int tid = ctx.tid(), nt = ctx.ntid();
+    const int64_t k0 = ((int64_t)it.chunk * nt + tid) * DIRECT_TPT;
+    cplx<T> cv[DIRECT_TPT];
+    for (int t = 0; t < DIRECT_TPT; ++t) {
+        const int64_t k = k0 + t;
+        cplx<T> v = k < N ? c[k] : mk<T>(0, 0);
+        if (deriv) {
+            const T sc = (T)(6.283185307179586476925286766559 * (double)k);
+            v = mk(-v.y * sc, v.x * sc);
+        }
+        cv[t] = v;
+    }
+    for (int gi = 0; gi < DIRECT_NG; ++gi) {
+        double sr = 0, si = 0;
+        if (gi < it.count && k0 < N) {
+            const int32_t j = dlist[it.first + gi];
+            const double x = pv.nx[j], y = pv.ny[j];
+            double sn, cs;
+            sincos(6.283185307179586476925286766559 * x, &sn, &cs);
+            const double m1 = exp(-y);
+            const cplx<T> w = mk<T>((T)(m1 * cs), (T)(m1 * sn));
+            const double mag = exp(-(double)k0 * y);
+            sincos(6.283185307179586476925286766559 * frac_kx((double)k0, x), &sn, &cs);
+            cplx<T> p = mk<T>((T)(mag * cs), (T)(mag * sn));
+            T ar = 0, ai = 0;
+            for (int t = 0; t < DIRECT_TPT; ++t) {
+                ar += cv[t].x * p.x - cv[t].y * p.y;
+                ai += cv[t].x * p.y + cv[t].y * p.x;
+                p = mul(p, w);
+            }
+            sr = (double)ar;
+            si = (double)ai;
+        }
+        red[(2 * gi) * nt + tid] = sr;
+        red[(2 * gi + 1) * nt + tid] = si;
+    }
+    ctx.sync();
+    for (int h = nt >> 1; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int r = 0; r < 2 * DIRECT_NG; ++r) red[r * nt + tid] += red[r * nt + tid + h];
+        ctx.sync();
+    }
+    if (tid < 2 * it.count) {
+        const int32_t j = dlist[it.first + (tid >> 1)];
+        ctx.atomic_add(dacc + 2 * (int64_t)j + (tid & 1), red[tid * nt]);
+    }
+}
+
+// Clear (op 0) or write out (op 1: f[perm[j]] = dacc[j]) the direct nodes.
+template <class Ctx, typename T>
+FLT_HD void body_direct_io(const Ctx& ctx, const PlanView<T>& pv, const int32_t* dlist, int64_t nd, double* dacc,
+                           cplx<T>* f, int op)
+{
+    const int64_t i = (int64_t)ctx.bid() * ctx.ntid() + ctx.tid();
+    if (i >= nd) return;
+    const int32_t j = dlist[i];
+    if (op == 0) {
+        dacc[2 * (int64_t)j] = 0.0;
+        dacc[2 * (int64_t)j + 1] = 0.0;
+    } else {
+        f[pv.perm[j]] = mk<T>((T)dacc[2 * (int64_t)j], (T)dacc[2 * (int64_t)j + 1]);
+    }
+}
+
+// Direct adjoint: acc_k += sum_j g_j conj(w_j)^k over a group of direct nodes,
+// DIRECT_ATPT consecutive k >= 1 per thread (k = 0 is summed over all nodes apart).
+template <class Ctx, typename T>
+FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
+                            const cplx<T>* gin, int64_t N, double* acc)
+{
+    const DirectItem it = items[ctx.bid()];
+    const int64_t k0 = ((int64_t)it.chunk * ctx.ntid() + ctx.tid()) * DIRECT_ATPT;
+    if (k0 >= N) return;
+    T ar[DIRECT_ATPT], ai[DIRECT_ATPT];
+    for (int t = 0; t < DIRECT_ATPT; ++t) ar[t] = ai[t] = 0;
+    for (int gi = 0; gi < it.count; ++gi) {
+        const int32_t j = dlist[it.first + gi];
+        const cplx<T> gv = gin[pv.perm[j]];
+        const double x = pv.nx[j], y = pv.ny[j];
+        double sn, cs;
+        sincos(6.283185307179586476925286766559 * x, &sn, &cs);
+        const double m1 = exp(-y);
+        const cplx<T> w = mk<T>((T)(m1 * cs), (T)(-m1 * sn));
+        const double mag = exp(-(double)k0 * y);
+        sincos(-6.283185307179586476925286766559 * frac_kx((double)k0, x), &sn, &cs);
+        cplx<T> p = mk<T>((T)(mag * cs), (T)(mag * sn));
+        for (int t = 0; t < DIRECT_ATPT; ++t) {
+            ar[t] += gv.x * p.x - gv.y * p.y;
+            ai[t] += gv.x * p.y + gv.y * p.x;
+            p = mul(p, w);
+        }
+    }
+    for (int t = 0; t < DIRECT_ATPT; ++t) {
+        const int64_t k = k0 + t;
+        if (k >= 1 && k < N) {
+            ctx.atomic_add(acc + 2 * k, (double)ar[t]);
+            ctx.atomic_add(acc + 2 * k + 1, (double)ai[t]);
         }
     }
 }
@@ -441,7 +673,7 @@ FLT_HD void body_spread(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
 // transposed contraction acc_k += sum_s t_k[s] Ghat_s[k - k0] (FP64, atomics).
 template <class Ctx, typename T, int ITEMS>
 FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                             const cplx<T>* grids, double* acc, cplx<T>* lds)
+                             const cplx<T>* grids, double* acc, cplx<T>* lds, T* lc)
 {
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
@@ -452,6 +684,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     for (int s = 0; s < B.q; ++s) {
         const cplx<T>* src = grids + B.grid_off + ((int64_t)s << log2n);
         for (int p = ctx.tid(); p < n; p += ctx.ntid()) lds[p] = src[p];
+        stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
         lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n, 1, -1, pv.tw_stage);
         for (int i = 0; i < ITEMS; ++i) {
@@ -460,7 +693,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
             const int64_t kp = p < (n >> 1) ? p : p - n;
             const int64_t k = kp + B.k0;
             if (k < 1 || k > B.kmax) continue;
-            const T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+            const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
             accr[i] += (double)(lds[p].x * w);
             acci[i] += (double)(lds[p].y * w);
         }
@@ -481,7 +714,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // inverse-sign DFT over l1 -> j1, deconvolve, transposed contraction into acc.
 template <class Ctx, typename T, int ITEMS>
 FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                           const cplx<T>* scratch, double* acc, cplx<T>* lds)
+                           const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc)
 {
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
@@ -502,6 +735,7 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const cplx<T> v = Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
             lds[(jj << log2n1) + l1] = mul(v, tw_grid_at(pv, j2 * l1, B.log2n, -1));
         }
+        stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
         lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, -1, pv.tw_stage);
         for (int i = 0; i < ITEMS; ++i) {
@@ -513,7 +747,7 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int64_t kp = j < (n >> 1) ? j : j - n;
             const int64_t k = kp + B.k0;
             if (k < 1 || k > B.kmax) continue;
-            const T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+            const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
             const cplx<T> v = lds[(jj << log2n1) + j1];
             accr[i] += (double)(v.x * w);
             acci[i] += (double)(v.y * w);

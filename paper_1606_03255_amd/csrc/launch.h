@@ -6,29 +6,43 @@
 
 namespace flt {
 
-// Device copies of a plan's work lists.
+// Device copies of a plan's work lists and index tables.
 struct DevLists {
     const FftItem* onepass_fwd = nullptr;
     const FftItem* passA_fwd = nullptr;
     const FftItem* passB = nullptr;
     const FftItem* onepass_adj = nullptr;
     const FftItem* passA_adj = nullptr;
+    const FftItem* owner = nullptr;
     const NodeItem* nodes = nullptr;
-    int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_nodes = 0;
+    const NodeItem* nfft_nodes = nullptr;
+    const DirectItem* direct_fwd = nullptr;
+    const DirectItem* direct_adj = nullptr;
+    const int32_t* dlist = nullptr;
+    const int32_t* cstart = nullptr;
+    int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_owner = 0;
+    int n_nodes = 0, n_nfft_nodes = 0, n_direct_fwd = 0, n_direct_adj = 0;
+    int64_t n_dlist = 0;
 };
 
-// a2-a6 (forward, or derivative when deriv != 0): c -> f on stream st.
-// If ev is not null, ev[0..4] are recorded on st before the first launch and
-// after each of the four stages (one-pass FFTs, pass A, pass B, gather).
+// Where a call's scratch lives inside the caller's workspace.
+struct WsLayout {
+    char* ws = nullptr;
+    size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
+    int qs = 1;
+    int64_t N = 0, M = 0, grid_elems = 0;
+};
+
+// a2-a6 (forward, or derivative when deriv != 0): c -> f on stream st.  If ev
+// is not null, ev[0..5] are recorded on st before the first launch and after
+// each stage (one-pass FFTs, pass A, pass B, gather, direct bands).
 template <typename T>
-hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const void* c, void* f, char* ws,
-                          size_t off_grid, size_t off_scratch, int deriv, hipStream_t st,
-                          hipEvent_t* ev = nullptr);
+hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* c, void* f,
+                          int deriv, hipStream_t st, hipEvent_t* ev = nullptr);
 
 // a7 (adjoint): g -> c_out on stream st.
 template <typename T>
-hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, int64_t N, int64_t grid_elems, const void* g,
-                          void* c_out, char* ws, size_t off_grid, size_t off_scratch, size_t off_acc,
+hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* g, void* c_out,
                           hipStream_t st);
 
 }  // namespace flt

@@ -42,7 +42,13 @@ static int log2_exact(int64_t v)
     return r;
 }
 
-int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype)
+// Direct-sum policy: a band whose grids cost more HBM time than summing its
+// nodes directly is evaluated exactly (nodes x N terms) instead of by NFFT.
+static const double POLICY_HBM_BYTES_PER_S = 4.0e12;
+static const double POLICY_TERMS_PER_S_C64 = 2.0e12;
+static const double POLICY_TERMS_PER_S_C128 = 1.5e12;
+
+int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
 {
     if (!z || N < 1 || M < 1 || (dtype != FLT_C64 && dtype != FLT_C128)) return FLT_EINVAL;
     if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
@@ -55,6 +61,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     }
 
     hp = HostPlan();
+    hp.flags = flags;
     hp.N = N;
     hp.M = M;
     hp.dtype = dtype;
@@ -115,7 +122,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         B.n_xi = hp.n_xi;
         B.kmax = std::min<int64_t>(K, N - 1);
         B.k0 = K / 2;
-        B.log2n = std::max(log2_exact(2 * K), 4);
+        B.log2n = std::max(log2_exact(2 * K), std::max(4, log2_exact(2 * hp.mw)));
         if (B.log2n <= LOG2P) {
             B.log2n1 = B.log2n;
             B.log2n2 = B.log2b = B.log2B = 0;
@@ -138,6 +145,22 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         hp.band_m.push_back(0);
     }
     const int nb = (int)hp.bands.size();
+    if ((int64_t)(D - hp.n_xi + 2) * q > MAX_COEF_LDS) return FLT_EPRECISION;
+
+    // ---- per-band choice: NFFT (Alg. 2) or the exact direct sum for sparsely filled bands
+    {
+        const double S = dtype == FLT_C64 ? 8.0 : 16.0;
+        const double rate = dtype == FLT_C64 ? POLICY_TERMS_PER_S_C64 : POLICY_TERMS_PER_S_C128;
+        for (int b = 0; b < nb; ++b) {
+            BandDesc& B = hp.bands[b];
+            if (B.q == 0 || (flags & FLT_FLAG_NFFT_ONLY)) continue;
+            const double n = ldexp(1.0, B.log2n);
+            const double passes = B.log2n > LOG2P ? 4.0 : 2.0;
+            const double t_nfft = (passes * B.q * n * S + (double)B.kmax * S) / POLICY_HBM_BYTES_PER_S;
+            const double t_direct = (double)count[hp.band_m[b]] * (double)N / rate;
+            B.direct = t_direct < t_nfft ? 1 : 0;
+        }
+    }
 
     // ---- sort nodes by (band, grid cell)
     std::vector<int> nb_of(M);
@@ -183,7 +206,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     for (int b = 0; b < nb; ++b) {
         BandDesc& B = hp.bands[b];
         const int m = hp.band_m[b];
-        if (B.q == 0) continue;
+        if (B.q == 0 || B.direct) continue;
         // y interpolation nodes (Y_m) and weights
         B.ycheb_off = (int32_t)(hp.ycheb.size() / 2);
         if (m < D) {
@@ -254,32 +277,61 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     int64_t goff = 0, soff = 0;
     for (int b = 0; b < nb; ++b) {
         BandDesc& B = hp.bands[b];
-        if (B.q == 0) continue;
+        if (B.q == 0 || B.direct) continue;
         const int64_t n = (int64_t)1 << B.log2n;
         B.grid_off = goff;
         goff += (int64_t)B.q * n;
+        // cell-start table: first sorted node with cell >= c, c = 0..n
+        B.cs_off = (int64_t)hp.cstart.size();
+        {
+            int64_t jn = B.node_start;
+            const int64_t end = B.node_start + B.node_count;
+            for (int64_t cc = 0; cc <= n; ++cc) {
+                while (jn < end && cell[idx[jn]] < cc) ++jn;
+                hp.cstart.push_back((int32_t)jn);
+            }
+        }
+        const int nOwn = (int)((n + GATHER_THREADS - 1) / GATHER_THREADS);
+        for (int k = 0; k < nOwn; ++k) hp.owner.push_back(FftItem{b, 0, 0, k});
         if (B.log2n2 > 0) {
             B.scratch_off = soff;
             soff += (int64_t)B.q * n;
-        }
-        if (B.log2n2 == 0) {
+            const int nA = 1 << (B.log2n2 - B.log2b), nB = 1 << (B.log2n1 - B.log2B);
+            for (int k = 0; k < nA; ++k) hp.passA_fwd.push_back(FftItem{b, 0, B.q, k});
+            for (int s = 0; s < B.q; ++s)
+                for (int k = 0; k < nB; ++k) hp.passB.push_back(FftItem{b, s, 1, k});
+            for (int k = 0; k < nA; ++k) hp.passA_adj.push_back(FftItem{b, 0, B.q, k});
+        } else {
             const int ns = std::max(1, std::min(B.q, 1 << (LOG2P - B.log2n)));
             for (int s0 = 0; s0 < B.q; s0 += ns) hp.onepass_fwd.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
             hp.onepass_adj.push_back(FftItem{b, 0, B.q, 0});
-        } else {
-            const int nA = 1 << (B.log2n2 - B.log2b), nB = 1 << (B.log2n1 - B.log2B);
-            for (int s = 0; s < B.q; ++s) {
-                for (int k = 0; k < nA; ++k) hp.passA_fwd.push_back(FftItem{b, s, 1, k});
-                for (int k = 0; k < nB; ++k) hp.passB.push_back(FftItem{b, s, 1, k});
-            }
-            for (int k = 0; k < nA; ++k) hp.passA_adj.push_back(FftItem{b, 0, B.q, k});
         }
+        hp.qs = std::max(hp.qs, B.q);
     }
     for (int b = 0; b < nb; ++b) {
         const BandDesc& B = hp.bands[b];
-        for (int64_t s = 0; s < B.node_count; s += GATHER_THREADS)
-            hp.nodes.push_back(NodeItem{b, (int32_t)std::min<int64_t>(GATHER_THREADS, B.node_count - s), B.node_start + s});
+        if (B.direct) {
+            for (int64_t s = 0; s < B.node_count; ++s) hp.dlist.push_back((int32_t)(B.node_start + s));
+            continue;
+        }
+        for (int64_t s = 0; s < B.node_count; s += GATHER_THREADS) {
+            const NodeItem it{b, (int32_t)std::min<int64_t>(GATHER_THREADS, B.node_count - s), B.node_start + s};
+            hp.nodes.push_back(it);
+            if (B.q > 0) hp.nfft_nodes.push_back(it);
+        }
     }
+    if (!hp.dlist.empty()) {
+        const int64_t nd = (int64_t)hp.dlist.size();
+        const int64_t fchunks = (N + (int64_t)256 * DIRECT_TPT - 1) / ((int64_t)256 * DIRECT_TPT);
+        for (int64_t g = 0; g < nd; g += DIRECT_NG)
+            for (int64_t ch = 0; ch < fchunks; ++ch)
+                hp.direct_fwd.push_back(DirectItem{(int32_t)g, (int32_t)std::min<int64_t>(DIRECT_NG, nd - g), (int32_t)ch, 0});
+        const int64_t achunks = (N + (int64_t)256 * DIRECT_ATPT - 1) / ((int64_t)256 * DIRECT_ATPT);
+        for (int64_t g = 0; g < nd; g += DIRECT_ANG)
+            for (int64_t ch = 0; ch < achunks; ++ch)
+                hp.direct_adj.push_back(DirectItem{(int32_t)g, (int32_t)std::min<int64_t>(DIRECT_ANG, nd - g), (int32_t)ch, 0});
+    }
+    if (hp.cstart.empty()) hp.cstart.push_back(0);
     hp.grid_elems = goff;
     hp.scratch_elems = soff;
     const size_t S = hp.elem_bytes();
@@ -287,7 +339,11 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     hp.off_grid = 0;
     hp.off_scratch = al(hp.off_grid + (size_t)goff * S);
     hp.off_acc = al(hp.off_scratch + (size_t)soff * S);
-    hp.ws_bytes = al(hp.off_acc + (size_t)N * 16);
+    hp.off_U = al(hp.off_acc + (size_t)N * 16);
+    hp.off_phi = al(hp.off_U + (size_t)M * hp.qs * S);
+    hp.off_l0 = al(hp.off_phi + (size_t)M * 2 * hp.mw * (S / 2));
+    hp.off_dacc = al(hp.off_l0 + (size_t)M * 4);
+    hp.ws_bytes = al(hp.off_dacc + (size_t)M * 16);
 
     // ---- algorithmic model of one forward: every band grid written once and
     // read once, c read once per band, node records and results once
@@ -296,6 +352,11 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     for (int b = 0; b < nb; ++b) {
         const BandDesc& B = hp.bands[b];
         if (B.q == 0) continue;
+        if (B.direct) {                                       // c read once per node group
+            bytes += (double)N * S * (double)((B.node_count + DIRECT_NG - 1) / DIRECT_NG);
+            flops += 16.0 * (double)N * (double)B.node_count;
+            continue;
+        }
         const double n = ldexp(1.0, B.log2n);
         bytes += 2.0 * B.q * n * S + (double)B.kmax * S;
         flops += 2.0 * B.q * B.q * (double)B.kmax + 8.0 * B.q * (double)B.kmax;   // contraction, scaling

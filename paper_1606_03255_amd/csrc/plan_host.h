@@ -33,13 +33,21 @@ struct HostPlan {
     std::vector<double> coef, deconv, ycheb;
     std::vector<double> tw_stage, tw_lo, tw_hi;   // interleaved complex
 
+    uint32_t flags = 0;
+
     // work lists
-    std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj;
-    std::vector<NodeItem> nodes;
+    std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj, owner;
+    std::vector<NodeItem> nodes;        // gather: NFFT bands and the constant band
+    std::vector<NodeItem> nfft_nodes;   // adjoint node side: NFFT bands only
+    std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands
+    std::vector<DirectItem> direct_fwd, direct_adj;
+    std::vector<int32_t> cstart;        // per NFFT band: first sorted node with cell >= c, c = 0..n
 
     // workspace layout (bytes)
+    int qs = 1;                         // stride of the per-node column values (max q)
     int64_t grid_elems = 0, scratch_elems = 0;
-    size_t off_grid = 0, off_scratch = 0, off_acc = 0, ws_bytes = 0;
+    size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
+    size_t ws_bytes = 0;
 
     // algorithmic model
     double bytes_forward = 0, flops_forward = 0;
@@ -48,7 +56,8 @@ struct HostPlan {
 };
 
 // Returns FLT_OK or a negative FLT_E* code (see flt.h).
-int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype);
+int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype,
+                    uint32_t flags = 0);
 
 // Modified Bessel function I_0 by its power series (host, FP64).
 double bessel_i0(double x);

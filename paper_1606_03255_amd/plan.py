@@ -46,10 +46,12 @@ class Plan:
     dtype ``complex64`` selects the FP32 form (FP32 bulk arithmetic, FP64
     phase reduction and per-node sums); ``complex128`` the plain FP64 form.
     With ``host_only=True`` only the host-side plan is built (parameters,
-    partition, byte model) and no GPU is touched.
+    partition, byte model) and no GPU is touched.  ``nfft_only=True`` keeps
+    every band on Algorithm 2's NFFT path; by default bands with few nodes and
+    large grids are summed directly (exactly).
     """
 
-    def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False):
+    def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False, nfft_only=False):
         self._lib = L.load()
         self._ptr = ctypes.c_void_p()
         self.N = int(N)
@@ -57,7 +59,7 @@ class Plan:
         self.M = int(zh.shape[0])
         self.dtype_code = _dtype_code(dtype)
         self.host_only = bool(host_only)
-        flags = L.FLT_FLAG_HOST_ONLY if host_only else 0
+        flags = (L.FLT_FLAG_HOST_ONLY if host_only else 0) | (L.FLT_FLAG_NFFT_ONLY if nfft_only else 0)
         self._ws = None
         if host_only:
             rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M,
@@ -97,7 +99,7 @@ class Plan:
         for i in range(self.info()["num_bands"]):
             b = L.FltBandInfo()
             L.check(self._lib.flt_plan_band(self._ptr, i, ctypes.byref(b)), "flt_plan_band")
-            out.append({name: getattr(b, name) for name, _ in L.FltBandInfo._fields_ if name != "pad"})
+            out.append({name: getattr(b, name) for name, _ in L.FltBandInfo._fields_})
         return out
 
     def node_bands(self):
@@ -146,12 +148,12 @@ class Plan:
         return self._run(self._lib.flt_adjoint, g, self.M, self.N, out, "g")
 
     def profile_forward(self, c, out=None):
-        """One forward with per-kernel HIP-event timing; returns (f, stage_ms)
-        with stage_ms for (one-pass FFTs, pass A, pass B, gather)."""
+        """One forward with per-stage HIP-event timing; returns (f, stage_ms)
+        with stage_ms for (one-pass FFTs, pass A, pass B, gather, direct bands)."""
         import torch
         c = self._prep(c, self.N, "c")
         out = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out is None else out
-        ms = (ctypes.c_double * 4)()
+        ms = (ctypes.c_double * 5)()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         L.check(self._lib.flt_profile_forward(self._ptr, ctypes.c_void_p(c.data_ptr()),
                                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream), ms),

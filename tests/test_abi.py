@@ -107,6 +107,16 @@ def test_byte_model_large_workload():
     info = p.info()
     bands = p.bands()
     S = 8
-    expect = w["M"] * (16 + 4 + S) + sum(2 * b["q"] * b["n"] * S + min(b["K"], w["N"] - 1) * S for b in bands)
+    expect = w["M"] * (16 + 4 + S)
+    for b in bands:
+        if b["direct"]:    # c read once per group of 8 nodes of a direct-sum band
+            expect += w["N"] * S * -(-b["nodes"] // 8)
+        else:              # every band grid written once and read once, c once
+            expect += 2 * b["q"] * b["n"] * S + min(b["K"], w["N"] - 1) * S
     assert info["bytes_forward"] == pytest.approx(expect, rel=1e-12)
     assert (info["q"], info["D"]) == (12, 47)
+    # the policy sends exactly the sparsely filled full-size bands to the direct sum
+    assert all(b["nodes"] < 300 for b in bands if b["direct"])
+    assert all(b["n"] == 1 << 21 for b in bands if b["direct"])
+    p2 = flt.Plan(w["N"], w["z"], 1e-6, "complex64", host_only=True, nfft_only=True)
+    assert not any(b["direct"] for b in p2.bands())

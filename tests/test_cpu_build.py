@@ -1,0 +1,66 @@
+"""The kernel bodies built for the CPU (OpenMP teams with real barriers, the
+same work lists and tables as the GPU launches) against the oracle: index
+arithmetic, synchronisation and both band policies are checked here, before
+and apart from any GPU run.  Bars as in the GPU parity tests."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import method as O
+from paper_1606_03255_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+EMU = os.path.join(os.path.dirname(HERE), "paper_1606_03255_amd", "libflt_emu.so")
+
+
+@pytest.fixture(scope="module")
+def emu():
+    if not os.path.exists(EMU):
+        from paper_1606_03255_amd import build
+        build.build_emu()
+    os.environ.setdefault("OMP_WAIT_POLICY", "passive")
+    lib = ctypes.CDLL(EMU)
+    lib.flt_emu_run.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    return lib
+
+
+def run(lib, x, z, eps, dt, op, N, flags):
+    z = np.ascontiguousarray(z, np.complex128)
+    ct = np.complex64 if dt == 1 else np.complex128
+    inp = np.ascontiguousarray(x, ct)
+    out = np.zeros(N if op == 2 else len(z), ct)
+    rc = lib.flt_emu_run(N, len(z), z.ctypes.data, eps, dt, flags, op, inp.ctypes.data, out.ctypes.data)
+    assert rc == 0
+    return out.astype(np.complex128)
+
+
+# N, M, eps, dtype (1 = c64, 2 = c128): one-pass only, two-pass FFT bands, ragged N
+CASES = [(300, 120, 1e-6, 1), (256, 100, 1e-10, 2), (2100, 60, 1e-9, 2), (9000, 40, 1e-6, 1), (2, 9, 1e-8, 2)]
+
+
+@pytest.mark.parametrize("N,M,eps,dt", CASES)
+@pytest.mark.parametrize("flags", [0, 2])
+def test_cpu_build_vs_oracle(emu, N, M, eps, dt, flags):
+    rng = np.random.default_rng(N + M + flags)
+    c = inputs.coefficients(rng, N)
+    g = inputs.coefficients(rng, M)
+    if dt == 1:
+        c = c.astype(np.complex64).astype(np.complex128)
+        g = g.astype(np.complex64).astype(np.complex128)
+    z = np.concatenate([inputs.nodes_disk(rng, M // 2), inputs.nodes_annulus(rng, M - M // 2)])
+    z[0] = complex(0.3, np.inf)
+    z[1] = 0.999999999 + 0j
+    f = run(emu, c, z, eps, dt, 0, N, flags)
+    assert np.abs(f - oracle.forward(c, z)).max() <= eps * np.abs(c).sum()
+    fp = run(emu, c, z, eps, dt, 1, N, flags)
+    assert np.abs(fp - oracle.derivative(c, z)).max() <= eps * np.abs(2 * np.pi * np.arange(N) * c).sum()
+    h = run(emu, g, z, eps, dt, 2, N, flags)
+    assert np.abs(h - oracle.adjoint(g, z, N)).max() <= eps * np.abs(g).sum()
+    if dt == 2 and flags == 2:
+        n1 = np.abs(c).sum()
+        assert np.abs(f - O.alg2_forward(c, z, eps, "nfft")).max() <= 1e-13 * n1
+        assert np.abs(h - O.alg2_adjoint(g, z, N, eps, "nfft")).max() <= 1e-13 * np.abs(g).sum()

@@ -30,11 +30,11 @@ def torch():
     return t
 
 
-def _run(torch, c, z, eps, dtype, op="forward", N=None):
+def _run(torch, c, z, eps, dtype, op="forward", N=None, nfft_only=False):
     from paper_1606_03255_amd import Plan
     tdt = torch.complex64 if dtype == "c64" else torch.complex128
     N = len(c) if N is None else N
-    plan = Plan(N, z, eps, tdt)
+    plan = Plan(N, z, eps, tdt, nfft_only=nfft_only)
     x = torch.from_numpy(np.ascontiguousarray(c)).to("cuda", tdt)
     out = getattr(plan, op)(x)
     torch.cuda.synchronize()
@@ -65,23 +65,25 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("nfft_only", [True, False])
 @pytest.mark.parametrize("N,M,eps,dtype,kind", CASES)
-def test_forward_vs_direct(torch, N, M, eps, dtype, kind):
-    _say("forward", N, M, eps, dtype, kind)
+def test_forward_vs_direct(torch, N, M, eps, dtype, kind, nfft_only):
+    _say("forward", N, M, eps, dtype, kind, "nfft_only" if nfft_only else "policy")
     rng = np.random.default_rng(N + M)
     c = inputs.coefficients(rng, N)
     if dtype == "c64":
         c = c.astype(np.complex64).astype(np.complex128)
     z = _nodes(rng, M, kind)
-    f = _run(torch, c, z, eps, dtype)
+    f = _run(torch, c, z, eps, dtype, nfft_only=nfft_only)
     E = np.abs(f - oracle.forward(c, z)).max() / np.abs(c).sum()
     _say("   E =", E)
     assert E <= eps
 
 
+@pytest.mark.parametrize("nfft_only", [True, False])
 @pytest.mark.parametrize("N,M,eps,dtype,kind", [c for c in CASES if c[0] * c[1] <= 2e7])
-def test_adjoint_and_derivative_vs_direct(torch, N, M, eps, dtype, kind):
-    _say("adjoint/derivative", N, M, eps, dtype, kind)
+def test_adjoint_and_derivative_vs_direct(torch, N, M, eps, dtype, kind, nfft_only):
+    _say("adjoint/derivative", N, M, eps, dtype, kind, "nfft_only" if nfft_only else "policy")
     rng = np.random.default_rng(N + 2 * M)
     z = _nodes(rng, M, kind)
     g = inputs.coefficients(rng, M)
@@ -89,9 +91,9 @@ def test_adjoint_and_derivative_vs_direct(torch, N, M, eps, dtype, kind):
     if dtype == "c64":
         g = g.astype(np.complex64).astype(np.complex128)
         c = c.astype(np.complex64).astype(np.complex128)
-    h = _run(torch, g, z, eps, dtype, "adjoint", N=N)
+    h = _run(torch, g, z, eps, dtype, "adjoint", N=N, nfft_only=nfft_only)
     Eh = np.abs(h - oracle.adjoint(g, z, N)).max() / np.abs(g).sum()
-    fp = _run(torch, c, z, eps, dtype, "derivative")
+    fp = _run(torch, c, z, eps, dtype, "derivative", nfft_only=nfft_only)
     Ed = np.abs(fp - oracle.derivative(c, z)).max() / np.abs(2 * np.pi * np.arange(N) * c).sum()
     _say("   E adjoint =", Eh, " E derivative =", Ed)
     assert Eh <= eps
@@ -106,10 +108,10 @@ def test_fp64_matches_algorithm2_step_by_step(torch, N, M, eps):
     c = inputs.coefficients(rng, N)
     z = _nodes(rng, M, "mixed")
     n1 = np.abs(c).sum()
-    f = _run(torch, c, z, eps, "c128")
+    f = _run(torch, c, z, eps, "c128", nfft_only=True)
     assert np.abs(f - O.alg2_forward(c, z, eps, "nfft")).max() <= 1e-13 * n1
     g = inputs.coefficients(rng, M)
-    h = _run(torch, g, z, eps, "c128", "adjoint", N=N)
+    h = _run(torch, g, z, eps, "c128", "adjoint", N=N, nfft_only=True)
     assert np.abs(h - O.alg2_adjoint(g, z, N, eps, "nfft")).max() <= 1e-13 * np.abs(g).sum()
 
 
@@ -171,16 +173,16 @@ def _sample_nodes(plan_bands, z, rng, k=1500):
     return np.array(sorted(idx))
 
 
-@pytest.mark.parametrize("dtype,eps", [("c64", 1e-6), ("c128", 1e-11)])
-def test_large_workload_sampled(torch, dtype, eps):
+@pytest.mark.parametrize("dtype,eps,nfft_only", [("c64", 1e-6, False), ("c128", 1e-11, False), ("c64", 1e-6, True)])
+def test_large_workload_sampled(torch, dtype, eps, nfft_only):
     """N = M = 2^20, half annulus / half disk, in the launch configuration the
     benchmark times; checked against the direct sums on sampled nodes."""
     from paper_1606_03255_amd import Plan
-    _say("large", dtype, eps)
+    _say("large", dtype, eps, nfft_only)
     w = inputs.workload("large")
     c = w["c"].astype(np.complex128)
     tdt = torch.complex64 if dtype == "c64" else torch.complex128
-    plan = Plan(w["N"], w["z"], eps, tdt)
+    plan = Plan(w["N"], w["z"], eps, tdt, nfft_only=nfft_only)
     f = plan.forward(torch.from_numpy(c).to("cuda", tdt)).cpu().numpy().astype(np.complex128)
     sel = _sample_nodes(plan.node_bands(), w["z"], np.random.default_rng(0))
     plan.close()
