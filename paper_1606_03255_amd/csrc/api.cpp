@@ -94,6 +94,7 @@ static int upload(flt_plan* p)
     const size_t o_l7 = pk.add(hp.nfft_nodes.data(), hp.nfft_nodes.size() * sizeof(NodeItem));
     const size_t o_l8 = pk.add(hp.direct_fwd.data(), hp.direct_fwd.size() * sizeof(DirectItem));
     const size_t o_l9 = pk.add(hp.direct_adj.data(), hp.direct_adj.size() * sizeof(DirectItem));
+    const size_t o_ti = pk.add(hp.tile_items.data(), hp.tile_items.size() * sizeof(NodeItem));
     const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
     const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
 
@@ -115,6 +116,8 @@ static int upload(flt_plan* p)
     L.nodes = (const NodeItem*)(base + o_l5);
     L.owner = (const FftItem*)(base + o_l6);
     L.nfft_nodes = (const NodeItem*)(base + o_l7);
+    L.tile_items = (const NodeItem*)(base + o_ti);
+    L.n_tile_items = (int)hp.tile_items.size();
     L.direct_fwd = (const DirectItem*)(base + o_l8);
     L.direct_adj = (const DirectItem*)(base + o_l9);
     L.dlist = (const int32_t*)(base + o_dl);
@@ -130,6 +133,11 @@ static int upload(flt_plan* p)
     L.n_direct_fwd = (int)hp.direct_fwd.size();
     L.n_direct_adj = (int)hp.direct_adj.size();
     L.n_dlist = (int64_t)hp.dlist.size();
+    L.g_onepass_fwd = hp.g_onepass_fwd;
+    L.g_passA_fwd = hp.g_passA_fwd;
+    L.g_passB = hp.g_passB;
+    L.g_onepass_adj = hp.g_onepass_adj;
+    L.g_passA_adj = hp.g_passA_adj;
     return FLT_OK;
 }
 

@@ -10,6 +10,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "flt.h"
@@ -52,6 +53,19 @@ template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body
     }
 }
 
+template <int LO, int HI, class F> static bool with_log2(int v, F&& f)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (v == LO) {
+            f(std::integral_constant<int, LO>{});
+            return true;
+        }
+        return with_log2<LO + 1, HI>(v, f);
+    }
+}
+
 template <typename T, int MW>
 static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, const cplx<T>* c, cplx<T>* grids,
                      cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0)
@@ -68,12 +82,15 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
     run_blocks(hp.owner.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
         body_adj_owner<HostCtx, T, MW>(ctx, pv, hp.owner.data(), hp.qs, U, Phi, L0, hp.cstart.data(), grids);
     });
+    std::vector<T> tile(2 * TILE_CELLS);
+    run_blocks(hp.tile_items.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_adj_tiles<HostCtx, T, MW>(ctx, pv, hp.tile_items.data(), hp.qs, U, Phi, L0, grids, tile.data());
+    });
 }
 
 template <typename T>
 static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
 {
-    constexpr int ITEMS = (1 << Sizes<T>::LOG2P) / FFT_THREADS;
     const std::vector<T> coef = cast<T>(hp.coef), deconv = cast<T>(hp.deconv);
     const std::vector<T> tws = cast<T>(hp.tw_stage), twl = cast<T>(hp.tw_lo), twh = cast<T>(hp.tw_hi);
     PlanView<T> pv;
@@ -111,16 +128,28 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         const cplx<T>* c = (const cplx<T>*)in;
         cplx<T>* f = (cplx<T>*)out;
         const int deriv = op == 1;
-        run_blocks(hp.onepass_fwd.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_onepass_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_fwd.data(), c, grids.data(), deriv, lds.data());
-        });
-        run_blocks(hp.passA_fwd.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_passA_fwd<HostCtx, T, ITEMS>(ctx, pv, hp.passA_fwd.data(), c, scratch.data(), deriv, lds.data(),
-                                              lc.data());
-        });
-        run_blocks(hp.passB.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_passB<HostCtx, T, ITEMS>(ctx, pv, hp.passB.data(), scratch.data(), 0, grids.data(), +1, lds.data());
-        });
+        constexpr int LP = Sizes<T>::LOG2P;
+        for (const LaunchGroup& g : hp.g_onepass_fwd)
+            with_log2<4, LP>(g.log2, [&](auto LG) {
+                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
+                    body_onepass_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.onepass_fwd.data() + g.start, c,
+                                                                      grids.data(), deriv, lds.data());
+                });
+            });
+        for (const LaunchGroup& g : hp.g_passA_fwd)
+            with_log2<(LP + 2) / 2, 11>(g.log2, [&](auto LG) {
+                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
+                    body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
+                                                                    scratch.data(), deriv, lds.data(), lc.data());
+                });
+            });
+        for (const LaunchGroup& g : hp.g_passB)
+            with_log2<(LP + 1) / 2, 11>(g.log2, [&](auto LG) {
+                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
+                    body_passB<HostCtx, T, decltype(LG)::value, +1>(ctx, pv, hp.passB.data() + g.start,
+                                                                    scratch.data(), 0, grids.data(), lds.data());
+                });
+            });
         mwsw(0, c, f, !deriv);
         if (nd) {
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
@@ -143,17 +172,28 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         const int64_t nsum = (hp.M + 256 * SUMG_PER_THREAD - 1) / (256 * SUMG_PER_THREAD);
         run_blocks(nsum, 256, [&](const HostCtx& ctx) { body_sum_g<HostCtx, T>(ctx, g, hp.M, acc.data(), red.data()); });
         mwsw(1, g, nullptr, 0);
-        run_blocks(hp.passB.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_passB<HostCtx, T, ITEMS>(ctx, pv, hp.passB.data(), grids.data(), 1, scratch.data(), -1, lds.data());
-        });
-        run_blocks(hp.passA_adj.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_passA_adj<HostCtx, T, ITEMS>(ctx, pv, hp.passA_adj.data(), scratch.data(), acc.data(), lds.data(),
-                                              lc.data());
-        });
-        run_blocks(hp.onepass_adj.size(), FFT_THREADS, [&](const HostCtx& ctx) {
-            body_onepass_adj<HostCtx, T, ITEMS>(ctx, pv, hp.onepass_adj.data(), grids.data(), acc.data(), lds.data(),
-                                                lc.data());
-        });
+        constexpr int LP = Sizes<T>::LOG2P;
+        for (const LaunchGroup& g : hp.g_passB)
+            with_log2<(LP + 1) / 2, 11>(g.log2, [&](auto LG) {
+                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
+                    body_passB<HostCtx, T, decltype(LG)::value, -1>(ctx, pv, hp.passB.data() + g.start, grids.data(),
+                                                                    1, scratch.data(), lds.data());
+                });
+            });
+        for (const LaunchGroup& g : hp.g_passA_adj)
+            with_log2<(LP + 2) / 2, 11>(g.log2, [&](auto LG) {
+                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
+                    body_passA_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_adj.data() + g.start,
+                                                                    scratch.data(), acc.data(), lds.data(), lc.data());
+                });
+            });
+        for (const LaunchGroup& g : hp.g_onepass_adj)
+            with_log2<4, LP>(g.log2, [&](auto LG) {
+                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
+                    body_onepass_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.onepass_adj.data() + g.start,
+                                                                      grids.data(), acc.data(), lds.data(), lc.data());
+                });
+            });
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
             body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, hp.N, acc.data());
         });

@@ -50,6 +50,8 @@ constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
 constexpr int DIRECT_ATPT = 8;            // direct adjoint: coefficients per thread
 constexpr int DIRECT_ANG = 256;           // direct adjoint: nodes per workgroup
 constexpr int SUMG_PER_THREAD = 16;       // sum of g: elements per thread
+constexpr int TILE_CELLS = 2048;          // adjoint LDS tile (cells of one column)
+constexpr int TILE_NODES = 2048;          // adjoint LDS tile: most nodes per chunk
 
 template <typename T> struct Sizes;
 template <> struct Sizes<float>  { static constexpr int LOG2P = 13; };   // 8192 complex64 = 64 KB of LDS
@@ -71,6 +73,7 @@ struct BandDesc {
     int32_t deconv_off;  // deconvolution table of this n: entries |k'| = 0..n/4
     int32_t ycheb_off;   // q (node, weight) pairs of the y interpolation in the ycheb table
     int32_t direct;      // 1: the band's nodes are evaluated by the direct sum (no grids)
+    int32_t tiles;       // 1: the adjoint spreads this (densely filled) band through LDS tiles
     int64_t k0;          // centre of the frequency support
     int64_t kmax;        // support is k = 1..kmax
     int64_t grid_off;    // complex offset of the band's q grids (column-major, n each)
@@ -86,6 +89,14 @@ struct FftItem {
     int32_t s0;          // first column
     int32_t ns;          // columns in this item (one-pass kernel) / unused
     int32_t blk;         // j2-block (pass A) or l1-block (pass B)
+};
+
+// A run of work items that share the FFT length 2^log2 (one kernel instance).
+struct LaunchGroup {
+    int32_t log2;
+    int32_t start;
+    int32_t count;
+    int32_t pad;
 };
 
 // Work item of the node kernels: up to GATHER_THREADS consecutive sorted nodes of one band.

@@ -4,6 +4,8 @@
 // 64 KB LDS tiles for the FFT kernels) and orders them on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "kernels_impl.h"
 #include "launch.h"
 
@@ -18,31 +20,29 @@ struct DevCtx {
     __device__ __forceinline__ void atomic_add(float* p, float v) const { unsafeAtomicAdd(p, v); }
 };
 
-template <typename T> constexpr int fft_items() { return (1 << Sizes<T>::LOG2P) / FFT_THREADS; }
-
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_onepass_fwd(PlanView<T> pv, const FftItem* items,
+template <typename T, int LOG2N>
+__global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, const FftItem* items,
                                                              const cplx<T>* c, cplx<T>* grids, int deriv)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_onepass_fwd<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, c, grids, deriv, lds);
+    body_onepass_fwd<DevCtx, T, LOG2N>(DevCtx(), pv, items, c, grids, deriv, lds);
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
+template <typename T, int LOG2N1>
+__global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
                                                            const cplx<T>* c, cplx<T>* scratch, int deriv)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
     __shared__ T lc[MAX_COEF_LDS];
-    body_passA_fwd<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, c, scratch, deriv, lds, lc);
+    body_passA_fwd<DevCtx, T, LOG2N1>(DevCtx(), pv, items, c, scratch, deriv, lds, lc);
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_passB(PlanView<T> pv, const FftItem* items, const cplx<T>* src,
-                                                       int64_t sel, cplx<T>* dst, int sign)
+template <typename T, int LOG2N2, int SIGN>
+__global__ __launch_bounds__(FFT_THREADS, 2) void k_passB(PlanView<T> pv, const FftItem* items, const cplx<T>* src,
+                                                       int64_t sel, cplx<T>* dst)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_passB<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, src, sel, dst, sign, lds);
+    body_passB<DevCtx, T, LOG2N2, SIGN>(DevCtx(), pv, items, src, sel, dst, lds);
 }
 
 template <typename T, int MW>
@@ -68,6 +68,15 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_adj_owner(PlanView<T> pv, co
     body_adj_owner<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, cstart, grids);
 }
 
+template <typename T, int MW>
+__global__ __launch_bounds__(GATHER_THREADS) void k_adj_tiles(PlanView<T> pv, const NodeItem* items, int qs,
+                                                              const cplx<T>* U, const T* Phi, const int32_t* L0,
+                                                              cplx<T>* grids)
+{
+    __shared__ T tile[2 * TILE_CELLS];
+    body_adj_tiles<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, grids, tile);
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_sum_g(const cplx<T>* g, int64_t M, double* acc)
 {
@@ -75,22 +84,22 @@ __global__ __launch_bounds__(256) void k_sum_g(const cplx<T>* g, int64_t M, doub
     body_sum_g<DevCtx, T>(DevCtx(), g, M, acc, red);
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_onepass_adj(PlanView<T> pv, const FftItem* items,
+template <typename T, int LOG2N>
+__global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, const FftItem* items,
                                                              const cplx<T>* grids, double* acc)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
     __shared__ T lc[MAX_COEF_LDS];
-    body_onepass_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, grids, acc, lds, lc);
+    body_onepass_adj<DevCtx, T, LOG2N>(DevCtx(), pv, items, grids, acc, lds, lc);
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void k_passA_adj(PlanView<T> pv, const FftItem* items,
+template <typename T, int LOG2N1>
+__global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, const FftItem* items,
                                                            const cplx<T>* scratch, double* acc)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
     __shared__ T lc[MAX_COEF_LDS];
-    body_passA_adj<DevCtx, T, fft_items<T>()>(DevCtx(), pv, items, scratch, acc, lds, lc);
+    body_passA_adj<DevCtx, T, LOG2N1>(DevCtx(), pv, items, scratch, acc, lds, lc);
 }
 
 template <typename T>
@@ -137,6 +146,79 @@ static int grid_for(int64_t work, int per_block)
     return (int)g;
 }
 
+// Calls f(std::integral_constant<int, v>) for the runtime value v in [LO, HI].
+template <int LO, int HI, class F> static bool with_log2(int v, F&& f)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (v == LO) {
+            f(std::integral_constant<int, LO>{});
+            return true;
+        }
+        return with_log2<LO + 1, HI>(v, f);
+    }
+}
+
+template <typename T> struct Log2Range {
+    static constexpr int P = Sizes<T>::LOG2P;
+    static constexpr int ONE_LO = 4, ONE_HI = P;                          // one-pass lengths
+    static constexpr int A_LO = (P + 2) / 2, A_HI = TW2_LOG2 - TW2_LOG2 / 2;  // pass A: ceil(log2n / 2)
+    static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;         // pass B: floor(log2n / 2)
+};
+
+template <typename T>
+static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, cplx<T>* grids,
+                                     cplx<T>* scratch, int deriv, hipStream_t st, hipEvent_t* ev)
+{
+    using RG = Log2Range<T>;
+    bool ok = true;
+    if (ev) (void)hipEventRecord(ev[0], st);
+    for (const LaunchGroup& g : L.g_onepass_fwd)
+        ok &= with_log2<RG::ONE_LO, RG::ONE_HI>(g.log2, [&](auto LG) {
+            hipLaunchKernelGGL((k_onepass_fwd<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
+                               L.onepass_fwd + g.start, c, grids, deriv);
+        });
+    if (ev) (void)hipEventRecord(ev[1], st);
+    for (const LaunchGroup& g : L.g_passA_fwd)
+        ok &= with_log2<RG::A_LO, RG::A_HI>(g.log2, [&](auto LG) {
+            hipLaunchKernelGGL((k_passA_fwd<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
+                               L.passA_fwd + g.start, c, scratch, deriv);
+        });
+    if (ev) (void)hipEventRecord(ev[2], st);
+    for (const LaunchGroup& g : L.g_passB)
+        ok &= with_log2<RG::B_LO, RG::B_HI>(g.log2, [&](auto LG) {
+            hipLaunchKernelGGL((k_passB<T, decltype(LG)::value, +1>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
+                               L.passB + g.start, (const cplx<T>*)scratch, (int64_t)0, grids);
+        });
+    if (ev) (void)hipEventRecord(ev[3], st);
+    return ok ? hipSuccess : hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, cplx<T>* grids, cplx<T>* scratch,
+                                     double* acc, hipStream_t st)
+{
+    using RG = Log2Range<T>;
+    bool ok = true;
+    for (const LaunchGroup& g : L.g_passB)
+        ok &= with_log2<RG::B_LO, RG::B_HI>(g.log2, [&](auto LG) {
+            hipLaunchKernelGGL((k_passB<T, decltype(LG)::value, -1>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
+                               L.passB + g.start, (const cplx<T>*)grids, (int64_t)1, scratch);
+        });
+    for (const LaunchGroup& g : L.g_passA_adj)
+        ok &= with_log2<RG::A_LO, RG::A_HI>(g.log2, [&](auto LG) {
+            hipLaunchKernelGGL((k_passA_adj<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
+                               L.passA_adj + g.start, (const cplx<T>*)scratch, acc);
+        });
+    for (const LaunchGroup& g : L.g_onepass_adj)
+        ok &= with_log2<RG::ONE_LO, RG::ONE_HI>(g.log2, [&](auto LG) {
+            hipLaunchKernelGGL((k_onepass_adj<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
+                               L.onepass_adj + g.start, (const cplx<T>*)grids, acc);
+        });
+    return ok ? hipSuccess : hipErrorInvalidValue;
+}
+
 template <typename T, int MW>
 static void mw_forward_nodes(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, const cplx<T>* grids,
                              cplx<T>* f, int with_c0, hipStream_t st)
@@ -158,6 +240,9 @@ static void mw_adjoint_nodes(const DevLists& L, const PlanView<T>& pv, const WsL
     if (L.n_owner)
         hipLaunchKernelGGL((k_adj_owner<T, MW>), dim3(L.n_owner), dim3(GATHER_THREADS), 0, st, pv, L.owner, W.qs,
                            (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, L.cstart, grids);
+    if (L.n_tile_items)
+        hipLaunchKernelGGL((k_adj_tiles<T, MW>), dim3(L.n_tile_items), dim3(GATHER_THREADS), 0, st, pv,
+                           L.tile_items, W.qs, (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, grids);
 }
 
 template <typename T>
@@ -169,19 +254,8 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
     double* dacc = (double*)(W.ws + W.off_dacc);
-    if (ev) (void)hipEventRecord(ev[0], st);
-    if (L.n_onepass_fwd)
-        hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(L.n_onepass_fwd), dim3(FFT_THREADS), 0, st, pv, L.onepass_fwd, c,
-                           grids, deriv);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    if (L.n_passA_fwd)
-        hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
-                           scratch, deriv);
-    if (ev) (void)hipEventRecord(ev[2], st);
-    if (L.n_passB)
-        hipLaunchKernelGGL(k_passB<T>, dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
-                           (const cplx<T>*)scratch, (int64_t)0, grids, +1);
-    if (ev) (void)hipEventRecord(ev[3], st);
+    hipError_t e = fft_forward_stages<T>(L, pv, c, grids, scratch, deriv, st, ev);
+    if (e != hipSuccess) return e;
     if (L.n_nodes) {
         switch (pv.mw) {
 #define G(MWV) case MWV: mw_forward_nodes<T, MWV>(L, pv, c, grids, f, !deriv, st); break;
@@ -219,15 +293,8 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayo
 #undef S
         default: return hipErrorInvalidValue;
     }
-    if (L.n_passB)
-        hipLaunchKernelGGL(k_passB<T>, dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
-                           (const cplx<T>*)grids, (int64_t)1, scratch, -1);
-    if (L.n_passA_adj)
-        hipLaunchKernelGGL(k_passA_adj<T>, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
-                           (const cplx<T>*)scratch, acc);
-    if (L.n_onepass_adj)
-        hipLaunchKernelGGL(k_onepass_adj<T>, dim3(L.n_onepass_adj), dim3(FFT_THREADS), 0, st, pv, L.onepass_adj,
-                           (const cplx<T>*)grids, acc);
+    hipError_t e = fft_adjoint_stages<T>(L, pv, grids, scratch, acc, st);
+    if (e != hipSuccess) return e;
     if (L.n_direct_adj)
         hipLaunchKernelGGL(k_direct_adj<T>, dim3(L.n_direct_adj), dim3(256), 0, st, pv, L.direct_adj, L.dlist, g,
                            W.N, acc);

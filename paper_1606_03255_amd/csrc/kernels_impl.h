@@ -104,11 +104,40 @@ template <typename T> FLT_HD void dft8(cplx<T>* v, int sign)
     v[3] = add(a[3], w3);   v[7] = sub(a[3], w3);
 }
 
+// 16 = 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle e^{sign 2 pi i n2 k1 / 16}, DFT4 over n2.
+template <typename T> FLT_HD void dft16(cplx<T>* v, int sign)
+{
+    const T C1 = T(0.92387953251128675612818318939679), S1 = T(0.38268343236508977172845998403040);
+    const T H = T(0.70710678118654752440084436210485);
+    const T sg = sign > 0 ? T(1) : T(-1);
+    cplx<T> a[4][4];
+    for (int n2 = 0; n2 < 4; ++n2) {
+        for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+        dft4(a[n2], sign);
+    }
+    // e^{sign 2 pi i m / 16} for m = n2 k1
+    a[1][1] = mul(a[1][1], mk(C1, sg * S1));
+    a[1][2] = mul(a[1][2], mk(H, sg * H));
+    a[1][3] = mul(a[1][3], mk(S1, sg * C1));
+    a[2][1] = mul(a[2][1], mk(H, sg * H));
+    a[2][2] = mul_isign(a[2][2], sign);
+    a[2][3] = mul(a[2][3], mk(-H, sg * H));
+    a[3][1] = mul(a[3][1], mk(S1, sg * C1));
+    a[3][2] = mul(a[3][2], mk(-H, sg * H));
+    a[3][3] = mul(a[3][3], mk(-C1, -sg * S1));
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cplx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4(b, sign);
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
+
 template <typename T, int R> FLT_HD void dft(cplx<T>* v, int sign)
 {
     if (R == 2) dft2(v);
     else if (R == 4) dft4(v, sign);
-    else dft8(v, sign);
+    else if (R == 8) dft8(v, sign);
+    else dft16(v, sign);
 }
 
 // e^{sign 2 pi i t / 2^TW_STAGE_LOG2}
@@ -128,59 +157,71 @@ template <typename T> FLT_HD cplx<T> tw_grid_at(const PlanView<T>& pv, int64_t e
     return w;
 }
 
-// One Stockham autosort radix-R stage over `nsub` contiguous transforms of
-// length 2^log2L held in `buf` (in place: reads, barrier, writes, barrier).
-template <class Ctx, typename T, int R, int ITEMS>
-FLT_HD void fft_stage(const Ctx& ctx, cplx<T>* buf, int log2L, int P, int log2Ns, int sign,
-                      const cplx<T>* tw)
+// Largest radix (log2) a thread handles in registers: the points it holds per stage.
+template <typename T> struct MaxRadix;
+template <> struct MaxRadix<float> { static constexpr int LOG2 = 4; };
+template <> struct MaxRadix<double> { static constexpr int LOG2 = 3; };
+
+constexpr int next_radix_log2(int rem, int maxr)
 {
-    constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : 3);
-    constexpr int NB = ITEMS / R > 0 ? ITEMS / R : 1;
-    const int nbut = P >> LR;
-    const int log2Lq = log2L - LR;
-    const int Nsm = (1 << log2Ns) - 1;
+    int r = rem < maxr ? rem : maxr;
+    if (rem - r == 1 && r > 2) r -= 1;   // leave no radix-2 stage when a larger split exists
+    return r;
+}
+
+// One Stockham autosort radix-2^LR stage over NSUB contiguous transforms of
+// length 2^LOG2L in `buf`, all geometry known at compile time (in place:
+// reads, barrier, writes, barrier).  Twiddles e^{SIGN 2 pi i k r / (Ns R)}.
+template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN>
+FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
+{
+    constexpr int R = 1 << LR;
+    constexpr int P = NSUB << LOG2L;
+    constexpr int NBUT = P >> LR;
+    constexpr int LOG2LQ = LOG2L - LR;
+    constexpr int NB = (NBUT + FFT_THREADS - 1) / FFT_THREADS;
     cplx<T> v[NB][R];
     int dst[NB];
     for (int i = 0; i < NB; ++i) {
-        const int u = ctx.tid() + i * ctx.ntid();
+        const int u = ctx.tid() + i * FFT_THREADS;
         dst[i] = -1;
-        if (u < nbut) {
-            const int sub = u >> log2Lq;
-            const int j = u & ((1 << log2Lq) - 1);
-            const cplx<T>* src = buf + (sub << log2L) + j;
-            for (int r = 0; r < R; ++r) v[i][r] = src[r << log2Lq];
-            const int k = j & Nsm;
-            if (log2Ns > 0) {
-                const int sh = TW_STAGE_LOG2 - log2Ns - LR;
-                for (int r = 1; r < R; ++r) v[i][r] = mul(v[i][r], tw_stage_at(tw, (k * r) << sh, sign));
+        if ((NBUT % FFT_THREADS) == 0 || u < NBUT) {
+            const int sub = u >> LOG2LQ;
+            const int j = u & ((1 << LOG2LQ) - 1);
+            const cplx<T>* src = buf + (sub << LOG2L) + j;
+            for (int r = 0; r < R; ++r) v[i][r] = src[r << LOG2LQ];
+            const int k = j & ((1 << LOG2NS) - 1);
+            if (LOG2NS > 0) {
+                constexpr int SH = TW_STAGE_LOG2 - LOG2NS - LR;
+                for (int r = 1; r < R; ++r) v[i][r] = mul(v[i][r], tw_stage_at(tw, (k * r) << SH, SIGN));
             }
-            dft<T, R>(v[i], sign);
-            dst[i] = (sub << log2L) + ((j >> log2Ns) << (log2Ns + LR)) + k;
+            dft<T, R>(v[i], SIGN);
+            dst[i] = (sub << LOG2L) + ((j >> LOG2NS) << (LOG2NS + LR)) + k;
         }
     }
     ctx.sync();
     for (int i = 0; i < NB; ++i)
         if (dst[i] >= 0)
-            for (int r = 0; r < R; ++r) buf[dst[i] + (r << log2Ns)] = v[i][r];
+            for (int r = 0; r < R; ++r) buf[dst[i] + (r << LOG2NS)] = v[i][r];
     ctx.sync();
 }
 
-// In-place DFTs X[l] = sum_j x[j] e^{sign 2 pi i j l / L} of `nsub` transforms
-// of length L = 2^log2L stored contiguously in LDS; nsub*L <= ITEMS*ntid.
-template <class Ctx, typename T, int ITEMS>
-FLT_HD void lds_fft(const Ctx& ctx, cplx<T>* buf, int log2L, int nsub, int sign, const cplx<T>* tw)
+// In-place DFTs X[l] = sum_j x[j] e^{SIGN 2 pi i j l / L} of NSUB transforms of
+// length L = 2^LOG2L stored contiguously in LDS (Stockham, natural order in and out).
+template <class Ctx, typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS = 0>
+FLT_HD void lds_fft_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
 {
-    const int P = nsub << log2L;
-    int log2Ns = 0, rem = log2L;
-    while (rem > 0) {
-        const int r = (rem % 3 == 0) ? 3 : ((rem % 3 == 2) ? 2 : (rem >= 4 ? 2 : 1));
-        if (r == 3) fft_stage<Ctx, T, 8, ITEMS>(ctx, buf, log2L, P, log2Ns, sign, tw);
-        else if (r == 2) fft_stage<Ctx, T, 4, ITEMS>(ctx, buf, log2L, P, log2Ns, sign, tw);
-        else fft_stage<Ctx, T, 2, ITEMS>(ctx, buf, log2L, P, log2Ns, sign, tw);
-        log2Ns += r;
-        rem -= r;
+    constexpr int REM = LOG2L - LOG2NS;
+    if constexpr (REM > 0) {
+        constexpr int LR = next_radix_log2(REM, MaxRadix<T>::LOG2);
+        fft_stage_ct<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN>(ctx, buf, tw);
+        lds_fft_ct<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, buf, tw);
     }
 }
+
+// Points of the 64 KB LDS tile: P = 2^LOG2P complex values, ITEMS per thread.
+template <typename T> constexpr int tile_points() { return 1 << Sizes<T>::LOG2P; }
+template <typename T> constexpr int tile_items() { return tile_points<T>() / FFT_THREADS; }
 
 // Column s's Chebyshev coefficients of every interpolated block of band B,
 // staged into LDS as lc[(l - ell_lo) q + i].
@@ -249,20 +290,24 @@ FLT_HD int64_t grid_addr(const BandDesc& B, int64_t l)
 // ---------------------------------------------------------------------------
 // a2-a4, one-pass bands: generate `ns` columns, FFT them in LDS, store.
 // ---------------------------------------------------------------------------
-template <class Ctx, typename T, int ITEMS>
+template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                              const cplx<T>* c, cplx<T>* grids, int deriv, cplx<T>* lds)
 {
+    constexpr int NSUB = tile_points<T>() >> LOG2N;
+    constexpr int P = NSUB << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int log2n = B.log2n;
-    const int P = it.ns << log2n;
-    for (int p = ctx.tid(); p < P; p += ctx.ntid())
-        lds[p] = grid_input(pv, B, c, it.s0 + (p >> log2n), (int64_t)(p & ((1 << log2n) - 1)), deriv);
+    for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
+        const int sl = p >> LOG2N;
+        lds[p] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, (int64_t)(p & ((1 << LOG2N) - 1)), deriv)
+                            : mk<T>(0, 0);
+    }
     ctx.sync();
-    lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n, it.ns, +1, pv.tw_stage);
-    cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << log2n);
-    for (int p = ctx.tid(); p < P; p += ctx.ntid()) out[p] = lds[p];
+    lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, pv.tw_stage);
+    cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << LOG2N);
+    const int Pv = it.ns << LOG2N;
+    for (int p = ctx.tid(); p < Pv; p += FFT_THREADS) out[p] = lds[p];
 }
 
 // ---------------------------------------------------------------------------
@@ -270,46 +315,37 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // DFTs over j1 of x[j2 + n2 j1] (generated from c), times e^{2 pi i j2 l1 / n},
 // stored as Y[l1 / B][j2][l1 mod B].
 // ---------------------------------------------------------------------------
-template <class Ctx, typename T, int ITEMS>
+template <class Ctx, typename T, int LOG2N1>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* c, cplx<T>* scratch, int deriv, cplx<T>* lds, T* lc)
 {
+    constexpr int ITEMS = tile_items<T>();
+    constexpr int log2n1 = LOG2N1, log2b = Sizes<T>::LOG2P - LOG2N1;
+    constexpr int P = tile_points<T>();
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int log2n1 = B.log2n1, log2n2 = B.log2n2, log2b = B.log2b, log2B = B.log2B;
-    const int P = 1 << (log2b + log2n1);
+    const int log2n2 = B.log2n2, log2B = B.log2B;
     const int64_t n = (int64_t)1 << B.log2n;
     const int64_t j2_0 = (int64_t)it.blk << log2b;
-    // c_k / (n phi_hat(k')) of this thread's points, shared by all q columns
-    cplx<T> base[ITEMS];
-    for (int i = 0; i < ITEMS; ++i) {
-        const int p = ctx.tid() + i * ctx.ntid();
-        base[i] = mk<T>(0, 0);
-        if (p < P) {
-            const int64_t j = j2_0 + (p & ((1 << log2b) - 1)) + ((int64_t)(p >> log2b) << log2n2);
-            const int64_t kp = j < (n >> 1) ? j : j - n;
-            const int64_t k = kp + B.k0;
-            if (k >= 1 && k <= B.kmax) base[i] = point_base(pv, B, c, kp, k, deriv);
-        }
-    }
     for (int s = 0; s < B.q; ++s) {
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
         for (int i = 0; i < ITEMS; ++i) {
-            const int p = ctx.tid() + i * ctx.ntid();
+            const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= P) break;
             const int jj = p & ((1 << log2b) - 1);
             const int j1 = p >> log2b;
             const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
-            const int64_t k = (j < (n >> 1) ? j : j - n) + B.k0;
-            cplx<T> v = base[i];
-            if (k >= 1 && k <= B.kmax) v = scale(v, laplace_row_lds(lc, B, k));
+            const int64_t kp = j < (n >> 1) ? j : j - n;
+            const int64_t k = kp + B.k0;
+            cplx<T> v = mk<T>(0, 0);
+            if (k >= 1 && k <= B.kmax) v = scale(point_base(pv, B, c, kp, k, deriv), laplace_row_lds(lc, B, k));
             lds[(jj << log2n1) + j1] = v;
         }
         ctx.sync();
-        lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, +1, pv.tw_stage);
+        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, pv.tw_stage);
         cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
-        for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+        for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
             const int l1lo = p & ((1 << log2B) - 1);
             const int jj = (p >> log2B) & ((1 << log2b) - 1);
             const int l1hi = p >> (log2B + log2b);
@@ -324,30 +360,29 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
 
 // pass B: for B = 2^log2B consecutive l1, the length-n2 DFTs over j2 of
 // Y[j2][l1]; X[l1 + n1 l2] stored blocked as [l1 / B][l2][l1 mod B].
-template <class Ctx, typename T, int ITEMS>
+template <class Ctx, typename T, int LOG2N2, int SIGN>
 FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                       const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base,
-                       int sign, cplx<T>* lds)
+                       const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base, cplx<T>* lds)
 {
     // src_band_off_sel: 0 -> source at scratch_off, destination at grid_off (forward);
     //                   1 -> source at grid_off, destination at scratch_off (adjoint)
+    constexpr int log2n2 = LOG2N2, log2B = Sizes<T>::LOG2P - LOG2N2;
+    constexpr int P = tile_points<T>();
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int log2n2 = B.log2n2, log2B = B.log2B;
-    const int P = 1 << (log2B + log2n2);
     const int64_t so = src_band_off_sel ? B.grid_off : B.scratch_off;
     const int64_t dso = src_band_off_sel ? B.scratch_off : B.grid_off;
     const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << (log2n2 + log2B));
     const cplx<T>* src = src_base + so + blk_off;
-    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+    for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int j2 = p >> log2B;
         const int lo = p & ((1 << log2B) - 1);
         lds[(lo << log2n2) + j2] = src[p];
     }
     ctx.sync();
-    lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n2, 1 << log2B, sign, pv.tw_stage);
+    lds_fft_ct<Ctx, T, LOG2N2, (1 << log2B), SIGN>(ctx, lds, pv.tw_stage);
     cplx<T>* dst = dst_base + dso + blk_off;
-    for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+    for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int l2 = p >> log2B;
         const int lo = p & ((1 << log2B) - 1);
         dst[p] = lds[(lo << log2n2) + l2];
@@ -501,6 +536,12 @@ FLT_HD void body_adj_owner(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     const int64_t n = (int64_t)1 << B.log2n;
     const int64_t l = (int64_t)it.blk * ctx.ntid() + ctx.tid();
     if (l >= n) return;
+    if (B.tiles) {                               // densely filled band: cleared here, filled by body_adj_tiles
+        cplx<T>* g = grids + B.grid_off;
+        const int64_t addr = grid_addr(B, l);
+        for (int s = 0; s < B.q; ++s) g[((int64_t)s << B.log2n) + addr] = mk<T>(0, 0);
+        return;
+    }
     const int32_t* c0 = cstart + B.cs_off;       // c0[c]: first sorted node of the band with cell >= c
     const int64_t a = l - MW, b = l + MW;
     int32_t r0s, r0e, r1s = 0, r1e = 0;
@@ -524,6 +565,48 @@ FLT_HD void body_adj_owner(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             }
         }
         g[((int64_t)s << B.log2n) + addr] = mk(ar, ai);
+    }
+}
+
+// Adjoint a7, grid side for densely filled bands: a chunk of consecutive
+// sorted nodes (cells l0_first..l0_last) accumulates u_j^s phi into an LDS
+// tile of the cells its windows cover, [l0_first - mw + 1, l0_last + mw],
+// which is then added to the band grid (zeroed by the owner kernel) with
+// global atomics, one column at a time.
+template <class Ctx, typename T, int MW>
+FLT_HD void body_adj_tiles(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items, int qs, const cplx<T>* U,
+                           const T* Phi, const int32_t* L0, cplx<T>* grids, T* tile)
+{
+    const NodeItem it = items[ctx.bid()];
+    const BandDesc& B = pv.bands[it.band];
+    const int64_t n = (int64_t)1 << B.log2n;
+    const int64_t l0a = L0[it.start];
+    const int64_t t0 = l0a - MW + 1;
+    const int span = (int)(L0[it.start + it.count - 1] - l0a) + 2 * MW;
+    T* g = (T*)(grids + B.grid_off);
+    for (int s = 0; s < B.q; ++s) {
+        for (int i = ctx.tid(); i < 2 * span; i += ctx.ntid()) tile[i] = T(0);
+        ctx.sync();
+        for (int64_t j = it.start + ctx.tid(); j < it.start + it.count; j += ctx.ntid()) {
+            const cplx<T> u = U[j * qs + s];
+            const int64_t base = (int64_t)L0[j] - MW + 1 - t0;
+            for (int t = 0; t < 2 * MW; ++t) {
+                const T w = Phi[j * (2 * MW) + t];
+                ctx.atomic_add(tile + 2 * (base + t), u.x * w);
+                ctx.atomic_add(tile + 2 * (base + t) + 1, u.y * w);
+            }
+        }
+        ctx.sync();
+        for (int i = ctx.tid(); i < span; i += ctx.ntid()) {
+            const T vr = tile[2 * i], vi = tile[2 * i + 1];
+            if (vr == T(0) && vi == T(0)) continue;
+            int64_t l = t0 + i;
+            l = ((l % n) + n) % n;
+            const int64_t a = ((int64_t)s << B.log2n) + grid_addr(B, l);
+            ctx.atomic_add(g + 2 * a, vr);
+            ctx.atomic_add(g + 2 * a + 1, vi);
+        }
+        ctx.sync();
     }
 }
 
@@ -671,62 +754,65 @@ FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectI
 
 // Adjoint of one-pass bands: per column, inverse-sign FFT in LDS, deconvolve,
 // transposed contraction acc_k += sum_s t_k[s] Ghat_s[k - k0] (FP64, atomics).
-template <class Ctx, typename T, int ITEMS>
+template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                              const cplx<T>* grids, double* acc, cplx<T>* lds, T* lc)
 {
+    constexpr int ITEMS = tile_items<T>();
+    constexpr int log2n = LOG2N;
+    constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int log2n = B.log2n;
-    const int n = 1 << log2n;
-    double accr[ITEMS], acci[ITEMS];
+    T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
         const cplx<T>* src = grids + B.grid_off + ((int64_t)s << log2n);
-        for (int p = ctx.tid(); p < n; p += ctx.ntid()) lds[p] = src[p];
+        for (int p = ctx.tid(); p < n; p += FFT_THREADS) lds[p] = src[p];
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
-        lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n, 1, -1, pv.tw_stage);
+        lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, pv.tw_stage);
         for (int i = 0; i < ITEMS; ++i) {
-            const int p = ctx.tid() + i * ctx.ntid();
+            const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= n) break;
             const int64_t kp = p < (n >> 1) ? p : p - n;
             const int64_t k = kp + B.k0;
             if (k < 1 || k > B.kmax) continue;
             const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-            accr[i] += (double)(lds[p].x * w);
-            acci[i] += (double)(lds[p].y * w);
+            accr[i] += lds[p].x * w;
+            acci[i] += lds[p].y * w;
         }
         ctx.sync();
     }
     for (int i = 0; i < ITEMS; ++i) {
-        const int p = ctx.tid() + i * ctx.ntid();
+        const int p = ctx.tid() + i * FFT_THREADS;
         if (p >= n) break;
         const int64_t kp = p < (n >> 1) ? p : p - n;
         const int64_t k = kp + B.k0;
         if (k < 1 || k > B.kmax) continue;
-        ctx.atomic_add(acc + 2 * k, accr[i]);
-        ctx.atomic_add(acc + 2 * k + 1, acci[i]);
+        ctx.atomic_add(acc + 2 * k, (double)accr[i]);
+        ctx.atomic_add(acc + 2 * k + 1, (double)acci[i]);
     }
 }
 
 // Adjoint pass A: for b consecutive j2, all columns s: Y[j2][l1] e^{-2 pi i j2 l1 / n},
 // inverse-sign DFT over l1 -> j1, deconvolve, transposed contraction into acc.
-template <class Ctx, typename T, int ITEMS>
+template <class Ctx, typename T, int LOG2N1>
 FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc)
 {
+    constexpr int ITEMS = tile_items<T>();
+    constexpr int log2n1 = LOG2N1, log2b = Sizes<T>::LOG2P - LOG2N1;
+    constexpr int P = tile_points<T>();
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int log2n1 = B.log2n1, log2n2 = B.log2n2, log2b = B.log2b, log2B = B.log2B;
-    const int P = 1 << (log2b + log2n1);
+    const int log2n2 = B.log2n2, log2B = B.log2B;
     const int64_t n = (int64_t)1 << B.log2n;
     const int64_t j2_0 = (int64_t)it.blk << log2b;
-    double accr[ITEMS], acci[ITEMS];
+    T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
         const cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
-        for (int p = ctx.tid(); p < P; p += ctx.ntid()) {
+        for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
             const int l1lo = p & ((1 << log2B) - 1);
             const int jj = (p >> log2B) & ((1 << log2b) - 1);
             const int l1hi = p >> (log2B + log2b);
@@ -737,9 +823,9 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         }
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
-        lds_fft<Ctx, T, ITEMS>(ctx, lds, log2n1, 1 << log2b, -1, pv.tw_stage);
+        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), -1>(ctx, lds, pv.tw_stage);
         for (int i = 0; i < ITEMS; ++i) {
-            const int p = ctx.tid() + i * ctx.ntid();
+            const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= P) break;
             const int jj = p & ((1 << log2b) - 1);
             const int j1 = p >> log2b;
@@ -749,13 +835,13 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             if (k < 1 || k > B.kmax) continue;
             const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
             const cplx<T> v = lds[(jj << log2n1) + j1];
-            accr[i] += (double)(v.x * w);
-            acci[i] += (double)(v.y * w);
+            accr[i] += v.x * w;
+            acci[i] += v.y * w;
         }
         ctx.sync();
     }
     for (int i = 0; i < ITEMS; ++i) {
-        const int p = ctx.tid() + i * ctx.ntid();
+        const int p = ctx.tid() + i * FFT_THREADS;
         if (p >= P) break;
         const int jj = p & ((1 << log2b) - 1);
         const int j1 = p >> log2b;
@@ -763,8 +849,8 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         const int64_t kp = j < (n >> 1) ? j : j - n;
         const int64_t k = kp + B.k0;
         if (k < 1 || k > B.kmax) continue;
-        ctx.atomic_add(acc + 2 * k, accr[i]);
-        ctx.atomic_add(acc + 2 * k + 1, acci[i]);
+        ctx.atomic_add(acc + 2 * k, (double)accr[i]);
+        ctx.atomic_add(acc + 2 * k + 1, (double)acci[i]);
     }
 }
 

@@ -129,8 +129,9 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         } else {
             B.log2n1 = (B.log2n + 1) / 2;
             B.log2n2 = B.log2n - B.log2n1;
-            B.log2b = std::min(LOG2P - B.log2n1, B.log2n2);
-            B.log2B = std::min(LOG2P - B.log2n2, B.log2n1);
+            B.log2b = LOG2P - B.log2n1;     // a full LDS tile of sub-transforms per workgroup
+            B.log2B = LOG2P - B.log2n2;
+            if (B.log2b > B.log2n2 || B.log2B > B.log2n1) return FLT_ERANGE;
         }
         band_of_m[m] = (int)hp.bands.size();
         hp.bands.push_back(B);
@@ -293,6 +294,19 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         }
         const int nOwn = (int)((n + GATHER_THREADS - 1) / GATHER_THREADS);
         for (int k = 0; k < nOwn; ++k) hp.owner.push_back(FftItem{b, 0, 0, k});
+        // densely filled bands (more than 2 nodes per cell) spread through LDS tiles:
+        // chunks of sorted nodes whose windows span at most TILE_CELLS cells
+        if (B.node_count > 2 * n) {
+            B.tiles = 1;
+            const int64_t end = B.node_start + B.node_count;
+            int64_t a = B.node_start;
+            while (a < end) {
+                int64_t e = a + 1;
+                while (e < end && e - a < TILE_NODES && cell[idx[e]] - cell[idx[a]] + 2 * hp.mw <= TILE_CELLS) ++e;
+                hp.tile_items.push_back(NodeItem{b, (int32_t)(e - a), a});
+                a = e;
+            }
+        }
         if (B.log2n2 > 0) {
             B.scratch_off = soff;
             soff += (int64_t)B.q * n;
@@ -331,6 +345,24 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
             for (int64_t ch = 0; ch < achunks; ++ch)
                 hp.direct_adj.push_back(DirectItem{(int32_t)g, (int32_t)std::min<int64_t>(DIRECT_ANG, nd - g), (int32_t)ch, 0});
     }
+    // FFT lists grouped by transform length (one compile-time kernel instance per length)
+    auto group = [&](std::vector<FftItem>& v, std::vector<LaunchGroup>& g, int which) {
+        auto len = [&](const FftItem& it) {
+            const BandDesc& B = hp.bands[it.band];
+            return which == 0 ? B.log2n : (which == 1 ? B.log2n1 : B.log2n2);
+        };
+        std::stable_sort(v.begin(), v.end(), [&](const FftItem& a, const FftItem& b) { return len(a) < len(b); });
+        g.clear();
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (g.empty() || g.back().log2 != len(v[i])) g.push_back(LaunchGroup{len(v[i]), (int32_t)i, 0, 0});
+            g.back().count++;
+        }
+    };
+    group(hp.onepass_fwd, hp.g_onepass_fwd, 0);
+    group(hp.onepass_adj, hp.g_onepass_adj, 0);
+    group(hp.passA_fwd, hp.g_passA_fwd, 1);
+    group(hp.passA_adj, hp.g_passA_adj, 1);
+    group(hp.passB, hp.g_passB, 2);
     if (hp.cstart.empty()) hp.cstart.push_back(0);
     hp.grid_elems = goff;
     hp.scratch_elems = soff;
