@@ -294,7 +294,8 @@ template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                              const cplx<T>* c, cplx<T>* grids, int deriv, cplx<T>* lds)
 {
-    constexpr int NSUB = tile_points<T>() >> LOG2N;
+    // columns per workgroup: a full tile, but never more than a band has (q <= MAX_Q)
+    constexpr int NSUB = (tile_points<T>() >> LOG2N) < MAX_Q ? (tile_points<T>() >> LOG2N) : MAX_Q;
     constexpr int P = NSUB << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
