@@ -261,6 +261,7 @@ static WsLayout layout(const flt_plan* p)
     W.off_phi = hp.off_phi;
     W.off_l0 = hp.off_l0;
     W.off_dacc = hp.off_dacc;
+    W.off_base = hp.off_base;
     W.qs = hp.qs;
     W.N = hp.N;
     W.M = hp.M;

@@ -44,7 +44,7 @@ constexpr int TW2_HALF = 11;              // lo/hi tables of 2^11 entries each
 constexpr int GATHER_THREADS = 256;       // nodes per gather/spread workgroup
 constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
 constexpr int MAX_MW = 10;                // largest window half-width supported
-constexpr int MAX_COEF_LDS = 2048;        // LDS slots for one column's Chebyshev coefficients
+constexpr int MAX_COEF_LDS = 2048;        // LDS slots for one column's Chebyshev coefficients (allocation)
 constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread
 constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
 constexpr int DIRECT_ATPT = 8;            // direct adjoint: coefficients per thread
@@ -54,8 +54,10 @@ constexpr int TILE_CELLS = 2048;          // adjoint LDS tile (cells of one colu
 constexpr int TILE_NODES = 2048;          // adjoint LDS tile: most nodes per chunk
 
 template <typename T> struct Sizes;
-template <> struct Sizes<float>  { static constexpr int LOG2P = 13; };   // 8192 complex64 = 64 KB of LDS
-template <> struct Sizes<double> { static constexpr int LOG2P = 12; };   // 4096 complex128 = 64 KB of LDS
+// LOG2P: FFT tile of 2^LOG2P complex values = 64 KB of LDS; COEF: LDS slots for
+// one column's Chebyshev coefficients of every block of a band
+template <> struct Sizes<float>  { static constexpr int LOG2P = 13; static constexpr int COEF = 2048; };
+template <> struct Sizes<double> { static constexpr int LOG2P = 12; static constexpr int COEF = 1536; };
 
 // One occupied band of the node partition (Def. 3.2 Y_m, or Y_D), or the
 // constant band (q = 0) that holds the Z^0 nodes.
@@ -81,6 +83,7 @@ struct BandDesc {
     int64_t node_start;  // first node of the band in the sorted node arrays
     int64_t node_count;
     int64_t cs_off;      // cell-start table of the band (n + 1 entries) for the adjoint
+    int64_t base_off;    // pass A: complex offset of the band's per-point c_k / (n phi_hat) slots
 };
 
 // Work item of an FFT kernel: band, first column, and a block index.

@@ -20,29 +20,66 @@ struct DevCtx {
     __device__ __forceinline__ void atomic_add(float* p, float v) const { unsafeAtomicAdd(p, v); }
 };
 
-template <typename T, int LOG2N>
+// Calls f(std::integral_constant<int, v>) for the runtime value v in [LO, HI]
+// (a uniform branch inside a kernel, or a host-side choice).
+template <int LO, int HI, class F> __host__ __device__ static bool with_log2(int v, F&& f)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (v == LO) {
+            f(std::integral_constant<int, LO>{});
+            return true;
+        }
+        return with_log2<LO + 1, HI>(v, f);
+    }
+}
+
+template <typename T> struct Log2Range {
+    static constexpr int P = Sizes<T>::LOG2P;
+    static constexpr int ONE_LO = 4, ONE_HI = P;                              // one-pass lengths
+    static constexpr int A_LO = (P + 2) / 2, A_HI = TW2_LOG2 - TW2_LOG2 / 2;  // pass A: ceil(log2n / 2)
+    static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;             // pass B: floor(log2n / 2)
+};
+
+// One launch per FFT kind; each workgroup picks the compile-time instance of
+// its band's transform length.
+template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, const FftItem* items,
-                                                             const cplx<T>* c, cplx<T>* grids, int deriv)
+                                                                const cplx<T>* c, cplx<T>* grids, int deriv)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_onepass_fwd<DevCtx, T, LOG2N>(DevCtx(), pv, items, c, grids, deriv, lds);
+    __shared__ cplx<T> tq[(1 << (Sizes<T>::LOG2P - 2)) + 1];
+    using RG = Log2Range<T>;
+    with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
+        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, lds, tq);
+    });
 }
 
-template <typename T, int LOG2N1>
+template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
-                                                           const cplx<T>* c, cplx<T>* scratch, int deriv)
+                                                              const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf,
+                                                              int deriv)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    __shared__ T lc[MAX_COEF_LDS];
-    body_passA_fwd<DevCtx, T, LOG2N1>(DevCtx(), pv, items, c, scratch, deriv, lds, lc);
+    __shared__ T lc[Sizes<T>::COEF];
+    __shared__ cplx<T> tq[(1 << (TW2_HALF - 2)) + 1];
+    using RG = Log2Range<T>;
+    with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
+        body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, lds, lc, tq);
+    });
 }
 
-template <typename T, int LOG2N2, int SIGN>
+template <typename T, int SIGN>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_passB(PlanView<T> pv, const FftItem* items, const cplx<T>* src,
-                                                       int64_t sel, cplx<T>* dst)
+                                                          int64_t sel, cplx<T>* dst)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    body_passB<DevCtx, T, LOG2N2, SIGN>(DevCtx(), pv, items, src, sel, dst, lds);
+    __shared__ cplx<T> tq[(1 << (TW2_HALF - 2)) + 1];
+    using RG = Log2Range<T>;
+    with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[blockIdx.x].band].log2n2, [&](auto LG) {
+        body_passB<DevCtx, T, decltype(LG)::value, SIGN>(DevCtx(), pv, items, src, sel, dst, lds, tq);
+    });
 }
 
 template <typename T, int MW>
@@ -84,22 +121,30 @@ __global__ __launch_bounds__(256) void k_sum_g(const cplx<T>* g, int64_t M, doub
     body_sum_g<DevCtx, T>(DevCtx(), g, M, acc, red);
 }
 
-template <typename T, int LOG2N>
+template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, const FftItem* items,
-                                                             const cplx<T>* grids, double* acc)
+                                                                const cplx<T>* grids, double* acc)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    __shared__ T lc[MAX_COEF_LDS];
-    body_onepass_adj<DevCtx, T, LOG2N>(DevCtx(), pv, items, grids, acc, lds, lc);
+    __shared__ T lc[Sizes<T>::COEF];
+    __shared__ cplx<T> tq[(1 << (Sizes<T>::LOG2P - 2)) + 1];
+    using RG = Log2Range<T>;
+    with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
+        body_onepass_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, grids, acc, lds, lc, tq);
+    });
 }
 
-template <typename T, int LOG2N1>
+template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, const FftItem* items,
-                                                           const cplx<T>* scratch, double* acc)
+                                                              const cplx<T>* scratch, double* acc)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    __shared__ T lc[MAX_COEF_LDS];
-    body_passA_adj<DevCtx, T, LOG2N1>(DevCtx(), pv, items, scratch, acc, lds, lc);
+    __shared__ T lc[Sizes<T>::COEF];
+    __shared__ cplx<T> tq[(1 << (TW2_HALF - 2)) + 1];
+    using RG = Log2Range<T>;
+    with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
+        body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc, tq);
+    });
 }
 
 template <typename T>
@@ -146,77 +191,43 @@ static int grid_for(int64_t work, int per_block)
     return (int)g;
 }
 
-// Calls f(std::integral_constant<int, v>) for the runtime value v in [LO, HI].
-template <int LO, int HI, class F> static bool with_log2(int v, F&& f)
-{
-    if constexpr (LO > HI) {
-        return false;
-    } else {
-        if (v == LO) {
-            f(std::integral_constant<int, LO>{});
-            return true;
-        }
-        return with_log2<LO + 1, HI>(v, f);
-    }
-}
-
-template <typename T> struct Log2Range {
-    static constexpr int P = Sizes<T>::LOG2P;
-    static constexpr int ONE_LO = 4, ONE_HI = P;                          // one-pass lengths
-    static constexpr int A_LO = (P + 2) / 2, A_HI = TW2_LOG2 - TW2_LOG2 / 2;  // pass A: ceil(log2n / 2)
-    static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;         // pass B: floor(log2n / 2)
-};
-
 template <typename T>
-static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, cplx<T>* grids,
-                                     cplx<T>* scratch, int deriv, hipStream_t st, hipEvent_t* ev)
+static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const cplx<T>* c,
+                                     int deriv, hipStream_t st, hipEvent_t* ev)
 {
-    using RG = Log2Range<T>;
-    bool ok = true;
+    cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
+    cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
+    cplx<T>* basebuf = (cplx<T>*)(W.ws + W.off_base);
     if (ev) (void)hipEventRecord(ev[0], st);
-    for (const LaunchGroup& g : L.g_onepass_fwd)
-        ok &= with_log2<RG::ONE_LO, RG::ONE_HI>(g.log2, [&](auto LG) {
-            hipLaunchKernelGGL((k_onepass_fwd<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
-                               L.onepass_fwd + g.start, c, grids, deriv);
-        });
+    if (L.n_onepass_fwd)
+        hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(L.n_onepass_fwd), dim3(FFT_THREADS), 0, st, pv, L.onepass_fwd, c,
+                           grids, deriv);
     if (ev) (void)hipEventRecord(ev[1], st);
-    for (const LaunchGroup& g : L.g_passA_fwd)
-        ok &= with_log2<RG::A_LO, RG::A_HI>(g.log2, [&](auto LG) {
-            hipLaunchKernelGGL((k_passA_fwd<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
-                               L.passA_fwd + g.start, c, scratch, deriv);
-        });
+    if (L.n_passA_fwd)
+        hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
+                           scratch, basebuf, deriv);
     if (ev) (void)hipEventRecord(ev[2], st);
-    for (const LaunchGroup& g : L.g_passB)
-        ok &= with_log2<RG::B_LO, RG::B_HI>(g.log2, [&](auto LG) {
-            hipLaunchKernelGGL((k_passB<T, decltype(LG)::value, +1>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
-                               L.passB + g.start, (const cplx<T>*)scratch, (int64_t)0, grids);
-        });
+    if (L.n_passB)
+        hipLaunchKernelGGL((k_passB<T, +1>), dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
+                           (const cplx<T>*)scratch, (int64_t)0, grids);
     if (ev) (void)hipEventRecord(ev[3], st);
-    return ok ? hipSuccess : hipErrorInvalidValue;
+    return hipSuccess;
 }
 
 template <typename T>
 static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, cplx<T>* grids, cplx<T>* scratch,
                                      double* acc, hipStream_t st)
 {
-    using RG = Log2Range<T>;
-    bool ok = true;
-    for (const LaunchGroup& g : L.g_passB)
-        ok &= with_log2<RG::B_LO, RG::B_HI>(g.log2, [&](auto LG) {
-            hipLaunchKernelGGL((k_passB<T, decltype(LG)::value, -1>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
-                               L.passB + g.start, (const cplx<T>*)grids, (int64_t)1, scratch);
-        });
-    for (const LaunchGroup& g : L.g_passA_adj)
-        ok &= with_log2<RG::A_LO, RG::A_HI>(g.log2, [&](auto LG) {
-            hipLaunchKernelGGL((k_passA_adj<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
-                               L.passA_adj + g.start, (const cplx<T>*)scratch, acc);
-        });
-    for (const LaunchGroup& g : L.g_onepass_adj)
-        ok &= with_log2<RG::ONE_LO, RG::ONE_HI>(g.log2, [&](auto LG) {
-            hipLaunchKernelGGL((k_onepass_adj<T, decltype(LG)::value>), dim3(g.count), dim3(FFT_THREADS), 0, st, pv,
-                               L.onepass_adj + g.start, (const cplx<T>*)grids, acc);
-        });
-    return ok ? hipSuccess : hipErrorInvalidValue;
+    if (L.n_passB)
+        hipLaunchKernelGGL((k_passB<T, -1>), dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
+                           (const cplx<T>*)grids, (int64_t)1, scratch);
+    if (L.n_passA_adj)
+        hipLaunchKernelGGL(k_passA_adj<T>, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
+                           (const cplx<T>*)scratch, acc);
+    if (L.n_onepass_adj)
+        hipLaunchKernelGGL(k_onepass_adj<T>, dim3(L.n_onepass_adj), dim3(FFT_THREADS), 0, st, pv, L.onepass_adj,
+                           (const cplx<T>*)grids, acc);
+    return hipSuccess;
 }
 
 template <typename T, int MW>
@@ -254,7 +265,7 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
     double* dacc = (double*)(W.ws + W.off_dacc);
-    hipError_t e = fft_forward_stages<T>(L, pv, c, grids, scratch, deriv, st, ev);
+    hipError_t e = fft_forward_stages<T>(L, pv, W, c, deriv, st, ev);
     if (e != hipSuccess) return e;
     if (L.n_nodes) {
         switch (pv.mw) {

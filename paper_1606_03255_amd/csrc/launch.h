@@ -34,6 +34,7 @@ struct DevLists {
 struct WsLayout {
     char* ws = nullptr;
     size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
+    size_t off_base = 0;
     int qs = 1;
     int64_t N = 0, M = 0, grid_elems = 0;
 };

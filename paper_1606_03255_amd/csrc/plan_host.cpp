@@ -146,7 +146,8 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         hp.band_m.push_back(0);
     }
     const int nb = (int)hp.bands.size();
-    if ((int64_t)(D - hp.n_xi + 2) * q > MAX_COEF_LDS) return FLT_EPRECISION;
+    if ((int64_t)(D - hp.n_xi + 2) * q > (dtype == FLT_C64 ? Sizes<float>::COEF : Sizes<double>::COEF))
+        return FLT_EPRECISION;
 
     // ---- per-band choice: NFFT (Alg. 2) or the exact direct sum for sparsely filled bands
     {
@@ -275,7 +276,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     }
 
     // ---- workspace layout and work lists
-    int64_t goff = 0, soff = 0;
+    int64_t goff = 0, soff = 0, boff = 0;
     for (int b = 0; b < nb; ++b) {
         BandDesc& B = hp.bands[b];
         if (B.q == 0 || B.direct) continue;
@@ -310,6 +311,8 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         if (B.log2n2 > 0) {
             B.scratch_off = soff;
             soff += (int64_t)B.q * n;
+            B.base_off = boff;
+            boff += n;
             const int nA = 1 << (B.log2n2 - B.log2b), nB = 1 << (B.log2n1 - B.log2B);
             for (int k = 0; k < nA; ++k) hp.passA_fwd.push_back(FftItem{b, 0, B.q, k});
             for (int s = 0; s < B.q; ++s)
@@ -375,7 +378,8 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     hp.off_phi = al(hp.off_U + (size_t)M * hp.qs * S);
     hp.off_l0 = al(hp.off_phi + (size_t)M * 2 * hp.mw * (S / 2));
     hp.off_dacc = al(hp.off_l0 + (size_t)M * 4);
-    hp.ws_bytes = al(hp.off_dacc + (size_t)M * 16);
+    hp.off_base = al(hp.off_dacc + (size_t)M * 16);
+    hp.ws_bytes = al(hp.off_base + (size_t)boff * S);
 
     // ---- algorithmic model of one forward: every band grid written once and
     // read once, c read once per band, node records and results once

@@ -50,6 +50,7 @@ struct HostPlan {
     int qs = 1;                         // stride of the per-node column values (max q)
     int64_t grid_elems = 0, scratch_elems = 0;
     size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
+    size_t off_base = 0;
     size_t ws_bytes = 0;
 
     // algorithmic model
