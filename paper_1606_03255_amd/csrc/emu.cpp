@@ -116,7 +116,6 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
     std::vector<cplx<T>> lds(1 << Sizes<T>::LOG2P);
     std::vector<T> lc(Sizes<T>::COEF);
-    std::vector<cplx<T>> tq((1 << (Sizes<T>::LOG2P - 2)) + 1);
     int64_t base_elems = 1;
     for (const BandDesc& B : hp.bands)
         if (B.q > 0 && !B.direct && B.log2n2 > 0) base_elems = std::max(base_elems, B.base_off + ((int64_t)1 << B.log2n));
@@ -138,7 +137,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             with_log2<4, LP>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_onepass_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.onepass_fwd.data() + g.start, c,
-                                                                      grids.data(), deriv, lds.data(), tq.data());
+                                                                      grids.data(), deriv, lds.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_passA_fwd)
@@ -146,15 +145,14 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
                                                                     scratch.data(), basebuf.data(), deriv, lds.data(),
-                                                                    lc.data(), tq.data());
+                                                                    lc.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_passB)
             with_log2<(LP + 1) / 2, 11>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passB<HostCtx, T, decltype(LG)::value, +1>(ctx, pv, hp.passB.data() + g.start,
-                                                                    scratch.data(), 0, grids.data(), lds.data(),
-                                                                    tq.data());
+                                                                    scratch.data(), 0, grids.data(), lds.data());
                 });
             });
         mwsw(0, c, f, !deriv);
@@ -184,23 +182,21 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             with_log2<(LP + 1) / 2, 11>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passB<HostCtx, T, decltype(LG)::value, -1>(ctx, pv, hp.passB.data() + g.start, grids.data(),
-                                                                    1, scratch.data(), lds.data(), tq.data());
+                                                                    1, scratch.data(), lds.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_passA_adj)
             with_log2<(LP + 2) / 2, 11>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passA_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_adj.data() + g.start,
-                                                                    scratch.data(), acc.data(), lds.data(), lc.data(),
-                                                                    tq.data());
+                                                                    scratch.data(), acc.data(), lds.data(), lc.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_onepass_adj)
             with_log2<4, LP>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_onepass_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.onepass_adj.data() + g.start,
-                                                                      grids.data(), acc.data(), lds.data(), lc.data(),
-                                                                      tq.data());
+                                                                      grids.data(), acc.data(), lds.data(), lc.data());
                 });
             });
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {

@@ -49,10 +49,9 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, 
                                                                 const cplx<T>* c, cplx<T>* grids, int deriv)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    __shared__ cplx<T> tq[(1 << (Sizes<T>::LOG2P - 2)) + 1];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, lds, tq);
+        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, lds);
     });
 }
 
@@ -63,10 +62,9 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, co
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
     __shared__ T lc[Sizes<T>::COEF];
-    __shared__ cplx<T> tq[(1 << (TW2_HALF - 2)) + 1];
     using RG = Log2Range<T>;
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
-        body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, lds, lc, tq);
+        body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, lds, lc);
     });
 }
 
@@ -75,10 +73,9 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passB(PlanView<T> pv, const 
                                                           int64_t sel, cplx<T>* dst)
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
-    __shared__ cplx<T> tq[(1 << (TW2_HALF - 2)) + 1];
     using RG = Log2Range<T>;
     with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[blockIdx.x].band].log2n2, [&](auto LG) {
-        body_passB<DevCtx, T, decltype(LG)::value, SIGN>(DevCtx(), pv, items, src, sel, dst, lds, tq);
+        body_passB<DevCtx, T, decltype(LG)::value, SIGN>(DevCtx(), pv, items, src, sel, dst, lds);
     });
 }
 
@@ -127,10 +124,9 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, 
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
     __shared__ T lc[Sizes<T>::COEF];
-    __shared__ cplx<T> tq[(1 << (Sizes<T>::LOG2P - 2)) + 1];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_onepass_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, grids, acc, lds, lc, tq);
+        body_onepass_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, grids, acc, lds, lc);
     });
 }
 
@@ -140,10 +136,9 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, co
 {
     __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
     __shared__ T lc[Sizes<T>::COEF];
-    __shared__ cplx<T> tq[(1 << (TW2_HALF - 2)) + 1];
     using RG = Log2Range<T>;
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
-        body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc, tq);
+        body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc);
     });
 }
 

@@ -169,29 +169,6 @@ constexpr int next_radix_log2(int rem, int maxr)
     return r;
 }
 
-// Twiddles of a length-L transform from a quarter table in LDS,
-// tq[t] = e^{-2 pi i t / L}, t <= L/4, and the quadrant rotation by (-i)^quad;
-// conjugated for SIGN = +1.
-template <class Ctx, typename T, int LOG2L>
-FLT_HD void stage_tw(const Ctx& ctx, const cplx<T>* tw_global, cplx<T>* tq)
-{
-    constexpr int Q = (1 << LOG2L) >> 2;
-    for (int t = ctx.tid(); t <= Q; t += ctx.ntid()) tq[t] = tw_global[t << (TW_STAGE_LOG2 - LOG2L)];
-}
-template <typename T, int LOG2L, int SIGN> FLT_HD cplx<T> tw_quarter(const cplx<T>* tq, int e)
-{
-    constexpr int LOG2Q = LOG2L >= 2 ? LOG2L - 2 : 0;
-    const int quad = e >> LOG2Q;
-    const cplx<T> w = tq[e & ((1 << LOG2Q) - 1)];
-    cplx<T> r;
-    if (quad == 0) r = w;
-    else if (quad == 1) r = mk(w.y, -w.x);
-    else if (quad == 2) r = mk(-w.x, -w.y);
-    else r = mk(-w.y, w.x);
-    if (SIGN > 0) r.y = -r.y;
-    return r;
-}
-
 // One Stockham autosort radix-2^LR stage over NSUB contiguous transforms of
 // length 2^LOG2L in `buf`, all geometry known at compile time (in place:
 // reads, barrier, writes, barrier).  Twiddles e^{SIGN 2 pi i k r / (Ns R)}.
@@ -215,8 +192,8 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
             for (int r = 0; r < R; ++r) v[i][r] = src[r << LOG2LQ];
             const int k = j & ((1 << LOG2NS) - 1);
             if (LOG2NS > 0) {
-                constexpr int SH = LOG2L - LOG2NS - LR;
-                for (int r = 1; r < R; ++r) v[i][r] = mul(v[i][r], tw_quarter<T, LOG2L, SIGN>(tw, (k * r) << SH));
+                constexpr int SH = TW_STAGE_LOG2 - LOG2NS - LR;
+                for (int r = 1; r < R; ++r) v[i][r] = mul(v[i][r], tw_stage_at(tw, (k * r) << SH, SIGN));
             }
             dft<T, R>(v[i], SIGN);
             dst[i] = (sub << LOG2L) + ((j >> LOG2NS) << (LOG2NS + LR)) + k;
@@ -231,7 +208,7 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
 
 // In-place DFTs X[l] = sum_j x[j] e^{SIGN 2 pi i j l / L} of NSUB transforms of
 // length L = 2^LOG2L stored contiguously in LDS (Stockham, natural order in and
-// out); tw is the quarter twiddle table of stage_tw.
+// out); tw is the stage twiddle table e^{-2 pi i t / 2^TW_STAGE_LOG2}.
 template <class Ctx, typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS = 0>
 FLT_HD void lds_fft_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
 {
@@ -316,21 +293,20 @@ FLT_HD int64_t grid_addr(const BandDesc& B, int64_t l)
 // ---------------------------------------------------------------------------
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                             const cplx<T>* c, cplx<T>* grids, int deriv, cplx<T>* lds, cplx<T>* tq)
+                             const cplx<T>* c, cplx<T>* grids, int deriv, cplx<T>* lds)
 {
     // columns per workgroup: a full tile, but never more than a band has (q <= MAX_Q)
     constexpr int NSUB = (tile_points<T>() >> LOG2N) < MAX_Q ? (tile_points<T>() >> LOG2N) : MAX_Q;
     constexpr int P = NSUB << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    stage_tw<Ctx, T, LOG2N>(ctx, pv.tw_stage, tq);
     for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int sl = p >> LOG2N;
         lds[p] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, (int64_t)(p & ((1 << LOG2N) - 1)), deriv)
                             : mk<T>(0, 0);
     }
     ctx.sync();
-    lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, tq);
+    lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, pv.tw_stage);
     cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << LOG2N);
     const int Pv = it.ns << LOG2N;
     for (int p = ctx.tid(); p < Pv; p += FFT_THREADS) out[p] = lds[p];
@@ -343,8 +319,7 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // ---------------------------------------------------------------------------
 template <class Ctx, typename T, int LOG2N1>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                           const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf, int deriv, cplx<T>* lds, T* lc,
-                           cplx<T>* tq)
+                           const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf, int deriv, cplx<T>* lds, T* lc)
 {
     constexpr int ITEMS = tile_items<T>();
     constexpr int log2n1 = LOG2N1, log2b = Sizes<T>::LOG2P - LOG2N1;
@@ -358,7 +333,6 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     // reads of c) and kept in the workgroup's own coalesced slot for the other
     // columns; every thread re-reads only what it wrote.
     cplx<T>* slot = basebuf + B.base_off + (int64_t)it.blk * P;
-    stage_tw<Ctx, T, LOG2N1>(ctx, pv.tw_stage, tq);
     for (int s = 0; s < B.q; ++s) {
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
@@ -380,7 +354,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             lds[(jj << log2n1) + j1] = valid ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
         }
         ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, tq);
+        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, pv.tw_stage);
         cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
         for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
             const int l1lo = p & ((1 << log2B) - 1);
@@ -399,8 +373,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
 // Y[j2][l1]; X[l1 + n1 l2] stored blocked as [l1 / B][l2][l1 mod B].
 template <class Ctx, typename T, int LOG2N2, int SIGN>
 FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                       const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base, cplx<T>* lds,
-                       cplx<T>* tq)
+                       const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base, cplx<T>* lds)
 {
     // src_band_off_sel: 0 -> source at scratch_off, destination at grid_off (forward);
     //                   1 -> source at grid_off, destination at scratch_off (adjoint)
@@ -408,7 +381,6 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
     constexpr int P = tile_points<T>();
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    stage_tw<Ctx, T, LOG2N2>(ctx, pv.tw_stage, tq);
     const int64_t so = src_band_off_sel ? B.grid_off : B.scratch_off;
     const int64_t dso = src_band_off_sel ? B.scratch_off : B.grid_off;
     const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << (log2n2 + log2B));
@@ -419,7 +391,7 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
         lds[(lo << log2n2) + j2] = src[p];
     }
     ctx.sync();
-    lds_fft_ct<Ctx, T, LOG2N2, (1 << log2B), SIGN>(ctx, lds, tq);
+    lds_fft_ct<Ctx, T, LOG2N2, (1 << log2B), SIGN>(ctx, lds, pv.tw_stage);
     cplx<T>* dst = dst_base + dso + blk_off;
     for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int l2 = p >> log2B;
@@ -795,14 +767,13 @@ FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectI
 // transposed contraction acc_k += sum_s t_k[s] Ghat_s[k - k0] (FP64, atomics).
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                             const cplx<T>* grids, double* acc, cplx<T>* lds, T* lc, cplx<T>* tq)
+                             const cplx<T>* grids, double* acc, cplx<T>* lds, T* lc)
 {
     constexpr int ITEMS = tile_items<T>();
     constexpr int log2n = LOG2N;
     constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    stage_tw<Ctx, T, LOG2N>(ctx, pv.tw_stage, tq);
     T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
@@ -810,7 +781,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
         for (int p = ctx.tid(); p < n; p += FFT_THREADS) lds[p] = src[p];
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, tq);
+        lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, pv.tw_stage);
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= n) break;
@@ -838,14 +809,13 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // inverse-sign DFT over l1 -> j1, deconvolve, transposed contraction into acc.
 template <class Ctx, typename T, int LOG2N1>
 FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                           const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc, cplx<T>* tq)
+                           const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc)
 {
     constexpr int ITEMS = tile_items<T>();
     constexpr int log2n1 = LOG2N1, log2b = Sizes<T>::LOG2P - LOG2N1;
     constexpr int P = tile_points<T>();
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    stage_tw<Ctx, T, LOG2N1>(ctx, pv.tw_stage, tq);
     const int log2n2 = B.log2n2, log2B = B.log2B;
     const int64_t n = (int64_t)1 << B.log2n;
     const int64_t j2_0 = (int64_t)it.blk << log2b;
@@ -864,7 +834,7 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         }
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), -1>(ctx, lds, tq);
+        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), -1>(ctx, lds, pv.tw_stage);
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= P) break;
