@@ -46,28 +46,28 @@ def kernel_source_hash():
 
 def stage_bytes(plan, S):
     """Algorithmic HBM bytes per launch of each forward stage.
-    FFT stages: each band grid written once by the stage that produces it and
-    read once by the stage that consumes it; c read once per band.  Gather:
-    node records (x, y: 16 B, index 4 B) and the result, plus the band grid
-    cells its nodes touch (at most the whole grid, at most 2 mw cells per
-    column and node).  Direct bands: c read once per group of DIRECT_NG
-    nodes, node records and results."""
+    c is read once per band by the stage that generates its columns.  One-pass
+    FFT: the band's q grids written once.  Pass A: its output written once.
+    Pass B: that output read once and the grid written at the cells some
+    node's window reads ("cells" per column).  Gather: those cells (at most
+    2 mw per node and column), node records (x, y: 16 B, index 4 B) and the
+    result.  Direct bands: c read once per group of DIRECT_NG nodes, node
+    records and results."""
     info = plan.info()
     mw = info["mw"]
     b = {k: 0.0 for k in STAGES}
     for band in plan.bands():
-        q, n, nodes = band["q"], band["n"], band["nodes"]
+        q, n, nodes, cells = band["q"], band["n"], band["nodes"], band["cells"]
         kmax = min(band["K"], plan.N - 1)
-        grid = q * n * S
         if band["direct"]:
             b["direct"] += -(-nodes // DIRECT_NG) * plan.N * S + nodes * (16 + 4 + S)
             continue
         if band["passes"] == 1:
-            b["onepass_fft"] += grid + kmax * S
+            b["onepass_fft"] += q * n * S + kmax * S
         else:
-            b["passA_fft"] += grid + kmax * S
-            b["passB_fft"] += 2 * grid
-        b["gather"] += min(grid, nodes * q * 2 * mw * S)
+            b["passA_fft"] += q * n * S + kmax * S
+            b["passB_fft"] += q * n * S + q * cells * S
+        b["gather"] += q * min(cells, nodes * 2 * mw) * S
     b["gather"] += plan.M * (16 + 4 + S)
     return b
 

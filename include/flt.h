@@ -91,6 +91,7 @@ typedef struct flt_band_info {
     int64_t nodes;           /* nodes in the band */
     int32_t passes;          /* FFT passes through HBM (1 or 2); 0 for a direct band */
     int32_t direct;          /* 1: the band's nodes are summed directly (exact), not by NFFT */
+    int64_t cells;           /* grid cells per column that some node's window reads (0 for a direct band) */
 } flt_band_info;
 
 /* Build a plan for N coefficients and M nodes z (host, 2*M doubles,

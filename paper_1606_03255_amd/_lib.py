@@ -42,7 +42,7 @@ class FltBandInfo(ctypes.Structure):
     _fields_ = [
         ("m", ctypes.c_int32), ("q", ctypes.c_int32), ("ell_lo", ctypes.c_int32), ("ell_hi", ctypes.c_int32),
         ("K", ctypes.c_int64), ("n", ctypes.c_int64), ("k0", ctypes.c_int64), ("nodes", ctypes.c_int64),
-        ("passes", ctypes.c_int32), ("direct", ctypes.c_int32),
+        ("passes", ctypes.c_int32), ("direct", ctypes.c_int32), ("cells", ctypes.c_int64),
     ]
 
 

@@ -51,7 +51,8 @@ struct Packer {
 
 template <typename T> static PlanView<T> make_view(const HostPlan& hp, char* base, size_t o_bands, size_t o_coef,
                                                    size_t o_deconv, size_t o_ycheb, size_t o_tws, size_t o_twl,
-                                                   size_t o_twh, size_t o_nx, size_t o_ny, size_t o_perm)
+                                                   size_t o_twh, size_t o_nx, size_t o_ny, size_t o_perm,
+                                                   size_t o_mask)
 {
     PlanView<T> pv;
     pv.bands = (const BandDesc*)(base + o_bands);
@@ -64,6 +65,7 @@ template <typename T> static PlanView<T> make_view(const HostPlan& hp, char* bas
     pv.nx = (const double*)(base + o_nx);
     pv.ny = (const double*)(base + o_ny);
     pv.perm = (const int32_t*)(base + o_perm);
+    pv.mask = (const uint32_t*)(base + o_mask);
     pv.mw = hp.mw;
     pv.kb_b = (T)hp.kb_b;
     return pv;
@@ -97,6 +99,7 @@ static int upload(flt_plan* p)
     const size_t o_ti = pk.add(hp.tile_items.data(), hp.tile_items.size() * sizeof(NodeItem));
     const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
     const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
+    const size_t o_mask = pk.add(hp.mask.data(), hp.mask.size() * sizeof(uint32_t));
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return hip_fail(e);
@@ -105,8 +108,8 @@ static int upload(flt_plan* p)
     e = hipMemcpy(p->dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e);
     char* base = (char*)p->dev;
-    p->pv32 = make_view<float>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm);
-    p->pv64 = make_view<double>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm);
+    p->pv32 = make_view<float>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask);
+    p->pv64 = make_view<double>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask);
     DevLists& L = p->lists;
     L.onepass_fwd = (const FftItem*)(base + o_l0);
     L.passA_fwd = (const FftItem*)(base + o_l1);
@@ -220,6 +223,7 @@ int flt_plan_band(const flt_plan* p, int32_t i, flt_band_info* o)
         o->nodes = B.node_count;
         o->passes = B.direct ? 0 : (B.log2n2 > 0 ? 2 : 1);
         o->direct = B.direct;
+        o->cells = B.direct ? 0 : B.cells;
         return FLT_OK;
     }
     return FLT_EINVAL;

@@ -104,6 +104,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     pv.nx = hp.nx.data();
     pv.ny = hp.ny.data();
     pv.perm = hp.perm.data();
+    pv.mask = hp.mask.data();
     pv.mw = hp.mw;
     pv.kb_b = (T)hp.kb_b;
 
@@ -114,7 +115,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<T> Phi((size_t)hp.M * 2 * hp.mw);
     std::vector<int32_t> L0(hp.M);
     std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
-    std::vector<cplx<T>> lds(1 << Sizes<T>::LOG2P);
+    std::vector<cplx<T>> lds(tile_alloc<T>());
     std::vector<T> lc(Sizes<T>::COEF);
     int64_t base_elems = 1;
     for (const BandDesc& B : hp.bands)

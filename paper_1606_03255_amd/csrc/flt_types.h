@@ -44,7 +44,6 @@ constexpr int TW2_HALF = 11;              // lo/hi tables of 2^11 entries each
 constexpr int GATHER_THREADS = 256;       // nodes per gather/spread workgroup
 constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
 constexpr int MAX_MW = 10;                // largest window half-width supported
-constexpr int MAX_COEF_LDS = 2048;        // LDS slots for one column's Chebyshev coefficients (allocation)
 constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread
 constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
 constexpr int DIRECT_ATPT = 8;            // direct adjoint: coefficients per thread
@@ -54,10 +53,17 @@ constexpr int TILE_CELLS = 2048;          // adjoint LDS tile (cells of one colu
 constexpr int TILE_NODES = 2048;          // adjoint LDS tile: most nodes per chunk
 
 template <typename T> struct Sizes;
-// LOG2P: FFT tile of 2^LOG2P complex values = 64 KB of LDS; COEF: LDS slots for
-// one column's Chebyshev coefficients of every block of a band
+// LOG2P: FFT tile of 2^LOG2P complex values (64 KB); COEF: LDS slots for one
+// column's Chebyshev coefficients of every block of a band.  Tile plus
+// coefficients stay under 80 KB, so two 512-thread workgroups share a CU.
 template <> struct Sizes<float>  { static constexpr int LOG2P = 13; static constexpr int COEF = 2048; };
-template <> struct Sizes<double> { static constexpr int LOG2P = 12; static constexpr int COEF = 1536; };
+template <> struct Sizes<double> { static constexpr int LOG2P = 12; static constexpr int COEF = 1472; };
+
+// Physical slot of element i of an FFT tile in LDS: one pad slot after every
+// 16 elements, so that the strided stores of the Stockham stages fall on
+// different banks (offsets of multiples of 16 stay compile-time constants).
+FLT_HD int lds_at(int i) { return i + (i >> 4); }
+template <typename T> constexpr int tile_alloc() { return (1 << Sizes<T>::LOG2P) + (1 << (Sizes<T>::LOG2P - 4)); }
 
 // One occupied band of the node partition (Def. 3.2 Y_m, or Y_D), or the
 // constant band (q = 0) that holds the Z^0 nodes.
@@ -84,7 +90,18 @@ struct BandDesc {
     int64_t node_count;
     int64_t cs_off;      // cell-start table of the band (n + 1 entries) for the adjoint
     int64_t base_off;    // pass A: complex offset of the band's per-point c_k / (n phi_hat) slots
+    int64_t mask_off;    // two-pass bands: first 32-bit word of the cell mask (bit per grid address)
+    int64_t cells;       // grid cells per column that some node's window reads
 };
+
+// Address of natural grid index l in a band's blocked layout
+// [l1 / B][l2][l1 mod B], l = l1 + n1 l2  (one-pass bands: address = l).
+FLT_HD int64_t grid_addr(const BandDesc& B, int64_t l)
+{
+    const int64_t l1 = l & (((int64_t)1 << B.log2n1) - 1);
+    const int64_t l2 = l >> B.log2n1;
+    return ((l1 >> B.log2B) << (B.log2n2 + B.log2B)) + (l2 << B.log2B) + (l1 & (((int64_t)1 << B.log2B) - 1));
+}
 
 // Work item of an FFT kernel: band, first column, and a block index.
 struct FftItem {
@@ -129,6 +146,7 @@ template <typename T> struct PlanView {
     const double* nx;        // sorted nodes: x in [0,1)
     const double* ny;        //               y = 2 pi Im z
     const int32_t* perm;     //               caller index
+    const uint32_t* mask;    // cell masks of the two-pass bands (bit set: some window reads the cell)
     int32_t mw;              // window half-width
     T kb_b;                  // Kaiser-Bessel shape b = pi (2 - 1/sigma)
 };

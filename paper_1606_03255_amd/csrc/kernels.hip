@@ -48,7 +48,7 @@ template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, const FftItem* items,
                                                                 const cplx<T>* c, cplx<T>* grids, int deriv)
 {
-    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    __shared__ cplx<T> lds[tile_alloc<T>()];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
         body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, lds);
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, co
                                                               const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf,
                                                               int deriv)
 {
-    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
@@ -72,7 +72,7 @@ template <typename T, int SIGN>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_passB(PlanView<T> pv, const FftItem* items, const cplx<T>* src,
                                                           int64_t sel, cplx<T>* dst)
 {
-    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    __shared__ cplx<T> lds[tile_alloc<T>()];
     using RG = Log2Range<T>;
     with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[blockIdx.x].band].log2n2, [&](auto LG) {
         body_passB<DevCtx, T, decltype(LG)::value, SIGN>(DevCtx(), pv, items, src, sel, dst, lds);
@@ -122,7 +122,7 @@ template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, const FftItem* items,
                                                                 const cplx<T>* grids, double* acc)
 {
-    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
@@ -134,7 +134,7 @@ template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, const FftItem* items,
                                                               const cplx<T>* scratch, double* acc)
 {
-    __shared__ cplx<T> lds[1 << Sizes<T>::LOG2P];
+    __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {

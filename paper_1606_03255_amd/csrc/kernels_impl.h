@@ -188,8 +188,13 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
         if ((NBUT % FFT_THREADS) == 0 || u < NBUT) {
             const int sub = u >> LOG2LQ;
             const int j = u & ((1 << LOG2LQ) - 1);
-            const cplx<T>* src = buf + (sub << LOG2L) + j;
-            for (int r = 0; r < R; ++r) v[i][r] = src[r << LOG2LQ];
+            const int src = (sub << LOG2L) + j;
+            if constexpr (LOG2LQ >= 4) {   // strides of multiples of 16: the pad is a constant offset
+                const int sp = lds_at(src);
+                for (int r = 0; r < R; ++r) v[i][r] = buf[sp + (r << LOG2LQ) + (r << (LOG2LQ - 4))];
+            } else {
+                for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at(src + (r << LOG2LQ))];
+            }
             const int k = j & ((1 << LOG2NS) - 1);
             if (LOG2NS > 0) {
                 constexpr int SH = TW_STAGE_LOG2 - LOG2NS - LR;
@@ -200,9 +205,19 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
         }
     }
     ctx.sync();
-    for (int i = 0; i < NB; ++i)
-        if (dst[i] >= 0)
-            for (int r = 0; r < R; ++r) buf[dst[i] + (r << LOG2NS)] = v[i][r];
+    for (int i = 0; i < NB; ++i) {
+        if (dst[i] < 0) continue;
+        if constexpr (LOG2NS >= 4) {
+            const int dp = lds_at(dst[i]);
+            for (int r = 0; r < R; ++r) buf[dp + (r << LOG2NS) + (r << (LOG2NS - 4))] = v[i][r];
+        } else if constexpr (LOG2NS + LR <= 4) {
+            // dst = base + k with base a multiple of NS R <= 16 and k + r NS < NS R: no carry into bit 4
+            const int dp = lds_at(dst[i]);
+            for (int r = 0; r < R; ++r) buf[dp + (r << LOG2NS)] = v[i][r];
+        } else {
+            for (int r = 0; r < R; ++r) buf[lds_at(dst[i] + (r << LOG2NS))] = v[i][r];
+        }
+    }
     ctx.sync();
 }
 
@@ -279,15 +294,6 @@ FLT_HD double frac_kx(double k, double x)
     return (p - rint(p)) + e;
 }
 
-// Address of natural grid index l in a band's blocked layout
-// [l1 / B][l2][l1 mod B], l = l1 + n1 l2  (one-pass bands: address = l).
-FLT_HD int64_t grid_addr(const BandDesc& B, int64_t l)
-{
-    const int64_t l1 = l & (((int64_t)1 << B.log2n1) - 1);
-    const int64_t l2 = l >> B.log2n1;
-    return ((l1 >> B.log2B) << (B.log2n2 + B.log2B)) + (l2 << B.log2B) + (l1 & (((int64_t)1 << B.log2B) - 1));
-}
-
 // ---------------------------------------------------------------------------
 // a2-a4, one-pass bands: generate `ns` columns, FFT them in LDS, store.
 // ---------------------------------------------------------------------------
@@ -302,14 +308,14 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     const BandDesc& B = pv.bands[it.band];
     for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int sl = p >> LOG2N;
-        lds[p] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, (int64_t)(p & ((1 << LOG2N) - 1)), deriv)
+        lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, (int64_t)(p & ((1 << LOG2N) - 1)), deriv)
                             : mk<T>(0, 0);
     }
     ctx.sync();
     lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, pv.tw_stage);
     cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << LOG2N);
     const int Pv = it.ns << LOG2N;
-    for (int p = ctx.tid(); p < Pv; p += FFT_THREADS) out[p] = lds[p];
+    for (int p = ctx.tid(); p < Pv; p += FFT_THREADS) out[p] = lds[lds_at(p)];
 }
 
 // ---------------------------------------------------------------------------
@@ -329,29 +335,43 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     const int log2n2 = B.log2n2, log2B = B.log2B;
     const int64_t n = (int64_t)1 << B.log2n;
     const int64_t j2_0 = (int64_t)it.blk << log2b;
-    // c_k / (n phi_hat(k')) of this workgroup's points, formed once (strided
-    // reads of c) and kept in the workgroup's own coalesced slot for the other
-    // columns; every thread re-reads only what it wrote.
+    // c_k / (n phi_hat(k')) of this workgroup's points: formed once, reading c
+    // in address order (jj fastest) and transposing through LDS, then kept in
+    // the workgroup's own slot for the other columns; every thread re-reads
+    // only what it wrote.  Tile element p = (jj << log2n1) + j1.
     cplx<T>* slot = basebuf + B.base_off + (int64_t)it.blk * P;
     for (int s = 0; s < B.q; ++s) {
         stage_coef(ctx, pv, B, s, lc);
+        if (s == 0) {
+#pragma unroll 1   // one point at a time: keeps the kernel at four waves per SIMD
+            for (int i = 0; i < ITEMS; ++i) {
+                const int p = ctx.tid() + i * FFT_THREADS;
+                const int jj = p & ((1 << log2b) - 1);
+                const int j1 = p >> log2b;
+                const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
+                const int64_t kp = j < (n >> 1) ? j : j - n;
+                const int64_t k = kp + B.k0;
+                lds[lds_at((jj << log2n1) + j1)] =
+                    k >= 1 && k <= B.kmax ? point_base(pv, B, c, kp, k, deriv) : mk<T>(0, 0);
+            }
+        }
         ctx.sync();
+#pragma unroll 1
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
-            const int jj = p & ((1 << log2b) - 1);
-            const int j1 = p >> log2b;
+            const int j1 = p & ((1 << log2n1) - 1);
+            const int jj = p >> log2n1;
             const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
             const int64_t kp = j < (n >> 1) ? j : j - n;
             const int64_t k = kp + B.k0;
-            const bool valid = k >= 1 && k <= B.kmax;
             cplx<T> base;
             if (s == 0) {
-                base = valid ? point_base(pv, B, c, kp, k, deriv) : mk<T>(0, 0);
+                base = lds[lds_at(p)];
                 slot[p] = base;
             } else {
                 base = slot[p];
             }
-            lds[(jj << log2n1) + j1] = valid ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
+            lds[lds_at(p)] = k >= 1 && k <= B.kmax ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
         }
         ctx.sync();
         lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, pv.tw_stage);
@@ -362,7 +382,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int l1hi = p >> (log2B + log2b);
             const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
             const int64_t j2 = j2_0 + jj;
-            cplx<T> v = mul(lds[(jj << log2n1) + l1], tw_grid_at(pv, j2 * l1, B.log2n, +1));
+            cplx<T> v = mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_at(pv, j2 * l1, B.log2n, +1));
             Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
         }
         ctx.sync();
@@ -370,7 +390,9 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
 }
 
 // pass B: for B = 2^log2B consecutive l1, the length-n2 DFTs over j2 of
-// Y[j2][l1]; X[l1 + n1 l2] stored blocked as [l1 / B][l2][l1 mod B].
+// Y[j2][l1]; X[l1 + n1 l2] stored blocked as [l1 / B][l2][l1 mod B], only at
+// the cells of the band's mask (the only ones a window reads).  Adjoint
+// direction: only the masked cells are loaded, the others are zero.
 template <class Ctx, typename T, int LOG2N2, int SIGN>
 FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                        const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base, cplx<T>* lds)
@@ -385,18 +407,30 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
     const int64_t dso = src_band_off_sel ? B.scratch_off : B.grid_off;
     const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << (log2n2 + log2B));
     const cplx<T>* src = src_base + so + blk_off;
-    for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
-        const int j2 = p >> log2B;
-        const int lo = p & ((1 << log2B) - 1);
-        lds[(lo << log2n2) + j2] = src[p];
+    const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (log2n2 + log2B - 5));
+    // each thread moves V consecutive elements of one row j2 (lanes take
+    // consecutive rows, so the transposed LDS accesses are contiguous)
+    constexpr int V = (1 << log2B) < 8 ? (1 << log2B) : 8;
+    constexpr int CHUNKS = P / V;
+    for (int t = ctx.tid(); t < CHUNKS; t += FFT_THREADS) {
+        const int j2 = t & ((1 << log2n2) - 1);
+        const int lo0 = (t >> log2n2) * V;
+        const int p0 = (j2 << log2B) + lo0;
+        const uint32_t bits = src_band_off_sel ? mask[p0 >> 5] >> (p0 & 31) : ~0u;
+        cplx<T> v[V];
+        for (int u = 0; u < V; ++u) v[u] = ((bits >> u) & 1u) ? src[p0 + u] : mk<T>(0, 0);
+        for (int u = 0; u < V; ++u) lds[lds_at(((lo0 + u) << log2n2) + j2)] = v[u];
     }
     ctx.sync();
     lds_fft_ct<Ctx, T, LOG2N2, (1 << log2B), SIGN>(ctx, lds, pv.tw_stage);
     cplx<T>* dst = dst_base + dso + blk_off;
-    for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
-        const int l2 = p >> log2B;
-        const int lo = p & ((1 << log2B) - 1);
-        dst[p] = lds[(lo << log2n2) + l2];
+    for (int t = ctx.tid(); t < CHUNKS; t += FFT_THREADS) {
+        const int l2 = t & ((1 << log2n2) - 1);
+        const int lo0 = (t >> log2n2) * V;
+        const int p0 = (l2 << log2B) + lo0;
+        const uint32_t bits = src_band_off_sel ? ~0u : mask[p0 >> 5] >> (p0 & 31);
+        for (int u = 0; u < V; ++u)
+            if ((bits >> u) & 1u) dst[p0 + u] = lds[lds_at(((lo0 + u) << log2n2) + l2)];
     }
 }
 
@@ -547,9 +581,11 @@ FLT_HD void body_adj_owner(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     const int64_t n = (int64_t)1 << B.log2n;
     const int64_t l = (int64_t)it.blk * ctx.ntid() + ctx.tid();
     if (l >= n) return;
+    const int64_t addr = grid_addr(B, l);
+    // a two-pass band's pass B loads only masked cells: the others stay untouched
+    if (B.log2n2 > 0 && !((pv.mask[B.mask_off + (addr >> 5)] >> (addr & 31)) & 1u)) return;
     if (B.tiles) {                               // densely filled band: cleared here, filled by body_adj_tiles
         cplx<T>* g = grids + B.grid_off;
-        const int64_t addr = grid_addr(B, l);
         for (int s = 0; s < B.q; ++s) g[((int64_t)s << B.log2n) + addr] = mk<T>(0, 0);
         return;
     }
@@ -560,7 +596,6 @@ FLT_HD void body_adj_owner(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     else if (b > n) { r0s = c0[a]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b - n]; }
     else { r0s = c0[a]; r0e = c0[b]; }
     cplx<T>* g = grids + B.grid_off;
-    const int64_t addr = grid_addr(B, l);
     for (int s = 0; s < B.q; ++s) {
         T ar = 0, ai = 0;
         for (int run = 0; run < 2; ++run) {
@@ -778,7 +813,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
         const cplx<T>* src = grids + B.grid_off + ((int64_t)s << log2n);
-        for (int p = ctx.tid(); p < n; p += FFT_THREADS) lds[p] = src[p];
+        for (int p = ctx.tid(); p < n; p += FFT_THREADS) lds[lds_at(p)] = src[p];
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
         lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, pv.tw_stage);
@@ -789,8 +824,9 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
             const int64_t k = kp + B.k0;
             if (k < 1 || k > B.kmax) continue;
             const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-            accr[i] += lds[p].x * w;
-            acci[i] += lds[p].y * w;
+            const cplx<T> v = lds[lds_at(p)];
+            accr[i] += v.x * w;
+            acci[i] += v.y * w;
         }
         ctx.sync();
     }
@@ -830,7 +866,7 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
             const int64_t j2 = j2_0 + jj;
             const cplx<T> v = Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
-            lds[(jj << log2n1) + l1] = mul(v, tw_grid_at(pv, j2 * l1, B.log2n, -1));
+            lds[lds_at((jj << log2n1) + l1)] = mul(v, tw_grid_at(pv, j2 * l1, B.log2n, -1));
         }
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
@@ -838,14 +874,14 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= P) break;
-            const int jj = p & ((1 << log2b) - 1);
-            const int j1 = p >> log2b;
+            const int j1 = p & ((1 << log2n1) - 1);   // tile element p = (jj << log2n1) + j1
+            const int jj = p >> log2n1;
             const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
             const int64_t kp = j < (n >> 1) ? j : j - n;
             const int64_t k = kp + B.k0;
             if (k < 1 || k > B.kmax) continue;
             const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-            const cplx<T> v = lds[(jj << log2n1) + j1];
+            const cplx<T> v = lds[lds_at(p)];
             accr[i] += v.x * w;
             acci[i] += v.y * w;
         }
@@ -854,8 +890,8 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     for (int i = 0; i < ITEMS; ++i) {
         const int p = ctx.tid() + i * FFT_THREADS;
         if (p >= P) break;
-        const int jj = p & ((1 << log2b) - 1);
-        const int j1 = p >> log2b;
+        const int j1 = p & ((1 << log2n1) - 1);
+        const int jj = p >> log2n1;
         const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
         const int64_t kp = j < (n >> 1) ? j : j - n;
         const int64_t k = kp + B.k0;

@@ -308,6 +308,27 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
                 a = e;
             }
         }
+        // cells some node's window reads: [l0 - mw + 1, l0 + mw] (mod n) around
+        // each node's cell l0 = floor(n x); a two-pass band keeps them as a bit
+        // mask over grid addresses, so pass B stores (and, for the adjoint,
+        // loads) only those cells
+        {
+            std::vector<uint8_t> hit((size_t)n, 0);
+            for (int64_t j = B.node_start; j < B.node_start + B.node_count; ++j)
+                for (int t = 0; t < 2 * hp.mw; ++t) hit[(size_t)((cell[idx[j]] - hp.mw + 1 + t) & (n - 1))] = 1;
+            B.cells = 0;
+            for (int64_t l = 0; l < n; ++l) B.cells += hit[(size_t)l];
+            if (B.log2n2 > 0) {
+                B.mask_off = (int64_t)hp.mask.size();
+                hp.mask.resize(hp.mask.size() + (size_t)(n >> 5), 0u);
+                uint32_t* mk = hp.mask.data() + B.mask_off;
+                for (int64_t l = 0; l < n; ++l)
+                    if (hit[(size_t)l]) {
+                        const int64_t a = grid_addr(B, l);
+                        mk[a >> 5] |= 1u << (a & 31);
+                    }
+            }
+        }
         if (B.log2n2 > 0) {
             B.scratch_off = soff;
             soff += (int64_t)B.q * n;
@@ -367,6 +388,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     group(hp.passA_adj, hp.g_passA_adj, 1);
     group(hp.passB, hp.g_passB, 2);
     if (hp.cstart.empty()) hp.cstart.push_back(0);
+    if (hp.mask.empty()) hp.mask.push_back(0u);
     hp.grid_elems = goff;
     hp.scratch_elems = soff;
     const size_t S = hp.elem_bytes();
@@ -381,8 +403,11 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     hp.off_base = al(hp.off_dacc + (size_t)M * 16);
     hp.ws_bytes = al(hp.off_base + (size_t)boff * S);
 
-    // ---- algorithmic model of one forward: every band grid written once and
-    // read once, c read once per band, node records and results once
+    // ---- algorithmic model of one forward: c read once per band; a one-pass
+    // band's grid written once; a two-pass band's pass-A output written and
+    // read once, its grid written only at the cells the windows read; the
+    // gather reads those cells (at most 2 mw per node and column); node
+    // records and results once
     double bytes = (double)M * (16.0 + 4.0 + S);
     double flops = 0;
     for (int b = 0; b < nb; ++b) {
@@ -394,7 +419,9 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
             continue;
         }
         const double n = ldexp(1.0, B.log2n);
-        bytes += 2.0 * B.q * n * S + (double)B.kmax * S;
+        const double cells = std::min((double)B.cells, (double)B.node_count * 2 * hp.mw);
+        bytes += (double)B.kmax * S + B.q * cells * S;
+        bytes += (B.log2n2 > 0 ? 2.0 * B.q * n + B.q * (double)B.cells : B.q * n) * S;
         flops += 2.0 * B.q * B.q * (double)B.kmax + 8.0 * B.q * (double)B.kmax;   // contraction, scaling
         flops += 5.0 * B.q * n * B.log2n;                                          // FFT
         flops += (double)B.node_count * (8.0 * B.q * 2 * hp.mw + 4.0 * B.q);       // gather, weighting

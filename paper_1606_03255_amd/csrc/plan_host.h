@@ -45,6 +45,7 @@ struct HostPlan {
     std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands
     std::vector<DirectItem> direct_fwd, direct_adj;
     std::vector<int32_t> cstart;        // per NFFT band: first sorted node with cell >= c, c = 0..n
+    std::vector<uint32_t> mask;         // per two-pass band: bit per grid address read by some window
 
     // workspace layout (bytes)
     int qs = 1;                         // stride of the per-node column values (max q)

@@ -111,8 +111,11 @@ def test_byte_model_large_workload():
     for b in bands:
         if b["direct"]:    # c read once per group of 8 nodes of a direct-sum band
             expect += w["N"] * S * -(-b["nodes"] // 8)
-        else:              # every band grid written once and read once, c once
-            expect += 2 * b["q"] * b["n"] * S + min(b["K"], w["N"] - 1) * S
+        else:              # c once; grids: one-pass written once, two-pass pass-A output
+            #                written and read once plus the masked cells; gather reads
+            cells = b["cells"]
+            expect += min(b["K"], w["N"] - 1) * S + b["q"] * min(cells, b["nodes"] * 2 * info["mw"]) * S
+            expect += (2 * b["q"] * b["n"] + b["q"] * cells if b["passes"] == 2 else b["q"] * b["n"]) * S
     assert info["bytes_forward"] == pytest.approx(expect, rel=1e-12)
     assert (info["q"], info["D"]) == (12, 47)
     # the policy sends exactly the sparsely filled full-size bands to the direct sum
@@ -120,3 +123,25 @@ def test_byte_model_large_workload():
     assert all(b["n"] == 1 << 21 for b in bands if b["direct"])
     p2 = flt.Plan(w["N"], w["z"], 1e-6, "complex64", host_only=True, nfft_only=True)
     assert not any(b["direct"] for b in p2.bands())
+
+
+def test_cell_counts_cover_every_window():
+    """cells = size of the union of the nodes' windows [l0 - mw + 1, l0 + mw]
+    (mod n), l0 = floor(n x): the cells pass B stores and the gather reads."""
+    rng = np.random.default_rng(11)
+    N, M = 70000, 3000
+    z = np.concatenate([inputs.nodes_annulus(rng, M // 2), inputs.nodes_disk(rng, M - M // 2)])
+    p = flt.Plan(N, z, 1e-6, "complex64", host_only=True)
+    mw = p.info()["mw"]
+    nb = p.node_bands()
+    x = z.real - np.floor(z.real)
+    for b in p.bands():
+        if b["direct"]:
+            assert b["cells"] == 0
+            continue
+        n = b["n"]
+        l0 = np.floor(np.ldexp(x[nb == b["m"]], int(np.log2(n)))).astype(np.int64)
+        hit = np.zeros(n, bool)
+        for t in range(2 * mw):
+            hit[(l0 - mw + 1 + t) % n] = True
+        assert b["cells"] == hit.sum(), b
