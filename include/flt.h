@@ -51,6 +51,8 @@ typedef struct flt_plan flt_plan;
 #define FLT_FLAG_HOST_ONLY (1u << 0) /* plan on the host only (parameters, partition, byte model); no device */
 #define FLT_FLAG_NFFT_ONLY (1u << 1) /* every band by Alg. 2's NFFT path; by default a band whose grids would
                                         cost more than summing its few nodes directly is summed exactly */
+#define FLT_FLAG_GRAPH     (1u << 2) /* capture each operation's launch sequence into a hipGraph on its first call
+                                        (and again whenever the buffers or the workspace change) and replay it */
 
 /* return codes */
 #define FLT_OK            0
@@ -101,6 +103,19 @@ typedef struct flt_band_info {
  * Im z = +inf is accepted (w = 0, f = c_0).  *out receives the plan or NULL. */
 int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z,
                     double eps, int dtype, uint32_t flags);
+
+/* One plan for `count` independent instances of Alg. 2 at one eps and dtype
+ * (instance i: N[i] coefficients, M[i] nodes; N, M host arrays of count
+ * entries).  z (host) holds the nodes instance after instance, sum M[i]
+ * complex128 values.  The plan's transforms act on packed arrays: c (and the
+ * adjoint's output) holds instance i's coefficients from sum_{i'<i} N[i'],
+ * f (and the adjoint's input) its nodes from sum_{i'<i} M[i'].  Every
+ * instance gets exactly what its own flt_plan_create plan would compute, with
+ * each transform kind of all instances in a single launch.  Errors as for
+ * flt_plan_create (the first failing instance decides); count < 1 or a null
+ * array is FLT_EINVAL. */
+int flt_plan_create_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M,
+                          const double* z, double eps, int dtype, uint32_t flags);
 
 /* Release the plan's device and host memory; NULL is a no-op.  The caller
  * must ensure no enqueued work of the plan is still pending. */

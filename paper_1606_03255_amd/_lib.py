@@ -13,6 +13,7 @@ FLT_C64 = 1
 FLT_C128 = 2
 FLT_FLAG_HOST_ONLY = 1
 FLT_FLAG_NFFT_ONLY = 2
+FLT_FLAG_GRAPH = 4
 
 ERRORS = {
     0: "FLT_OK", -1: "FLT_EINVAL", -2: "FLT_EDOMAIN", -3: "FLT_EPRECISION", -4: "FLT_ENOWORKSPACE",
@@ -21,7 +22,7 @@ ERRORS = {
 
 # every symbol include/flt.h declares
 EXPORTS = (
-    "flt_plan_create", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
+    "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
     "flt_profile_forward", "flt_strerror", "flt_last_hip_error",
 )
@@ -71,6 +72,8 @@ def load():
     P = ctypes.POINTER
     lib.flt_plan_create.argtypes = [P(vp), ctypes.c_int64, ctypes.c_int64, P(ctypes.c_double), ctypes.c_double,
                                     ctypes.c_int, ctypes.c_uint32]
+    lib.flt_plan_create_batch.argtypes = [P(vp), ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_int64),
+                                          P(ctypes.c_double), ctypes.c_double, ctypes.c_int, ctypes.c_uint32]
     lib.flt_plan_destroy.argtypes = [vp]
     lib.flt_plan_destroy.restype = None
     lib.flt_plan_info.argtypes = [vp, P(FltInfo)]

@@ -13,6 +13,15 @@ using namespace flt;
 
 static thread_local int g_last_hip = 0;
 
+// A captured launch sequence (FLT_FLAG_GRAPH): valid for one operation and
+// one set of buffers; a call with other buffers captures anew.
+struct GraphSlot {
+    const void* in = nullptr;
+    void* out = nullptr;
+    char* ws = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct flt_plan {
     HostPlan hp;
     bool host_only = true;
@@ -23,6 +32,8 @@ struct flt_plan {
     DevLists lists{};
     char* ws = nullptr;
     size_t ws_bytes = 0;
+    hipStream_t capture = nullptr;   // FLT_FLAG_GRAPH: stream the sequences are captured on
+    GraphSlot graphs[3];             // forward, derivative, adjoint
 };
 
 static int hip_fail(hipError_t e)
@@ -52,7 +63,7 @@ struct Packer {
 template <typename T> static PlanView<T> make_view(const HostPlan& hp, char* base, size_t o_bands, size_t o_coef,
                                                    size_t o_deconv, size_t o_ycheb, size_t o_tws, size_t o_twl,
                                                    size_t o_twh, size_t o_nx, size_t o_ny, size_t o_perm,
-                                                   size_t o_mask)
+                                                   size_t o_mask, size_t o_inst)
 {
     PlanView<T> pv;
     pv.bands = (const BandDesc*)(base + o_bands);
@@ -66,6 +77,7 @@ template <typename T> static PlanView<T> make_view(const HostPlan& hp, char* bas
     pv.ny = (const double*)(base + o_ny);
     pv.perm = (const int32_t*)(base + o_perm);
     pv.mask = (const uint32_t*)(base + o_mask);
+    pv.inst = (const InstDesc*)(base + o_inst);
     pv.mw = hp.mw;
     pv.kb_b = (T)hp.kb_b;
     return pv;
@@ -100,6 +112,8 @@ static int upload(flt_plan* p)
     const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
     const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
     const size_t o_mask = pk.add(hp.mask.data(), hp.mask.size() * sizeof(uint32_t));
+    const size_t o_inst = pk.add(hp.inst.data(), hp.inst.size() * sizeof(InstDesc));
+    const size_t o_sum = pk.add(hp.sum_items.data(), hp.sum_items.size() * sizeof(SumItem));
 
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) return hip_fail(e);
@@ -108,8 +122,8 @@ static int upload(flt_plan* p)
     e = hipMemcpy(p->dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e);
     char* base = (char*)p->dev;
-    p->pv32 = make_view<float>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask);
-    p->pv64 = make_view<double>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask);
+    p->pv32 = make_view<float>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask, o_inst);
+    p->pv64 = make_view<double>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask, o_inst);
     DevLists& L = p->lists;
     L.onepass_fwd = (const FftItem*)(base + o_l0);
     L.passA_fwd = (const FftItem*)(base + o_l1);
@@ -125,6 +139,8 @@ static int upload(flt_plan* p)
     L.direct_adj = (const DirectItem*)(base + o_l9);
     L.dlist = (const int32_t*)(base + o_dl);
     L.cstart = (const int32_t*)(base + o_cs);
+    L.sum_items = (const SumItem*)(base + o_sum);
+    L.n_sum = (int)hp.sum_items.size();
     L.n_onepass_fwd = (int)hp.onepass_fwd.size();
     L.n_passA_fwd = (int)hp.passA_fwd.size();
     L.n_passB = (int)hp.passB.size();
@@ -144,24 +160,28 @@ static int upload(flt_plan* p)
     return FLT_OK;
 }
 
-extern "C" {
+static const uint32_t KNOWN_FLAGS = FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY | FLT_FLAG_GRAPH;
 
-int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+template <class Build> static int create(flt_plan** out, uint32_t flags, Build&& build)
 {
     if (!out) return FLT_EINVAL;
     *out = nullptr;
-    if (flags & ~(uint32_t)(FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY)) return FLT_EINVAL;
+    if (flags & ~KNOWN_FLAGS) return FLT_EINVAL;
     flt_plan* p = new (std::nothrow) flt_plan();
     if (!p) return FLT_ENOMEM;
     int rc;
     try {
-        rc = build_host_plan(p->hp, N, M, z, eps, dtype, flags);
+        rc = build(p->hp);
     } catch (const std::bad_alloc&) {
         rc = FLT_ENOMEM;
     }
     if (rc == FLT_OK && !(flags & FLT_FLAG_HOST_ONLY)) {
         p->host_only = false;
         rc = upload(p);
+        if (rc == FLT_OK && (flags & FLT_FLAG_GRAPH)) {
+            const hipError_t e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
     }
     if (rc != FLT_OK) {
         flt_plan_destroy(p);
@@ -171,9 +191,25 @@ int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, doubl
     return FLT_OK;
 }
 
+extern "C" {
+
+int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+{
+    return create(out, flags, [&](HostPlan& hp) { return build_host_plan(hp, N, M, z, eps, dtype, flags); });
+}
+
+int flt_plan_create_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M, const double* z,
+                          double eps, int dtype, uint32_t flags)
+{
+    return create(out, flags, [&](HostPlan& hp) { return build_batch_plan(hp, count, N, M, z, eps, dtype, flags); });
+}
+
 void flt_plan_destroy(flt_plan* p)
 {
     if (!p) return;
+    for (GraphSlot& g : p->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (p->capture) (void)hipStreamDestroy(p->capture);
     if (p->dev) (void)hipFree(p->dev);
     delete p;
 }
@@ -281,33 +317,64 @@ static int check_call(const flt_plan* p, const void* a, const void* b)
     return FLT_OK;
 }
 
-static int run_forward(flt_plan* p, const void* c, void* f, int deriv, void* stream)
+// op 0: forward, 1: derivative, 2: adjoint; enqueues the launch sequence on st.
+static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, hipStream_t st)
 {
-    int rc = check_call(p, c, f);
-    if (rc != FLT_OK) return rc;
-    const HostPlan& hp = p->hp;
     const WsLayout W = layout(p);
-    hipError_t e = hp.dtype == FLT_C64
-        ? launch_forward<float>(p->lists, p->pv32, W, c, f, deriv, (hipStream_t)stream)
-        : launch_forward<double>(p->lists, p->pv64, W, c, f, deriv, (hipStream_t)stream);
+    if (op == 2)
+        return p->hp.dtype == FLT_C64 ? launch_adjoint<float>(p->lists, p->pv32, W, in, out, st)
+                                      : launch_adjoint<double>(p->lists, p->pv64, W, in, out, st);
+    return p->hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, in, out, op, st)
+                                  : launch_forward<double>(p->lists, p->pv64, W, in, out, op, st);
+}
+
+// FLT_FLAG_GRAPH: replay the captured sequence when the buffers match the last
+// capture of this operation, else capture anew on the plan's own stream (the
+// kernels do not run during capture) and launch the graph on the caller's.
+static hipError_t run_graph(flt_plan* p, int op, const void* in, void* out, hipStream_t st)
+{
+    GraphSlot& g = p->graphs[op];
+    if (!g.exec || g.in != in || g.out != out || g.ws != p->ws) {
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        const hipError_t le = enqueue(p, op, in, out, p->capture);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(p->capture, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return le != hipSuccess ? le : e;
+        }
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return e;
+        }
+        g.in = in;
+        g.out = out;
+        g.ws = p->ws;
+    }
+    return hipGraphLaunch(g.exec, st);
+}
+
+static int run(flt_plan* p, int op, const void* in, void* out, void* stream)
+{
+    const int rc = check_call(p, in, out);
+    if (rc != FLT_OK) return rc;
+    const hipError_t e = p->capture ? run_graph(p, op, in, out, (hipStream_t)stream)
+                                    : enqueue(p, op, in, out, (hipStream_t)stream);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
 
-int flt_forward(flt_plan* p, const void* c, void* f, void* stream) { return run_forward(p, c, f, 0, stream); }
+int flt_forward(flt_plan* p, const void* c, void* f, void* stream) { return run(p, 0, c, f, stream); }
 
-int flt_derivative(flt_plan* p, const void* c, void* fp, void* stream) { return run_forward(p, c, fp, 1, stream); }
+int flt_derivative(flt_plan* p, const void* c, void* fp, void* stream) { return run(p, 1, c, fp, stream); }
 
-int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream)
-{
-    int rc = check_call(p, g, c_out);
-    if (rc != FLT_OK) return rc;
-    const HostPlan& hp = p->hp;
-    const WsLayout W = layout(p);
-    hipError_t e = hp.dtype == FLT_C64
-        ? launch_adjoint<float>(p->lists, p->pv32, W, g, c_out, (hipStream_t)stream)
-        : launch_adjoint<double>(p->lists, p->pv64, W, g, c_out, (hipStream_t)stream);
-    return e == hipSuccess ? FLT_OK : hip_fail(e);
-}
+int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream) { return run(p, 2, g, c_out, stream); }
 
 int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, double* stage_ms)
 {

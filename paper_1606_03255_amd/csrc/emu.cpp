@@ -105,6 +105,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     pv.ny = hp.ny.data();
     pv.perm = hp.perm.data();
     pv.mask = hp.mask.data();
+    pv.inst = hp.inst.data();
     pv.mw = hp.mw;
     pv.kb_b = (T)hp.kb_b;
 
@@ -162,8 +163,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 0);
             });
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
-                body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, hp.N, deriv,
-                                            dacc.data(), red.data());
+                body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, deriv, dacc.data(),
+                                            red.data());
             });
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 1);
@@ -175,8 +176,9 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         const cplx<T>* g = (const cplx<T>*)in;
         cplx<T>* co = (cplx<T>*)out;
         std::vector<double> acc(2 * hp.N, 0.0);
-        const int64_t nsum = (hp.M + 256 * SUMG_PER_THREAD - 1) / (256 * SUMG_PER_THREAD);
-        run_blocks(nsum, 256, [&](const HostCtx& ctx) { body_sum_g<HostCtx, T>(ctx, g, hp.M, acc.data(), red.data()); });
+        run_blocks(hp.sum_items.size(), 256, [&](const HostCtx& ctx) {
+            body_sum_g<HostCtx, T>(ctx, pv, hp.sum_items.data(), g, acc.data(), red.data());
+        });
         mwsw(1, g, nullptr, 0);
         constexpr int LP = Sizes<T>::LOG2P;
         for (const LaunchGroup& g : hp.g_passB)
@@ -201,7 +203,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 });
             });
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
-            body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, hp.N, acc.data());
+            body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, acc.data());
         });
         for (int64_t k = 0; k < hp.N; ++k) co[k] = mk<T>((T)acc[2 * k], (T)acc[2 * k + 1]);
         return FLT_OK;
@@ -216,6 +218,16 @@ extern "C" int flt_emu_run(int64_t N, int64_t M, const double* z, double eps, in
 {
     flt::HostPlan hp;
     int rc = flt::build_host_plan(hp, N, M, z, eps, dtype, flags);
+    if (rc != FLT_OK) return rc;
+    return dtype == FLT_C64 ? flt::emu_run<float>(hp, op, in, out) : flt::emu_run<double>(hp, op, in, out);
+}
+
+// The same for a batched plan (packed in / out, see flt_plan_create_batch).
+extern "C" int flt_emu_run_batch(int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
+                                 int dtype, uint32_t flags, int op, const void* in, void* out)
+{
+    flt::HostPlan hp;
+    int rc = flt::build_batch_plan(hp, count, N, M, z, eps, dtype, flags);
     if (rc != FLT_OK) return rc;
     return dtype == FLT_C64 ? flt::emu_run<float>(hp, op, in, out) : flt::emu_run<double>(hp, op, in, out);
 }

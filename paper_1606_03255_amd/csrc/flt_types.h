@@ -92,6 +92,7 @@ struct BandDesc {
     int64_t base_off;    // pass A: complex offset of the band's per-point c_k / (n phi_hat) slots
     int64_t mask_off;    // two-pass bands: first 32-bit word of the cell mask (bit per grid address)
     int64_t cells;       // grid cells per column that some node's window reads
+    int64_t c_off;       // first coefficient of the band's instance in the packed c (and adjoint output)
 };
 
 // Address of natural grid index l in a band's blocked layout
@@ -131,7 +132,21 @@ struct DirectItem {
     int32_t first;
     int32_t count;
     int32_t chunk;
+    int32_t inst;        // instance whose coefficients the chunk covers
+};
+
+// One instance of a plan (a single plan has one; a batched plan one per
+// member): where its coefficients and nodes sit in the packed arrays.
+struct InstDesc {
+    int64_t c_off, N;    // coefficients c_off .. c_off + N - 1
+    int64_t f_off, M;    // nodes (caller order) f_off .. f_off + M - 1
+};
+
+// Work item of the adjoint's k = 0 sum: a run of one instance's g.
+struct SumItem {
+    int32_t inst;
     int32_t pad;
+    int64_t start;       // caller index of the run's first node
 };
 
 // Everything a kernel needs to read from the plan (device or host pointers).
@@ -147,6 +162,7 @@ template <typename T> struct PlanView {
     const double* ny;        //               y = 2 pi Im z
     const int32_t* perm;     //               caller index
     const uint32_t* mask;    // cell masks of the two-pass bands (bit set: some window reads the cell)
+    const InstDesc* inst;    // instances (one for a single plan)
     int32_t mw;              // window half-width
     T kb_b;                  // Kaiser-Bessel shape b = pi (2 - 1/sigma)
 };

@@ -112,10 +112,10 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_adj_tiles(PlanView<T> pv, co
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_sum_g(const cplx<T>* g, int64_t M, double* acc)
+__global__ __launch_bounds__(256) void k_sum_g(PlanView<T> pv, const SumItem* items, const cplx<T>* g, double* acc)
 {
     __shared__ double red[2 * 256];
-    body_sum_g<DevCtx, T>(DevCtx(), g, M, acc, red);
+    body_sum_g<DevCtx, T>(DevCtx(), pv, items, g, acc, red);
 }
 
 template <typename T>
@@ -144,10 +144,10 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, co
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_direct_fwd(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
-                                                    const cplx<T>* c, int64_t N, int deriv, double* dacc)
+                                                    const cplx<T>* c, int deriv, double* dacc)
 {
     __shared__ double red[2 * DIRECT_NG * 256];
-    body_direct_fwd<DevCtx, T>(DevCtx(), pv, items, dlist, c, N, deriv, dacc, red);
+    body_direct_fwd<DevCtx, T>(DevCtx(), pv, items, dlist, c, deriv, dacc, red);
 }
 
 template <typename T>
@@ -159,9 +159,9 @@ __global__ __launch_bounds__(256) void k_direct_io(PlanView<T> pv, const int32_t
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_direct_adj(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
-                                                    const cplx<T>* g, int64_t N, double* acc)
+                                                    const cplx<T>* g, double* acc)
 {
-    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, N, acc);
+    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, acc);
 }
 
 // Clear `n` 16-byte words (a fill kernel, so the sequence stays capturable).
@@ -275,7 +275,7 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
         const int gb = (int)((L.n_dlist + 255) / 256);
         hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, f, 0);
         hipLaunchKernelGGL(k_direct_fwd<T>, dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd, L.dlist, c,
-                           W.N, deriv, dacc);
+                           deriv, dacc);
         hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, f, 1);
     }
     if (ev) (void)hipEventRecord(ev[5], st);
@@ -292,7 +292,7 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayo
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
     double* acc = (double*)(W.ws + W.off_acc);
     hipLaunchKernelGGL(k_zero16, dim3(grid_for(W.N, 256 * 8)), dim3(256), 0, st, (double2*)acc, W.N);
-    hipLaunchKernelGGL(k_sum_g<T>, dim3(grid_for(W.M, 256 * SUMG_PER_THREAD)), dim3(256), 0, st, g, W.M, acc);
+    hipLaunchKernelGGL(k_sum_g<T>, dim3(L.n_sum), dim3(256), 0, st, pv, L.sum_items, g, acc);
     switch (pv.mw) {
 #define S(MWV) case MWV: mw_adjoint_nodes<T, MWV>(L, pv, W, g, grids, st); break;
         S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
@@ -303,7 +303,7 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayo
     if (e != hipSuccess) return e;
     if (L.n_direct_adj)
         hipLaunchKernelGGL(k_direct_adj<T>, dim3(L.n_direct_adj), dim3(256), 0, st, pv, L.direct_adj, L.dlist, g,
-                           W.N, acc);
+                           acc);
     hipLaunchKernelGGL(k_finalize_adj<T>, dim3(grid_for(W.N, 256 * 4)), dim3(256), 0, st, acc, out, W.N);
     return hipGetLastError();
 }

@@ -61,7 +61,7 @@ FLT_HD cplx<T> grid_input(const PlanView<T>& pv, const BandDesc& B, const cplx<T
     const int64_t k = kp + B.k0;
     if (k < 1 || k > B.kmax) return mk<T>(0, 0);
     T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-    cplx<T> v = c[k];
+    cplx<T> v = c[B.c_off + k];
     if (deriv) {                                // c'_k = 2 pi i k c_k
         w *= (T)(6.283185307179586476925286766559 * (double)k);
         v = mk(-v.y, v.x);
@@ -278,7 +278,7 @@ FLT_HD cplx<T> point_base(const PlanView<T>& pv, const BandDesc& B, const cplx<T
                           int deriv)
 {
     T w = pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-    cplx<T> v = c[k];
+    cplx<T> v = c[B.c_off + k];
     if (deriv) {
         w *= (T)(6.283185307179586476925286766559 * (double)k);
         v = mk(-v.y, v.x);
@@ -491,8 +491,8 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     const int64_t jj = it.start + i;
     const BandDesc& B = pv.bands[it.band];
     const int32_t dst = pv.perm[jj];
-    const double c0r = with_c0 ? (double)c[0].x : 0.0;
-    const double c0i = with_c0 ? (double)c[0].y : 0.0;
+    const double c0r = with_c0 ? (double)c[B.c_off].x : 0.0;
+    const double c0i = with_c0 ? (double)c[B.c_off].y : 0.0;
     if (B.q == 0) {
         f[dst] = mk<T>((T)c0r, (T)c0i);
         return;
@@ -656,16 +656,20 @@ FLT_HD void body_adj_tiles(const Ctx& ctx, const PlanView<T>& pv, const NodeItem
     }
 }
 
-// sum_j g_j (the k = 0 coefficient of the adjoint), FP64, into acc[0..1].
+// sum_j g_j over a run of one instance's nodes (the k = 0 coefficient of the
+// adjoint), FP64, into that instance's acc[0..1].
 template <class Ctx, typename T>
-FLT_HD void body_sum_g(const Ctx& ctx, const cplx<T>* g, int64_t M, double* acc, double* red)
+FLT_HD void body_sum_g(const Ctx& ctx, const PlanView<T>& pv, const SumItem* items, const cplx<T>* g, double* acc,
+                       double* red)
 {
     const int tid = ctx.tid(), nt = ctx.ntid();
-    const int64_t base = (int64_t)ctx.bid() * nt * SUMG_PER_THREAD;
+    const SumItem it = items[ctx.bid()];
+    const InstDesc I = pv.inst[it.inst];
+    const int64_t end = I.f_off + I.M;
     double sr = 0, si = 0;
     for (int t = 0; t < SUMG_PER_THREAD; ++t) {
-        const int64_t i = base + (int64_t)t * nt + tid;
-        if (i < M) {
+        const int64_t i = it.start + (int64_t)t * nt + tid;
+        if (i < end) {
             sr += (double)g[i].x;
             si += (double)g[i].y;
         }
@@ -681,8 +685,8 @@ FLT_HD void body_sum_g(const Ctx& ctx, const cplx<T>* g, int64_t M, double* acc,
         ctx.sync();
     }
     if (tid == 0) {
-        ctx.atomic_add(acc, red[0]);
-        ctx.atomic_add(acc + 1, red[1]);
+        ctx.atomic_add(acc + 2 * I.c_off, red[0]);
+        ctx.atomic_add(acc + 2 * I.c_off + 1, red[1]);
     }
 }
 
@@ -694,9 +698,11 @@ FLT_HD void body_sum_g(const Ctx& ctx, const cplx<T>* g, int64_t M, double* acc,
 // ---------------------------------------------------------------------------
 template <class Ctx, typename T>
 FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
-                            const cplx<T>* c, int64_t N, int deriv, double* dacc, double* red)
+                            const cplx<T>* call, int deriv, double* dacc, double* red)
 {
     const DirectItem it = items[ctx.bid()];
+    const int64_t N = pv.inst[it.inst].N;
+    const cplx<T>* c = call + pv.inst[it.inst].c_off;
     const int tid = ctx.tid(), nt = ctx.ntid();
     const int64_t k0 = ((int64_t)it.chunk * nt + tid) * DIRECT_TPT;
     cplx<T> cv[DIRECT_TPT];
@@ -765,9 +771,11 @@ FLT_HD void body_direct_io(const Ctx& ctx, const PlanView<T>& pv, const int32_t*
 // DIRECT_ATPT consecutive k >= 1 per thread (k = 0 is summed over all nodes apart).
 template <class Ctx, typename T>
 FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
-                            const cplx<T>* gin, int64_t N, double* acc)
+                            const cplx<T>* gin, double* accall)
 {
     const DirectItem it = items[ctx.bid()];
+    const int64_t N = pv.inst[it.inst].N;
+    double* acc = accall + 2 * pv.inst[it.inst].c_off;
     const int64_t k0 = ((int64_t)it.chunk * ctx.ntid() + ctx.tid()) * DIRECT_ATPT;
     if (k0 >= N) return;
     T ar[DIRECT_ATPT], ai[DIRECT_ATPT];
@@ -836,8 +844,8 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
         const int64_t kp = p < (n >> 1) ? p : p - n;
         const int64_t k = kp + B.k0;
         if (k < 1 || k > B.kmax) continue;
-        ctx.atomic_add(acc + 2 * k, (double)accr[i]);
-        ctx.atomic_add(acc + 2 * k + 1, (double)acci[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k), (double)accr[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, (double)acci[i]);
     }
 }
 
@@ -896,8 +904,8 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         const int64_t kp = j < (n >> 1) ? j : j - n;
         const int64_t k = kp + B.k0;
         if (k < 1 || k > B.kmax) continue;
-        ctx.atomic_add(acc + 2 * k, (double)accr[i]);
-        ctx.atomic_add(acc + 2 * k + 1, (double)acci[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k), (double)accr[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, (double)acci[i]);
     }
 }
 

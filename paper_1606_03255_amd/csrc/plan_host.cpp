@@ -48,7 +48,8 @@ static const double POLICY_HBM_BYTES_PER_S = 4.0e12;
 static const double POLICY_TERMS_PER_S_C64 = 2.0e12;
 static const double POLICY_TERMS_PER_S_C128 = 1.5e12;
 
-int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+// One instance, everything but the launch groups and the workspace layout.
+static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
 {
     if (!z || N < 1 || M < 1 || (dtype != FLT_C64 && dtype != FLT_C128)) return FLT_EINVAL;
     if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
@@ -204,6 +205,27 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         t[s] = cos(theta[s]);                                   // Sect. 2: zeros of T_q
         lam[s] = ((s & 1) ? -1.0 : 1.0) * sin(theta[s]);        // barycentric weights
     }
+    // Chebyshev coefficients of xi -> sum_r K[s,r] L_r^{Omega_l}(xi) (Lemma A.1 with
+    // the barycentric L_r of Sect. 2 written in the Chebyshev basis).  The block
+    // (Omega_l, Y_m) is the pair (2^d (1,2], y_1 (1,2]) scaled by powers of two,
+    // d = n_xi - l - m, and e^{-y x} depends only on the product, so one table
+    // over d = -1, -2, ..., n_xi - D serves every band (a band's blocks
+    // l_lo..l_hi are consecutive entries), a[d][s][i].
+    for (int d = -1; d >= hp.n_xi - D; --d) {
+        const double xlo = ldexp(1.0, d), xhi = ldexp(1.0, d + 1);
+        const double ylo = hp.y1, yhi = 2.0 * hp.y1;
+        for (int s = 0; s < q; ++s) {
+            const double ysn = 0.5 * (ylo + yhi) + 0.5 * (yhi - ylo) * t[s];
+            for (int i = 0; i < q; ++i) {
+                double a = 0.0;
+                for (int r = 0; r < q; ++r) {
+                    const double xr = 0.5 * (xlo + xhi) + 0.5 * (xhi - xlo) * t[r];
+                    a += exp(-ysn * xr) * cos(i * theta[r]);   // K[s,r] T_i(t_r)
+                }
+                hp.coef.push_back(a * (i == 0 ? 1.0 : 2.0) / q);
+            }
+        }
+    }
     std::map<int, int> deconv_of;
     for (int b = 0; b < nb; ++b) {
         BandDesc& B = hp.bands[b];
@@ -221,25 +243,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
             hp.ycheb.push_back(0.5 * ldexp(hp.y1, 1 - D));
             hp.ycheb.push_back(1.0);
         }
-        // Chebyshev coefficients of xi -> sum_r K[s,r] L_r^{Omega_l}(xi) per block l
-        B.coef_off = (int32_t)hp.coef.size();
-        if (m < D) {
-            const double ylo = ldexp(hp.y1, -m), yhi = ldexp(hp.y1, 1 - m);
-            for (int ell = B.ell_lo; ell <= B.ell_hi; ++ell) {
-                const double xlo = ldexp(xi1, -ell), xhi = ldexp(xi1, 1 - ell);
-                for (int s = 0; s < q; ++s) {
-                    const double ysn = 0.5 * (ylo + yhi) + 0.5 * (yhi - ylo) * t[s];
-                    for (int i = 0; i < q; ++i) {
-                        double a = 0.0;
-                        for (int r = 0; r < q; ++r) {
-                            const double xr = 0.5 * (xlo + xhi) + 0.5 * (xhi - xlo) * t[r];
-                            a += exp(-ysn * xr) * cos(i * theta[r]);   // K[s,r] T_i(t_r)
-                        }
-                        hp.coef.push_back(a * (i == 0 ? 1.0 : 2.0) / q);
-                    }
-                }
-            }
-        }
+        B.coef_off = m < D ? (int32_t)((-1 - (hp.n_xi - B.ell_lo - m)) * q * q) : 0;
         // deconvolution 1 / (n phi_hat(k')) = 1 / I_0(mw sqrt(b^2 - (2 pi k'/n)^2)), |k'| <= n/4
         auto it = deconv_of.find(B.log2n);
         if (it == deconv_of.end()) {
@@ -253,9 +257,6 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
         }
         B.deconv_off = it->second;
     }
-    if (hp.coef.empty()) hp.coef.push_back(0.0);
-    if (hp.deconv.empty()) hp.deconv.push_back(0.0);
-    if (hp.ycheb.empty()) { hp.ycheb.push_back(0.0); hp.ycheb.push_back(0.0); }
     const int TWN = 1 << TW_STAGE_LOG2;
     hp.tw_stage.resize(2 * TWN);
     for (int i = 0; i < TWN; ++i) {
@@ -369,39 +370,12 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
             for (int64_t ch = 0; ch < achunks; ++ch)
                 hp.direct_adj.push_back(DirectItem{(int32_t)g, (int32_t)std::min<int64_t>(DIRECT_ANG, nd - g), (int32_t)ch, 0});
     }
-    // FFT lists grouped by transform length (one compile-time kernel instance per length)
-    auto group = [&](std::vector<FftItem>& v, std::vector<LaunchGroup>& g, int which) {
-        auto len = [&](const FftItem& it) {
-            const BandDesc& B = hp.bands[it.band];
-            return which == 0 ? B.log2n : (which == 1 ? B.log2n1 : B.log2n2);
-        };
-        std::stable_sort(v.begin(), v.end(), [&](const FftItem& a, const FftItem& b) { return len(a) < len(b); });
-        g.clear();
-        for (size_t i = 0; i < v.size(); ++i) {
-            if (g.empty() || g.back().log2 != len(v[i])) g.push_back(LaunchGroup{len(v[i]), (int32_t)i, 0, 0});
-            g.back().count++;
-        }
-    };
-    group(hp.onepass_fwd, hp.g_onepass_fwd, 0);
-    group(hp.onepass_adj, hp.g_onepass_adj, 0);
-    group(hp.passA_fwd, hp.g_passA_fwd, 1);
-    group(hp.passA_adj, hp.g_passA_adj, 1);
-    group(hp.passB, hp.g_passB, 2);
-    if (hp.cstart.empty()) hp.cstart.push_back(0);
-    if (hp.mask.empty()) hp.mask.push_back(0u);
     hp.grid_elems = goff;
     hp.scratch_elems = soff;
+    hp.base_elems = boff;
+    hp.inst.push_back(InstDesc{0, N, 0, M});
+    for (int64_t s0 = 0; s0 < M; s0 += (int64_t)256 * SUMG_PER_THREAD) hp.sum_items.push_back(SumItem{0, 0, s0});
     const size_t S = hp.elem_bytes();
-    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
-    hp.off_grid = 0;
-    hp.off_scratch = al(hp.off_grid + (size_t)goff * S);
-    hp.off_acc = al(hp.off_scratch + (size_t)soff * S);
-    hp.off_U = al(hp.off_acc + (size_t)N * 16);
-    hp.off_phi = al(hp.off_U + (size_t)M * hp.qs * S);
-    hp.off_l0 = al(hp.off_phi + (size_t)M * 2 * hp.mw * (S / 2));
-    hp.off_dacc = al(hp.off_l0 + (size_t)M * 4);
-    hp.off_base = al(hp.off_dacc + (size_t)M * 16);
-    hp.ws_bytes = al(hp.off_base + (size_t)boff * S);
 
     // ---- algorithmic model of one forward: c read once per band; a one-pass
     // band's grid written once; a two-pass band's pass-A output written and
@@ -428,6 +402,169 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
     }
     hp.bytes_forward = bytes;
     hp.flops_forward = flops;
+    return FLT_OK;
+}
+
+// Launch groups (FFT lists sorted by transform length, one compile-time kernel
+// instance per length) and the workspace layout.
+static void finish(HostPlan& hp)
+{
+    auto group = [&](std::vector<FftItem>& v, std::vector<LaunchGroup>& g, int which) {
+        auto len = [&](const FftItem& it) {
+            const BandDesc& B = hp.bands[it.band];
+            return which == 0 ? B.log2n : (which == 1 ? B.log2n1 : B.log2n2);
+        };
+        std::stable_sort(v.begin(), v.end(), [&](const FftItem& a, const FftItem& b) { return len(a) < len(b); });
+        g.clear();
+        for (size_t i = 0; i < v.size(); ++i) {
+            if (g.empty() || g.back().log2 != len(v[i])) g.push_back(LaunchGroup{len(v[i]), (int32_t)i, 0, 0});
+            g.back().count++;
+        }
+    };
+    group(hp.onepass_fwd, hp.g_onepass_fwd, 0);
+    group(hp.onepass_adj, hp.g_onepass_adj, 0);
+    group(hp.passA_fwd, hp.g_passA_fwd, 1);
+    group(hp.passA_adj, hp.g_passA_adj, 1);
+    group(hp.passB, hp.g_passB, 2);
+    if (hp.cstart.empty()) hp.cstart.push_back(0);
+    if (hp.mask.empty()) hp.mask.push_back(0u);
+    if (hp.coef.empty()) hp.coef.push_back(0.0);
+    if (hp.deconv.empty()) hp.deconv.push_back(0.0);
+    if (hp.ycheb.empty()) { hp.ycheb.push_back(0.0); hp.ycheb.push_back(0.0); }
+    const size_t S = hp.elem_bytes();
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    hp.off_grid = 0;
+    hp.off_scratch = al(hp.off_grid + (size_t)hp.grid_elems * S);
+    hp.off_acc = al(hp.off_scratch + (size_t)hp.scratch_elems * S);
+    hp.off_U = al(hp.off_acc + (size_t)hp.N * 16);
+    hp.off_phi = al(hp.off_U + (size_t)hp.M * hp.qs * S);
+    hp.off_l0 = al(hp.off_phi + (size_t)hp.M * 2 * hp.mw * (S / 2));
+    hp.off_dacc = al(hp.off_l0 + (size_t)hp.M * 4);
+    hp.off_base = al(hp.off_dacc + (size_t)hp.M * 16);
+    hp.ws_bytes = al(hp.off_base + (size_t)hp.base_elems * S);
+}
+
+int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+{
+    const int rc = build_one(hp, N, M, z, eps, dtype, flags);
+    if (rc != FLT_OK) return rc;
+    finish(hp);
+    return FLT_OK;
+}
+
+int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
+                     int dtype, uint32_t flags)
+{
+    if (count < 1 || !N || !M || !z) return FLT_EINVAL;
+    out = HostPlan();
+    int64_t zoff = 0;
+    std::map<int, int> deconv_at;                 // log2 n -> offset in the merged deconvolution table
+    std::map<int, int> ycheb_at;                  // m (or -D for Y_D) -> pair offset in the merged ycheb table
+    for (int32_t i = 0; i < count; ++i) {
+        HostPlan p;
+        const int rc = build_one(p, N[i], M[i], z + 2 * zoff, eps, dtype, flags);
+        if (rc != FLT_OK) return rc;
+        zoff += M[i];
+        if (i == 0) {
+            out.dtype = p.dtype;
+            out.eps = p.eps;
+            out.eps_K = p.eps_K;
+            out.eps_A = p.eps_A;
+            out.y1 = p.y1;
+            out.q = p.q;
+            out.mw = p.mw;
+            out.kb_b = p.kb_b;
+            out.flags = p.flags;
+            out.tw_stage = p.tw_stage;
+            out.tw_lo = p.tw_lo;
+            out.tw_hi = p.tw_hi;
+        }
+        // the coefficient table depends on q, y_1 and D - n_xi only (see build_one):
+        // share it, appending when a member's table differs (never for one eps)
+        int32_t coef_shift = 0;
+        if (out.coef.empty()) out.coef = p.coef;
+        else if (p.coef.size() > out.coef.size() ||
+                 !std::equal(p.coef.begin(), p.coef.end(), out.coef.begin())) {
+            coef_shift = (int32_t)out.coef.size();
+            out.coef.insert(out.coef.end(), p.coef.begin(), p.coef.end());
+        }
+        const int32_t bo = (int32_t)out.bands.size();
+        const int64_t no = out.M;                    // sorted-node (and caller-index) offset
+        const int64_t co = out.N;                    // coefficient offset
+        const int64_t dlo = (int64_t)out.dlist.size();
+        const int64_t cso = (int64_t)out.cstart.size(), mko = (int64_t)out.mask.size();
+        for (size_t b = 0; b < p.bands.size(); ++b) {
+            BandDesc B = p.bands[b];
+            const int m = p.band_m[b];
+            B.c_off = co;
+            B.node_start += no;
+            if (B.q > 0 && !B.direct) {
+                B.coef_off += coef_shift;
+                B.grid_off += out.grid_elems;
+                B.scratch_off += out.scratch_elems;
+                B.base_off += out.base_elems;
+                B.cs_off += cso;
+                B.mask_off += mko;
+                auto dt = deconv_at.find(B.log2n);
+                if (dt == deconv_at.end()) {
+                    const int64_t len = ((int64_t)1 << B.log2n) / 4 + 1;
+                    dt = deconv_at.emplace(B.log2n, (int)out.deconv.size()).first;
+                    out.deconv.insert(out.deconv.end(), p.deconv.begin() + B.deconv_off,
+                                      p.deconv.begin() + B.deconv_off + len);
+                }
+                B.deconv_off = dt->second;
+                const int key = m < p.D ? m : -p.D;
+                auto yt = ycheb_at.find(key);
+                if (yt == ycheb_at.end()) {
+                    yt = ycheb_at.emplace(key, (int)(out.ycheb.size() / 2)).first;
+                    out.ycheb.insert(out.ycheb.end(), p.ycheb.begin() + 2 * B.ycheb_off,
+                                     p.ycheb.begin() + 2 * (B.ycheb_off + B.q));
+                }
+                B.ycheb_off = yt->second;
+            }
+            out.bands.push_back(B);
+            out.band_m.push_back(m);
+        }
+        out.node_band.insert(out.node_band.end(), p.node_band.begin(), p.node_band.end());
+        out.nx.insert(out.nx.end(), p.nx.begin(), p.nx.end());
+        out.ny.insert(out.ny.end(), p.ny.begin(), p.ny.end());
+        for (int32_t v : p.perm) out.perm.push_back((int32_t)(v + no));
+        auto shift_fft = [&](std::vector<FftItem>& dst, const std::vector<FftItem>& src) {
+            for (FftItem it : src) { it.band += bo; dst.push_back(it); }
+        };
+        shift_fft(out.onepass_fwd, p.onepass_fwd);
+        shift_fft(out.passA_fwd, p.passA_fwd);
+        shift_fft(out.passB, p.passB);
+        shift_fft(out.onepass_adj, p.onepass_adj);
+        shift_fft(out.passA_adj, p.passA_adj);
+        shift_fft(out.owner, p.owner);
+        auto shift_nodes = [&](std::vector<NodeItem>& dst, const std::vector<NodeItem>& src) {
+            for (NodeItem it : src) { it.band += bo; it.start += no; dst.push_back(it); }
+        };
+        shift_nodes(out.nodes, p.nodes);
+        shift_nodes(out.nfft_nodes, p.nfft_nodes);
+        shift_nodes(out.tile_items, p.tile_items);
+        for (int32_t v : p.dlist) out.dlist.push_back((int32_t)(v + no));
+        for (DirectItem it : p.direct_fwd) { it.first += (int32_t)dlo; it.inst = i; out.direct_fwd.push_back(it); }
+        for (DirectItem it : p.direct_adj) { it.first += (int32_t)dlo; it.inst = i; out.direct_adj.push_back(it); }
+        for (int32_t v : p.cstart) out.cstart.push_back((int32_t)(v + no));
+        out.mask.insert(out.mask.end(), p.mask.begin(), p.mask.end());
+        out.inst.push_back(InstDesc{co, p.N, no, p.M});
+        for (SumItem it : p.sum_items) { it.inst = i; it.start += no; out.sum_items.push_back(it); }
+        out.qs = std::max(out.qs, p.qs);
+        out.D = std::max(out.D, p.D);
+        out.n_xi = std::max(out.n_xi, p.n_xi);
+        out.nodes_z0 += p.nodes_z0;
+        out.grid_elems += p.grid_elems;
+        out.scratch_elems += p.scratch_elems;
+        out.base_elems += p.base_elems;
+        out.bytes_forward += p.bytes_forward;
+        out.flops_forward += p.flops_forward;
+        out.N += p.N;
+        out.M += p.M;
+    }
+    if (out.M > (int64_t)INT32_MAX) return FLT_ERANGE;
+    finish(out);
     return FLT_OK;
 }
 

@@ -46,10 +46,12 @@ struct HostPlan {
     std::vector<DirectItem> direct_fwd, direct_adj;
     std::vector<int32_t> cstart;        // per NFFT band: first sorted node with cell >= c, c = 0..n
     std::vector<uint32_t> mask;         // per two-pass band: bit per grid address read by some window
+    std::vector<InstDesc> inst;         // instances: one, or the members of a batched plan
+    std::vector<SumItem> sum_items;     // adjoint k = 0 sums: runs of one instance's g
 
     // workspace layout (bytes)
     int qs = 1;                         // stride of the per-node column values (max q)
-    int64_t grid_elems = 0, scratch_elems = 0;
+    int64_t grid_elems = 0, scratch_elems = 0, base_elems = 0;
     size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
     size_t off_base = 0;
     size_t ws_bytes = 0;
@@ -63,6 +65,14 @@ struct HostPlan {
 // Returns FLT_OK or a negative FLT_E* code (see flt.h).
 int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype,
                     uint32_t flags = 0);
+
+// One plan for `count` independent instances (N[i] coefficients, M[i] nodes,
+// z packed instance after instance): the members' bands, nodes and work lists
+// side by side, with shared interpolation / window / twiddle tables.  The
+// packed c (and adjoint output) holds instance i at sum_{i' < i} N[i'], the
+// packed f (and adjoint input) at sum_{i' < i} M[i'].
+int build_batch_plan(HostPlan& hp, int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
+                     int dtype, uint32_t flags = 0);
 
 // Modified Bessel function I_0 by its power series (host, FP64).
 double bessel_i0(double x);

@@ -48,24 +48,46 @@ class Plan:
     With ``host_only=True`` only the host-side plan is built (parameters,
     partition, byte model) and no GPU is touched.  ``nfft_only=True`` keeps
     every band on Algorithm 2's NFFT path; by default bands with few nodes and
-    large grids are summed directly (exactly).
+    large grids are summed directly (exactly).  ``graph=True`` captures each
+    operation's launch sequence into a hipGraph on first use and replays it.
+
+    ``Plan.batch`` builds one plan for many independent instances; its
+    transforms act on packed arrays (instance after instance).
     """
 
-    def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False, nfft_only=False):
+    def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False, nfft_only=False, graph=False,
+                 _sizes=None):
         self._lib = L.load()
         self._ptr = ctypes.c_void_p()
-        self.N = int(N)
         zh = _as_host_z(z)
-        self.M = int(zh.shape[0])
+        if _sizes is None:
+            self.Ns = np.array([int(N)], np.int64)
+            self.Ms = np.array([zh.shape[0]], np.int64)
+        else:
+            self.Ns, self.Ms = _sizes
+        self.N = int(self.Ns.sum())
+        self.M = int(self.Ms.sum())
+        self.count = len(self.Ns)
         self.dtype_code = _dtype_code(dtype)
         self.host_only = bool(host_only)
-        flags = (L.FLT_FLAG_HOST_ONLY if host_only else 0) | (L.FLT_FLAG_NFFT_ONLY if nfft_only else 0)
+        flags = ((L.FLT_FLAG_HOST_ONLY if host_only else 0) | (L.FLT_FLAG_NFFT_ONLY if nfft_only else 0)
+                 | (L.FLT_FLAG_GRAPH if graph else 0))
         self._ws = None
+        zp = zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        I64 = ctypes.POINTER(ctypes.c_int64)
+
+        def create():
+            if _sizes is None:
+                rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M, zp, float(eps),
+                                               self.dtype_code, flags)
+            else:
+                rc = self._lib.flt_plan_create_batch(ctypes.byref(self._ptr), self.count,
+                                                     self.Ns.ctypes.data_as(I64), self.Ms.ctypes.data_as(I64),
+                                                     zp, float(eps), self.dtype_code, flags)
+            L.check(rc, "flt_plan_create" if _sizes is None else "flt_plan_create_batch")
+
         if host_only:
-            rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M,
-                                           zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                           float(eps), self.dtype_code, flags)
-            L.check(rc, "flt_plan_create")
+            create()
             self.device = None
             return
         import torch
@@ -73,15 +95,33 @@ class Plan:
         if self.device.index is None:
             self.device = torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(self.device):
-            rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M,
-                                           zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                           float(eps), self.dtype_code, flags)
-            L.check(rc, "flt_plan_create")
+            create()
             nbytes = ctypes.c_size_t()
             L.check(self._lib.flt_plan_workspace_size(self._ptr, ctypes.byref(nbytes)), "flt_plan_workspace_size")
             self._ws = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
             L.check(self._lib.flt_plan_set_workspace(self._ptr, ctypes.c_void_p(self._ws.data_ptr()),
                                                      self._ws.numel()), "flt_plan_set_workspace")
+
+    @classmethod
+    def batch(cls, Ns, zs, eps, dtype="complex64", device=None, host_only=False, nfft_only=False, graph=False):
+        """One plan for independent instances: instance i has Ns[i] coefficients
+        and the nodes zs[i].  Coefficients, results and adjoint inputs are packed
+        instance after instance (offsets in ``c_offsets`` / ``f_offsets``)."""
+        zl = [_as_host_z(z) for z in zs]
+        Ns = np.ascontiguousarray(np.asarray(Ns, np.int64).reshape(-1))
+        Ms = np.array([len(z) for z in zl], np.int64)
+        if len(Ns) != len(Ms) or len(Ns) == 0:
+            raise ValueError("need one coefficient count per node set, and at least one instance")
+        z = np.concatenate(zl) if len(zl) > 1 else zl[0]
+        return cls(None, z, eps, dtype, device, host_only, nfft_only, graph, _sizes=(Ns, Ms))
+
+    @property
+    def c_offsets(self):
+        return np.concatenate([[0], np.cumsum(self.Ns)[:-1]]).astype(np.int64)
+
+    @property
+    def f_offsets(self):
+        return np.concatenate([[0], np.cumsum(self.Ms)[:-1]]).astype(np.int64)
 
     # ---------------------------------------------------------------- queries
     @property

@@ -145,3 +145,39 @@ def test_cell_counts_cover_every_window():
         for t in range(2 * mw):
             hit[(l0 - mw + 1 + t) % n] = True
         assert b["cells"] == hit.sum(), b
+
+
+def test_batched_host_plan_concatenates_members():
+    """A batched host plan holds every member's bands and nodes: counts, band
+    lists and per-node bands equal those of the members' own plans."""
+    rng = np.random.default_rng(3)
+    Ns = [300, 1, 5000, 70000]
+    zs = [inputs.nodes_disk(rng, m) for m in (100, 7, 1000, 2000)]
+    bp = flt.Plan.batch(Ns, zs, 1e-6, "complex64", host_only=True)
+    singles = [flt.Plan(n, z, 1e-6, "complex64", host_only=True) for n, z in zip(Ns, zs)]
+    info = bp.info()
+    assert info["N"] == sum(Ns) and info["M"] == sum(len(z) for z in zs)
+    assert info["num_bands"] == sum(s.info()["num_bands"] for s in singles)
+    assert info["bytes_forward"] == pytest.approx(sum(s.info()["bytes_forward"] for s in singles), rel=1e-12)
+    assert [b for s in singles for b in s.bands()] == bp.bands()
+    assert np.array_equal(bp.node_bands(), np.concatenate([s.node_bands() for s in singles]))
+    assert list(bp.c_offsets) == [0, 300, 301, 5301] and list(bp.f_offsets) == [0, 100, 107, 1107]
+
+
+def test_batched_errors():
+    lib = L.load()
+    ptr = ctypes.c_void_p()
+    N = np.array([10, 20], np.int64)
+    M = np.array([2, 2], np.int64)
+    z = np.zeros(4, np.complex128)
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    zp = z.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    host = L.FLT_FLAG_HOST_ONLY
+    assert lib.flt_plan_create_batch(ctypes.byref(ptr), 0, N.ctypes.data_as(I64), M.ctypes.data_as(I64), zp,
+                                     1e-6, 1, host) == -1
+    assert lib.flt_plan_create_batch(ctypes.byref(ptr), 2, None, M.ctypes.data_as(I64), zp, 1e-6, 1, host) == -1
+    z[3] = -1j                                   # Im z < 0 in the second member
+    assert lib.flt_plan_create_batch(ctypes.byref(ptr), 2, N.ctypes.data_as(I64), M.ctypes.data_as(I64), zp,
+                                     1e-6, 1, host) == -2
+    assert lib.flt_plan_create_batch(ctypes.byref(ptr), 2, N.ctypes.data_as(I64), M.ctypes.data_as(I64), zp,
+                                     1e-6, 1, 1 << 7) == -1

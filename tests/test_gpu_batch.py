@@ -1,0 +1,158 @@
+"""GPU parity of the batched plan and of graph replay, through the C ABI.
+
+* A batched plan evaluates 512 independent instances (sizes log-uniform in
+  [2^8, 2^16], FP32 form, eps = 1e-6) in one launch per transform kind; each
+  instance must meet the bar E <= eps against the FP64 direct sums (on sampled
+  nodes / coefficients), and agree with its own single plan.
+* With graph replay the captured launch sequence is replayed several times,
+  with eager work and synchronisations between replays; every replay must
+  give the eager result.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1606_03255_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+@pytest.fixture(scope="module")
+def batch(torch):
+    from paper_1606_03255_amd import Plan
+    w = inputs.workload("batched")
+    cs = [c for c, _ in w["instances"]]
+    zs = [z for _, z in w["instances"]]
+    plan = Plan.batch(w["N"], zs, 1e-6, torch.complex64)
+    yield w, cs, zs, plan
+    plan.close()
+
+
+def _sample(rng, n, k=48):
+    return np.sort(rng.choice(n, size=min(k, n), replace=False))
+
+
+def test_batched_forward_every_instance(torch, batch):
+    w, cs, zs, plan = batch
+    _say("batched forward", w["count"], "instances, sum N", plan.N, "sum M", plan.M)
+    c = torch.from_numpy(np.concatenate(cs)).to("cuda")
+    f = plan.forward(c).cpu().numpy().astype(np.complex128)
+    fo = plan.f_offsets
+    rng = np.random.default_rng(1)
+    worst = 0.0
+    for i in range(w["count"]):
+        sel = _sample(rng, int(w["M"][i]))
+        ci = cs[i].astype(np.complex128)
+        ref = oracle.forward(ci, zs[i][sel])
+        E = np.abs(f[fo[i] + sel] - ref).max() / np.abs(ci).sum()
+        worst = max(worst, E)
+        assert E <= 1e-6, (i, E)
+    _say("   worst E", worst)
+
+
+def test_batched_adjoint_and_derivative(torch, batch):
+    w, cs, zs, plan = batch
+    rng = np.random.default_rng(2)
+    gs = [inputs.coefficients(rng, int(m)).astype(np.complex64) for m in w["M"]]
+    g = torch.from_numpy(np.concatenate(gs)).to("cuda")
+    h = plan.adjoint(g).cpu().numpy().astype(np.complex128)
+    c = torch.from_numpy(np.concatenate(cs)).to("cuda")
+    fp = plan.derivative(c).cpu().numpy().astype(np.complex128)
+    co, fo = plan.c_offsets, plan.f_offsets
+    worst_h = worst_d = 0.0
+    for i in range(0, w["count"], 4):       # every fourth instance (the oracle's adjoint is N x M)
+        gi = gs[i].astype(np.complex128)
+        ks = _sample(rng, int(w["N"][i]))
+        ref = oracle.adjoint(gi, zs[i], int(w["N"][i]))[ks]
+        Eh = np.abs(h[co[i] + ks] - ref).max() / np.abs(gi).sum()
+        sel = _sample(rng, int(w["M"][i]))
+        ci = cs[i].astype(np.complex128)
+        refd = oracle.derivative(ci, zs[i][sel])
+        Ed = np.abs(fp[fo[i] + sel] - refd).max() / np.abs(2 * np.pi * np.arange(len(ci)) * ci).sum()
+        worst_h, worst_d = max(worst_h, Eh), max(worst_d, Ed)
+        assert Eh <= 1e-6 and Ed <= 1e-6, (i, Eh, Ed)
+    _say("   worst E adjoint", worst_h, "derivative", worst_d)
+
+
+def test_batched_equals_single_plans(torch, batch):
+    from paper_1606_03255_amd import Plan
+    w, cs, zs, plan = batch
+    c = torch.from_numpy(np.concatenate(cs)).to("cuda")
+    f = plan.forward(c).cpu().numpy()
+    fo = plan.f_offsets
+    for i in (0, 1, 7, 100, 311, 511):
+        p = Plan(int(w["N"][i]), zs[i], 1e-6, torch.complex64)
+        fi = p.forward(torch.from_numpy(cs[i]).to("cuda")).cpu().numpy()
+        p.close()
+        scale = np.abs(cs[i].astype(np.complex128)).sum()
+        d = np.abs(f[fo[i]:fo[i] + len(fi)].astype(np.complex128) - fi).max()
+        _say("instance", i, "N", int(w["N"][i]), "M", int(w["M"][i]), "batched - single", d / scale)
+        assert d <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("dtype,eps", [("c64", 1e-6), ("c128", 1e-11)])
+def test_graph_replays_match_eager(torch, dtype, eps):
+    from paper_1606_03255_amd import Plan
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    rng = np.random.default_rng(9)
+    N, M = 70000, 3000
+    z = np.concatenate([inputs.nodes_annulus(rng, M // 2), inputs.nodes_disk(rng, M - M // 2)])
+    c = torch.from_numpy(inputs.coefficients(rng, N)).to("cuda", tdt)
+    g = torch.from_numpy(inputs.coefficients(rng, M)).to("cuda", tdt)
+    eager = Plan(N, z, eps, tdt)
+    graph = Plan(N, z, eps, tdt, graph=True)
+    f0, h0, d0 = eager.forward(c), eager.adjoint(g), eager.derivative(c)
+    f1 = torch.empty_like(f0)
+    h1 = torch.empty_like(h0)
+    d1 = torch.empty_like(d0)
+    n1c = float(c.abs().sum())
+    n1g = float(g.abs().sum())
+    tol = 1e-12 if dtype == "c128" else 1e-7
+    for rep in range(3):
+        _say("graph replay", dtype, rep)
+        graph.forward(c, out=f1)
+        graph.adjoint(g, out=h1)
+        graph.derivative(c, out=d1)
+        torch.cuda.synchronize()
+        x = (c * 2).sum()            # eager work between replays
+        torch.cuda.synchronize()
+        del x
+        assert float((f1 - f0).abs().max()) <= tol * n1c
+        assert float((h1 - h0).abs().max()) <= tol * n1g
+        assert float((d1 - d0).abs().max()) <= tol * n1c * 2 * np.pi * N
+    # new buffers: the plan captures again
+    f2 = graph.forward(c)
+    torch.cuda.synchronize()
+    assert float((f2 - f0).abs().max()) <= tol * n1c
+    eager.close()
+    graph.close()
+
+
+def test_batched_graph_replays(torch, batch):
+    from paper_1606_03255_amd import Plan
+    w, cs, zs, plan = batch
+    gplan = Plan.batch(w["N"], zs, 1e-6, torch.complex64, graph=True)
+    c = torch.from_numpy(np.concatenate(cs)).to("cuda")
+    f0 = plan.forward(c)
+    f1 = torch.empty_like(f0)
+    for rep in range(3):
+        _say("batched graph replay", rep)
+        gplan.forward(c, out=f1)
+        torch.cuda.synchronize()
+        # equal up to the last bit of the FP32 rounding of FP64 sums (atomic order)
+        assert float((f1 - f0).abs().max()) <= 2e-7 * float(f0.abs().max())
+    gplan.close()
