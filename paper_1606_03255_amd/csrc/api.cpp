@@ -141,6 +141,9 @@ static int upload(flt_plan* p)
     L.cstart = (const int32_t*)(base + o_cs);
     L.sum_items = (const SumItem*)(base + o_sum);
     L.n_sum = (int)hp.sum_items.size();
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+        L.persist_blocks = 2 * cus;
     L.n_onepass_fwd = (int)hp.onepass_fwd.size();
     L.n_passA_fwd = (int)hp.passA_fwd.size();
     L.n_passB = (int)hp.passB.size();

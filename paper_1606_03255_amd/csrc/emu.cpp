@@ -10,6 +10,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <type_traits>
 #include <vector>
 
@@ -37,6 +38,10 @@ struct HostCtx {
     }
 };
 
+// Workgroups of the persistent kernels here: few, so that every one of them
+// takes several items of different transform lengths.
+static const int EMU_PERSIST_BLOCKS = 5;
+
 template <typename T> static std::vector<T> cast(const std::vector<double>& v)
 {
     return std::vector<T>(v.begin(), v.end());
@@ -50,19 +55,6 @@ template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body
             HostCtx ctx{omp_get_thread_num(), omp_get_num_threads(), (int)b};
             body(ctx);
         }
-    }
-}
-
-template <int LO, int HI, class F> static bool with_log2(int v, F&& f)
-{
-    if constexpr (LO > HI) {
-        return false;
-    } else {
-        if (v == LO) {
-            f(std::integral_constant<int, LO>{});
-            return true;
-        }
-        return with_log2<LO + 1, HI>(v, f);
     }
 }
 
@@ -150,13 +142,13 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                                                                     lc.data());
                 });
             });
-        for (const LaunchGroup& g : hp.g_passB)
-            with_log2<(LP + 1) / 2, 11>(g.log2, [&](auto LG) {
-                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
-                    body_passB<HostCtx, T, decltype(LG)::value, +1>(ctx, pv, hp.passB.data() + g.start,
-                                                                    scratch.data(), 0, grids.data(), lds.data());
-                });
+        if (!hp.passB.empty()) {
+            // persistent: a few workgroups, each taking every nb-th item
+            const int n = (int)hp.passB.size(), nb = std::min(n, EMU_PERSIST_BLOCKS);
+            run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
+                body_passB<HostCtx, T, +1>(ctx, pv, hp.passB.data(), n, nb, scratch.data(), grids.data(), lds.data());
             });
+        }
         mwsw(0, c, f, !deriv);
         if (nd) {
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
@@ -181,13 +173,12 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         });
         mwsw(1, g, nullptr, 0);
         constexpr int LP = Sizes<T>::LOG2P;
-        for (const LaunchGroup& g : hp.g_passB)
-            with_log2<(LP + 1) / 2, 11>(g.log2, [&](auto LG) {
-                run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
-                    body_passB<HostCtx, T, decltype(LG)::value, -1>(ctx, pv, hp.passB.data() + g.start, grids.data(),
-                                                                    1, scratch.data(), lds.data());
-                });
+        if (!hp.passB.empty()) {
+            const int n = (int)hp.passB.size(), nb = std::min(n, EMU_PERSIST_BLOCKS);
+            run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
+                body_passB<HostCtx, T, -1>(ctx, pv, hp.passB.data(), n, nb, grids.data(), scratch.data(), lds.data());
             });
+        }
         for (const LaunchGroup& g : hp.g_passA_adj)
             with_log2<(LP + 2) / 2, 11>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {

@@ -4,6 +4,7 @@
 // 64 KB LDS tiles for the FFT kernels) and orders them on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "kernels_impl.h"
@@ -18,28 +19,6 @@ struct DevCtx {
     __device__ __forceinline__ void sync() const { __syncthreads(); }
     __device__ __forceinline__ void atomic_add(double* p, double v) const { unsafeAtomicAdd(p, v); }
     __device__ __forceinline__ void atomic_add(float* p, float v) const { unsafeAtomicAdd(p, v); }
-};
-
-// Calls f(std::integral_constant<int, v>) for the runtime value v in [LO, HI]
-// (a uniform branch inside a kernel, or a host-side choice).
-template <int LO, int HI, class F> __host__ __device__ static bool with_log2(int v, F&& f)
-{
-    if constexpr (LO > HI) {
-        return false;
-    } else {
-        if (v == LO) {
-            f(std::integral_constant<int, LO>{});
-            return true;
-        }
-        return with_log2<LO + 1, HI>(v, f);
-    }
-}
-
-template <typename T> struct Log2Range {
-    static constexpr int P = Sizes<T>::LOG2P;
-    static constexpr int ONE_LO = 4, ONE_HI = P;                              // one-pass lengths
-    static constexpr int A_LO = (P + 2) / 2, A_HI = TW2_LOG2 - TW2_LOG2 / 2;  // pass A: ceil(log2n / 2)
-    static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;             // pass B: floor(log2n / 2)
 };
 
 // One launch per FFT kind; each workgroup picks the compile-time instance of
@@ -69,14 +48,13 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, co
 }
 
 template <typename T, int SIGN>
-__global__ __launch_bounds__(FFT_THREADS, 2) void k_passB(PlanView<T> pv, const FftItem* items, const cplx<T>* src,
-                                                          int64_t sel, cplx<T>* dst)
+// four waves per SIMD (two workgroups per CU, as the LDS allows): the
+// register budget the prefetched tile has to fit in
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passB(PlanView<T> pv, const FftItem* items, int nitems,
+                                                          const cplx<T>* src, cplx<T>* dst)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    using RG = Log2Range<T>;
-    with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[blockIdx.x].band].log2n2, [&](auto LG) {
-        body_passB<DevCtx, T, decltype(LG)::value, SIGN>(DevCtx(), pv, items, src, sel, dst, lds);
-    });
+    body_passB<DevCtx, T, SIGN>(DevCtx(), pv, items, nitems, (int)gridDim.x, src, dst, lds);
 }
 
 template <typename T, int MW>
@@ -203,8 +181,8 @@ static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, c
                            scratch, basebuf, deriv);
     if (ev) (void)hipEventRecord(ev[2], st);
     if (L.n_passB)
-        hipLaunchKernelGGL((k_passB<T, +1>), dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
-                           (const cplx<T>*)scratch, (int64_t)0, grids);
+        hipLaunchKernelGGL((k_passB<T, +1>), dim3(std::min(L.n_passB, L.persist_blocks)), dim3(FFT_THREADS), 0, st,
+                           pv, L.passB, L.n_passB, (const cplx<T>*)scratch, grids);
     if (ev) (void)hipEventRecord(ev[3], st);
     return hipSuccess;
 }
@@ -214,8 +192,8 @@ static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, c
                                      double* acc, hipStream_t st)
 {
     if (L.n_passB)
-        hipLaunchKernelGGL((k_passB<T, -1>), dim3(L.n_passB), dim3(FFT_THREADS), 0, st, pv, L.passB,
-                           (const cplx<T>*)grids, (int64_t)1, scratch);
+        hipLaunchKernelGGL((k_passB<T, -1>), dim3(std::min(L.n_passB, L.persist_blocks)), dim3(FFT_THREADS), 0, st,
+                           pv, L.passB, L.n_passB, (const cplx<T>*)grids, scratch);
     if (L.n_passA_adj)
         hipLaunchKernelGGL(k_passA_adj<T>, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
                            (const cplx<T>*)scratch, acc);

@@ -17,9 +17,35 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "flt_types.h"
 
 namespace flt {
+
+// Calls f(std::integral_constant<int, v>) for the run-time value v in [LO, HI]
+// (a uniform branch inside a kernel, or a host-side choice).
+template <int LO, int HI, class F> FLT_HD bool with_log2(int v, F&& f)
+{
+    if constexpr (LO > HI) {
+        return false;
+    } else {
+        if (v == LO) {
+            f(std::integral_constant<int, LO>{});
+            return true;
+        }
+        return with_log2<LO + 1, HI>(v, f);
+    }
+}
+
+// Transform lengths (log2) of the FFT kernels: one-pass bands, pass A
+// (ceil(log2 n / 2)) and pass B (floor(log2 n / 2)).
+template <typename T> struct Log2Range {
+    static constexpr int P = Sizes<T>::LOG2P;
+    static constexpr int ONE_LO = 4, ONE_HI = P;
+    static constexpr int A_LO = (P + 2) / 2, A_HI = TW2_LOG2 - TW2_LOG2 / 2;
+    static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;
+};
 
 FLT_HD int ceil_log2_u64(int64_t k)  // k >= 1
 {
@@ -389,48 +415,129 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     }
 }
 
+// The thread index, hidden from the optimiser once per loop iteration: in the
+// persistent loops every per-thread address depends only on it, and hoisting
+// all of them out of the loop (for every transform length) would exhaust the
+// registers.  An empty asm statement on the value; no instruction is emitted.
+FLT_HD int opaque(int v)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    asm volatile("" : "+v"(v));
+#else
+    asm volatile("" : "+r"(v));
+#endif
+    return v;
+}
+
+template <class Ctx> struct IterCtx {
+    const Ctx& c;
+    int t;
+    FLT_HD int tid() const { return t; }
+    FLT_HD int ntid() const { return c.ntid(); }
+    FLT_HD int bid() const { return c.bid(); }
+    FLT_HD void sync() const { c.sync(); }
+};
+
 // pass B: for B = 2^log2B consecutive l1, the length-n2 DFTs over j2 of
 // Y[j2][l1]; X[l1 + n1 l2] stored blocked as [l1 / B][l2][l1 mod B], only at
 // the cells of the band's mask (the only ones a window reads).  Adjoint
-// direction: only the masked cells are loaded, the others are zero.
-template <class Ctx, typename T, int LOG2N2, int SIGN>
-FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                       const cplx<T>* src_base, int64_t src_band_off_sel, cplx<T>* dst_base, cplx<T>* lds)
+// direction (SIGN = -1): grid -> scratch, only the masked cells are loaded,
+// the others are zero.
+//
+// A tile's elements are held by the threads as rows of B consecutive HBM
+// elements cut into runs of V = min(B, 8): element r < tile_items of a
+// thread is row j2 = ch mod n2, column lo = (ch / n2) V + r mod V, with run
+// ch = tid + (r / V) FFT_THREADS; lanes take consecutive rows, so the
+// transposed LDS accesses are contiguous.
+template <typename T, int LOG2N2> struct PassBGeo {
+    static constexpr int log2n2 = LOG2N2, log2B = Sizes<T>::LOG2P - LOG2N2;
+    static constexpr int log2V = log2B < 3 ? log2B : 3;
+    static constexpr int V = 1 << log2V;
+    FLT_HD static int ch(int tid, int r) { return tid + (r >> log2V) * FFT_THREADS; }
+    FLT_HD static int row(int ch) { return ch & ((1 << log2n2) - 1); }
+    FLT_HD static int col(int ch, int r) { return ((ch >> log2n2) << log2V) + (r & (V - 1)); }
+};
+
+// Load item `it`'s tile into the registers v; for the adjoint direction (ADJ:
+// grid -> scratch) also the mask bits of each run of V elements (bits[m] for
+// run m, bit u for its element u), applied when the tile goes to LDS.
+template <class Ctx, typename T, int LOG2N2, bool ADJ>
+FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it, const cplx<T>* src_base,
+                        cplx<T>* v, uint32_t* bits)
 {
-    // src_band_off_sel: 0 -> source at scratch_off, destination at grid_off (forward);
-    //                   1 -> source at grid_off, destination at scratch_off (adjoint)
-    constexpr int log2n2 = LOG2N2, log2B = Sizes<T>::LOG2P - LOG2N2;
-    constexpr int P = tile_points<T>();
-    const FftItem it = items[ctx.bid()];
+    using G = PassBGeo<T, LOG2N2>;
     const BandDesc& B = pv.bands[it.band];
-    const int64_t so = src_band_off_sel ? B.grid_off : B.scratch_off;
-    const int64_t dso = src_band_off_sel ? B.scratch_off : B.grid_off;
-    const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << (log2n2 + log2B));
-    const cplx<T>* src = src_base + so + blk_off;
-    const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (log2n2 + log2B - 5));
-    // each thread moves V consecutive elements of one row j2 (lanes take
-    // consecutive rows, so the transposed LDS accesses are contiguous)
-    constexpr int V = (1 << log2B) < 8 ? (1 << log2B) : 8;
-    constexpr int CHUNKS = P / V;
-    for (int t = ctx.tid(); t < CHUNKS; t += FFT_THREADS) {
-        const int j2 = t & ((1 << log2n2) - 1);
-        const int lo0 = (t >> log2n2) * V;
-        const int p0 = (j2 << log2B) + lo0;
-        const uint32_t bits = src_band_off_sel ? mask[p0 >> 5] >> (p0 & 31) : ~0u;
-        cplx<T> v[V];
-        for (int u = 0; u < V; ++u) v[u] = ((bits >> u) & 1u) ? src[p0 + u] : mk<T>(0, 0);
-        for (int u = 0; u < V; ++u) lds[lds_at(((lo0 + u) << log2n2) + j2)] = v[u];
+    const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
+    const cplx<T>* src = src_base + (ADJ ? B.grid_off : B.scratch_off) + blk_off;
+    const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (Sizes<T>::LOG2P - 5));
+    for (int m = 0; m < tile_items<T>() / G::V; ++m) {
+        const int ch = ctx.tid() + m * FFT_THREADS;
+        const int p0 = (G::row(ch) << G::log2B) + G::col(ch, 0);   // multiple of V: one mask word
+        if (ADJ) bits[m] = mask[p0 >> 5] >> (p0 & 31);
+        for (int u = 0; u < G::V; ++u) v[m * G::V + u] = src[p0 + u];
     }
-    ctx.sync();
-    lds_fft_ct<Ctx, T, LOG2N2, (1 << log2B), SIGN>(ctx, lds, pv.tw_stage);
-    cplx<T>* dst = dst_base + dso + blk_off;
-    for (int t = ctx.tid(); t < CHUNKS; t += FFT_THREADS) {
-        const int l2 = t & ((1 << log2n2) - 1);
-        const int lo0 = (t >> log2n2) * V;
-        const int p0 = (l2 << log2B) + lo0;
-        const uint32_t bits = src_band_off_sel ? ~0u : mask[p0 >> 5] >> (p0 & 31);
-        for (int u = 0; u < V; ++u)
-            if ((bits >> u) & 1u) dst[p0 + u] = lds[lds_at(((lo0 + u) << log2n2) + l2)];
+}
+
+// Pass-B items of one transform length, as long as the workgroup's next item
+// has that length: each tile is in the registers v before its FFT, and the
+// next item's tile is fetched into v right after v went to LDS, so its loads
+// are in flight while this tile is transformed.  Returns the index of the
+// workgroup's first item not processed.
+template <class Ctx, typename T, int LOG2N2, int SIGN>
+FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* items, int i, int nitems, int nblocks,
+                     const cplx<T>* src_base, cplx<T>* dst_base, cplx<T>* lds)
+{
+    constexpr bool ADJ = SIGN < 0;
+    using G = PassBGeo<T, LOG2N2>;
+    constexpr int CHUNKS = tile_points<T>() / G::V;
+    constexpr int RUNS = tile_items<T>() / G::V;
+    cplx<T> v[tile_items<T>()];
+    uint32_t bits[RUNS];
+    passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, v, bits);
+    for (;;) {
+        const IterCtx<Ctx> ctx{ctx0, opaque(ctx0.tid())};
+        const FftItem it = items[i];
+        const BandDesc& B = pv.bands[it.band];
+        for (int r = 0; r < tile_items<T>(); ++r) {
+            const int ch = G::ch(ctx.tid(), r);
+            const bool keep = !ADJ || ((bits[r / G::V] >> (r % G::V)) & 1u);
+            lds[lds_at((G::col(ch, r) << LOG2N2) + G::row(ch))] = keep ? v[r] : mk<T>(0, 0);
+        }
+        ctx.sync();
+        const int nx = i + nblocks;
+        const bool more = nx < nitems && pv.bands[items[nx].band].log2n2 == LOG2N2;
+        if (more) passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, v, bits);
+        lds_fft_ct<IterCtx<Ctx>, T, LOG2N2, (1 << G::log2B), SIGN>(ctx, lds, pv.tw_stage);
+        const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
+        cplx<T>* dst = dst_base + (ADJ ? B.scratch_off : B.grid_off) + blk_off;
+        const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (Sizes<T>::LOG2P - 5));
+        for (int t = ctx.tid(); t < CHUNKS; t += FFT_THREADS) {
+            const int l2 = t & ((1 << LOG2N2) - 1);
+            const int lo0 = (t >> LOG2N2) * G::V;
+            const int p0 = (l2 << G::log2B) + lo0;
+            const uint32_t keep = ADJ ? ~0u : mask[p0 >> 5] >> (p0 & 31);
+            for (int u = 0; u < G::V; ++u)
+                if ((keep >> u) & 1u) dst[p0 + u] = lds[lds_at(((lo0 + u) << LOG2N2) + l2)];
+        }
+        ctx.sync();
+        i = nx;
+        if (!more) return i;
+    }
+}
+
+// Persistent pass B: workgroup g takes items g, g + nblocks, g + 2 nblocks, ...
+// (forward: scratch -> grids, SIGN = +1; adjoint: grids -> scratch, SIGN = -1).
+template <class Ctx, typename T, int SIGN>
+FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items, int nitems, int nblocks,
+                       const cplx<T>* src_base, cplx<T>* dst_base, cplx<T>* lds)
+{
+    using RG = Log2Range<T>;
+    int i = ctx.bid();
+    while (i < nitems) {
+        with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
+            i = passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nblocks, src_base, dst_base,
+                                                             lds);
+        });
     }
 }
 

@@ -25,6 +25,7 @@ struct DevLists {
     const int32_t* cstart = nullptr;
     const SumItem* sum_items = nullptr;
     int n_sum = 0;
+    int persist_blocks = 512;   // workgroups of the persistent FFT kernels (two per compute unit)
     int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_owner = 0;
     int n_nodes = 0, n_nfft_nodes = 0, n_tile_items = 0, n_direct_fwd = 0, n_direct_adj = 0;
     int64_t n_dlist = 0;
