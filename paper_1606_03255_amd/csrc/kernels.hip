@@ -40,7 +40,7 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, co
                                                               int deriv)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    __shared__ T lc[Sizes<T>::COEF];
+    __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
         body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, lds, lc);
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, 
                                                                 const cplx<T>* grids, double* acc)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    __shared__ T lc[Sizes<T>::COEF];
+    __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
         body_onepass_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, grids, acc, lds, lc);
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, co
                                                               const cplx<T>* scratch, double* acc)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    __shared__ T lc[Sizes<T>::COEF];
+    __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
         body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc);

@@ -47,9 +47,9 @@ template <typename T> struct Log2Range {
     static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;
 };
 
-FLT_HD int ceil_log2_u64(int64_t k)  // k >= 1
+FLT_HD int ceil_log2_u32(int k)  // 1 <= k < 2^31
 {
-    return k <= 1 ? 0 : 64 - __builtin_clzll((unsigned long long)(k - 1));
+    return k <= 1 ? 0 : 32 - __builtin_clz((unsigned)(k - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -58,9 +58,9 @@ FLT_HD int ceil_log2_u64(int64_t k)  // k >= 1
 // polynomial as sum_r K[s,r] L_r(k); coefficients built by the planner).
 // ---------------------------------------------------------------------------
 template <typename T>
-FLT_HD T laplace_row(const PlanView<T>& pv, const BandDesc& B, int s, int64_t k)
+FLT_HD T laplace_row(const PlanView<T>& pv, const BandDesc& B, int s, int k)
 {
-    const int cl = ceil_log2_u64(k);           // Omega_l = (2^(cl-1), 2^cl] holds k
+    const int cl = ceil_log2_u32(k);           // Omega_l = (2^(cl-1), 2^cl] holds k
     const int ell = B.n_xi + 1 - cl;
     if (ell > B.ell_hi) return T(1);           // kernel ~ 1 on l > L_m (Lemma A.2 iv)
     const int q = B.q;
@@ -80,11 +80,11 @@ FLT_HD T laplace_row(const PlanView<T>& pv, const BandDesc& B, int s, int64_t k)
 // Value of column s of band B's FFT input at natural grid index j.
 template <typename T>
 FLT_HD cplx<T> grid_input(const PlanView<T>& pv, const BandDesc& B, const cplx<T>* c,
-                          int s, int64_t j, int deriv)
+                          int s, int j, int deriv)
 {
-    const int64_t n = (int64_t)1 << B.log2n;
-    const int64_t kp = j < (n >> 1) ? j : j - n;
-    const int64_t k = kp + B.k0;
+    const int n = 1 << B.log2n;
+    const int kp = j < (n >> 1) ? j : j - n;
+    const int k = kp + (int)B.k0;
     if (k < 1 || k > B.kmax) return mk<T>(0, 0);
     T w = laplace_row(pv, B, s, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
     cplx<T> v = c[B.c_off + k];
@@ -174,10 +174,11 @@ template <typename T> FLT_HD cplx<T> tw_stage_at(const cplx<T>* tw, int t, int s
     return w;
 }
 
-// e^{sign 2 pi i e / n}, n = 2^log2n <= 2^22, from the two-level table
-template <typename T> FLT_HD cplx<T> tw_grid_at(const PlanView<T>& pv, int64_t e, int log2n, int sign)
+// e^{sign 2 pi i e / n}, n = 2^log2n <= 2^22, from the two-level table; e is
+// taken mod 2^32 (n divides 2^32, so a wrapped product j2 l1 gives e mod n)
+template <typename T> FLT_HD cplx<T> tw_grid_at(const PlanView<T>& pv, uint32_t e, int log2n, int sign)
 {
-    const int64_t ee = (e & (((int64_t)1 << log2n) - 1)) << (TW2_LOG2 - log2n);
+    const uint32_t ee = (e & ((1u << log2n) - 1u)) << (TW2_LOG2 - log2n);
     cplx<T> w = mul(pv.tw_hi[ee >> TW2_HALF], pv.tw_lo[ee & ((1 << TW2_HALF) - 1)]);
     if (sign > 0) w.y = -w.y;
     return w;
@@ -265,43 +266,61 @@ FLT_HD void lds_fft_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
 template <typename T> constexpr int tile_points() { return 1 << Sizes<T>::LOG2P; }
 template <typename T> constexpr int tile_items() { return tile_points<T>() / FFT_THREADS; }
 
+// Chebyshev coefficients staged in LDS: each block's q coefficients padded
+// with zeros to a whole number of 16-byte vectors (CV values), read as vectors.
+template <typename T> struct alignas(16) CoefVec {
+    static constexpr int N = 16 / (int)sizeof(T);
+    T a[N];
+};
+FLT_HD int coef_stride(int q, int cv) { return (q + cv - 1) / cv * cv; }
+
 // Column s's Chebyshev coefficients of every interpolated block of band B,
-// staged into LDS as lc[(l - ell_lo) q + i].
+// staged into LDS as lc[(l - ell_lo) QP + i], QP = q padded to whole vectors.
 template <class Ctx, typename T>
 FLT_HD void stage_coef(const Ctx& ctx, const PlanView<T>& pv, const BandDesc& B, int s, T* lc)
 {
-    const int q = B.q;
+    const int q = B.q, qp = coef_stride(q, CoefVec<T>::N);
     const int nblk = B.ell_hi - B.ell_lo + 1;
-    for (int idx = ctx.tid(); idx < nblk * q; idx += ctx.ntid()) {
-        const int e = idx / q, i = idx - e * q;
-        lc[idx] = pv.coef[B.coef_off + (e * q + s) * q + i];
+    for (int idx = ctx.tid(); idx < nblk * qp; idx += ctx.ntid()) {
+        const int e = idx / qp, i = idx - e * qp;
+        lc[idx] = i < q ? pv.coef[B.coef_off + (e * q + s) * q + i] : T(0);
     }
 }
 
-// t_k[s] from the staged coefficients of column s (see laplace_row).
+// t_k[s] from the staged coefficients of column s (see laplace_row): the
+// same Clenshaw recurrence, the zero padding on top leaving it unchanged.
 template <typename T>
-FLT_HD T laplace_row_lds(const T* lc, const BandDesc& B, int64_t k)
+FLT_HD T laplace_row_lds(const T* lc, const BandDesc& B, int k)
 {
-    const int cl = ceil_log2_u64(k);
+    constexpr int CV = CoefVec<T>::N;
+    const int cl = ceil_log2_u32(k);
     const int ell = B.n_xi + 1 - cl;
     if (ell > B.ell_hi) return T(1);
-    const int q = B.q;
-    const T* a = lc + (ell - B.ell_lo) * q;
+    const int qp = coef_stride(B.q, CV);
+    const CoefVec<T>* a = (const CoefVec<T>*)(lc + (ell - B.ell_lo) * qp);
     const T u = ldexp((T)k, 2 - cl) - T(3);
     const T u2 = u + u;
     T b1 = 0, b2 = 0;
-    for (int i = q - 1; i >= 1; --i) {
-        T b0 = a[i] + u2 * b1 - b2;
+    for (int c = qp / CV - 1; c >= 1; --c) {
+        const CoefVec<T> w = a[c];
+        for (int j = CV - 1; j >= 0; --j) {
+            const T b0 = w.a[j] + u2 * b1 - b2;
+            b2 = b1;
+            b1 = b0;
+        }
+    }
+    const CoefVec<T> w = a[0];
+    for (int j = CV - 1; j >= 1; --j) {
+        const T b0 = w.a[j] + u2 * b1 - b2;
         b2 = b1;
         b1 = b0;
     }
-    return a[0] + u * b1 - b2;
+    return w.a[0] + u * b1 - b2;
 }
 
 // c_k / (n phi_hat(k - k0)), times 2 pi i k for the derivative transform.
 template <typename T>
-FLT_HD cplx<T> point_base(const PlanView<T>& pv, const BandDesc& B, const cplx<T>* c, int64_t kp, int64_t k,
-                          int deriv)
+FLT_HD cplx<T> point_base(const PlanView<T>& pv, const BandDesc& B, const cplx<T>* c, int kp, int k, int deriv)
 {
     T w = pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
     cplx<T> v = c[B.c_off + k];
@@ -334,7 +353,7 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     const BandDesc& B = pv.bands[it.band];
     for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int sl = p >> LOG2N;
-        lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, (int64_t)(p & ((1 << LOG2N) - 1)), deriv)
+        lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, p & ((1 << LOG2N) - 1), deriv)
                             : mk<T>(0, 0);
     }
     ctx.sync();
@@ -359,8 +378,9 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
     const int log2n2 = B.log2n2, log2B = B.log2B;
-    const int64_t n = (int64_t)1 << B.log2n;
-    const int64_t j2_0 = (int64_t)it.blk << log2b;
+    const int n = 1 << B.log2n;
+    const int k0 = (int)B.k0, kmax = (int)B.kmax;
+    const int j2_0 = it.blk << log2b;
     // c_k / (n phi_hat(k')) of this workgroup's points: formed once, reading c
     // in address order (jj fastest) and transposing through LDS, then kept in
     // the workgroup's own slot for the other columns; every thread re-reads
@@ -374,11 +394,11 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
                 const int p = ctx.tid() + i * FFT_THREADS;
                 const int jj = p & ((1 << log2b) - 1);
                 const int j1 = p >> log2b;
-                const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
-                const int64_t kp = j < (n >> 1) ? j : j - n;
-                const int64_t k = kp + B.k0;
+                const int j = j2_0 + jj + (j1 << log2n2);
+                const int kp = j < (n >> 1) ? j : j - n;
+                const int k = kp + k0;
                 lds[lds_at((jj << log2n1) + j1)] =
-                    k >= 1 && k <= B.kmax ? point_base(pv, B, c, kp, k, deriv) : mk<T>(0, 0);
+                    k >= 1 && k <= kmax ? point_base(pv, B, c, kp, k, deriv) : mk<T>(0, 0);
             }
         }
         ctx.sync();
@@ -387,9 +407,9 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int p = ctx.tid() + i * FFT_THREADS;
             const int j1 = p & ((1 << log2n1) - 1);
             const int jj = p >> log2n1;
-            const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
-            const int64_t kp = j < (n >> 1) ? j : j - n;
-            const int64_t k = kp + B.k0;
+            const int j = j2_0 + jj + (j1 << log2n2);
+            const int kp = j < (n >> 1) ? j : j - n;
+            const int k = kp + k0;
             cplx<T> base;
             if (s == 0) {
                 base = lds[lds_at(p)];
@@ -397,7 +417,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             } else {
                 base = slot[p];
             }
-            lds[lds_at(p)] = k >= 1 && k <= B.kmax ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
+            lds[lds_at(p)] = k >= 1 && k <= kmax ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
         }
         ctx.sync();
         lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, pv.tw_stage);
@@ -406,10 +426,10 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int l1lo = p & ((1 << log2B) - 1);
             const int jj = (p >> log2B) & ((1 << log2b) - 1);
             const int l1hi = p >> (log2B + log2b);
-            const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
-            const int64_t j2 = j2_0 + jj;
-            cplx<T> v = mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_at(pv, j2 * l1, B.log2n, +1));
-            Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
+            const int l1 = (l1hi << log2B) + l1lo;
+            const int j2 = j2_0 + jj;
+            cplx<T> v = mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_at(pv, (uint32_t)j2 * (uint32_t)l1, B.log2n, +1));
+            Y[(l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
         }
         ctx.sync();
     }
@@ -935,8 +955,8 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= n) break;
-            const int64_t kp = p < (n >> 1) ? p : p - n;
-            const int64_t k = kp + B.k0;
+            const int kp = p < (n >> 1) ? p : p - n;
+            const int k = kp + (int)B.k0;
             if (k < 1 || k > B.kmax) continue;
             const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
             const cplx<T> v = lds[lds_at(p)];
@@ -948,8 +968,8 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     for (int i = 0; i < ITEMS; ++i) {
         const int p = ctx.tid() + i * FFT_THREADS;
         if (p >= n) break;
-        const int64_t kp = p < (n >> 1) ? p : p - n;
-        const int64_t k = kp + B.k0;
+        const int kp = p < (n >> 1) ? p : p - n;
+        const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
         ctx.atomic_add(acc + 2 * (B.c_off + k), (double)accr[i]);
         ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, (double)acci[i]);
@@ -968,8 +988,8 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
     const int log2n2 = B.log2n2, log2B = B.log2B;
-    const int64_t n = (int64_t)1 << B.log2n;
-    const int64_t j2_0 = (int64_t)it.blk << log2b;
+    const int n = 1 << B.log2n;
+    const int j2_0 = it.blk << log2b;
     T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
@@ -978,10 +998,10 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int l1lo = p & ((1 << log2B) - 1);
             const int jj = (p >> log2B) & ((1 << log2b) - 1);
             const int l1hi = p >> (log2B + log2b);
-            const int64_t l1 = ((int64_t)l1hi << log2B) + l1lo;
-            const int64_t j2 = j2_0 + jj;
-            const cplx<T> v = Y[((int64_t)l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
-            lds[lds_at((jj << log2n1) + l1)] = mul(v, tw_grid_at(pv, j2 * l1, B.log2n, -1));
+            const int l1 = (l1hi << log2B) + l1lo;
+            const int j2 = j2_0 + jj;
+            const cplx<T> v = Y[(l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
+            lds[lds_at((jj << log2n1) + l1)] = mul(v, tw_grid_at(pv, (uint32_t)j2 * (uint32_t)l1, B.log2n, -1));
         }
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
@@ -991,9 +1011,9 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             if (p >= P) break;
             const int j1 = p & ((1 << log2n1) - 1);   // tile element p = (jj << log2n1) + j1
             const int jj = p >> log2n1;
-            const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
-            const int64_t kp = j < (n >> 1) ? j : j - n;
-            const int64_t k = kp + B.k0;
+            const int j = j2_0 + jj + (j1 << log2n2);
+            const int kp = j < (n >> 1) ? j : j - n;
+            const int k = kp + (int)B.k0;
             if (k < 1 || k > B.kmax) continue;
             const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
             const cplx<T> v = lds[lds_at(p)];
@@ -1007,9 +1027,9 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         if (p >= P) break;
         const int j1 = p & ((1 << log2n1) - 1);
         const int jj = p >> log2n1;
-        const int64_t j = j2_0 + jj + ((int64_t)j1 << log2n2);
-        const int64_t kp = j < (n >> 1) ? j : j - n;
-        const int64_t k = kp + B.k0;
+        const int j = j2_0 + jj + (j1 << log2n2);
+        const int kp = j < (n >> 1) ? j : j - n;
+        const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
         ctx.atomic_add(acc + 2 * (B.c_off + k), (double)accr[i]);
         ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, (double)acci[i]);

@@ -147,8 +147,14 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
         hp.band_m.push_back(0);
     }
     const int nb = (int)hp.bands.size();
-    if ((int64_t)(D - hp.n_xi + 2) * q > (dtype == FLT_C64 ? Sizes<float>::COEF : Sizes<double>::COEF))
-        return FLT_EPRECISION;
+    // one column's coefficients of every block of a band are staged in LDS,
+    // q padded to whole 16-byte vectors; a band has at most D - n_xi blocks
+    {
+        const int cv = dtype == FLT_C64 ? 4 : 2;
+        const int qp = (q + cv - 1) / cv * cv;
+        if ((int64_t)(D - hp.n_xi) * qp > (dtype == FLT_C64 ? Sizes<float>::COEF : Sizes<double>::COEF))
+            return FLT_EPRECISION;
+    }
 
     // ---- per-band choice: NFFT (Alg. 2) or the exact direct sum for sparsely filled bands
     {
