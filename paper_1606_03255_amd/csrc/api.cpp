@@ -104,11 +104,10 @@ static int upload(flt_plan* p)
     const size_t o_l3 = pk.add(hp.onepass_adj.data(), hp.onepass_adj.size() * sizeof(FftItem));
     const size_t o_l4 = pk.add(hp.passA_adj.data(), hp.passA_adj.size() * sizeof(FftItem));
     const size_t o_l5 = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
-    const size_t o_l6 = pk.add(hp.owner.data(), hp.owner.size() * sizeof(FftItem));
+    const size_t o_l6 = pk.add(hp.cells.data(), hp.cells.size() * sizeof(CellItem));
     const size_t o_l7 = pk.add(hp.nfft_nodes.data(), hp.nfft_nodes.size() * sizeof(NodeItem));
     const size_t o_l8 = pk.add(hp.direct_fwd.data(), hp.direct_fwd.size() * sizeof(DirectItem));
     const size_t o_l9 = pk.add(hp.direct_adj.data(), hp.direct_adj.size() * sizeof(DirectItem));
-    const size_t o_ti = pk.add(hp.tile_items.data(), hp.tile_items.size() * sizeof(NodeItem));
     const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
     const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
     const size_t o_mask = pk.add(hp.mask.data(), hp.mask.size() * sizeof(uint32_t));
@@ -131,10 +130,8 @@ static int upload(flt_plan* p)
     L.onepass_adj = (const FftItem*)(base + o_l3);
     L.passA_adj = (const FftItem*)(base + o_l4);
     L.nodes = (const NodeItem*)(base + o_l5);
-    L.owner = (const FftItem*)(base + o_l6);
+    L.cells = (const CellItem*)(base + o_l6);
     L.nfft_nodes = (const NodeItem*)(base + o_l7);
-    L.tile_items = (const NodeItem*)(base + o_ti);
-    L.n_tile_items = (int)hp.tile_items.size();
     L.direct_fwd = (const DirectItem*)(base + o_l8);
     L.direct_adj = (const DirectItem*)(base + o_l9);
     L.dlist = (const int32_t*)(base + o_dl);
@@ -150,7 +147,7 @@ static int upload(flt_plan* p)
     L.n_onepass_adj = (int)hp.onepass_adj.size();
     L.n_passA_adj = (int)hp.passA_adj.size();
     L.n_nodes = (int)hp.nodes.size();
-    L.n_owner = (int)hp.owner.size();
+    L.n_cells = (int)hp.cells.size();
     L.n_nfft_nodes = (int)hp.nfft_nodes.size();
     L.n_direct_fwd = (int)hp.direct_fwd.size();
     L.n_direct_adj = (int)hp.direct_adj.size();

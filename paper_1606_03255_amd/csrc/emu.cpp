@@ -71,12 +71,10 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
     run_blocks(hp.nfft_nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
         body_adj_prep<HostCtx, T, MW>(ctx, pv, hp.nfft_nodes.data(), c, hp.qs, U, Phi, L0);
     });
-    run_blocks(hp.owner.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-        body_adj_owner<HostCtx, T, MW>(ctx, pv, hp.owner.data(), hp.qs, U, Phi, L0, hp.cstart.data(), grids);
-    });
-    std::vector<T> tile(2 * TILE_CELLS);
-    run_blocks(hp.tile_items.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-        body_adj_tiles<HostCtx, T, MW>(ctx, pv, hp.tile_items.data(), hp.qs, U, Phi, L0, grids, tile.data());
+    std::vector<T> red(2 * ADJ_RC * GATHER_THREADS);
+    run_blocks(hp.cells.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_adj_cells<HostCtx, T, MW>(ctx, pv, hp.cells.data(), hp.qs, U, Phi, L0, hp.cstart.data(), grids,
+                                       red.data());
     });
 }
 
@@ -144,7 +142,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             });
         if (!hp.passB.empty()) {
             // persistent: a few workgroups, each taking every nb-th item
-            const int n = (int)hp.passB.size(), nb = std::min(n, EMU_PERSIST_BLOCKS);
+            const int n = (int)hp.passB.size();
+            const int nb = passB_prefetch<T, +1>() ? std::min(n, EMU_PERSIST_BLOCKS) : n;
             run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
                 body_passB<HostCtx, T, +1>(ctx, pv, hp.passB.data(), n, nb, scratch.data(), grids.data(), lds.data());
             });
@@ -174,7 +173,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         mwsw(1, g, nullptr, 0);
         constexpr int LP = Sizes<T>::LOG2P;
         if (!hp.passB.empty()) {
-            const int n = (int)hp.passB.size(), nb = std::min(n, EMU_PERSIST_BLOCKS);
+            const int n = (int)hp.passB.size();
+            const int nb = passB_prefetch<T, -1>() ? std::min(n, EMU_PERSIST_BLOCKS) : n;
             run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
                 body_passB<HostCtx, T, -1>(ctx, pv, hp.passB.data(), n, nb, grids.data(), scratch.data(), lds.data());
             });

@@ -49,8 +49,7 @@ constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
 constexpr int DIRECT_ATPT = 8;            // direct adjoint: coefficients per thread
 constexpr int DIRECT_ANG = 256;           // direct adjoint: nodes per workgroup
 constexpr int SUMG_PER_THREAD = 16;       // sum of g: elements per thread
-constexpr int TILE_CELLS = 2048;          // adjoint LDS tile (cells of one column)
-constexpr int TILE_NODES = 2048;          // adjoint LDS tile: most nodes per chunk
+constexpr int CELL_TARGET = 16;           // adjoint spread: contributions per thread a cell's group aims at
 
 template <typename T> struct Sizes;
 // LOG2P: FFT tile of 2^LOG2P complex values (64 KB); COEF: LDS slots for one
@@ -81,7 +80,6 @@ struct BandDesc {
     int32_t deconv_off;  // deconvolution table of this n: entries |k'| = 0..n/4
     int32_t ycheb_off;   // q (node, weight) pairs of the y interpolation in the ycheb table
     int32_t direct;      // 1: the band's nodes are evaluated by the direct sum (no grids)
-    int32_t tiles;       // 1: the adjoint spreads this (densely filled) band through LDS tiles
     int64_t k0;          // centre of the frequency support
     int64_t kmax;        // support is k = 1..kmax
     int64_t grid_off;    // complex offset of the band's q grids (column-major, n each)
@@ -125,6 +123,15 @@ struct NodeItem {
     int32_t band;
     int32_t count;
     int64_t start;
+};
+
+// Work item of the adjoint's grid side: 256 >> log2tpc consecutive cells of a
+// band, each summed by a group of 2^log2tpc threads.
+struct CellItem {
+    int32_t band;
+    int32_t cell0;
+    int32_t log2tpc;
+    int32_t pad;
 };
 
 // Work item of the direct-sum kernels: a run of the direct-node list and a chunk of k.

@@ -73,20 +73,12 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_adj_prep(PlanView<T> pv, con
 }
 
 template <typename T, int MW>
-__global__ __launch_bounds__(GATHER_THREADS) void k_adj_owner(PlanView<T> pv, const FftItem* items, int qs,
+__global__ __launch_bounds__(GATHER_THREADS) void k_adj_cells(PlanView<T> pv, const CellItem* items, int qs,
                                                               const cplx<T>* U, const T* Phi, const int32_t* L0,
                                                               const int32_t* cstart, cplx<T>* grids)
 {
-    body_adj_owner<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, cstart, grids);
-}
-
-template <typename T, int MW>
-__global__ __launch_bounds__(GATHER_THREADS) void k_adj_tiles(PlanView<T> pv, const NodeItem* items, int qs,
-                                                              const cplx<T>* U, const T* Phi, const int32_t* L0,
-                                                              cplx<T>* grids)
-{
-    __shared__ T tile[2 * TILE_CELLS];
-    body_adj_tiles<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, grids, tile);
+    __shared__ T red[2 * ADJ_RC * GATHER_THREADS];
+    body_adj_cells<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, cstart, grids, red);
 }
 
 template <typename T>
@@ -109,8 +101,8 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, const FftItem* items,
-                                                              const cplx<T>* scratch, double* acc)
+__device__ __forceinline__ void passA_adj_kernel(const PlanView<T>& pv, const FftItem* items, const cplx<T>* scratch,
+                                                 double* acc)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ alignas(16) T lc[Sizes<T>::COEF];
@@ -118,6 +110,21 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj(PlanView<T> pv, co
     with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
         body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc);
     });
+}
+
+// FP32: held to four waves per SIMD (two workgroups per CU, as the LDS
+// allows); a few of the per-point column sums then live in scratch.  FP64
+// would spill far more and keeps the compiler's own choice.
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passA_adj_f32(
+    PlanView<float> pv, const FftItem* items, const cplx<float>* scratch, double* acc)
+{
+    passA_adj_kernel<float>(pv, items, scratch, acc);
+}
+
+__global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj_f64(PlanView<double> pv, const FftItem* items,
+                                                                  const cplx<double>* scratch, double* acc)
+{
+    passA_adj_kernel<double>(pv, items, scratch, acc);
 }
 
 template <typename T>
@@ -181,7 +188,9 @@ static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, c
                            scratch, basebuf, deriv);
     if (ev) (void)hipEventRecord(ev[2], st);
     if (L.n_passB)
-        hipLaunchKernelGGL((k_passB<T, +1>), dim3(std::min(L.n_passB, L.persist_blocks)), dim3(FFT_THREADS), 0, st,
+        hipLaunchKernelGGL((k_passB<T, +1>),
+                           dim3(passB_prefetch<T, +1>() ? std::min(L.n_passB, L.persist_blocks) : L.n_passB),
+                           dim3(FFT_THREADS), 0, st,
                            pv, L.passB, L.n_passB, (const cplx<T>*)scratch, grids);
     if (ev) (void)hipEventRecord(ev[3], st);
     return hipSuccess;
@@ -192,11 +201,18 @@ static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, c
                                      double* acc, hipStream_t st)
 {
     if (L.n_passB)
-        hipLaunchKernelGGL((k_passB<T, -1>), dim3(std::min(L.n_passB, L.persist_blocks)), dim3(FFT_THREADS), 0, st,
+        hipLaunchKernelGGL((k_passB<T, -1>),
+                           dim3(passB_prefetch<T, -1>() ? std::min(L.n_passB, L.persist_blocks) : L.n_passB),
+                           dim3(FFT_THREADS), 0, st,
                            pv, L.passB, L.n_passB, (const cplx<T>*)grids, scratch);
-    if (L.n_passA_adj)
-        hipLaunchKernelGGL(k_passA_adj<T>, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
-                           (const cplx<T>*)scratch, acc);
+    if (L.n_passA_adj) {
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL(k_passA_adj_f32, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
+                               (const cplx<T>*)scratch, acc);
+        else
+            hipLaunchKernelGGL(k_passA_adj_f64, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
+                               (const cplx<T>*)scratch, acc);
+    }
     if (L.n_onepass_adj)
         hipLaunchKernelGGL(k_onepass_adj<T>, dim3(L.n_onepass_adj), dim3(FFT_THREADS), 0, st, pv, L.onepass_adj,
                            (const cplx<T>*)grids, acc);
@@ -221,12 +237,9 @@ static void mw_adjoint_nodes(const DevLists& L, const PlanView<T>& pv, const WsL
     if (L.n_nfft_nodes)
         hipLaunchKernelGGL((k_adj_prep<T, MW>), dim3(L.n_nfft_nodes), dim3(GATHER_THREADS), 0, st, pv,
                            L.nfft_nodes, g, W.qs, U, Phi, L0);
-    if (L.n_owner)
-        hipLaunchKernelGGL((k_adj_owner<T, MW>), dim3(L.n_owner), dim3(GATHER_THREADS), 0, st, pv, L.owner, W.qs,
+    if (L.n_cells)
+        hipLaunchKernelGGL((k_adj_cells<T, MW>), dim3(L.n_cells), dim3(GATHER_THREADS), 0, st, pv, L.cells, W.qs,
                            (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, L.cstart, grids);
-    if (L.n_tile_items)
-        hipLaunchKernelGGL((k_adj_tiles<T, MW>), dim3(L.n_tile_items), dim3(GATHER_THREADS), 0, st, pv,
-                           L.tile_items, W.qs, (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, grids);
 }
 
 template <typename T>

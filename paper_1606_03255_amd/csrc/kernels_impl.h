@@ -478,12 +478,27 @@ template <typename T, int LOG2N2> struct PassBGeo {
     FLT_HD static int col(int ch, int r) { return ((ch >> log2n2) << log2V) + (r & (V - 1)); }
 };
 
+// A pass-B tile held in registers, tile_items<T>() values per thread: complex
+// pairs for FP32, separate real and imaginary parts for FP64 (the form the
+// compiler keeps in registers rather than in scratch memory).
+template <typename T> struct TileRegs;
+template <> struct TileRegs<float> {
+    cplx<float> v[tile_items<float>()];
+    FLT_HD void set(int r, cplx<float> x) { v[r] = x; }
+    FLT_HD cplx<float> get(int r) const { return v[r]; }
+};
+template <> struct TileRegs<double> {
+    double re[tile_items<double>()], im[tile_items<double>()];
+    FLT_HD void set(int r, cplx<double> x) { re[r] = x.x; im[r] = x.y; }
+    FLT_HD cplx<double> get(int r) const { return mk(re[r], im[r]); }
+};
+
 // Load item `it`'s tile into the registers v; for the adjoint direction (ADJ:
 // grid -> scratch) also the mask bits of each run of V elements (bits[m] for
 // run m, bit u for its element u), applied when the tile goes to LDS.
 template <class Ctx, typename T, int LOG2N2, bool ADJ>
 FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it, const cplx<T>* src_base,
-                        cplx<T>* v, uint32_t* bits)
+                        TileRegs<T>& v, uint32_t* bits)
 {
     using G = PassBGeo<T, LOG2N2>;
     const BandDesc& B = pv.bands[it.band];
@@ -494,24 +509,30 @@ FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it
         const int ch = ctx.tid() + m * FFT_THREADS;
         const int p0 = (G::row(ch) << G::log2B) + G::col(ch, 0);   // multiple of V: one mask word
         if (ADJ) bits[m] = mask[p0 >> 5] >> (p0 & 31);
-        for (int u = 0; u < G::V; ++u) v[m * G::V + u] = src[p0 + u];
+        for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, src[p0 + u]);
     }
 }
 
+// Whether the pass-B variant prefetches the next tile during the current
+// FFT: the FP32 forward, the one whose registers hold the extra tile within
+// four waves per SIMD.  The others are launched one workgroup per item.
+template <typename T, int SIGN> constexpr bool passB_prefetch() { return sizeof(T) == 4 && SIGN > 0; }
+
 // Pass-B items of one transform length, as long as the workgroup's next item
-// has that length: each tile is in the registers v before its FFT, and the
-// next item's tile is fetched into v right after v went to LDS, so its loads
-// are in flight while this tile is transformed.  Returns the index of the
-// workgroup's first item not processed.
+// has that length: each tile is in the registers (vr, vi) before its FFT; with
+// prefetch the next item's tile is fetched right after this one went to LDS,
+// so its loads are in flight while this tile is transformed.  Returns the
+// index of the workgroup's first item not processed.
 template <class Ctx, typename T, int LOG2N2, int SIGN>
 FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* items, int i, int nitems, int nblocks,
                      const cplx<T>* src_base, cplx<T>* dst_base, cplx<T>* lds)
 {
     constexpr bool ADJ = SIGN < 0;
+    constexpr bool PREFETCH = passB_prefetch<T, SIGN>();
     using G = PassBGeo<T, LOG2N2>;
     constexpr int CHUNKS = tile_points<T>() / G::V;
     constexpr int RUNS = tile_items<T>() / G::V;
-    cplx<T> v[tile_items<T>()];
+    TileRegs<T> v;
     uint32_t bits[RUNS];
     passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, v, bits);
     for (;;) {
@@ -521,12 +542,12 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
         for (int r = 0; r < tile_items<T>(); ++r) {
             const int ch = G::ch(ctx.tid(), r);
             const bool keep = !ADJ || ((bits[r / G::V] >> (r % G::V)) & 1u);
-            lds[lds_at((G::col(ch, r) << LOG2N2) + G::row(ch))] = keep ? v[r] : mk<T>(0, 0);
+            lds[lds_at((G::col(ch, r) << LOG2N2) + G::row(ch))] = keep ? v.get(r) : mk<T>(0, 0);
         }
         ctx.sync();
         const int nx = i + nblocks;
         const bool more = nx < nitems && pv.bands[items[nx].band].log2n2 == LOG2N2;
-        if (more) passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, v, bits);
+        if (PREFETCH && more) passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, v, bits);
         lds_fft_ct<IterCtx<Ctx>, T, LOG2N2, (1 << G::log2B), SIGN>(ctx, lds, pv.tw_stage);
         const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
         cplx<T>* dst = dst_base + (ADJ ? B.scratch_off : B.grid_off) + blk_off;
@@ -541,7 +562,7 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
         }
         ctx.sync();
         i = nx;
-        if (!more) return i;
+        if (!PREFETCH || !more) return i;
     }
 }
 
@@ -553,6 +574,14 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
 {
     using RG = Log2Range<T>;
     int i = ctx.bid();
+    if constexpr (!passB_prefetch<T, SIGN>()) {   // one item per workgroup (nblocks = nitems)
+        if (i < nitems)
+            with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
+                passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nitems, src_base, dst_base,
+                                                             lds);
+            });
+        return;
+    }
     while (i < nitems) {
         with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
             i = passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nblocks, src_base, dst_base,
@@ -693,93 +722,91 @@ FLT_HD void body_adj_prep(const Ctx& ctx, const PlanView<T>& pv, const NodeItem*
     }
 }
 
-// Adjoint a7, grid side (owner computes, no atomics): cell l of each column of
-// band B receives sum_j u_j^s phi(n x_j - l) over the nodes whose window
-// covers l.  Nodes are sorted by cell l0 = floor(n x), and l is covered iff
-// l0 lies in [l - mw, l + mw) (mod n), so the contributors form at most two
-// runs of the sorted order, found in the band's cell-start table.
+// Adjoint a7, grid side (no atomics): cell l of each column of band B
+// receives sum_j u_j^s phi(n x_j - l) over the nodes whose window covers l.
+// Nodes are sorted by cell l0 = floor(n x), and l is covered iff l0 lies in
+// [l - mw, l + mw) (mod n), so the contributors form at most two runs of the
+// sorted order, found in the band's cell-start table.  Each cell is summed by
+// a group of 2^log2tpc threads (sized by the band's node density) that split
+// its runs: every contributor's weight is read once per ADJ_QC columns, which
+// are summed in registers and reduced through LDS, ADJ_RC columns at a time.  Cells of two-pass bands that no window
+// reads are skipped (pass B loads only masked cells); one-pass bands get
+// every cell, zeros included.
+template <typename T> constexpr int ADJ_QC() { return sizeof(T) == 4 ? 12 : 8; }
+constexpr int ADJ_RC = 4;
+
 template <class Ctx, typename T, int MW>
-FLT_HD void body_adj_owner(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items, int qs,
+FLT_HD void body_adj_cells(const Ctx& ctx, const PlanView<T>& pv, const CellItem* items, int qs,
                            const cplx<T>* U, const T* Phi, const int32_t* L0, const int32_t* cstart,
-                           cplx<T>* grids)
+                           cplx<T>* grids, T* red)
 {
-    const FftItem it = items[ctx.bid()];
+    const CellItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int64_t n = (int64_t)1 << B.log2n;
-    const int64_t l = (int64_t)it.blk * ctx.ntid() + ctx.tid();
-    if (l >= n) return;
-    const int64_t addr = grid_addr(B, l);
-    // a two-pass band's pass B loads only masked cells: the others stay untouched
-    if (B.log2n2 > 0 && !((pv.mask[B.mask_off + (addr >> 5)] >> (addr & 31)) & 1u)) return;
-    if (B.tiles) {                               // densely filled band: cleared here, filled by body_adj_tiles
-        cplx<T>* g = grids + B.grid_off;
-        for (int s = 0; s < B.q; ++s) g[((int64_t)s << B.log2n) + addr] = mk<T>(0, 0);
-        return;
+    const int n = 1 << B.log2n;
+    const int lt = it.log2tpc, tpc = 1 << lt;
+    const int tid = ctx.tid();
+    const int r = tid & (tpc - 1);
+    const int l = it.cell0 + (tid >> lt);
+    bool write = l < n;
+    int64_t addr = 0;
+    if (write) {
+        addr = grid_addr(B, l);
+        if (B.log2n2 > 0 && !((pv.mask[B.mask_off + (addr >> 5)] >> (addr & 31)) & 1u)) write = false;
     }
-    const int32_t* c0 = cstart + B.cs_off;       // c0[c]: first sorted node of the band with cell >= c
-    const int64_t a = l - MW, b = l + MW;
-    int32_t r0s, r0e, r1s = 0, r1e = 0;
-    if (a < 0) { r0s = c0[a + n]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b]; }
-    else if (b > n) { r0s = c0[a]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b - n]; }
-    else { r0s = c0[a]; r0e = c0[b]; }
-    cplx<T>* g = grids + B.grid_off;
-    for (int s = 0; s < B.q; ++s) {
-        T ar = 0, ai = 0;
+    int32_t r0s = 0, r0e = 0, r1s = 0, r1e = 0;
+    if (write) {
+        const int32_t* c0 = cstart + B.cs_off;   // c0[c]: first sorted node of the band with cell >= c
+        const int a = l - MW, b = l + MW;
+        if (a < 0) { r0s = c0[a + n]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b]; }
+        else if (b > n) { r0s = c0[a]; r0e = c0[n]; r1s = c0[0]; r1e = c0[b - n]; }
+        else { r0s = c0[a]; r0e = c0[b]; }
+    }
+    cplx<T> * const g = grids + B.grid_off;
+    for (int s0 = 0; s0 < B.q; s0 += ADJ_QC<T>()) {
+        constexpr int QC = ADJ_QC<T>(), RC = ADJ_RC;
+        T ar[QC], ai[QC];
+        for (int c = 0; c < QC; ++c) ar[c] = ai[c] = 0;
         for (int run = 0; run < 2; ++run) {
             const int32_t js = run ? r1s : r0s, je = run ? r1e : r0e;
-            for (int32_t j = js; j < je; ++j) {
-                int64_t t = l - (int64_t)L0[j] + (MW - 1);   // tap index of l in node j's window
+            for (int32_t j = js + r; j < je; j += tpc) {
+                int t = l - L0[j] + (MW - 1);   // tap index of l in node j's window
                 if (t < 0) t += n;
                 if (t >= n) t -= n;
                 const T w = Phi[(int64_t)j * (2 * MW) + t];
-                const cplx<T> u = U[(int64_t)j * qs + s];
-                ar += u.x * w;
-                ai += u.y * w;
+                const cplx<T>* u = U + (int64_t)j * qs + s0;
+                for (int c = 0; c < QC; ++c)
+                    if (s0 + c < B.q) {
+                        const cplx<T> uv = u[c];
+                        ar[c] += uv.x * w;
+                        ai[c] += uv.y * w;
+                    }
             }
         }
-        g[((int64_t)s << B.log2n) + addr] = mk(ar, ai);
-    }
-}
-
-// Adjoint a7, grid side for densely filled bands: a chunk of consecutive
-// sorted nodes (cells l0_first..l0_last) accumulates u_j^s phi into an LDS
-// tile of the cells its windows cover, [l0_first - mw + 1, l0_last + mw],
-// which is then added to the band grid (zeroed by the owner kernel) with
-// global atomics, one column at a time.
-template <class Ctx, typename T, int MW>
-FLT_HD void body_adj_tiles(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items, int qs, const cplx<T>* U,
-                           const T* Phi, const int32_t* L0, cplx<T>* grids, T* tile)
-{
-    const NodeItem it = items[ctx.bid()];
-    const BandDesc& B = pv.bands[it.band];
-    const int64_t n = (int64_t)1 << B.log2n;
-    const int64_t l0a = L0[it.start];
-    const int64_t t0 = l0a - MW + 1;
-    const int span = (int)(L0[it.start + it.count - 1] - l0a) + 2 * MW;
-    T* g = (T*)(grids + B.grid_off);
-    for (int s = 0; s < B.q; ++s) {
-        for (int i = ctx.tid(); i < 2 * span; i += ctx.ntid()) tile[i] = T(0);
-        ctx.sync();
-        for (int64_t j = it.start + ctx.tid(); j < it.start + it.count; j += ctx.ntid()) {
-            const cplx<T> u = U[j * qs + s];
-            const int64_t base = (int64_t)L0[j] - MW + 1 - t0;
-            for (int t = 0; t < 2 * MW; ++t) {
-                const T w = Phi[j * (2 * MW) + t];
-                ctx.atomic_add(tile + 2 * (base + t), u.x * w);
-                ctx.atomic_add(tile + 2 * (base + t) + 1, u.y * w);
+        if (tpc > 1) {                           // uniform over the workgroup
+            for (int c0 = 0; c0 < QC; c0 += RC) {
+                for (int c = 0; c < RC; ++c) {
+                    red[2 * (tid * RC + c)] = ar[c0 + c];
+                    red[2 * (tid * RC + c) + 1] = ai[c0 + c];
+                }
+                ctx.sync();
+                for (int h = tpc >> 1; h > 0; h >>= 1) {
+                    if (r < h)
+                        for (int c = 0; c < RC; ++c) {
+                            red[2 * (tid * RC + c)] += red[2 * ((tid + h) * RC + c)];
+                            red[2 * (tid * RC + c) + 1] += red[2 * ((tid + h) * RC + c) + 1];
+                        }
+                    ctx.sync();
+                }
+                for (int c = 0; c < RC; ++c) {
+                    ar[c0 + c] = red[2 * (tid * RC + c)];
+                    ai[c0 + c] = red[2 * (tid * RC + c) + 1];
+                }
+                ctx.sync();
             }
         }
-        ctx.sync();
-        for (int i = ctx.tid(); i < span; i += ctx.ntid()) {
-            const T vr = tile[2 * i], vi = tile[2 * i + 1];
-            if (vr == T(0) && vi == T(0)) continue;
-            int64_t l = t0 + i;
-            l = ((l % n) + n) % n;
-            const int64_t a = ((int64_t)s << B.log2n) + grid_addr(B, l);
-            ctx.atomic_add(g + 2 * a, vr);
-            ctx.atomic_add(g + 2 * a + 1, vi);
-        }
-        ctx.sync();
+        if (write && r == 0)
+            for (int c = 0; c < QC; ++c)
+                if (s0 + c < B.q) g[((int64_t)(s0 + c) << B.log2n) + addr] = mk(ar[c], ai[c]);
     }
 }
 

@@ -15,10 +15,9 @@ struct DevLists {
     const FftItem* passB = nullptr;
     const FftItem* onepass_adj = nullptr;
     const FftItem* passA_adj = nullptr;
-    const FftItem* owner = nullptr;
+    const CellItem* cells = nullptr;
     const NodeItem* nodes = nullptr;
     const NodeItem* nfft_nodes = nullptr;
-    const NodeItem* tile_items = nullptr;
     const DirectItem* direct_fwd = nullptr;
     const DirectItem* direct_adj = nullptr;
     const int32_t* dlist = nullptr;
@@ -26,8 +25,8 @@ struct DevLists {
     const SumItem* sum_items = nullptr;
     int n_sum = 0;
     int persist_blocks = 512;   // workgroups of the persistent FFT kernels (two per compute unit)
-    int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_owner = 0;
-    int n_nodes = 0, n_nfft_nodes = 0, n_tile_items = 0, n_direct_fwd = 0, n_direct_adj = 0;
+    int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_cells = 0;
+    int n_nodes = 0, n_nfft_nodes = 0, n_direct_fwd = 0, n_direct_adj = 0;
     int64_t n_dlist = 0;
     // host copies of the FFT launch groups (one kernel instance per transform length)
     std::vector<LaunchGroup> g_onepass_fwd, g_passA_fwd, g_passB, g_onepass_adj, g_passA_adj;

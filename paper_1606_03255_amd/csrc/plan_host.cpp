@@ -300,20 +300,14 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
                 hp.cstart.push_back((int32_t)jn);
             }
         }
-        const int nOwn = (int)((n + GATHER_THREADS - 1) / GATHER_THREADS);
-        for (int k = 0; k < nOwn; ++k) hp.owner.push_back(FftItem{b, 0, 0, k});
-        // densely filled bands (more than 2 nodes per cell) spread through LDS tiles:
-        // chunks of sorted nodes whose windows span at most TILE_CELLS cells
-        if (B.node_count > 2 * n) {
-            B.tiles = 1;
-            const int64_t end = B.node_start + B.node_count;
-            int64_t a = B.node_start;
-            while (a < end) {
-                int64_t e = a + 1;
-                while (e < end && e - a < TILE_NODES && cell[idx[e]] - cell[idx[a]] + 2 * hp.mw <= TILE_CELLS) ++e;
-                hp.tile_items.push_back(NodeItem{b, (int32_t)(e - a), a});
-                a = e;
-            }
+        // adjoint grid side: groups of 2^lt threads per cell, sized so that a
+        // thread handles about CELL_TARGET of the cell's ~2 mw nodes/n x n contributions
+        {
+            const double contrib = 2.0 * hp.mw * (double)B.node_count / (double)n;
+            int lt = 0;
+            while (lt < 8 && (double)(1 << lt) * CELL_TARGET < contrib) ++lt;
+            const int per = GATHER_THREADS >> lt;
+            for (int64_t c0 = 0; c0 < n; c0 += per) hp.cells.push_back(CellItem{b, (int32_t)c0, lt, 0});
         }
         // cells some node's window reads: [l0 - mw + 1, l0 + mw] (mod n) around
         // each node's cell l0 = floor(n x); a two-pass band keeps them as a bit
@@ -543,13 +537,12 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
         shift_fft(out.passB, p.passB);
         shift_fft(out.onepass_adj, p.onepass_adj);
         shift_fft(out.passA_adj, p.passA_adj);
-        shift_fft(out.owner, p.owner);
+        for (CellItem it : p.cells) { it.band += bo; out.cells.push_back(it); }
         auto shift_nodes = [&](std::vector<NodeItem>& dst, const std::vector<NodeItem>& src) {
             for (NodeItem it : src) { it.band += bo; it.start += no; dst.push_back(it); }
         };
         shift_nodes(out.nodes, p.nodes);
         shift_nodes(out.nfft_nodes, p.nfft_nodes);
-        shift_nodes(out.tile_items, p.tile_items);
         for (int32_t v : p.dlist) out.dlist.push_back((int32_t)(v + no));
         for (DirectItem it : p.direct_fwd) { it.first += (int32_t)dlo; it.inst = i; out.direct_fwd.push_back(it); }
         for (DirectItem it : p.direct_adj) { it.first += (int32_t)dlo; it.inst = i; out.direct_adj.push_back(it); }

@@ -36,12 +36,12 @@ struct HostPlan {
     uint32_t flags = 0;
 
     // work lists
-    std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj, owner;
+    std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj;
+    std::vector<CellItem> cells;        // adjoint grid side: cell groups of the NFFT bands
     // FFT item lists are sorted by transform length; one group per length
     std::vector<LaunchGroup> g_onepass_fwd, g_passA_fwd, g_passB, g_onepass_adj, g_passA_adj;
     std::vector<NodeItem> nodes;        // gather: NFFT bands and the constant band
     std::vector<NodeItem> nfft_nodes;   // adjoint node side: NFFT bands only
-    std::vector<NodeItem> tile_items;   // adjoint LDS-tile chunks of densely filled bands
     std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands
     std::vector<DirectItem> direct_fwd, direct_adj;
     std::vector<int32_t> cstart;        // per NFFT band: first sorted node with cell >= c, c = 0..n
