@@ -138,6 +138,34 @@ def cpu_baseline(w, f32, f64, plan_bands, target_s=12.0):
                       "FP64 direct sum, %.1f s" % (S, M, len(c), dt)}, E32, E64, int(len(allsel))
 
 
+def batched_leg(torch, dev, args, tune, log):
+    """512 independent instances (N_i, M_i log-uniform in [2^8, 2^16], FP32 form,
+    eps 1e-6) in one batched plan: forward per step, eager and graph-replayed."""
+    import numpy as np
+
+    from paper_1606_03255_amd import Plan, inputs
+    w = inputs.workload("batched")
+    zs = [z for _, z in w["instances"]]
+    c = torch.from_numpy(np.concatenate([ci for ci, _ in w["instances"]])).to(dev)
+    t = time.perf_counter()
+    pe = Plan.batch(w["N"], zs, 1e-6, torch.complex64, device=dev, autotune=tune)
+    plan_ms = (time.perf_counter() - t) * 1e3
+    pg = Plan.batch(w["N"], zs, 1e-6, torch.complex64, device=dev, graph=True, autotune=tune)
+    f = torch.empty(pe.M, dtype=torch.complex64, device=dev)
+    steps = max(5, args.steps)
+    ms_e, _ = time_steps(torch, lambda: pe.forward(c, out=f), steps, args.warmup)
+    ms_g, _ = time_steps(torch, lambda: pg.forward(c, out=f), steps, args.warmup)
+    M = pe.M
+    rec = {"instances": int(w["count"]), "sum_N": int(pe.N), "sum_M": int(M), "eps": 1e-6,
+           "ms_forward_eager": round(ms_e, 4), "ms_forward_graph": round(ms_g, 4),
+           "node_evals_per_s_graph": M / (ms_g * 1e-3), "plan_ms": round(plan_ms, 1),
+           "direct_scale": pe.info()["direct_scale"]}
+    log("batched: %d instances, forward eager %.3f ms, graph %.3f ms" % (rec["instances"], ms_e, ms_g))
+    pe.close()
+    pg.close()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -145,6 +173,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forward-only", action="store_true", help="skip the fwd+bwd and FP64 legs")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="plans with the default band policy instead of the timed choice")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched leg")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size reference "
                          "for HBM counter readings)")
@@ -173,7 +204,8 @@ def main():
     w = inputs.workload("large")
     N, M = w["N"], w["M"]
     t = time.perf_counter()
-    p32 = Plan(N, w["z"], 1e-6, torch.complex64, device=dev)
+    tune = not args.no_autotune
+    p32 = Plan(N, w["z"], 1e-6, torch.complex64, device=dev, autotune=tune)
     plan32_ms = (time.perf_counter() - t) * 1e3
     log("FP32 plan built in %.0f ms" % plan32_ms)
     c32 = torch.from_numpy(w["c"]).to(dev)
@@ -212,7 +244,7 @@ def main():
             p32.adjoint(g32)
             p32.derivative(c32)
         ms32, _ = time_steps(torch, step32, max(3, args.steps // 2), 1)
-        p64 = Plan(N, w["z"], 1e-11, torch.complex128, device=dev)
+        p64 = Plan(N, w["z"], 1e-11, torch.complex128, device=dev, autotune=tune)
         c64 = c32.to(torch.complex128)
         g64 = g32.to(torch.complex128)
         f64_out = torch.empty(M, dtype=torch.complex128, device=dev)
@@ -228,6 +260,10 @@ def main():
         fwd_bwd = {"ms_fp32_form": round(ms32, 4), "ms_fp64_path": round(ms64, 4),
                    "speedup": round(ms64 / ms32, 3), "ms_fp64_forward": round(ms64_fwd, 4)}
         log("fwd+bwd FP32 %.3f ms, FP64 %.3f ms, speedup %.2f" % (ms32, ms64, ms64 / ms32))
+
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(torch, dev, args, tune, log)
 
     cpu = None
     E32 = None
@@ -252,6 +288,8 @@ def main():
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_bytes": sb,
         "plan_ms": round(plan32_ms, 1),
+        "direct_scale": info["direct_scale"],
+        "batched": batched,
         "bytes_forward_model": info["bytes_forward"],
         "wall_s_timed": round(wall, 3),
     }

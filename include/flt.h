@@ -53,6 +53,11 @@ typedef struct flt_plan flt_plan;
                                         cost more than summing its few nodes directly is summed exactly */
 #define FLT_FLAG_GRAPH     (1u << 2) /* capture each operation's launch sequence into a hipGraph on its first call
                                         (and again whenever the buffers or the workspace change) and replay it */
+#define FLT_FLAG_AUTOTUNE  (1u << 3) /* choose the band policy by timing: candidate plans (the direct-sum rate of
+                                        the policy scaled by 0, 1/2, 1, 2, 4; distinct band choices only) run
+                                        forward + adjoint on the device during creation and the fastest is kept;
+                                        the choice is cached per (dtype, eps, instances, size class) for the
+                                        process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
 
 /* return codes */
 #define FLT_OK            0
@@ -80,6 +85,7 @@ typedef struct flt_info {
     size_t workspace_bytes;  /* device workspace a transform call needs */
     double bytes_forward;    /* algorithmic HBM bytes of one forward call */
     double flops_forward;    /* algorithmic flops of one forward call */
+    double direct_scale;     /* factor on the direct-sum rate the band policy used (1, or the tuned choice) */
 } flt_info;
 
 /* One occupied band (Def. 3.2 Y_m, or Y_D). */

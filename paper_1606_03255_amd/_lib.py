@@ -14,6 +14,7 @@ FLT_C128 = 2
 FLT_FLAG_HOST_ONLY = 1
 FLT_FLAG_NFFT_ONLY = 2
 FLT_FLAG_GRAPH = 4
+FLT_FLAG_AUTOTUNE = 8
 
 ERRORS = {
     0: "FLT_OK", -1: "FLT_EINVAL", -2: "FLT_EDOMAIN", -3: "FLT_EPRECISION", -4: "FLT_ENOWORKSPACE",
@@ -35,7 +36,7 @@ class FltInfo(ctypes.Structure):
         ("mw", ctypes.c_int32), ("num_bands", ctypes.c_int32),
         ("eps", ctypes.c_double), ("eps_K", ctypes.c_double), ("eps_A", ctypes.c_double),
         ("y1", ctypes.c_double), ("nodes_z0", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
-        ("bytes_forward", ctypes.c_double), ("flops_forward", ctypes.c_double),
+        ("bytes_forward", ctypes.c_double), ("flops_forward", ctypes.c_double), ("direct_scale", ctypes.c_double),
     ]
 
 

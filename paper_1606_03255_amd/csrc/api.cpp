@@ -2,7 +2,10 @@
 #include <hip/hip_runtime_api.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "flt.h"
@@ -160,18 +163,139 @@ static int upload(flt_plan* p)
     return FLT_OK;
 }
 
-static const uint32_t KNOWN_FLAGS = FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY | FLT_FLAG_GRAPH;
+static const uint32_t KNOWN_FLAGS = FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY | FLT_FLAG_GRAPH | FLT_FLAG_AUTOTUNE;
+
+static void release(flt_plan* p);
+static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, hipStream_t st);
+
+// FLT_FLAG_AUTOTUNE: the band policy's direct-sum rate factor chosen by timing
+// forward + adjoint of candidate plans, cached per (dtype, eps, instances,
+// size class of sum N and sum M) for the life of the process.
+namespace {
+const double TUNE_SCALES[] = {0.0, 0.5, 1.0, 2.0, 4.0};
+using TuneKey = std::tuple<int, double, int64_t, int, int>;
+std::map<TuneKey, double> g_tuned;
+std::mutex g_tune_mu;
+
+int size_class(int64_t v)
+{
+    int r = 0;
+    while (((int64_t)1 << r) < v) ++r;
+    return r;
+}
+
+// Mean time (ms) of forward + adjoint of an uploaded candidate, on buffers and
+// a workspace of its own; FLT_OK or an error code.
+int time_candidate(flt_plan* p, double* ms)
+{
+    const HostPlan& hp = p->hp;
+    const size_t S = hp.elem_bytes();
+    void *ws = nullptr, *c = nullptr, *f = nullptr, *g = nullptr, *h = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMalloc(&ws, hp.ws_bytes);
+    if (e == hipSuccess) e = hipMalloc(&c, (size_t)hp.N * S);
+    if (e == hipSuccess) e = hipMalloc(&h, (size_t)hp.N * S);
+    if (e == hipSuccess) e = hipMalloc(&f, (size_t)hp.M * S);
+    if (e == hipSuccess) e = hipMalloc(&g, (size_t)hp.M * S);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMemsetAsync(c, 0, (size_t)hp.N * S, st);
+    if (e == hipSuccess) e = hipMemsetAsync(g, 0, (size_t)hp.M * S, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) {
+        p->ws = (char*)ws;
+        p->ws_bytes = hp.ws_bytes;
+        const int reps = 3;
+        e = enqueue(p, 0, c, f, st);                       // warm-up
+        if (e == hipSuccess) e = enqueue(p, 2, g, h, st);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            e = enqueue(p, 0, c, f, st);
+            if (e == hipSuccess) e = enqueue(p, 2, g, h, st);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        *ms = t / reps;
+        p->ws = nullptr;
+        p->ws_bytes = 0;
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    for (void* q : {ws, c, f, g, h})
+        if (q) (void)hipFree(q);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+}  // namespace
+
+template <class Build> static int tuned_scale(uint32_t flags, Build&& build, double* scale)
+{
+    HostPlan probe;
+    int rc = build(probe, 1.0);
+    if (rc != FLT_OK) return rc;
+    const TuneKey key{probe.dtype, probe.eps, (int64_t)probe.inst.size(), size_class(probe.N), size_class(probe.M)};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            *scale = it->second;
+            return FLT_OK;
+        }
+    }
+    std::vector<std::vector<int>> seen;
+    double best = 1e300;
+    *scale = 1.0;
+    for (double sc : TUNE_SCALES) {
+        flt_plan* cand = new (std::nothrow) flt_plan();
+        if (!cand) return FLT_ENOMEM;
+        rc = build(cand->hp, sc);
+        std::vector<int> sig;
+        for (const BandDesc& B : cand->hp.bands) sig.push_back(B.direct);
+        bool dup = false;
+        for (const auto& v : seen) dup = dup || v == sig;
+        if (rc == FLT_OK && !dup) {
+            seen.push_back(sig);
+            cand->host_only = false;
+            rc = upload(cand);
+            double ms = 0;
+            if (rc == FLT_OK) rc = time_candidate(cand, &ms);
+            if (rc == FLT_OK && ms < best) {
+                best = ms;
+                *scale = sc;
+            }
+        }
+        release(cand);
+        if (rc != FLT_OK) return rc;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = *scale;
+    return FLT_OK;
+}
 
 template <class Build> static int create(flt_plan** out, uint32_t flags, Build&& build)
 {
     if (!out) return FLT_EINVAL;
     *out = nullptr;
     if (flags & ~KNOWN_FLAGS) return FLT_EINVAL;
+    double scale = 1.0;
+    if ((flags & FLT_FLAG_AUTOTUNE) && !(flags & (FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY))) {
+        int rc;
+        try {
+            rc = tuned_scale(flags, build, &scale);
+        } catch (const std::bad_alloc&) {
+            rc = FLT_ENOMEM;
+        }
+        if (rc != FLT_OK) return rc;
+    }
     flt_plan* p = new (std::nothrow) flt_plan();
     if (!p) return FLT_ENOMEM;
     int rc;
     try {
-        rc = build(p->hp);
+        rc = build(p->hp, scale);
     } catch (const std::bad_alloc&) {
         rc = FLT_ENOMEM;
     }
@@ -184,27 +308,14 @@ template <class Build> static int create(flt_plan** out, uint32_t flags, Build&&
         }
     }
     if (rc != FLT_OK) {
-        flt_plan_destroy(p);
+        release(p);
         return rc;
     }
     *out = p;
     return FLT_OK;
 }
 
-extern "C" {
-
-int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
-{
-    return create(out, flags, [&](HostPlan& hp) { return build_host_plan(hp, N, M, z, eps, dtype, flags); });
-}
-
-int flt_plan_create_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M, const double* z,
-                          double eps, int dtype, uint32_t flags)
-{
-    return create(out, flags, [&](HostPlan& hp) { return build_batch_plan(hp, count, N, M, z, eps, dtype, flags); });
-}
-
-void flt_plan_destroy(flt_plan* p)
+static void release(flt_plan* p)
 {
     if (!p) return;
     for (GraphSlot& g : p->graphs)
@@ -213,6 +324,25 @@ void flt_plan_destroy(flt_plan* p)
     if (p->dev) (void)hipFree(p->dev);
     delete p;
 }
+
+extern "C" {
+
+int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+{
+    return create(out, flags, [&](HostPlan& hp, double scale) {
+        return build_host_plan(hp, N, M, z, eps, dtype, flags, scale);
+    });
+}
+
+int flt_plan_create_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M, const double* z,
+                          double eps, int dtype, uint32_t flags)
+{
+    return create(out, flags, [&](HostPlan& hp, double scale) {
+        return build_batch_plan(hp, count, N, M, z, eps, dtype, flags, scale);
+    });
+}
+
+void flt_plan_destroy(flt_plan* p) { release(p); }
 
 int flt_plan_info(const flt_plan* p, flt_info* o)
 {
@@ -237,6 +367,7 @@ int flt_plan_info(const flt_plan* p, flt_info* o)
     o->workspace_bytes = hp.ws_bytes;
     o->bytes_forward = hp.bytes_forward;
     o->flops_forward = hp.flops_forward;
+    o->direct_scale = hp.direct_scale;
     return FLT_OK;
 }
 

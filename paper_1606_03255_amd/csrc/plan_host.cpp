@@ -49,7 +49,8 @@ static const double POLICY_TERMS_PER_S_C64 = 2.0e12;
 static const double POLICY_TERMS_PER_S_C128 = 1.5e12;
 
 // One instance, everything but the launch groups and the workspace layout.
-static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags,
+                     double direct_scale)
 {
     if (!z || N < 1 || M < 1 || (dtype != FLT_C64 && dtype != FLT_C128)) return FLT_EINVAL;
     if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
@@ -63,6 +64,7 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
 
     hp = HostPlan();
     hp.flags = flags;
+    hp.direct_scale = direct_scale;
     hp.N = N;
     hp.M = M;
     hp.dtype = dtype;
@@ -159,10 +161,12 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
     // ---- per-band choice: NFFT (Alg. 2) or the exact direct sum for sparsely filled bands
     {
         const double S = dtype == FLT_C64 ? 8.0 : 16.0;
-        const double rate = dtype == FLT_C64 ? POLICY_TERMS_PER_S_C64 : POLICY_TERMS_PER_S_C128;
+        // direct_scale: factor on the assumed direct-sum rate (a tuned plan's
+        // choice among candidates; 0 keeps every band on the NFFT path)
+        const double rate = (dtype == FLT_C64 ? POLICY_TERMS_PER_S_C64 : POLICY_TERMS_PER_S_C128) * direct_scale;
         for (int b = 0; b < nb; ++b) {
             BandDesc& B = hp.bands[b];
-            if (B.q == 0 || (flags & FLT_FLAG_NFFT_ONLY)) continue;
+            if (B.q == 0 || (flags & FLT_FLAG_NFFT_ONLY) || !(direct_scale > 0.0)) continue;
             const double n = ldexp(1.0, B.log2n);
             const double passes = B.log2n > LOG2P ? 4.0 : 2.0;
             const double t_nfft = (passes * B.q * n * S + (double)B.kmax * S) / POLICY_HBM_BYTES_PER_S;
@@ -444,16 +448,17 @@ static void finish(HostPlan& hp)
     hp.ws_bytes = al(hp.off_base + (size_t)hp.base_elems * S);
 }
 
-int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
+int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags,
+                    double direct_scale)
 {
-    const int rc = build_one(hp, N, M, z, eps, dtype, flags);
+    const int rc = build_one(hp, N, M, z, eps, dtype, flags, direct_scale);
     if (rc != FLT_OK) return rc;
     finish(hp);
     return FLT_OK;
 }
 
 int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
-                     int dtype, uint32_t flags)
+                     int dtype, uint32_t flags, double direct_scale)
 {
     if (count < 1 || !N || !M || !z) return FLT_EINVAL;
     out = HostPlan();
@@ -462,7 +467,7 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
     std::map<int, int> ycheb_at;                  // m (or -D for Y_D) -> pair offset in the merged ycheb table
     for (int32_t i = 0; i < count; ++i) {
         HostPlan p;
-        const int rc = build_one(p, N[i], M[i], z + 2 * zoff, eps, dtype, flags);
+        const int rc = build_one(p, N[i], M[i], z + 2 * zoff, eps, dtype, flags, direct_scale);
         if (rc != FLT_OK) return rc;
         zoff += M[i];
         if (i == 0) {
@@ -475,6 +480,7 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
             out.mw = p.mw;
             out.kb_b = p.kb_b;
             out.flags = p.flags;
+            out.direct_scale = p.direct_scale;
             out.tw_stage = p.tw_stage;
             out.tw_lo = p.tw_lo;
             out.tw_hi = p.tw_hi;

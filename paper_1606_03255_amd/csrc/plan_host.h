@@ -34,6 +34,7 @@ struct HostPlan {
     std::vector<double> tw_stage, tw_lo, tw_hi;   // interleaved complex
 
     uint32_t flags = 0;
+    double direct_scale = 1.0;          // factor on the direct-sum rate of the band policy
 
     // work lists
     std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj;
@@ -64,7 +65,7 @@ struct HostPlan {
 
 // Returns FLT_OK or a negative FLT_E* code (see flt.h).
 int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype,
-                    uint32_t flags = 0);
+                    uint32_t flags = 0, double direct_scale = 1.0);
 
 // One plan for `count` independent instances (N[i] coefficients, M[i] nodes,
 // z packed instance after instance): the members' bands, nodes and work lists
@@ -72,7 +73,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
 // packed c (and adjoint output) holds instance i at sum_{i' < i} N[i'], the
 // packed f (and adjoint input) at sum_{i' < i} M[i'].
 int build_batch_plan(HostPlan& hp, int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
-                     int dtype, uint32_t flags = 0);
+                     int dtype, uint32_t flags = 0, double direct_scale = 1.0);
 
 // Modified Bessel function I_0 by its power series (host, FP64).
 double bessel_i0(double x);

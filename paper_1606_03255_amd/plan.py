@@ -50,13 +50,15 @@ class Plan:
     every band on Algorithm 2's NFFT path; by default bands with few nodes and
     large grids are summed directly (exactly).  ``graph=True`` captures each
     operation's launch sequence into a hipGraph on first use and replays it.
+    ``autotune=True`` chooses the band policy by timing candidate plans on the
+    device (cached per size class for the process).
 
     ``Plan.batch`` builds one plan for many independent instances; its
     transforms act on packed arrays (instance after instance).
     """
 
     def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False, nfft_only=False, graph=False,
-                 _sizes=None):
+                 autotune=False, _sizes=None):
         self._lib = L.load()
         self._ptr = ctypes.c_void_p()
         zh = _as_host_z(z)
@@ -71,7 +73,7 @@ class Plan:
         self.dtype_code = _dtype_code(dtype)
         self.host_only = bool(host_only)
         flags = ((L.FLT_FLAG_HOST_ONLY if host_only else 0) | (L.FLT_FLAG_NFFT_ONLY if nfft_only else 0)
-                 | (L.FLT_FLAG_GRAPH if graph else 0))
+                 | (L.FLT_FLAG_GRAPH if graph else 0) | (L.FLT_FLAG_AUTOTUNE if autotune else 0))
         self._ws = None
         zp = zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         I64 = ctypes.POINTER(ctypes.c_int64)
@@ -103,7 +105,8 @@ class Plan:
                                                      self._ws.numel()), "flt_plan_set_workspace")
 
     @classmethod
-    def batch(cls, Ns, zs, eps, dtype="complex64", device=None, host_only=False, nfft_only=False, graph=False):
+    def batch(cls, Ns, zs, eps, dtype="complex64", device=None, host_only=False, nfft_only=False, graph=False,
+              autotune=False):
         """One plan for independent instances: instance i has Ns[i] coefficients
         and the nodes zs[i].  Coefficients, results and adjoint inputs are packed
         instance after instance (offsets in ``c_offsets`` / ``f_offsets``)."""
@@ -113,7 +116,7 @@ class Plan:
         if len(Ns) != len(Ms) or len(Ns) == 0:
             raise ValueError("need one coefficient count per node set, and at least one instance")
         z = np.concatenate(zl) if len(zl) > 1 else zl[0]
-        return cls(None, z, eps, dtype, device, host_only, nfft_only, graph, _sizes=(Ns, Ms))
+        return cls(None, z, eps, dtype, device, host_only, nfft_only, graph, autotune, _sizes=(Ns, Ms))
 
     @property
     def c_offsets(self):

@@ -181,3 +181,12 @@ def test_batched_errors():
                                      1e-6, 1, host) == -2
     assert lib.flt_plan_create_batch(ctypes.byref(ptr), 2, N.ctypes.data_as(I64), M.ctypes.data_as(I64), zp,
                                      1e-6, 1, 1 << 7) == -1
+
+
+def test_autotune_flag_on_host_only_plans_keeps_the_default_policy():
+    rng = np.random.default_rng(4)
+    z = inputs.nodes_disk(rng, 500)
+    p = flt.Plan(3000, z, 1e-6, "complex64", host_only=True, autotune=True)
+    q = flt.Plan(3000, z, 1e-6, "complex64", host_only=True)
+    assert p.info()["direct_scale"] == 1.0
+    assert p.bands() == q.bands()

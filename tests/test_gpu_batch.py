@@ -156,3 +156,25 @@ def test_batched_graph_replays(torch, batch):
         # equal up to the last bit of the FP32 rounding of FP64 sums (atomic order)
         assert float((f1 - f0).abs().max()) <= 2e-7 * float(f0.abs().max())
     gplan.close()
+
+
+def test_autotuned_plans(torch):
+    """A tuned plan picks one of the candidate policies, meets the bar, and a
+    second plan of the same size class reuses the cached choice."""
+    from paper_1606_03255_amd import Plan
+    rng = np.random.default_rng(12)
+    N, M = 70000, 3000
+    z = np.concatenate([inputs.nodes_annulus(rng, M // 2), inputs.nodes_disk(rng, M - M // 2)])
+    c = inputs.coefficients(rng, N).astype(np.complex64)
+    p = Plan(N, z, 1e-6, torch.complex64, autotune=True)
+    sc = p.info()["direct_scale"]
+    _say("tuned direct-rate factor", sc)
+    assert sc in (0.0, 0.5, 1.0, 2.0, 4.0)
+    f = p.forward(torch.from_numpy(c).to("cuda")).cpu().numpy().astype(np.complex128)
+    ci = c.astype(np.complex128)
+    assert np.abs(f - oracle.forward(ci, z)).max() <= 1e-6 * np.abs(ci).sum()
+    p.close()
+    z2 = inputs.nodes_disk(rng, M)
+    p2 = Plan(N, z2, 1e-6, torch.complex64, autotune=True)
+    assert p2.info()["direct_scale"] == sc
+    p2.close()
