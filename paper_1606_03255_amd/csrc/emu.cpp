@@ -153,9 +153,10 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 0);
             });
+            std::vector<cplx<T>> nw(DIRECT_NG);
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
                 body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, deriv, dacc.data(),
-                                            red.data());
+                                            red.data(), nw.data());
             });
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 1);
@@ -193,8 +194,10 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                                                                       grids.data(), acc.data(), lds.data(), lc.data());
                 });
             });
+        std::vector<cplx<T>> nw(DIRECT_ANG), ngv(DIRECT_ANG);
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
-            body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, acc.data());
+            body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, acc.data(), nw.data(),
+                                        ngv.data());
         });
         for (int64_t k = 0; k < hp.N; ++k) co[k] = mk<T>((T)acc[2 * k], (T)acc[2 * k + 1]);
         return FLT_OK;

@@ -44,10 +44,13 @@ constexpr int TW2_HALF = 11;              // lo/hi tables of 2^11 entries each
 constexpr int GATHER_THREADS = 256;       // nodes per gather/spread workgroup
 constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
 constexpr int MAX_MW = 10;                // largest window half-width supported
-constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread
+constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread and chunk (one anchor each)
 constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
-constexpr int DIRECT_ATPT = 8;            // direct adjoint: coefficients per thread
+// direct sum: most chunks of 256 * DIRECT_TPT terms per workgroup, by working type
+constexpr int direct_cpw(int dtype_bytes) { return dtype_bytes == 4 ? 4 : 1; }
 constexpr int DIRECT_ANG = 256;           // direct adjoint: nodes per workgroup
+// direct adjoint: consecutive coefficients per thread (one anchor each), by working type
+constexpr int direct_atpt(int dtype_bytes) { return dtype_bytes == 4 ? 32 : 16; }
 constexpr int SUMG_PER_THREAD = 16;       // sum of g: elements per thread
 constexpr int CELL_TARGET = 16;           // adjoint spread: contributions per thread a cell's group aims at
 
@@ -136,10 +139,11 @@ struct CellItem {
 
 // Work item of the direct-sum kernels: a run of the direct-node list and a chunk of k.
 struct DirectItem {
-    int32_t first;
-    int32_t count;
+    int32_t first;       // first entry of the run in the direct-node list
+    int16_t count;       // nodes in the run
+    int16_t nch;         // forward: chunks of 256 * DIRECT_TPT terms, from `chunk` on
     int32_t chunk;
-    int32_t inst;        // instance whose coefficients the chunk covers
+    int32_t inst;        // instance whose coefficients the chunks cover
 };
 
 // One instance of a plan (a single plan has one; a batched plan one per

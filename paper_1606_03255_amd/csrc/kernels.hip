@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void k_direct_fwd(PlanView<T> pv, const Direct
                                                     const cplx<T>* c, int deriv, double* dacc)
 {
     __shared__ double red[2 * DIRECT_NG * 256];
-    body_direct_fwd<DevCtx, T>(DevCtx(), pv, items, dlist, c, deriv, dacc, red);
+    __shared__ cplx<T> nw[DIRECT_NG];
+    body_direct_fwd<DevCtx, T>(DevCtx(), pv, items, dlist, c, deriv, dacc, red, nw);
 }
 
 template <typename T>
@@ -146,7 +147,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_direct_adj(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
                                                     const cplx<T>* g, double* acc)
 {
-    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, acc);
+    __shared__ cplx<T> nw[DIRECT_ANG], ng[DIRECT_ANG];
+    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, acc, nw, ng);
 }
 
 // Clear `n` 16-byte words (a fill kernel, so the sequence stays capturable).

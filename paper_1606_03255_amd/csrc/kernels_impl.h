@@ -847,51 +847,78 @@ FLT_HD void body_sum_g(const Ctx& ctx, const PlanView<T>& pv, const SumItem* ite
 // ---------------------------------------------------------------------------
 // Bands the plan evaluates by the direct sum (few nodes, large grids): the
 // exact f_j = sum_{k<N} c_k w_j^k.  Every thread takes DIRECT_TPT consecutive
-// terms from an anchor w^{k0} formed in FP64 (exact phase reduction of k0 x),
-// then the recurrence p <- p w in T; partial sums are combined in FP64.
+// terms from an anchor w^{k0}, then the recurrence p <- p w in T; partial sums
+// are combined in FP64.  A workgroup holds DIRECT_NG nodes (their w in LDS)
+// and up to direct_cpw chunks of terms, reduced once.
 // ---------------------------------------------------------------------------
+
+// w^k0 = e^{-k0 y} cis(sign 2 pi k0 x) with the phase reduced exactly in FP64
+// (frac_kx, |phase| <= pi); FP32 plans evaluate exp and sincos in FP32 on
+// the reduced arguments, FP64 plans in FP64.
+template <typename T>
+FLT_HD cplx<T> direct_anchor(double k0, double x, double y, double sign)
+{
+    const double r = frac_kx(k0, x);
+    if constexpr (sizeof(T) == 4) {
+        float sn, cs;
+        sincosf((float)(sign * 6.283185307179586476925286766559 * r), &sn, &cs);
+        const float mag = expf((float)(-k0 * y));
+        return mk(mag * cs, mag * sn);
+    } else {
+        double sn, cs;
+        sincos(sign * 6.283185307179586476925286766559 * r, &sn, &cs);
+        const double mag = exp(-k0 * y);
+        return mk(mag * cs, mag * sn);
+    }
+}
+
+// w = e^{-y} cis(sign 2 pi x) of sorted node j, in FP64, rounded to T.
+template <typename T> FLT_HD cplx<T> direct_w(const PlanView<T>& pv, int32_t j, double sign)
+{
+    double sn, cs;
+    sincos(sign * 6.283185307179586476925286766559 * pv.nx[j], &sn, &cs);
+    const double m1 = exp(-pv.ny[j]);
+    return mk<T>((T)(m1 * cs), (T)(m1 * sn));
+}
+
 template <class Ctx, typename T>
 FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
-                            const cplx<T>* call, int deriv, double* dacc, double* red)
+                            const cplx<T>* call, int deriv, double* dacc, double* red, cplx<T>* nw)
 {
     const DirectItem it = items[ctx.bid()];
     const int64_t N = pv.inst[it.inst].N;
     const cplx<T>* c = call + pv.inst[it.inst].c_off;
     const int tid = ctx.tid(), nt = ctx.ntid();
-    const int64_t k0 = ((int64_t)it.chunk * nt + tid) * DIRECT_TPT;
-    cplx<T> cv[DIRECT_TPT];
-    for (int t = 0; t < DIRECT_TPT; ++t) {
-        const int64_t k = k0 + t;
-        cplx<T> v = k < N ? c[k] : mk<T>(0, 0);
-        if (deriv) {
-            const T sc = (T)(6.283185307179586476925286766559 * (double)k);
-            v = mk(-v.y * sc, v.x * sc);
+    if (tid < it.count) nw[tid] = direct_w(pv, dlist[it.first + tid], +1.0);
+    for (int r = 0; r < 2 * DIRECT_NG; ++r) red[r * nt + tid] = 0.0;   // this thread's partial sums
+    ctx.sync();
+    for (int cc = 0; cc < it.nch; ++cc) {
+        const int64_t k0 = (((int64_t)it.chunk + cc) * nt + tid) * DIRECT_TPT;
+        if (k0 >= N) break;
+        cplx<T> cv[DIRECT_TPT];
+        for (int t = 0; t < DIRECT_TPT; ++t) {
+            const int64_t k = k0 + t;
+            cplx<T> v = k < N ? c[k] : mk<T>(0, 0);
+            if (deriv) {
+                const T sc = (T)(6.283185307179586476925286766559 * (double)k);
+                v = mk(-v.y * sc, v.x * sc);
+            }
+            cv[t] = v;
         }
-        cv[t] = v;
-    }
-    for (int gi = 0; gi < DIRECT_NG; ++gi) {
-        double sr = 0, si = 0;
-        if (gi < it.count && k0 < N) {
+        for (int gi = 0; gi < DIRECT_NG; ++gi) {
+            if (gi >= it.count) break;
             const int32_t j = dlist[it.first + gi];
-            const double x = pv.nx[j], y = pv.ny[j];
-            double sn, cs;
-            sincos(6.283185307179586476925286766559 * x, &sn, &cs);
-            const double m1 = exp(-y);
-            const cplx<T> w = mk<T>((T)(m1 * cs), (T)(m1 * sn));
-            const double mag = exp(-(double)k0 * y);
-            sincos(6.283185307179586476925286766559 * frac_kx((double)k0, x), &sn, &cs);
-            cplx<T> p = mk<T>((T)(mag * cs), (T)(mag * sn));
+            cplx<T> p = direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], +1.0);
+            const cplx<T> w = nw[gi];
             T ar = 0, ai = 0;
             for (int t = 0; t < DIRECT_TPT; ++t) {
                 ar += cv[t].x * p.x - cv[t].y * p.y;
                 ai += cv[t].x * p.y + cv[t].y * p.x;
                 p = mul(p, w);
             }
-            sr = (double)ar;
-            si = (double)ai;
+            red[(2 * gi) * nt + tid] += (double)ar;
+            red[(2 * gi + 1) * nt + tid] += (double)ai;
         }
-        red[(2 * gi) * nt + tid] = sr;
-        red[(2 * gi + 1) * nt + tid] = si;
     }
     ctx.sync();
     for (int h = nt >> 1; h > 0; h >>= 1) {
@@ -905,7 +932,6 @@ FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectI
     }
 }
 
-// Clear (op 0) or write out (op 1: f[perm[j]] = dacc[j]) the direct nodes.
 template <class Ctx, typename T>
 FLT_HD void body_direct_io(const Ctx& ctx, const PlanView<T>& pv, const int32_t* dlist, int64_t nd, double* dacc,
                            cplx<T>* f, int op)
@@ -921,37 +947,38 @@ FLT_HD void body_direct_io(const Ctx& ctx, const PlanView<T>& pv, const int32_t*
     }
 }
 
-// Direct adjoint: acc_k += sum_j g_j conj(w_j)^k over a group of direct nodes,
-// DIRECT_ATPT consecutive k >= 1 per thread (k = 0 is summed over all nodes apart).
+// Direct adjoint: acc_k += sum_j g_j conj(w_j)^k over a group of up to
+// DIRECT_ANG direct nodes (their conj(w) and g in LDS), direct_atpt
+// consecutive k >= 1 per thread (k = 0 is summed over all nodes apart).
 template <class Ctx, typename T>
 FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
-                            const cplx<T>* gin, double* accall)
+                            const cplx<T>* gin, double* accall, cplx<T>* nw, cplx<T>* ng)
 {
+    constexpr int ATPT = direct_atpt((int)sizeof(T));
     const DirectItem it = items[ctx.bid()];
     const int64_t N = pv.inst[it.inst].N;
     double* acc = accall + 2 * pv.inst[it.inst].c_off;
-    const int64_t k0 = ((int64_t)it.chunk * ctx.ntid() + ctx.tid()) * DIRECT_ATPT;
+    for (int gi = ctx.tid(); gi < it.count; gi += ctx.ntid()) {
+        const int32_t j = dlist[it.first + gi];
+        nw[gi] = direct_w(pv, j, -1.0);
+        ng[gi] = gin[pv.perm[j]];
+    }
+    ctx.sync();
+    const int64_t k0 = ((int64_t)it.chunk * ctx.ntid() + ctx.tid()) * ATPT;
     if (k0 >= N) return;
-    T ar[DIRECT_ATPT], ai[DIRECT_ATPT];
-    for (int t = 0; t < DIRECT_ATPT; ++t) ar[t] = ai[t] = 0;
+    T ar[ATPT], ai[ATPT];
+    for (int t = 0; t < ATPT; ++t) ar[t] = ai[t] = 0;
     for (int gi = 0; gi < it.count; ++gi) {
         const int32_t j = dlist[it.first + gi];
-        const cplx<T> gv = gin[pv.perm[j]];
-        const double x = pv.nx[j], y = pv.ny[j];
-        double sn, cs;
-        sincos(6.283185307179586476925286766559 * x, &sn, &cs);
-        const double m1 = exp(-y);
-        const cplx<T> w = mk<T>((T)(m1 * cs), (T)(-m1 * sn));
-        const double mag = exp(-(double)k0 * y);
-        sincos(-6.283185307179586476925286766559 * frac_kx((double)k0, x), &sn, &cs);
-        cplx<T> p = mk<T>((T)(mag * cs), (T)(mag * sn));
-        for (int t = 0; t < DIRECT_ATPT; ++t) {
+        const cplx<T> gv = ng[gi], w = nw[gi];
+        cplx<T> p = direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], -1.0);
+        for (int t = 0; t < ATPT; ++t) {
             ar[t] += gv.x * p.x - gv.y * p.y;
             ai[t] += gv.x * p.y + gv.y * p.x;
             p = mul(p, w);
         }
     }
-    for (int t = 0; t < DIRECT_ATPT; ++t) {
+    for (int t = 0; t < ATPT; ++t) {
         const int64_t k = k0 + t;
         if (k >= 1 && k < N) {
             ctx.atomic_add(acc + 2 * k, (double)ar[t]);

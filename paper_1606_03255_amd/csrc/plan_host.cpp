@@ -366,13 +366,17 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
     if (!hp.dlist.empty()) {
         const int64_t nd = (int64_t)hp.dlist.size();
         const int64_t fchunks = (N + (int64_t)256 * DIRECT_TPT - 1) / ((int64_t)256 * DIRECT_TPT);
+        const int cpw = direct_cpw(dtype == FLT_C64 ? 4 : 8);
         for (int64_t g = 0; g < nd; g += DIRECT_NG)
-            for (int64_t ch = 0; ch < fchunks; ++ch)
-                hp.direct_fwd.push_back(DirectItem{(int32_t)g, (int32_t)std::min<int64_t>(DIRECT_NG, nd - g), (int32_t)ch, 0});
-        const int64_t achunks = (N + (int64_t)256 * DIRECT_ATPT - 1) / ((int64_t)256 * DIRECT_ATPT);
+            for (int64_t ch = 0; ch < fchunks; ch += cpw)
+                hp.direct_fwd.push_back(DirectItem{(int32_t)g, (int16_t)std::min<int64_t>(DIRECT_NG, nd - g),
+                                                   (int16_t)std::min<int64_t>(cpw, fchunks - ch), (int32_t)ch, 0});
+        const int64_t aspan = (int64_t)256 * direct_atpt(dtype == FLT_C64 ? 4 : 8);   // adjoint workgroup
+        const int64_t achunks = (N + aspan - 1) / aspan;
         for (int64_t g = 0; g < nd; g += DIRECT_ANG)
             for (int64_t ch = 0; ch < achunks; ++ch)
-                hp.direct_adj.push_back(DirectItem{(int32_t)g, (int32_t)std::min<int64_t>(DIRECT_ANG, nd - g), (int32_t)ch, 0});
+                hp.direct_adj.push_back(DirectItem{(int32_t)g, (int16_t)std::min<int64_t>(DIRECT_ANG, nd - g), 1,
+                                                   (int32_t)ch, 0});
     }
     hp.grid_elems = goff;
     hp.scratch_elems = soff;
