@@ -410,14 +410,15 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int j = j2_0 + jj + (j1 << log2n2);
             const int kp = j < (n >> 1) ? j : j - n;
             const int k = kp + k0;
-            cplx<T> base;
+            const bool valid = k >= 1 && k <= kmax;   // outside the support (half the grid) the input is zero
+            cplx<T> base = mk<T>(0, 0);
             if (s == 0) {
                 base = lds[lds_at(p)];
-                slot[p] = base;
-            } else {
+                if (valid) slot[p] = base;
+            } else if (valid) {
                 base = slot[p];
             }
-            lds[lds_at(p)] = k >= 1 && k <= kmax ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
+            lds[lds_at(p)] = valid ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
         }
         ctx.sync();
         lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, pv.tw_stage);
@@ -987,8 +988,9 @@ FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectI
     }
 }
 
-// Adjoint of one-pass bands: per column, inverse-sign FFT in LDS, deconvolve,
-// transposed contraction acc_k += sum_s t_k[s] Ghat_s[k - k0] (FP64, atomics).
+// Adjoint of one-pass bands: per column, inverse-sign FFT in LDS and the
+// transposed contraction sum_s t_k[s] Ghat_s[k - k0], deconvolved once and
+// added into acc_k (FP64, atomics).
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                              const cplx<T>* grids, double* acc, cplx<T>* lds, T* lc)
@@ -1012,7 +1014,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
             const int kp = p < (n >> 1) ? p : p - n;
             const int k = kp + (int)B.k0;
             if (k < 1 || k > B.kmax) continue;
-            const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+            const T w = laplace_row_lds(lc, B, k);   // the deconvolution is applied once, below
             const cplx<T> v = lds[lds_at(p)];
             accr[i] += v.x * w;
             acci[i] += v.y * w;
@@ -1025,13 +1027,15 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
         const int kp = p < (n >> 1) ? p : p - n;
         const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
-        ctx.atomic_add(acc + 2 * (B.c_off + k), (double)accr[i]);
-        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, (double)acci[i]);
+        const double d = (double)pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)accr[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)acci[i]);
     }
 }
 
 // Adjoint pass A: for b consecutive j2, all columns s: Y[j2][l1] e^{-2 pi i j2 l1 / n},
-// inverse-sign DFT over l1 -> j1, deconvolve, transposed contraction into acc.
+// inverse-sign DFT over l1 -> j1, transposed contraction over s, deconvolved
+// once and added into acc.
 template <class Ctx, typename T, int LOG2N1>
 FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc)
@@ -1069,7 +1073,7 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             const int kp = j < (n >> 1) ? j : j - n;
             const int k = kp + (int)B.k0;
             if (k < 1 || k > B.kmax) continue;
-            const T w = laplace_row_lds(lc, B, k) * pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+            const T w = laplace_row_lds(lc, B, k);   // the deconvolution is applied once, below
             const cplx<T> v = lds[lds_at(p)];
             accr[i] += v.x * w;
             acci[i] += v.y * w;
@@ -1085,8 +1089,9 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         const int kp = j < (n >> 1) ? j : j - n;
         const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
-        ctx.atomic_add(acc + 2 * (B.c_off + k), (double)accr[i]);
-        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, (double)acci[i]);
+        const double d = (double)pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)accr[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)acci[i]);
     }
 }
 
