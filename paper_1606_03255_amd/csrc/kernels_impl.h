@@ -224,8 +224,18 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
             }
             const int k = j & ((1 << LOG2NS) - 1);
             if (LOG2NS > 0) {
+                // w^r for r = r1 + 2^LA r2 as w^{r1} w^{2^LA r2}: 2^LA + 2^LB - 2 table
+                // reads instead of R - 1, at most one extra rounded product each
                 constexpr int SH = TW_STAGE_LOG2 - LOG2NS - LR;
-                for (int r = 1; r < R; ++r) v[i][r] = mul(v[i][r], tw_stage_at(tw, (k * r) << SH, SIGN));
+                constexpr int LA = LR / 2, LB = LR - LA;
+                cplx<T> wa[1 << LA], wb[1 << LB];
+                for (int r1 = 1; r1 < (1 << LA); ++r1) wa[r1] = tw_stage_at(tw, (k * r1) << SH, SIGN);
+                for (int r2 = 1; r2 < (1 << LB); ++r2) wb[r2] = tw_stage_at(tw, (k * r2) << (SH + LA), SIGN);
+                for (int r = 1; r < R; ++r) {
+                    const int r1 = r & ((1 << LA) - 1), r2 = r >> LA;
+                    const cplx<T> w = r2 == 0 ? wa[r1] : r1 == 0 ? wb[r2] : mul(wa[r1], wb[r2]);
+                    v[i][r] = mul(v[i][r], w);
+                }
             }
             dft<T, R>(v[i], SIGN);
             dst[i] = (sub << LOG2L) + ((j >> LOG2NS) << (LOG2NS + LR)) + k;
