@@ -196,11 +196,76 @@ constexpr int next_radix_log2(int rem, int maxr)
     return r;
 }
 
+// Stage twiddles w^r, w = e^{SIGN 2 pi i k / (Ns R)}, r < R, are formed as
+// w^{r1} w^{2^LA r2} (r = r1 + 2^LA r2, LA = LR / 2, LB = LR - LA): 2^LA + 2^LB - 2
+// factors instead of R - 1, at most one extra rounded product each.  Two
+// sources of the factors:
+//
+// TableTw reads them from the stage table at every stage;
+template <typename T> struct TableTw {
+    const cplx<T>* tw;   // e^{-2 pi i t / 2^TW_STAGE_LOG2}
+    template <int LR, int LOG2NS, int SIGN>
+    FLT_HD void factors(int /*i*/, int k, cplx<T>* wa, cplx<T>* wb) const
+    {
+        constexpr int SH = TW_STAGE_LOG2 - LOG2NS - LR;
+        constexpr int LA = LR / 2, LB = LR - LA;
+        for (int r1 = 1; r1 < (1 << LA); ++r1) wa[r1] = tw_stage_at(tw, (k * r1) << SH, SIGN);
+        for (int r2 = 1; r2 < (1 << LB); ++r2) wb[r2] = tw_stage_at(tw, (k * r2) << (SH + LA), SIGN);
+    }
+    template <class Ctx> FLT_HD void load(const Ctx&, const cplx<T>* t) { tw = t; }
+    FLT_HD const TableTw& next() const { return *this; }
+};
+
+// StageTw holds one thread's factors of every stage of a transform geometry
+// (LOG2L, NSUB) in registers.  They depend on the thread index alone, so one
+// load serves every tile of that geometry the workgroup transforms.
+template <typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS = 0, bool MORE = (LOG2L > LOG2NS)>
+struct StageTw {
+    template <class Ctx> FLT_HD void load(const Ctx&, const cplx<T>*) {}
+};
+template <typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS>
+struct StageTw<T, LOG2L, NSUB, SIGN, LOG2NS, true> {
+    static constexpr int LR = next_radix_log2(LOG2L - LOG2NS, MaxRadix<T>::LOG2);
+    static constexpr int LA = LR / 2, LB = LR - LA;
+    static constexpr int LOG2LQ = LOG2L - LR;
+    static constexpr int NBUT = (NSUB << LOG2L) >> LR;
+    static constexpr int NB = (NBUT + FFT_THREADS - 1) / FFT_THREADS;
+    static constexpr int NW = LOG2NS > 0 ? NB : 1;   // the first stage (Ns = 1) has no twiddles
+    cplx<T> wa[NW][1 << LA], wb[NW][1 << LB];
+    StageTw<T, LOG2L, NSUB, SIGN, LOG2NS + LR> nx;
+
+    template <class Ctx> FLT_HD void load(const Ctx& ctx, const cplx<T>* tw)
+    {
+        if constexpr (LOG2NS > 0) {
+            const TableTw<T> tab{tw};
+            for (int i = 0; i < NB; ++i) {
+                const int u = ctx.tid() + i * FFT_THREADS;
+                const int k = u & ((1 << LOG2NS) - 1);   // u mod (L / R) mod Ns
+                if ((NBUT % FFT_THREADS) == 0 || u < NBUT) tab.template factors<LR, LOG2NS, SIGN>(i, k, wa[i], wb[i]);
+            }
+        }
+        nx.load(ctx, tw);
+    }
+    template <int LR_, int LOG2NS_, int SIGN_>
+    FLT_HD void factors(int i, int /*k*/, cplx<T>* a, cplx<T>* b) const
+    {
+        static_assert(LR_ == LR && LOG2NS_ == LOG2NS && SIGN_ == SIGN, "twiddles of another geometry");
+        for (int r1 = 1; r1 < (1 << LA); ++r1) a[r1] = wa[i][r1];
+        for (int r2 = 1; r2 < (1 << LB); ++r2) b[r2] = wb[i][r2];
+    }
+    FLT_HD const StageTw<T, LOG2L, NSUB, SIGN, LOG2NS + LR>& next() const { return nx; }
+};
+
+// The twiddle source of an FFT: registers (REG) or the table.
+template <bool REG, typename T, int LOG2L, int NSUB, int SIGN> struct TwSel { using type = StageTw<T, LOG2L, NSUB, SIGN>; };
+template <typename T, int LOG2L, int NSUB, int SIGN> struct TwSel<false, T, LOG2L, NSUB, SIGN> { using type = TableTw<T>; };
+
 // One Stockham autosort radix-2^LR stage over NSUB contiguous transforms of
 // length 2^LOG2L in `buf`, all geometry known at compile time (in place:
-// reads, barrier, writes, barrier).  Twiddles e^{SIGN 2 pi i k r / (Ns R)}.
-template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN>
-FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
+// reads, barrier, writes, barrier).  Twiddles e^{SIGN 2 pi i k r / (Ns R)}
+// from the provider tw (TableTw or StageTw).
+template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, class TW>
+FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
 {
     constexpr int R = 1 << LR;
     constexpr int P = NSUB << LOG2L;
@@ -223,14 +288,10 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
                 for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at(src + (r << LOG2LQ))];
             }
             const int k = j & ((1 << LOG2NS) - 1);
-            if (LOG2NS > 0) {
-                // w^r for r = r1 + 2^LA r2 as w^{r1} w^{2^LA r2}: 2^LA + 2^LB - 2 table
-                // reads instead of R - 1, at most one extra rounded product each
-                constexpr int SH = TW_STAGE_LOG2 - LOG2NS - LR;
+            if constexpr (LOG2NS > 0) {
                 constexpr int LA = LR / 2, LB = LR - LA;
                 cplx<T> wa[1 << LA], wb[1 << LB];
-                for (int r1 = 1; r1 < (1 << LA); ++r1) wa[r1] = tw_stage_at(tw, (k * r1) << SH, SIGN);
-                for (int r2 = 1; r2 < (1 << LB); ++r2) wb[r2] = tw_stage_at(tw, (k * r2) << (SH + LA), SIGN);
+                tw.template factors<LR, LOG2NS, SIGN>(i, k, wa, wb);
                 for (int r = 1; r < R; ++r) {
                     const int r1 = r & ((1 << LA) - 1), r2 = r >> LA;
                     const cplx<T> w = r2 == 0 ? wa[r1] : r1 == 0 ? wb[r2] : mul(wa[r1], wb[r2]);
@@ -260,15 +321,15 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
 
 // In-place DFTs X[l] = sum_j x[j] e^{SIGN 2 pi i j l / L} of NSUB transforms of
 // length L = 2^LOG2L stored contiguously in LDS (Stockham, natural order in and
-// out); tw is the stage twiddle table e^{-2 pi i t / 2^TW_STAGE_LOG2}.
-template <class Ctx, typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS = 0>
-FLT_HD void lds_fft_ct(const Ctx& ctx, cplx<T>* buf, const cplx<T>* tw)
+// out); tw supplies the stage twiddles (TableTw, or the StageTw of this geometry).
+template <class Ctx, typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS = 0, class TW>
+FLT_HD void lds_fft_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
 {
     constexpr int REM = LOG2L - LOG2NS;
     if constexpr (REM > 0) {
         constexpr int LR = next_radix_log2(REM, MaxRadix<T>::LOG2);
         fft_stage_ct<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN>(ctx, buf, tw);
-        lds_fft_ct<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, buf, tw);
+        lds_fft_ct<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, buf, tw.next());
     }
 }
 
@@ -361,13 +422,15 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     constexpr int P = NSUB << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
+    StageTw<T, LOG2N, NSUB, +1> stw;
+    stw.load(ctx, pv.tw_stage);
     for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int sl = p >> LOG2N;
         lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, p & ((1 << LOG2N) - 1), deriv)
                             : mk<T>(0, 0);
     }
     ctx.sync();
-    lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, pv.tw_stage);
+    lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, stw);
     cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << LOG2N);
     const int Pv = it.ns << LOG2N;
     for (int p = ctx.tid(); p < Pv; p += FFT_THREADS) out[p] = lds[lds_at(p)];
@@ -396,6 +459,10 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     // the workgroup's own slot for the other columns; every thread re-reads
     // only what it wrote.  Tile element p = (jj << log2n1) + j1.
     cplx<T>* slot = basebuf + B.base_off + (int64_t)it.blk * P;
+    // FP32: twiddles in registers; FP64: from the table (its registers would
+    // cost the second workgroup per CU)
+    typename TwSel<sizeof(T) == 4, T, LOG2N1, (1 << log2b), +1>::type stw;
+    stw.load(ctx, pv.tw_stage);
     for (int s = 0; s < B.q; ++s) {
         stage_coef(ctx, pv, B, s, lc);
         if (s == 0) {
@@ -431,7 +498,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             lds[lds_at(p)] = valid ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
         }
         ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, pv.tw_stage);
+        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, stw);
         cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
         for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
             const int l1lo = p & ((1 << log2B) - 1);
@@ -546,6 +613,9 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
     TileRegs<T> v;
     uint32_t bits[RUNS];
     passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, v, bits);
+    // with prefetch the registers hold the next tile instead of the twiddles
+    typename TwSel<!PREFETCH, T, LOG2N2, (1 << G::log2B), SIGN>::type stw;
+    stw.load(ctx0, pv.tw_stage);
     for (;;) {
         const IterCtx<Ctx> ctx{ctx0, opaque(ctx0.tid())};
         const FftItem it = items[i];
@@ -559,7 +629,7 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
         const int nx = i + nblocks;
         const bool more = nx < nitems && pv.bands[items[nx].band].log2n2 == LOG2N2;
         if (PREFETCH && more) passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, v, bits);
-        lds_fft_ct<IterCtx<Ctx>, T, LOG2N2, (1 << G::log2B), SIGN>(ctx, lds, pv.tw_stage);
+        lds_fft_ct<IterCtx<Ctx>, T, LOG2N2, (1 << G::log2B), SIGN>(ctx, lds, stw);
         const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
         cplx<T>* dst = dst_base + (ADJ ? B.scratch_off : B.grid_off) + blk_off;
         const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (Sizes<T>::LOG2P - 5));
@@ -1010,6 +1080,8 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
+    StageTw<T, LOG2N, 1, -1> stw;
+    stw.load(ctx, pv.tw_stage);
     T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
@@ -1017,7 +1089,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
         for (int p = ctx.tid(); p < n; p += FFT_THREADS) lds[lds_at(p)] = src[p];
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, pv.tw_stage);
+        lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, stw);
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= n) break;
@@ -1058,6 +1130,10 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     const int log2n2 = B.log2n2, log2B = B.log2B;
     const int n = 1 << B.log2n;
     const int j2_0 = it.blk << log2b;
+    // FP64: twiddles in registers (one workgroup per CU either way); FP32: from
+    // the table, as the accumulators already fill the four-wave register budget
+    typename TwSel<sizeof(T) == 8, T, LOG2N1, (1 << log2b), -1>::type stw;
+    stw.load(ctx, pv.tw_stage);
     T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
@@ -1073,7 +1149,7 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         }
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), -1>(ctx, lds, pv.tw_stage);
+        lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), -1>(ctx, lds, stw);
         for (int i = 0; i < ITEMS; ++i) {
             const int p = ctx.tid() + i * FFT_THREADS;
             if (p >= P) break;
