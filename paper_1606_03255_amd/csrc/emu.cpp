@@ -133,7 +133,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 });
             });
         for (const LaunchGroup& g : hp.g_passA_fwd)
-            with_log2<(LP + 2) / 2, 11>(g.log2, [&](auto LG) {
+            with_log2<LP + 1, TW2_LOG2>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
                                                                     scratch.data(), basebuf.data(), deriv, lds.data(),
@@ -181,7 +181,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             });
         }
         for (const LaunchGroup& g : hp.g_passA_adj)
-            with_log2<(LP + 2) / 2, 11>(g.log2, [&](auto LG) {
+            with_log2<LP + 1, TW2_LOG2>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passA_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_adj.data() + g.start,
                                                                     scratch.data(), acc.data(), lds.data(), lc.data());

@@ -35,14 +35,15 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
+// four waves per SIMD (two workgroups per CU, as the LDS allows)
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
                                                               const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf,
                                                               int deriv)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
-    with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
+    with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
         body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, lds, lc);
     });
 }
@@ -107,7 +108,7 @@ __device__ __forceinline__ void passA_adj_kernel(const PlanView<T>& pv, const Ff
     __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
-    with_log2<RG::A_LO, RG::A_HI>(pv.bands[items[blockIdx.x].band].log2n1, [&](auto LG) {
+    with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
         body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc);
     });
 }

@@ -38,14 +38,24 @@ template <int LO, int HI, class F> FLT_HD bool with_log2(int v, F&& f)
     }
 }
 
-// Transform lengths (log2) of the FFT kernels: one-pass bands, pass A
-// (ceil(log2 n / 2)) and pass B (floor(log2 n / 2)).
+// Transform lengths (log2) of the FFT kernels: one-pass bands, two-pass grids
+// (pass A is specialised on the whole length n) and pass B (floor(log2 n / 2)).
 template <typename T> struct Log2Range {
     static constexpr int P = Sizes<T>::LOG2P;
     static constexpr int ONE_LO = 4, ONE_HI = P;
-    static constexpr int A_LO = (P + 2) / 2, A_HI = TW2_LOG2 - TW2_LOG2 / 2;
+    static constexpr int TWO_LO = P + 1, TWO_HI = TW2_LOG2;
     static constexpr int B_LO = (P + 1) / 2, B_HI = TW2_LOG2 / 2;
 };
+
+// a * b for 0 <= a, b and a * b < 2^23 (a full-rate 24-bit multiply on the GPU)
+FLT_HD int mul_small(int a, int b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(a, b);
+#else
+    return a * b;
+#endif
+}
 
 FLT_HD int ceil_log2_u32(int k)  // 1 <= k < 2^31
 {
@@ -175,13 +185,24 @@ template <typename T> FLT_HD cplx<T> tw_stage_at(const cplx<T>* tw, int t, int s
 }
 
 // e^{sign 2 pi i e / n}, n = 2^log2n <= 2^22, from the two-level table; e is
-// taken mod 2^32 (n divides 2^32, so a wrapped product j2 l1 gives e mod n)
-template <typename T> FLT_HD cplx<T> tw_grid_at(const PlanView<T>& pv, uint32_t e, int log2n, int sign)
+// taken mod 2^32 (n divides 2^32, so a wrapped product j2 l1 gives e mod n).
+// In two steps where several are wanted at once: the two table factors
+// (tw_grid_fetch), then their product (tw_grid_join).
+template <typename T> struct TwPair { cplx<T> hi, lo; };
+template <typename T> FLT_HD TwPair<T> tw_grid_fetch(const PlanView<T>& pv, uint32_t e, int log2n)
 {
     const uint32_t ee = (e & ((1u << log2n) - 1u)) << (TW2_LOG2 - log2n);
-    cplx<T> w = mul(pv.tw_hi[ee >> TW2_HALF], pv.tw_lo[ee & ((1 << TW2_HALF) - 1)]);
+    return TwPair<T>{pv.tw_hi[ee >> TW2_HALF], pv.tw_lo[ee & ((1 << TW2_HALF) - 1)]};
+}
+template <typename T> FLT_HD cplx<T> tw_grid_join(const TwPair<T>& t, int sign)
+{
+    cplx<T> w = mul(t.hi, t.lo);
     if (sign > 0) w.y = -w.y;
     return w;
+}
+template <typename T> FLT_HD cplx<T> tw_grid_at(const PlanView<T>& pv, uint32_t e, int log2n, int sign)
+{
+    return tw_grid_join(tw_grid_fetch(pv, e, log2n), sign);
 }
 
 // Largest radix (log2) a thread handles in registers: the points it holds per stage.
@@ -368,7 +389,7 @@ FLT_HD T laplace_row_lds(const T* lc, const BandDesc& B, int k)
     const int ell = B.n_xi + 1 - cl;
     if (ell > B.ell_hi) return T(1);
     const int qp = coef_stride(B.q, CV);
-    const CoefVec<T>* a = (const CoefVec<T>*)(lc + (ell - B.ell_lo) * qp);
+    const CoefVec<T>* a = (const CoefVec<T>*)(lc + mul_small(ell - B.ell_lo, qp));
     const T u = ldexp((T)k, 2 - cl) - T(3);
     const T u2 = u + u;
     T b1 = 0, b2 = 0;
@@ -441,17 +462,27 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // DFTs over j1 of x[j2 + n2 j1] (generated from c), times e^{2 pi i j2 l1 / n},
 // stored as Y[l1 / B][j2][l1 mod B].
 // ---------------------------------------------------------------------------
-template <class Ctx, typename T, int LOG2N1>
+// The split n = n1 n2 of a two-pass grid of length 2^LOG2N and the tile
+// shapes of both passes (as the planner sets them), known at compile time.
+template <typename T, int LOG2N> struct TwoPassGeo {
+    static constexpr int log2n = LOG2N;
+    static constexpr int log2n1 = (LOG2N + 1) / 2, log2n2 = LOG2N - log2n1;
+    static constexpr int log2b = Sizes<T>::LOG2P - log2n1;   // pass A: sub-transforms per tile
+    static constexpr int log2B = Sizes<T>::LOG2P - log2n2;   // pass B: sub-transforms per tile
+};
+
+template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf, int deriv, cplx<T>* lds, T* lc)
 {
+    using G = TwoPassGeo<T, LOG2N>;
     constexpr int ITEMS = tile_items<T>();
-    constexpr int log2n1 = LOG2N1, log2b = Sizes<T>::LOG2P - LOG2N1;
+    constexpr int log2n1 = G::log2n1, log2n2 = G::log2n2, log2b = G::log2b, log2B = G::log2B;
+    constexpr int LOG2N1 = log2n1;
     constexpr int P = tile_points<T>();
+    constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
-    const BandDesc& B = pv.bands[it.band];
-    const int log2n2 = B.log2n2, log2B = B.log2B;
-    const int n = 1 << B.log2n;
+    const BandDesc B = pv.bands[it.band];   // a copy: the stores below cannot alias it
     const int k0 = (int)B.k0, kmax = (int)B.kmax;
     const int j2_0 = it.blk << log2b;
     // c_k / (n phi_hat(k')) of this workgroup's points: formed once, reading c
@@ -479,35 +510,76 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             }
         }
         ctx.sync();
-#pragma unroll 1
-        for (int i = 0; i < ITEMS; ++i) {
-            const int p = ctx.tid() + i * FFT_THREADS;
+        // points in groups of GU: the group's bases are fetched first (for
+        // s > 0 the slot reads are in flight together), then its Chebyshev rows
+        // evaluated; k = 0 marks a point outside the support (half the grid),
+        // whose input is zero
+        constexpr int GU = sizeof(T) == 4 ? 8 : 2;
+        auto point_k = [&](int p) {
             const int j1 = p & ((1 << log2n1) - 1);
             const int jj = p >> log2n1;
             const int j = j2_0 + jj + (j1 << log2n2);
-            const int kp = j < (n >> 1) ? j : j - n;
-            const int k = kp + k0;
-            const bool valid = k >= 1 && k <= kmax;   // outside the support (half the grid) the input is zero
-            cplx<T> base = mk<T>(0, 0);
-            if (s == 0) {
-                base = lds[lds_at(p)];
-                if (valid) slot[p] = base;
-            } else if (valid) {
-                base = slot[p];
+            const int k = (j < (n >> 1) ? j : j - n) + k0;
+            return k >= 1 && k <= kmax ? k : 0;
+        };
+        auto finish = [&](int i0, const cplx<T>* base, const int* kk) {
+            for (int u = 0; u < GU; ++u) {
+                const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                lds[lds_at(p)] = kk[u] > 0 ? scale(base[u], laplace_row_lds(lc, B, kk[u])) : mk<T>(0, 0);
             }
-            lds[lds_at(p)] = valid ? scale(base, laplace_row_lds(lc, B, k)) : mk<T>(0, 0);
+        };
+        if (s == 0) {
+#pragma unroll 1
+            for (int i0 = 0; i0 < ITEMS; i0 += GU) {
+                cplx<T> base[GU];
+                int kk[GU];
+                for (int u = 0; u < GU; ++u) {
+                    const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                    kk[u] = point_k(p);
+                    base[u] = lds[lds_at(p)];
+                    if (kk[u] > 0) slot[p] = base[u];
+                }
+                finish(i0, base, kk);
+            }
+        } else {
+#pragma unroll 1
+            for (int i0 = 0; i0 < ITEMS; i0 += GU) {
+                cplx<T> base[GU];
+                int kk[GU];
+                for (int u = 0; u < GU; ++u) {
+                    const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                    kk[u] = point_k(p);
+                    base[u] = kk[u] > 0 ? slot[p] : mk<T>(0, 0);
+                }
+                finish(i0, base, kk);
+            }
         }
         ctx.sync();
         lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, stw);
-        cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
-        for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
-            const int l1lo = p & ((1 << log2B) - 1);
-            const int jj = (p >> log2B) & ((1 << log2b) - 1);
-            const int l1hi = p >> (log2B + log2b);
-            const int l1 = (l1hi << log2B) + l1lo;
-            const int j2 = j2_0 + jj;
-            cplx<T> v = mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_at(pv, (uint32_t)j2 * (uint32_t)l1, B.log2n, +1));
-            Y[(l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] = v;
+        cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << LOG2N);
+        // in groups of GO points: the group's table reads first (in flight
+        // together), then the products and stores
+        constexpr int GO = sizeof(T) == 4 ? 8 : 4;
+#pragma unroll 1
+        for (int i0 = 0; i0 < ITEMS; i0 += GO) {
+            TwPair<T> w[GO];
+            for (int u = 0; u < GO; ++u) {
+                const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                const int l1lo = p & ((1 << log2B) - 1);
+                const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                const int l1 = ((p >> (log2B + log2b)) << log2B) + l1lo;
+                w[u] = tw_grid_fetch(pv, (uint32_t)(j2_0 + jj) * (uint32_t)l1, LOG2N);
+            }
+            for (int u = 0; u < GO; ++u) {
+                const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                const int l1lo = p & ((1 << log2B) - 1);
+                const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                const int l1hi = p >> (log2B + log2b);
+                const int l1 = (l1hi << log2B) + l1lo;
+                const int j2 = j2_0 + jj;
+                Y[(l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo] =
+                    mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_join(w[u], +1));
+            }
         }
         ctx.sync();
     }
@@ -1079,7 +1151,7 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     constexpr int log2n = LOG2N;
     constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
-    const BandDesc& B = pv.bands[it.band];
+    const BandDesc B = pv.bands[it.band];   // a copy: the stores below cannot alias it
     StageTw<T, LOG2N, 1, -1> stw;
     stw.load(ctx, pv.tw_stage);
     T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
@@ -1118,17 +1190,18 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 // Adjoint pass A: for b consecutive j2, all columns s: Y[j2][l1] e^{-2 pi i j2 l1 / n},
 // inverse-sign DFT over l1 -> j1, transposed contraction over s, deconvolved
 // once and added into acc.
-template <class Ctx, typename T, int LOG2N1>
+template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc)
 {
+    using G = TwoPassGeo<T, LOG2N>;
     constexpr int ITEMS = tile_items<T>();
-    constexpr int log2n1 = LOG2N1, log2b = Sizes<T>::LOG2P - LOG2N1;
+    constexpr int log2n1 = G::log2n1, log2n2 = G::log2n2, log2b = G::log2b, log2B = G::log2B;
+    constexpr int LOG2N1 = log2n1;
     constexpr int P = tile_points<T>();
+    constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
-    const int log2n2 = B.log2n2, log2B = B.log2B;
-    const int n = 1 << B.log2n;
     const int j2_0 = it.blk << log2b;
     // FP64: twiddles in registers (one workgroup per CU either way); FP32: from
     // the table, as the accumulators already fill the four-wave register budget
@@ -1137,15 +1210,31 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
     for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
     for (int s = 0; s < B.q; ++s) {
-        const cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << B.log2n);
-        for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
-            const int l1lo = p & ((1 << log2B) - 1);
-            const int jj = (p >> log2B) & ((1 << log2b) - 1);
-            const int l1hi = p >> (log2B + log2b);
-            const int l1 = (l1hi << log2B) + l1lo;
-            const int j2 = j2_0 + jj;
-            const cplx<T> v = Y[(l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
-            lds[lds_at((jj << log2n1) + l1)] = mul(v, tw_grid_at(pv, (uint32_t)j2 * (uint32_t)l1, B.log2n, -1));
+        const cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << LOG2N);
+        // in groups of GI points: the group's reads (values and table
+        // factors) in flight together, then the products go to LDS
+        constexpr int GI = sizeof(T) == 4 ? 8 : 4;
+#pragma unroll 1
+        for (int i0 = 0; i0 < ITEMS; i0 += GI) {
+            cplx<T> v[GI];
+            TwPair<T> w[GI];
+            for (int u = 0; u < GI; ++u) {
+                const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                const int l1lo = p & ((1 << log2B) - 1);
+                const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                const int l1hi = p >> (log2B + log2b);
+                const int l1 = (l1hi << log2B) + l1lo;
+                const int j2 = j2_0 + jj;
+                v[u] = Y[(l1hi << (log2n2 + log2B)) + (j2 << log2B) + l1lo];
+                w[u] = tw_grid_fetch(pv, (uint32_t)j2 * (uint32_t)l1, LOG2N);
+            }
+            for (int u = 0; u < GI; ++u) {
+                const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
+                const int l1lo = p & ((1 << log2B) - 1);
+                const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                const int l1 = ((p >> (log2B + log2b)) << log2B) + l1lo;
+                lds[lds_at((jj << log2n1) + l1)] = mul(v[u], tw_grid_join(w[u], -1));
+            }
         }
         stage_coef(ctx, pv, B, s, lc);
         ctx.sync();

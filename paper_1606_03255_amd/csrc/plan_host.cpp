@@ -431,8 +431,8 @@ static void finish(HostPlan& hp)
     };
     group(hp.onepass_fwd, hp.g_onepass_fwd, 0);
     group(hp.onepass_adj, hp.g_onepass_adj, 0);
-    group(hp.passA_fwd, hp.g_passA_fwd, 1);
-    group(hp.passA_adj, hp.g_passA_adj, 1);
+    group(hp.passA_fwd, hp.g_passA_fwd, 0);   // pass A instances are per grid length
+    group(hp.passA_adj, hp.g_passA_adj, 0);
     group(hp.passB, hp.g_passB, 2);
     if (hp.cstart.empty()) hp.cstart.push_back(0);
     if (hp.mask.empty()) hp.mask.push_back(0u);
