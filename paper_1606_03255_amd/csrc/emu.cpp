@@ -191,7 +191,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             with_log2<4, LP>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_onepass_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.onepass_adj.data() + g.start,
-                                                                      grids.data(), acc.data(), lds.data(), lc.data());
+                                                                      grids.data(), acc.data(), lds.data());
                 });
             });
         std::vector<cplx<T>> nw(DIRECT_ANG), ngv(DIRECT_ANG);

@@ -94,10 +94,9 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, 
                                                                 const cplx<T>* grids, double* acc)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_onepass_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, grids, acc, lds, lc);
+        body_onepass_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, grids, acc, lds);
     });
 }
 

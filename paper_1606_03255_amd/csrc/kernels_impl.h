@@ -1000,9 +1000,11 @@ FLT_HD void body_sum_g(const Ctx& ctx, const PlanView<T>& pv, const SumItem* ite
 // ---------------------------------------------------------------------------
 // Bands the plan evaluates by the direct sum (few nodes, large grids): the
 // exact f_j = sum_{k<N} c_k w_j^k.  Every thread takes DIRECT_TPT consecutive
-// terms from an anchor w^{k0}, then the recurrence p <- p w in T; partial sums
-// are combined in FP64.  A workgroup holds DIRECT_NG nodes (their w in LDS)
-// and up to direct_cpw chunks of terms, reduced once.
+// terms k0 .. k0 + DIRECT_TPT - 1: forward, w^{k0} sum_t c_{k0+t} w^t with the
+// inner sum by Horner's scheme in T and the anchor w^{k0} formed directly;
+// adjoint, the powers by the recurrence p <- p w from the anchor.  Partial
+// sums are combined in FP64.  A forward workgroup holds DIRECT_NG nodes (their
+// w in LDS) and up to direct_cpw chunks of terms, reduced once.
 // ---------------------------------------------------------------------------
 
 // w^k0 = e^{-k0 y} cis(sign 2 pi k0 x) with the phase reduced exactly in FP64
@@ -1061,16 +1063,16 @@ FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectI
         for (int gi = 0; gi < DIRECT_NG; ++gi) {
             if (gi >= it.count) break;
             const int32_t j = dlist[it.first + gi];
-            cplx<T> p = direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], +1.0);
             const cplx<T> w = nw[gi];
-            T ar = 0, ai = 0;
-            for (int t = 0; t < DIRECT_TPT; ++t) {
-                ar += cv[t].x * p.x - cv[t].y * p.y;
-                ai += cv[t].x * p.y + cv[t].y * p.x;
-                p = mul(p, w);
+            T hr = cv[DIRECT_TPT - 1].x, hi = cv[DIRECT_TPT - 1].y;   // Horner: h <- h w + c_t, t descending
+            for (int t = DIRECT_TPT - 2; t >= 0; --t) {
+                const T nr = hr * w.x - hi * w.y + cv[t].x;
+                hi = hr * w.y + hi * w.x + cv[t].y;
+                hr = nr;
             }
-            red[(2 * gi) * nt + tid] += (double)ar;
-            red[(2 * gi + 1) * nt + tid] += (double)ai;
+            const cplx<T> a = mul(direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], +1.0), mk(hr, hi));
+            red[(2 * gi) * nt + tid] += (double)a.x;
+            red[(2 * gi + 1) * nt + tid] += (double)a.y;
         }
     }
     ctx.sync();
@@ -1140,50 +1142,41 @@ FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectI
     }
 }
 
-// Adjoint of one-pass bands: per column, inverse-sign FFT in LDS and the
-// transposed contraction sum_s t_k[s] Ghat_s[k - k0], deconvolved once and
-// added into acc_k (FP64, atomics).
+// Adjoint of one-pass bands: the item's ns columns as sub-transforms of one
+// LDS tile (as in the forward), one inverse-sign FFT over all of them, then
+// per frequency the transposed contraction sum_s t_k[s] Ghat_s[k - k0] over
+// the item's columns, deconvolved and added into acc_k (FP64, atomics; a band
+// with more columns than a tile holds has several items).
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                             const cplx<T>* grids, double* acc, cplx<T>* lds, T* lc)
+                             const cplx<T>* grids, double* acc, cplx<T>* lds)
 {
-    constexpr int ITEMS = tile_items<T>();
-    constexpr int log2n = LOG2N;
+    constexpr int NSUB = (tile_points<T>() >> LOG2N) < MAX_Q ? (tile_points<T>() >> LOG2N) : MAX_Q;
+    constexpr int P = NSUB << LOG2N;
     constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc B = pv.bands[it.band];   // a copy: the stores below cannot alias it
-    StageTw<T, LOG2N, 1, -1> stw;
+    StageTw<T, LOG2N, NSUB, -1> stw;
     stw.load(ctx, pv.tw_stage);
-    T accr[ITEMS], acci[ITEMS];   // sum over the q columns of one frequency
-    for (int i = 0; i < ITEMS; ++i) accr[i] = acci[i] = 0;
-    for (int s = 0; s < B.q; ++s) {
-        const cplx<T>* src = grids + B.grid_off + ((int64_t)s << log2n);
-        for (int p = ctx.tid(); p < n; p += FFT_THREADS) lds[lds_at(p)] = src[p];
-        stage_coef(ctx, pv, B, s, lc);
-        ctx.sync();
-        lds_fft_ct<Ctx, T, LOG2N, 1, -1>(ctx, lds, stw);
-        for (int i = 0; i < ITEMS; ++i) {
-            const int p = ctx.tid() + i * FFT_THREADS;
-            if (p >= n) break;
-            const int kp = p < (n >> 1) ? p : p - n;
-            const int k = kp + (int)B.k0;
-            if (k < 1 || k > B.kmax) continue;
-            const T w = laplace_row_lds(lc, B, k);   // the deconvolution is applied once, below
-            const cplx<T> v = lds[lds_at(p)];
-            accr[i] += v.x * w;
-            acci[i] += v.y * w;
-        }
-        ctx.sync();
-    }
-    for (int i = 0; i < ITEMS; ++i) {
-        const int p = ctx.tid() + i * FFT_THREADS;
-        if (p >= n) break;
+    const cplx<T>* src = grids + B.grid_off + ((int64_t)it.s0 << LOG2N);
+    const int Pv = it.ns << LOG2N;
+    for (int p = ctx.tid(); p < P; p += FFT_THREADS) lds[lds_at(p)] = p < Pv ? src[p] : mk<T>(0, 0);
+    ctx.sync();
+    lds_fft_ct<Ctx, T, LOG2N, NSUB, -1>(ctx, lds, stw);
+    for (int p = ctx.tid(); p < n; p += FFT_THREADS) {
         const int kp = p < (n >> 1) ? p : p - n;
         const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
+        T ar = 0, ai = 0;
+        for (int sl = 0; sl < it.ns; ++sl) {
+            const T w = laplace_row(pv, B, it.s0 + sl, k);   // the deconvolution is applied once, below
+            const cplx<T> v = lds[lds_at((sl << LOG2N) + p)];
+            ar += v.x * w;
+            ai += v.y * w;
+        }
         const double d = (double)pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)accr[i]);
-        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)acci[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)ar);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)ai);
     }
 }
 

@@ -346,8 +346,10 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
             for (int k = 0; k < nA; ++k) hp.passA_adj.push_back(FftItem{b, 0, B.q, k});
         } else {
             const int ns = std::max(1, std::min(B.q, std::min(MAX_Q, 1 << (LOG2P - B.log2n))));
-            for (int s0 = 0; s0 < B.q; s0 += ns) hp.onepass_fwd.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
-            hp.onepass_adj.push_back(FftItem{b, 0, B.q, 0});
+            for (int s0 = 0; s0 < B.q; s0 += ns) {
+                hp.onepass_fwd.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
+                hp.onepass_adj.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
+            }
         }
         hp.qs = std::max(hp.qs, B.q);
     }
