@@ -113,6 +113,7 @@ static int upload(flt_plan* p)
     const size_t o_l9 = pk.add(hp.direct_adj.data(), hp.direct_adj.size() * sizeof(DirectItem));
     const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
     const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
+    const size_t o_cl = pk.add(hp.clist.data(), hp.clist.size() * sizeof(int32_t));
     const size_t o_mask = pk.add(hp.mask.data(), hp.mask.size() * sizeof(uint32_t));
     const size_t o_inst = pk.add(hp.inst.data(), hp.inst.size() * sizeof(InstDesc));
     const size_t o_sum = pk.add(hp.sum_items.data(), hp.sum_items.size() * sizeof(SumItem));
@@ -139,6 +140,7 @@ static int upload(flt_plan* p)
     L.direct_adj = (const DirectItem*)(base + o_l9);
     L.dlist = (const int32_t*)(base + o_dl);
     L.cstart = (const int32_t*)(base + o_cs);
+    L.clist = (const int32_t*)(base + o_cl);
     L.sum_items = (const SumItem*)(base + o_sum);
     L.n_sum = (int)hp.sum_items.size();
     int cus = 0;

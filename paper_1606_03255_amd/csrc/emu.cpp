@@ -73,8 +73,8 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
     });
     std::vector<T> red(2 * ADJ_RC * GATHER_THREADS);
     run_blocks(hp.cells.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-        body_adj_cells<HostCtx, T, MW>(ctx, pv, hp.cells.data(), hp.qs, U, Phi, L0, hp.cstart.data(), grids,
-                                       red.data());
+        body_adj_cells<HostCtx, T, MW>(ctx, pv, hp.cells.data(), hp.qs, U, Phi, L0, hp.cstart.data(),
+                                       hp.clist.data(), grids, red.data());
     });
 }
 

@@ -128,13 +128,15 @@ struct NodeItem {
     int64_t start;
 };
 
-// Work item of the adjoint's grid side: 256 >> log2tpc consecutive cells of a
-// band, each summed by a group of 2^log2tpc threads.
+// Work item of the adjoint's grid side: 256 >> log2tpc cells of a band, each
+// summed by a group of 2^log2tpc threads: consecutive cells from cell0, or
+// (listed) the entries clist[cell0 ..] of the plan's list of touched cells
+// (-1: none).
 struct CellItem {
     int32_t band;
     int32_t cell0;
     int32_t log2tpc;
-    int32_t pad;
+    int32_t listed;
 };
 
 // Work item of the direct-sum kernels: a run of the direct-node list and a chunk of k.

@@ -76,10 +76,11 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_adj_prep(PlanView<T> pv, con
 template <typename T, int MW>
 __global__ __launch_bounds__(GATHER_THREADS) void k_adj_cells(PlanView<T> pv, const CellItem* items, int qs,
                                                               const cplx<T>* U, const T* Phi, const int32_t* L0,
-                                                              const int32_t* cstart, cplx<T>* grids)
+                                                              const int32_t* cstart, const int32_t* clist,
+                                                              cplx<T>* grids)
 {
     __shared__ T red[2 * ADJ_RC * GATHER_THREADS];
-    body_adj_cells<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, cstart, grids, red);
+    body_adj_cells<DevCtx, T, MW>(DevCtx(), pv, items, qs, U, Phi, L0, cstart, clist, grids, red);
 }
 
 template <typename T>
@@ -241,7 +242,7 @@ static void mw_adjoint_nodes(const DevLists& L, const PlanView<T>& pv, const WsL
                            L.nfft_nodes, g, W.qs, U, Phi, L0);
     if (L.n_cells)
         hipLaunchKernelGGL((k_adj_cells<T, MW>), dim3(L.n_cells), dim3(GATHER_THREADS), 0, st, pv, L.cells, W.qs,
-                           (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, L.cstart, grids);
+                           (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, L.cstart, L.clist, grids);
 }
 
 template <typename T>

@@ -891,7 +891,7 @@ constexpr int ADJ_RC = 4;
 template <class Ctx, typename T, int MW>
 FLT_HD void body_adj_cells(const Ctx& ctx, const PlanView<T>& pv, const CellItem* items, int qs,
                            const cplx<T>* U, const T* Phi, const int32_t* L0, const int32_t* cstart,
-                           cplx<T>* grids, T* red)
+                           const int32_t* clist, cplx<T>* grids, T* red)
 {
     const CellItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
@@ -899,8 +899,8 @@ FLT_HD void body_adj_cells(const Ctx& ctx, const PlanView<T>& pv, const CellItem
     const int lt = it.log2tpc, tpc = 1 << lt;
     const int tid = ctx.tid();
     const int r = tid & (tpc - 1);
-    const int l = it.cell0 + (tid >> lt);
-    bool write = l < n;
+    const int l = it.listed ? clist[it.cell0 + (tid >> lt)] : it.cell0 + (tid >> lt);
+    bool write = l >= 0 && l < n;
     int64_t addr = 0;
     if (write) {
         addr = grid_addr(B, l);

@@ -22,6 +22,7 @@ struct DevLists {
     const DirectItem* direct_adj = nullptr;
     const int32_t* dlist = nullptr;
     const int32_t* cstart = nullptr;
+    const int32_t* clist = nullptr;
     const SumItem* sum_items = nullptr;
     int n_sum = 0;
     int persist_blocks = 512;   // workgroups of the persistent FFT kernels (two per compute unit)

@@ -304,15 +304,6 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
                 hp.cstart.push_back((int32_t)jn);
             }
         }
-        // adjoint grid side: groups of 2^lt threads per cell, sized so that a
-        // thread handles about CELL_TARGET of the cell's ~2 mw nodes/n x n contributions
-        {
-            const double contrib = 2.0 * hp.mw * (double)B.node_count / (double)n;
-            int lt = 0;
-            while (lt < 8 && (double)(1 << lt) * CELL_TARGET < contrib) ++lt;
-            const int per = GATHER_THREADS >> lt;
-            for (int64_t c0 = 0; c0 < n; c0 += per) hp.cells.push_back(CellItem{b, (int32_t)c0, lt, 0});
-        }
         // cells some node's window reads: [l0 - mw + 1, l0 + mw] (mod n) around
         // each node's cell l0 = floor(n x); a two-pass band keeps them as a bit
         // mask over grid addresses, so pass B stores (and, for the adjoint,
@@ -332,6 +323,27 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
                         const int64_t a = grid_addr(B, l);
                         mk[a >> 5] |= 1u << (a & 31);
                     }
+            }
+            // adjoint grid side: groups of 2^lt threads per cell, sized so that a
+            // thread handles about CELL_TARGET of a cell's contributions.  A
+            // one-pass band gets every cell (its adjoint FFT reads whole columns);
+            // a two-pass band whose windows leave cells untouched gets only the
+            // touched ones, listed in clist (pass B loads only those)
+            const bool listed = B.log2n2 > 0 && B.cells < n;
+            const double span = listed ? (double)B.cells : (double)n;
+            const double contrib = 2.0 * hp.mw * (double)B.node_count / span;
+            int lt = 0;
+            while (lt < 8 && (double)(1 << lt) * CELL_TARGET < contrib) ++lt;
+            const int per = GATHER_THREADS >> lt;
+            if (listed) {
+                const int64_t first = (int64_t)hp.clist.size();
+                for (int64_t l = 0; l < n; ++l)
+                    if (hit[(size_t)l]) hp.clist.push_back((int32_t)l);
+                while ((hp.clist.size() - (size_t)first) % (size_t)per) hp.clist.push_back(-1);
+                for (int64_t c0 = first; c0 < (int64_t)hp.clist.size(); c0 += per)
+                    hp.cells.push_back(CellItem{b, (int32_t)c0, lt, 1});
+            } else {
+                for (int64_t c0 = 0; c0 < n; c0 += per) hp.cells.push_back(CellItem{b, (int32_t)c0, lt, 0});
             }
         }
         if (B.log2n2 > 0) {
@@ -437,6 +449,7 @@ static void finish(HostPlan& hp)
     group(hp.passA_adj, hp.g_passA_adj, 0);
     group(hp.passB, hp.g_passB, 2);
     if (hp.cstart.empty()) hp.cstart.push_back(0);
+    if (hp.clist.empty()) hp.clist.push_back(-1);
     if (hp.mask.empty()) hp.mask.push_back(0u);
     if (hp.coef.empty()) hp.coef.push_back(0.0);
     if (hp.deconv.empty()) hp.deconv.push_back(0.0);
@@ -549,7 +562,13 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
         shift_fft(out.passB, p.passB);
         shift_fft(out.onepass_adj, p.onepass_adj);
         shift_fft(out.passA_adj, p.passA_adj);
-        for (CellItem it : p.cells) { it.band += bo; out.cells.push_back(it); }
+        const int32_t clo = (int32_t)out.clist.size();
+        for (CellItem it : p.cells) {
+            it.band += bo;
+            if (it.listed) it.cell0 += clo;
+            out.cells.push_back(it);
+        }
+        out.clist.insert(out.clist.end(), p.clist.begin(), p.clist.end());
         auto shift_nodes = [&](std::vector<NodeItem>& dst, const std::vector<NodeItem>& src) {
             for (NodeItem it : src) { it.band += bo; it.start += no; dst.push_back(it); }
         };

@@ -46,6 +46,7 @@ struct HostPlan {
     std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands
     std::vector<DirectItem> direct_fwd, direct_adj;
     std::vector<int32_t> cstart;        // per NFFT band: first sorted node with cell >= c, c = 0..n
+    std::vector<int32_t> clist;         // touched cells of the listed cell items (-1 pads)
     std::vector<uint32_t> mask;         // per two-pass band: bit per grid address read by some window
     std::vector<InstDesc> inst;         // instances: one, or the members of a batched plan
     std::vector<SumItem> sum_items;     // adjoint k = 0 sums: runs of one instance's g
