@@ -8,9 +8,10 @@ the unit disk (seed 3, see paper_1606_03255_amd/inputs.py).
 value      node evaluations per second of the FP32 form (eps = 1e-6): M times
            the number of timed forward calls over their wall time, inputs
            resident in HBM, plan built beforehand (plan time reported apart).
-fwd_bwd    forward + adjoint (dL/dc) + derivative (dL/dz) per step, for the
-           FP32 form and for the plain FP64 path (eps = 1e-11) on the same
-           inputs; speedup = t(FP64) / t(FP32).
+fwd_bwd    forward and derivative (f and f' for dL/dz, one fused call) plus the
+           adjoint (dL/dc) per step, for the FP32 form and for the plain FP64
+           path (eps = 1e-11) on the same inputs; speedup = t(FP64) / t(FP32).
+           ms_separate_fp32 times the three calls made one by one.
 roofline   the dominant kernel's algorithmic bytes per launch over its launch
            duration (HIP events recorded between the launches on the stream
            the kernels run on), against the 8 TB/s HBM peak.
@@ -239,26 +240,34 @@ def main():
     f64 = None
     E64 = None
     if not args.forward_only:
+        fp32_out = torch.empty_like(f32_out)
+
         def step32():
+            p32.forward_derivative(c32, out=f32_out, out_prime=fp32_out)
+            p32.adjoint(g32)
+        ms32, _ = time_steps(torch, step32, max(3, args.steps // 2), 1)
+
+        def step32_separate():
             p32.forward(c32, out=f32_out)
             p32.adjoint(g32)
             p32.derivative(c32)
-        ms32, _ = time_steps(torch, step32, max(3, args.steps // 2), 1)
+        ms32_sep, _ = time_steps(torch, step32_separate, max(3, args.steps // 2), 1)
         p64 = Plan(N, w["z"], 1e-11, torch.complex128, device=dev, autotune=tune)
         c64 = c32.to(torch.complex128)
         g64 = g32.to(torch.complex128)
         f64_out = torch.empty(M, dtype=torch.complex128, device=dev)
+        fp64_out = torch.empty_like(f64_out)
 
         def step64():
-            p64.forward(c64, out=f64_out)
+            p64.forward_derivative(c64, out=f64_out, out_prime=fp64_out)
             p64.adjoint(g64)
-            p64.derivative(c64)
         ms64, _ = time_steps(torch, step64, max(3, args.steps // 2), 1)
         ms64_fwd, _ = time_steps(torch, lambda: p64.forward(c64, out=f64_out), max(3, args.steps // 2), 1)
         f64 = f64_out.cpu().numpy()
         p64.close()
         fwd_bwd = {"ms_fp32_form": round(ms32, 4), "ms_fp64_path": round(ms64, 4),
-                   "speedup": round(ms64 / ms32, 3), "ms_fp64_forward": round(ms64_fwd, 4)}
+                   "speedup": round(ms64 / ms32, 3), "ms_fp64_forward": round(ms64_fwd, 4),
+                   "ms_separate_fp32": round(ms32_sep, 4)}
         log("fwd+bwd FP32 %.3f ms, FP64 %.3f ms, speedup %.2f" % (ms32, ms64, ms64 / ms32))
 
     batched = None

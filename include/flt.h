@@ -82,7 +82,7 @@ typedef struct flt_info {
     double eps, eps_K, eps_A;/* target accuracy and its Laplace / Fourier shares */
     double y1;               /* ln(1/eps_K): nodes with y = 2 pi Im z > y1 form Z^0 */
     int64_t nodes_z0;        /* nodes in Z^0 (f = c_0 there) */
-    size_t workspace_bytes;  /* device workspace a transform call needs */
+    size_t workspace_bytes;  /* device workspace every transform call needs (the fused one included) */
     double bytes_forward;    /* algorithmic HBM bytes of one forward call */
     double flops_forward;    /* algorithmic flops of one forward call */
     double direct_scale;     /* factor on the direct-sum rate the band policy used (1, or the tuned choice) */
@@ -147,6 +147,16 @@ int flt_forward(flt_plan* plan, const void* c, void* f, void* stream);
 /* Derivative: fp[j] ~ f'(z_j) = sum_{k<N} 2 pi i k c_k w_j^k, i.e. Alg. 2
  * applied to c'_k = 2 pi i k c_k; error <= eps * sum_k |2 pi k c_k|. */
 int flt_derivative(flt_plan* plan, const void* c, void* fp, void* stream);
+
+/* Forward and derivative in one pass: f as flt_forward, fp as flt_derivative,
+ * with the derivative's q columns per band transformed alongside the
+ * forward's (2q columns; the interpolant rows, cell positions, window weights
+ * and node-side weights are shared).  f, fp: device complex[M], distinct,
+ * overwritten.  The workspace of flt_plan_workspace_size covers this call.
+ * Errors as for flt_forward; fp null or equal to f is FLT_EINVAL.  For callers
+ * that need both values, e.g. an autograd forward that keeps f' for the
+ * gradient with respect to z. */
+int flt_forward_derivative(flt_plan* plan, const void* c, void* f, void* fp, void* stream);
 
 /* Adjoint (Sect. 4, closing remarks: C^* by the adjoints of the K and A
  * factors): c_out[k] ~ sum_{j<M} g_j conj(w_j)^k, k < N.

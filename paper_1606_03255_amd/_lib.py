@@ -25,7 +25,7 @@ ERRORS = {
 EXPORTS = (
     "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
-    "flt_profile_forward", "flt_strerror", "flt_last_hip_error",
+    "flt_forward_derivative", "flt_profile_forward", "flt_strerror", "flt_last_hip_error",
 )
 
 
@@ -84,6 +84,7 @@ def load():
     lib.flt_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
     for name in ("flt_forward", "flt_derivative", "flt_adjoint"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
+    lib.flt_forward_derivative.argtypes = [vp, vp, vp, vp, vp]
     lib.flt_profile_forward.argtypes = [vp, vp, vp, vp, P(ctypes.c_double)]
     lib.flt_strerror.argtypes = [ctypes.c_int]
     lib.flt_strerror.restype = ctypes.c_char_p

@@ -21,6 +21,7 @@ static thread_local int g_last_hip = 0;
 struct GraphSlot {
     const void* in = nullptr;
     void* out = nullptr;
+    void* out2 = nullptr;
     char* ws = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -36,7 +37,7 @@ struct flt_plan {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t capture = nullptr;   // FLT_FLAG_GRAPH: stream the sequences are captured on
-    GraphSlot graphs[3];             // forward, derivative, adjoint
+    GraphSlot graphs[4];             // forward, derivative, adjoint, forward + derivative
 };
 
 static int hip_fail(hipError_t e)
@@ -106,6 +107,8 @@ static int upload(flt_plan* p)
     const size_t o_l2 = pk.add(hp.passB.data(), hp.passB.size() * sizeof(FftItem));
     const size_t o_l3 = pk.add(hp.onepass_adj.data(), hp.onepass_adj.size() * sizeof(FftItem));
     const size_t o_l4 = pk.add(hp.passA_adj.data(), hp.passA_adj.size() * sizeof(FftItem));
+    const size_t o_lf0 = pk.add(hp.onepass_fused.data(), hp.onepass_fused.size() * sizeof(FftItem));
+    const size_t o_lf2 = pk.add(hp.passB_fused.data(), hp.passB_fused.size() * sizeof(FftItem));
     const size_t o_l5 = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
     const size_t o_l6 = pk.add(hp.cells.data(), hp.cells.size() * sizeof(CellItem));
     const size_t o_l7 = pk.add(hp.nfft_nodes.data(), hp.nfft_nodes.size() * sizeof(NodeItem));
@@ -133,6 +136,10 @@ static int upload(flt_plan* p)
     L.passB = (const FftItem*)(base + o_l2);
     L.onepass_adj = (const FftItem*)(base + o_l3);
     L.passA_adj = (const FftItem*)(base + o_l4);
+    L.onepass_fused = (const FftItem*)(base + o_lf0);
+    L.passB_fused = (const FftItem*)(base + o_lf2);
+    L.n_onepass_fused = (int)hp.onepass_fused.size();
+    L.n_passB_fused = (int)hp.passB_fused.size();
     L.nodes = (const NodeItem*)(base + o_l5);
     L.cells = (const CellItem*)(base + o_l6);
     L.nfft_nodes = (const NodeItem*)(base + o_l7);
@@ -168,7 +175,7 @@ static int upload(flt_plan* p)
 static const uint32_t KNOWN_FLAGS = FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY | FLT_FLAG_GRAPH | FLT_FLAG_AUTOTUNE;
 
 static void release(flt_plan* p);
-static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, hipStream_t st);
+static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, void* out2, hipStream_t st);
 
 // FLT_FLAG_AUTOTUNE: the band policy's direct-sum rate factor chosen by timing
 // forward + adjoint of candidate plans, cached per (dtype, eps, instances,
@@ -209,12 +216,12 @@ int time_candidate(flt_plan* p, double* ms)
         p->ws = (char*)ws;
         p->ws_bytes = hp.ws_bytes;
         const int reps = 3;
-        e = enqueue(p, 0, c, f, st);                       // warm-up
-        if (e == hipSuccess) e = enqueue(p, 2, g, h, st);
+        e = enqueue(p, 0, c, f, nullptr, st);                       // warm-up
+        if (e == hipSuccess) e = enqueue(p, 2, g, h, nullptr, st);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
-            e = enqueue(p, 0, c, f, st);
-            if (e == hipSuccess) e = enqueue(p, 2, g, h, st);
+            e = enqueue(p, 0, c, f, nullptr, st);
+            if (e == hipSuccess) e = enqueue(p, 2, g, h, nullptr, st);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -450,31 +457,34 @@ static int check_call(const flt_plan* p, const void* a, const void* b)
     return FLT_OK;
 }
 
-// op 0: forward, 1: derivative, 2: adjoint; enqueues the launch sequence on st.
-static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, hipStream_t st)
+// op 0: forward, 1: derivative, 2: adjoint, 3: forward (out) and derivative
+// (out2) in one pass; enqueues the launch sequence on st.
+static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, void* out2, hipStream_t st)
 {
     const WsLayout W = layout(p);
     if (op == 2)
         return p->hp.dtype == FLT_C64 ? launch_adjoint<float>(p->lists, p->pv32, W, in, out, st)
                                       : launch_adjoint<double>(p->lists, p->pv64, W, in, out, st);
-    return p->hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, in, out, op, st)
-                                  : launch_forward<double>(p->lists, p->pv64, W, in, out, op, st);
+    void* f2 = op == 3 ? out2 : nullptr;
+    const int deriv = op == 1;
+    return p->hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, in, out, f2, deriv, st)
+                                  : launch_forward<double>(p->lists, p->pv64, W, in, out, f2, deriv, st);
 }
 
 // FLT_FLAG_GRAPH: replay the captured sequence when the buffers match the last
 // capture of this operation, else capture anew on the plan's own stream (the
 // kernels do not run during capture) and launch the graph on the caller's.
-static hipError_t run_graph(flt_plan* p, int op, const void* in, void* out, hipStream_t st)
+static hipError_t run_graph(flt_plan* p, int op, const void* in, void* out, void* out2, hipStream_t st)
 {
     GraphSlot& g = p->graphs[op];
-    if (!g.exec || g.in != in || g.out != out || g.ws != p->ws) {
+    if (!g.exec || g.in != in || g.out != out || g.out2 != out2 || g.ws != p->ws) {
         if (g.exec) {
             (void)hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
         }
         hipError_t e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return e;
-        const hipError_t le = enqueue(p, op, in, out, p->capture);
+        const hipError_t le = enqueue(p, op, in, out, out2, p->capture);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(p->capture, &graph);
         if (le != hipSuccess || e != hipSuccess) {
@@ -489,17 +499,19 @@ static hipError_t run_graph(flt_plan* p, int op, const void* in, void* out, hipS
         }
         g.in = in;
         g.out = out;
+        g.out2 = out2;
         g.ws = p->ws;
     }
     return hipGraphLaunch(g.exec, st);
 }
 
-static int run(flt_plan* p, int op, const void* in, void* out, void* stream)
+static int run(flt_plan* p, int op, const void* in, void* out, void* stream, void* out2 = nullptr)
 {
     const int rc = check_call(p, in, out);
     if (rc != FLT_OK) return rc;
-    const hipError_t e = p->capture ? run_graph(p, op, in, out, (hipStream_t)stream)
-                                    : enqueue(p, op, in, out, (hipStream_t)stream);
+    if (op == 3 && (!out2 || out2 == out)) return FLT_EINVAL;
+    const hipError_t e = p->capture ? run_graph(p, op, in, out, out2, (hipStream_t)stream)
+                                    : enqueue(p, op, in, out, out2, (hipStream_t)stream);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
 
@@ -508,6 +520,11 @@ int flt_forward(flt_plan* p, const void* c, void* f, void* stream) { return run(
 int flt_derivative(flt_plan* p, const void* c, void* fp, void* stream) { return run(p, 1, c, fp, stream); }
 
 int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream) { return run(p, 2, g, c_out, stream); }
+
+int flt_forward_derivative(flt_plan* p, const void* c, void* f, void* fp, void* stream)
+{
+    return run(p, 3, c, f, stream, fp);
+}
 
 int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, double* stage_ms)
 {
@@ -520,8 +537,9 @@ int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, doubl
     for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     const WsLayout W = layout(p);
     if (e == hipSuccess)
-        e = hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, c, f, 0, (hipStream_t)stream, ev)
-                                : launch_forward<double>(p->lists, p->pv64, W, c, f, 0, (hipStream_t)stream, ev);
+        e = hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, c, f, nullptr, 0, (hipStream_t)stream, ev)
+                                : launch_forward<double>(p->lists, p->pv64, W, c, f, nullptr, 0, (hipStream_t)stream,
+                                                         ev);
     if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
     for (int i = 0; i < 5 && e == hipSuccess; ++i) {
         float ms = 0;

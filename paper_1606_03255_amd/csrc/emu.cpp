@@ -60,11 +60,11 @@ template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body
 
 template <typename T, int MW>
 static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, const cplx<T>* c, cplx<T>* grids,
-                     cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0)
+                     cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0, cplx<T>* f2)
 {
     if (!adjoint) {
         run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-            body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0);
+            body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0, f2);
         });
         return;
     }
@@ -100,8 +100,9 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     pv.kb_b = (T)hp.kb_b;
 
     // exactly sized buffers, so AddressSanitizer sees any out-of-range access
-    std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems, 1));
-    std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems, 1));
+    const int cols = op == 3 ? 2 : 1;   // op 3: forward and derivative, 2q columns per band
+    std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems * cols, 1));
+    std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems * cols, 1));
     std::vector<cplx<T>> U((size_t)hp.M * hp.qs);
     std::vector<T> Phi((size_t)hp.M * 2 * hp.mw);
     std::vector<int32_t> L0(hp.M);
@@ -113,53 +114,57 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         if (B.q > 0 && !B.direct && B.log2n2 > 0) base_elems = std::max(base_elems, B.base_off + ((int64_t)1 << B.log2n));
     std::vector<cplx<T>> basebuf(base_elems);
     const int64_t nd = (int64_t)hp.dlist.size();
-    auto mwsw = [&](int adjoint, const cplx<T>* c, cplx<T>* f, int with_c0) {
+    auto mwsw = [&](int adjoint, const cplx<T>* c, cplx<T>* f, int with_c0, cplx<T>* f2) {
         switch (hp.mw) {
-#define G(MWV) case MWV: nodes_mw<T, MWV>(pv, hp, adjoint, c, grids.data(), f, with_c0, U.data(), Phi.data(), L0.data()); break;
+#define G(MWV) case MWV: nodes_mw<T, MWV>(pv, hp, adjoint, c, grids.data(), f, with_c0, U.data(), Phi.data(), L0.data(), f2); break;
             G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
 #undef G
         }
     };
-    if (op == 0 || op == 1) {
+    if (op == 0 || op == 1 || op == 3) {
         const cplx<T>* c = (const cplx<T>*)in;
         cplx<T>* f = (cplx<T>*)out;
+        cplx<T>* f2 = op == 3 ? f + hp.M : nullptr;   // op 3: out holds f, then f'
         const int deriv = op == 1;
         constexpr int LP = Sizes<T>::LOG2P;
-        for (const LaunchGroup& g : hp.g_onepass_fwd)
+        const std::vector<FftItem>& one = cols == 2 ? hp.onepass_fused : hp.onepass_fwd;
+        const std::vector<FftItem>& pb = cols == 2 ? hp.passB_fused : hp.passB;
+        for (const LaunchGroup& g : (cols == 2 ? hp.g_onepass_fused : hp.g_onepass_fwd))
             with_log2<4, LP>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
-                    body_onepass_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.onepass_fwd.data() + g.start, c,
-                                                                      grids.data(), deriv, lds.data());
+                    body_onepass_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, one.data() + g.start, c,
+                                                                      grids.data(), deriv, cols, lds.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_passA_fwd)
             with_log2<LP + 1, TW2_LOG2>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
-                                                                    scratch.data(), basebuf.data(), deriv, lds.data(),
-                                                                    lc.data());
+                                                                    scratch.data(), basebuf.data(), deriv, cols,
+                                                                    lds.data(), lc.data());
                 });
             });
-        if (!hp.passB.empty()) {
+        if (!pb.empty()) {
             // persistent: a few workgroups, each taking every nb-th item
-            const int n = (int)hp.passB.size();
+            const int n = (int)pb.size();
             const int nb = passB_prefetch<T, +1>() ? std::min(n, EMU_PERSIST_BLOCKS) : n;
             run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
-                body_passB<HostCtx, T, +1>(ctx, pv, hp.passB.data(), n, nb, scratch.data(), grids.data(), lds.data());
+                body_passB<HostCtx, T, +1>(ctx, pv, pb.data(), n, nb, scratch.data(), grids.data(), cols, lds.data());
             });
         }
-        mwsw(0, c, f, !deriv);
-        if (nd) {
+        mwsw(0, c, f, !deriv, f2);
+        for (int d = 0; d < cols && nd; ++d) {
+            cplx<T>* o = d ? f2 : f;
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
-                body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 0);
+                body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 0);
             });
             std::vector<cplx<T>> nw(DIRECT_NG);
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
-                body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, deriv, dacc.data(),
-                                            red.data(), nw.data());
+                body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, deriv || d,
+                                            dacc.data(), red.data(), nw.data());
             });
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
-                body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), f, 1);
+                body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 1);
             });
         }
         return FLT_OK;
@@ -171,13 +176,13 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         run_blocks(hp.sum_items.size(), 256, [&](const HostCtx& ctx) {
             body_sum_g<HostCtx, T>(ctx, pv, hp.sum_items.data(), g, acc.data(), red.data());
         });
-        mwsw(1, g, nullptr, 0);
+        mwsw(1, g, nullptr, 0, nullptr);
         constexpr int LP = Sizes<T>::LOG2P;
         if (!hp.passB.empty()) {
             const int n = (int)hp.passB.size();
             const int nb = passB_prefetch<T, -1>() ? std::min(n, EMU_PERSIST_BLOCKS) : n;
             run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
-                body_passB<HostCtx, T, -1>(ctx, pv, hp.passB.data(), n, nb, grids.data(), scratch.data(), lds.data());
+                body_passB<HostCtx, T, -1>(ctx, pv, hp.passB.data(), n, nb, grids.data(), scratch.data(), 1, lds.data());
             });
         }
         for (const LaunchGroup& g : hp.g_passA_adj)
@@ -207,6 +212,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
 
 }  // namespace flt
 
+// The kernel bodies on the CPU for one call: op 0 forward, 1 derivative,
+// 2 adjoint, 3 forward and derivative in one pass (out: f, then f', 2M values).
 extern "C" int flt_emu_run(int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags, int op,
                            const void* in, void* out)
 {

@@ -25,12 +25,13 @@ struct DevCtx {
 // its band's transform length.
 template <typename T>
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, const FftItem* items,
-                                                                const cplx<T>* c, cplx<T>* grids, int deriv)
+                                                                const cplx<T>* c, cplx<T>* grids, int deriv,
+                                                                int cols)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, lds);
+        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, cols, lds);
     });
 }
 
@@ -38,13 +39,14 @@ template <typename T>
 // four waves per SIMD (two workgroups per CU, as the LDS allows)
 __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
                                                               const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf,
-                                                              int deriv)
+                                                              int deriv, int cols)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
     __shared__ alignas(16) T lc[Sizes<T>::COEF];
     using RG = Log2Range<T>;
     with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, lds, lc);
+        body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, cols, lds,
+                                                       lc);
     });
 }
 
@@ -52,17 +54,18 @@ template <typename T, int SIGN>
 // four waves per SIMD (two workgroups per CU, as the LDS allows): the
 // register budget the prefetched tile has to fit in
 __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passB(PlanView<T> pv, const FftItem* items, int nitems,
-                                                          const cplx<T>* src, cplx<T>* dst)
+                                                          const cplx<T>* src, cplx<T>* dst, int cols)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    body_passB<DevCtx, T, SIGN>(DevCtx(), pv, items, nitems, (int)gridDim.x, src, dst, lds);
+    body_passB<DevCtx, T, SIGN>(DevCtx(), pv, items, nitems, (int)gridDim.x, src, dst, cols, lds);
 }
 
 template <typename T, int MW>
 __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PlanView<T> pv, const NodeItem* items, const cplx<T>* c,
-                                                           const cplx<T>* grids, cplx<T>* f, int with_c0)
+                                                           const cplx<T>* grids, cplx<T>* f, int with_c0,
+                                                           cplx<T>* f2)
 {
-    body_gather<DevCtx, T, MW>(DevCtx(), pv, items, c, grids, f, with_c0);
+    body_gather<DevCtx, T, MW>(DevCtx(), pv, items, c, grids, f, with_c0, f2);
 }
 
 template <typename T, int MW>
@@ -176,25 +179,28 @@ static int grid_for(int64_t work, int per_block)
 
 template <typename T>
 static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const cplx<T>* c,
-                                     int deriv, hipStream_t st, hipEvent_t* ev)
+                                     int deriv, int cols, hipStream_t st, hipEvent_t* ev)
 {
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
     cplx<T>* basebuf = (cplx<T>*)(W.ws + W.off_base);
+    // cols = 2: the item lists over 2q columns per band
+    const FftItem* one = cols == 2 ? L.onepass_fused : L.onepass_fwd;
+    const int n_one = cols == 2 ? L.n_onepass_fused : L.n_onepass_fwd;
+    const FftItem* pb = cols == 2 ? L.passB_fused : L.passB;
+    const int n_pb = cols == 2 ? L.n_passB_fused : L.n_passB;
     if (ev) (void)hipEventRecord(ev[0], st);
-    if (L.n_onepass_fwd)
-        hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(L.n_onepass_fwd), dim3(FFT_THREADS), 0, st, pv, L.onepass_fwd, c,
-                           grids, deriv);
+    if (n_one)
+        hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(n_one), dim3(FFT_THREADS), 0, st, pv, one, c, grids, deriv, cols);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (L.n_passA_fwd)
         hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
-                           scratch, basebuf, deriv);
+                           scratch, basebuf, deriv, cols);
     if (ev) (void)hipEventRecord(ev[2], st);
-    if (L.n_passB)
+    if (n_pb)
         hipLaunchKernelGGL((k_passB<T, +1>),
-                           dim3(passB_prefetch<T, +1>() ? std::min(L.n_passB, L.persist_blocks) : L.n_passB),
-                           dim3(FFT_THREADS), 0, st,
-                           pv, L.passB, L.n_passB, (const cplx<T>*)scratch, grids);
+                           dim3(passB_prefetch<T, +1>() ? std::min(n_pb, L.persist_blocks) : n_pb),
+                           dim3(FFT_THREADS), 0, st, pv, pb, n_pb, (const cplx<T>*)scratch, grids, cols);
     if (ev) (void)hipEventRecord(ev[3], st);
     return hipSuccess;
 }
@@ -207,7 +213,7 @@ static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, c
         hipLaunchKernelGGL((k_passB<T, -1>),
                            dim3(passB_prefetch<T, -1>() ? std::min(L.n_passB, L.persist_blocks) : L.n_passB),
                            dim3(FFT_THREADS), 0, st,
-                           pv, L.passB, L.n_passB, (const cplx<T>*)grids, scratch);
+                           pv, L.passB, L.n_passB, (const cplx<T>*)grids, scratch, 1);
     if (L.n_passA_adj) {
         if constexpr (std::is_same<T, float>::value)
             hipLaunchKernelGGL(k_passA_adj_f32, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
@@ -224,10 +230,10 @@ static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, c
 
 template <typename T, int MW>
 static void mw_forward_nodes(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, const cplx<T>* grids,
-                             cplx<T>* f, int with_c0, hipStream_t st)
+                             cplx<T>* f, int with_c0, cplx<T>* f2, hipStream_t st)
 {
     hipLaunchKernelGGL((k_gather<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, c, grids, f,
-                       with_c0);
+                       with_c0, f2);
 }
 
 template <typename T, int MW>
@@ -247,18 +253,20 @@ static void mw_adjoint_nodes(const DevLists& L, const PlanView<T>& pv, const WsL
 
 template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* cv, void* fv,
-                          int deriv, hipStream_t st, hipEvent_t* ev)
+                          void* f2v, int deriv, hipStream_t st, hipEvent_t* ev)
 {
     const cplx<T>* c = (const cplx<T>*)cv;
     cplx<T>* f = (cplx<T>*)fv;
+    cplx<T>* f2 = (cplx<T>*)f2v;   // non-null: the derivative too, in the same pass (2q columns per band)
+    const int cols = f2 ? 2 : 1;
+    if (f2) deriv = 0;
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
-    cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
     double* dacc = (double*)(W.ws + W.off_dacc);
-    hipError_t e = fft_forward_stages<T>(L, pv, W, c, deriv, st, ev);
+    hipError_t e = fft_forward_stages<T>(L, pv, W, c, deriv, cols, st, ev);
     if (e != hipSuccess) return e;
     if (L.n_nodes) {
         switch (pv.mw) {
-#define G(MWV) case MWV: mw_forward_nodes<T, MWV>(L, pv, c, grids, f, !deriv, st); break;
+#define G(MWV) case MWV: mw_forward_nodes<T, MWV>(L, pv, c, grids, f, !deriv, f2, st); break;
             G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
 #undef G
             default: return hipErrorInvalidValue;
@@ -267,10 +275,13 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
     if (ev) (void)hipEventRecord(ev[4], st);
     if (L.n_dlist) {
         const int gb = (int)((L.n_dlist + 255) / 256);
-        hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, f, 0);
-        hipLaunchKernelGGL(k_direct_fwd<T>, dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd, L.dlist, c,
-                           deriv, dacc);
-        hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, f, 1);
+        for (int d = 0; d < cols; ++d) {   // direct bands: exact sums, of c and (cols = 2) of c'
+            cplx<T>* out = d ? f2 : f;
+            hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 0);
+            hipLaunchKernelGGL(k_direct_fwd<T>, dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd, L.dlist,
+                               c, deriv || d, dacc);
+            hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 1);
+        }
     }
     if (ev) (void)hipEventRecord(ev[5], st);
     return hipGetLastError();
@@ -303,9 +314,9 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayo
 }
 
 template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,
-                                          void*, int, hipStream_t, hipEvent_t*);
+                                          void*, void*, int, hipStream_t, hipEvent_t*);
 template hipError_t launch_forward<double>(const DevLists&, const PlanView<double>&, const WsLayout&, const void*,
-                                           void*, int, hipStream_t, hipEvent_t*);
+                                           void*, void*, int, hipStream_t, hipEvent_t*);
 template hipError_t launch_adjoint<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,
                                           void*, hipStream_t);
 template hipError_t launch_adjoint<double>(const DevLists&, const PlanView<double>&, const WsLayout&, const void*,

@@ -434,9 +434,12 @@ FLT_HD double frac_kx(double k, double x)
 // ---------------------------------------------------------------------------
 // a2-a4, one-pass bands: generate `ns` columns, FFT them in LDS, store.
 // ---------------------------------------------------------------------------
+// cols = 2 (forward and derivative in one pass): the band has 2q columns,
+// column q + s being column s of the derivative transform; the band's grid
+// region is then twice as long (offsets doubled).
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                             const cplx<T>* c, cplx<T>* grids, int deriv, cplx<T>* lds)
+                             const cplx<T>* c, cplx<T>* grids, int deriv, int cols, cplx<T>* lds)
 {
     // columns per workgroup: a full tile, but never more than a band has (q <= MAX_Q)
     constexpr int NSUB = (tile_points<T>() >> LOG2N) < MAX_Q ? (tile_points<T>() >> LOG2N) : MAX_Q;
@@ -447,12 +450,15 @@ FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftIte
     stw.load(ctx, pv.tw_stage);
     for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
         const int sl = p >> LOG2N;
-        lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, it.s0 + sl, p & ((1 << LOG2N) - 1), deriv)
-                            : mk<T>(0, 0);
+        const int s = it.s0 + sl;
+        const bool dcol = s >= B.q;   // a derivative column (cols = 2)
+        lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, dcol ? s - B.q : s, p & ((1 << LOG2N) - 1),
+                                                 deriv || dcol)
+                                    : mk<T>(0, 0);
     }
     ctx.sync();
     lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, stw);
-    cplx<T>* out = grids + B.grid_off + ((int64_t)it.s0 << LOG2N);
+    cplx<T>* out = grids + B.grid_off * cols + ((int64_t)it.s0 << LOG2N);
     const int Pv = it.ns << LOG2N;
     for (int p = ctx.tid(); p < Pv; p += FFT_THREADS) out[p] = lds[lds_at(p)];
 }
@@ -473,7 +479,8 @@ template <typename T, int LOG2N> struct TwoPassGeo {
 
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                           const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf, int deriv, cplx<T>* lds, T* lc)
+                           const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf, int deriv, int cols,
+                           cplx<T>* lds, T* lc)
 {
     using G = TwoPassGeo<T, LOG2N>;
     constexpr int ITEMS = tile_items<T>();
@@ -494,8 +501,11 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     // cost the second workgroup per CU)
     typename TwSel<sizeof(T) == 4, T, LOG2N1, (1 << log2b), +1>::type stw;
     stw.load(ctx, pv.tw_stage);
-    for (int s = 0; s < B.q; ++s) {
-        stage_coef(ctx, pv, B, s, lc);
+    // cols = 2: columns q .. 2q - 1 are the derivative's, the same interpolant
+    // rows times 2 pi i k (base slot shared)
+    for (int s = 0; s < cols * B.q; ++s) {
+        const bool dcol = s >= B.q;
+        stage_coef(ctx, pv, B, dcol ? s - B.q : s, lc);
         if (s == 0) {
 #pragma unroll 1   // one point at a time: keeps the kernel at four waves per SIMD
             for (int i = 0; i < ITEMS; ++i) {
@@ -525,7 +535,13 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         auto finish = [&](int i0, const cplx<T>* base, const int* kk) {
             for (int u = 0; u < GU; ++u) {
                 const int p = ctx.tid() + (i0 + u) * FFT_THREADS;
-                lds[lds_at(p)] = kk[u] > 0 ? scale(base[u], laplace_row_lds(lc, B, kk[u])) : mk<T>(0, 0);
+                T w = kk[u] > 0 ? laplace_row_lds(lc, B, kk[u]) : T(0);
+                cplx<T> b = base[u];
+                if (dcol) {   // c'_k = 2 pi i k c_k
+                    w *= (T)(6.283185307179586476925286766559 * (double)kk[u]);
+                    b = mk(-b.y, b.x);
+                }
+                lds[lds_at(p)] = kk[u] > 0 ? scale(b, w) : mk<T>(0, 0);
             }
         };
         if (s == 0) {
@@ -556,7 +572,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         }
         ctx.sync();
         lds_fft_ct<Ctx, T, LOG2N1, (1 << log2b), +1>(ctx, lds, stw);
-        cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << LOG2N);
+        cplx<T>* Y = scratch + B.scratch_off * cols + ((int64_t)s << LOG2N);
         // in groups of GO points: the group's table reads first (in flight
         // together), then the products and stores
         constexpr int GO = sizeof(T) == 4 ? 8 : 4;
@@ -648,12 +664,12 @@ template <> struct TileRegs<double> {
 // run m, bit u for its element u), applied when the tile goes to LDS.
 template <class Ctx, typename T, int LOG2N2, bool ADJ>
 FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it, const cplx<T>* src_base,
-                        TileRegs<T>& v, uint32_t* bits)
+                        int cols, TileRegs<T>& v, uint32_t* bits)
 {
     using G = PassBGeo<T, LOG2N2>;
     const BandDesc& B = pv.bands[it.band];
     const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
-    const cplx<T>* src = src_base + (ADJ ? B.grid_off : B.scratch_off) + blk_off;
+    const cplx<T>* src = src_base + (ADJ ? B.grid_off : B.scratch_off) * cols + blk_off;
     const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (Sizes<T>::LOG2P - 5));
     for (int m = 0; m < tile_items<T>() / G::V; ++m) {
         const int ch = ctx.tid() + m * FFT_THREADS;
@@ -675,7 +691,7 @@ template <typename T, int SIGN> constexpr bool passB_prefetch() { return sizeof(
 // index of the workgroup's first item not processed.
 template <class Ctx, typename T, int LOG2N2, int SIGN>
 FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* items, int i, int nitems, int nblocks,
-                     const cplx<T>* src_base, cplx<T>* dst_base, cplx<T>* lds)
+                     const cplx<T>* src_base, cplx<T>* dst_base, int cols, cplx<T>* lds)
 {
     constexpr bool ADJ = SIGN < 0;
     constexpr bool PREFETCH = passB_prefetch<T, SIGN>();
@@ -684,7 +700,7 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
     constexpr int RUNS = tile_items<T>() / G::V;
     TileRegs<T> v;
     uint32_t bits[RUNS];
-    passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, v, bits);
+    passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, cols, v, bits);
     // with prefetch the registers hold the next tile instead of the twiddles
     typename TwSel<!PREFETCH, T, LOG2N2, (1 << G::log2B), SIGN>::type stw;
     stw.load(ctx0, pv.tw_stage);
@@ -700,10 +716,11 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
         ctx.sync();
         const int nx = i + nblocks;
         const bool more = nx < nitems && pv.bands[items[nx].band].log2n2 == LOG2N2;
-        if (PREFETCH && more) passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, v, bits);
+        if (PREFETCH && more)
+            passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, cols, v, bits);
         lds_fft_ct<IterCtx<Ctx>, T, LOG2N2, (1 << G::log2B), SIGN>(ctx, lds, stw);
         const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
-        cplx<T>* dst = dst_base + (ADJ ? B.scratch_off : B.grid_off) + blk_off;
+        cplx<T>* dst = dst_base + (ADJ ? B.scratch_off : B.grid_off) * cols + blk_off;
         const uint32_t* mask = pv.mask + B.mask_off + ((int64_t)it.blk << (Sizes<T>::LOG2P - 5));
         for (int t = ctx.tid(); t < CHUNKS; t += FFT_THREADS) {
             const int l2 = t & ((1 << LOG2N2) - 1);
@@ -723,7 +740,7 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
 // (forward: scratch -> grids, SIGN = +1; adjoint: grids -> scratch, SIGN = -1).
 template <class Ctx, typename T, int SIGN>
 FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items, int nitems, int nblocks,
-                       const cplx<T>* src_base, cplx<T>* dst_base, cplx<T>* lds)
+                       const cplx<T>* src_base, cplx<T>* dst_base, int cols, cplx<T>* lds)
 {
     using RG = Log2Range<T>;
     int i = ctx.bid();
@@ -731,14 +748,14 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
         if (i < nitems)
             with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
                 passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nitems, src_base, dst_base,
-                                                             lds);
+                                                             cols, lds);
             });
         return;
     }
     while (i < nitems) {
         with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
             i = passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nblocks, src_base, dst_base,
-                                                             lds);
+                                                             cols, lds);
         });
     }
 }
@@ -790,9 +807,11 @@ FLT_HD double bary_at(const double* yc, const BaryY& b, int s, double y)
 // a5 + a6: per node, gather the window from the q grids, weight by L_s(y),
 // sum in FP64, modulate by e^{2 pi i k0 x} and add c0.
 // ---------------------------------------------------------------------------
+// f2 != null (cols = 2): columns q .. 2q - 1 of each band hold the derivative
+// transform's grids, whose sums go to f2 (no c_0 term: c'_0 = 0).
 template <class Ctx, typename T, int MW>
 FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items,
-                        const cplx<T>* c, const cplx<T>* grids, cplx<T>* f, int with_c0)
+                        const cplx<T>* c, const cplx<T>* grids, cplx<T>* f, int with_c0, cplx<T>* f2)
 {
     const NodeItem it = items[ctx.bid()];
     const int i = ctx.tid();
@@ -804,6 +823,7 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     const double c0i = with_c0 ? (double)c[B.c_off].y : 0.0;
     if (B.q == 0) {
         f[dst] = mk<T>((T)c0r, (T)c0i);
+        if (f2) f2[dst] = mk<T>(0, 0);
         return;
     }
     const double x = pv.nx[jj], y = pv.ny[jj];
@@ -818,8 +838,8 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     const BaryY by = bary_setup(yc, B.q, y);
     int64_t addr[2 * MW];
     for (int t = 0; t < 2 * MW; ++t) addr[t] = grid_addr(B, (l0 - MW + 1 + t) & nmask);
-    const cplx<T>* g = grids + B.grid_off;
-    double ar = 0, ai = 0;
+    const cplx<T>* g = grids + B.grid_off * (f2 ? 2 : 1);
+    double ar = 0, ai = 0, dr = 0, di = 0;
     for (int s = 0; s < B.q; ++s) {
         const cplx<T>* gs = g + ((int64_t)s << log2n);
         T fr = 0, fi = 0;
@@ -831,6 +851,17 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
         const double Ls = bary_at(yc, by, s, y);
         ar += Ls * (double)fr;
         ai += Ls * (double)fi;
+        if (f2) {
+            const cplx<T>* gd = g + ((int64_t)(s + B.q) << log2n);
+            T er = 0, ei = 0;
+            for (int t = 0; t < 2 * MW; ++t) {
+                const cplx<T> v = gd[addr[t]];
+                er += v.x * phi[t];
+                ei += v.y * phi[t];
+            }
+            dr += Ls * (double)er;
+            di += Ls * (double)ei;
+        }
     }
     // e^{2 pi i k0 x}: k0 is 0 or a power of two, so k0 x and its fraction are exact
     double ph = (double)B.k0 * x;
@@ -838,6 +869,7 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     double sn, cs;
     sincos(6.283185307179586476925286766559 * ph, &sn, &cs);
     f[dst] = mk<T>((T)(c0r + ar * cs - ai * sn), (T)(c0i + ar * sn + ai * cs));
+    if (f2) f2[dst] = mk<T>((T)(dr * cs - di * sn), (T)(dr * sn + di * cs));
 }
 
 // ---------------------------------------------------------------------------

@@ -15,6 +15,8 @@ struct DevLists {
     const FftItem* passB = nullptr;
     const FftItem* onepass_adj = nullptr;
     const FftItem* passA_adj = nullptr;
+    const FftItem* onepass_fused = nullptr;   // forward + derivative: 2q columns per band
+    const FftItem* passB_fused = nullptr;
     const CellItem* cells = nullptr;
     const NodeItem* nodes = nullptr;
     const NodeItem* nfft_nodes = nullptr;
@@ -27,6 +29,7 @@ struct DevLists {
     int n_sum = 0;
     int persist_blocks = 512;   // workgroups of the persistent FFT kernels (two per compute unit)
     int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_cells = 0;
+    int n_onepass_fused = 0, n_passB_fused = 0;
     int n_nodes = 0, n_nfft_nodes = 0, n_direct_fwd = 0, n_direct_adj = 0;
     int64_t n_dlist = 0;
     // host copies of the FFT launch groups (one kernel instance per transform length)
@@ -42,12 +45,14 @@ struct WsLayout {
     int64_t N = 0, M = 0, grid_elems = 0;
 };
 
-// a2-a6 (forward, or derivative when deriv != 0): c -> f on stream st.  If ev
-// is not null, ev[0..5] are recorded on st before the first launch and after
-// each stage (one-pass FFTs, pass A, pass B, gather, direct bands).
+// a2-a6 (forward, or derivative when deriv != 0): c -> f on stream st; with
+// f2 not null, the forward into f and the derivative into f2 in one pass (2q
+// columns per band).  If ev is not null, ev[0..5] are recorded on st before
+// the first launch and after each stage (one-pass FFTs, pass A, pass B,
+// gather, direct bands).
 template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* c, void* f,
-                          int deriv, hipStream_t st, hipEvent_t* ev = nullptr);
+                          void* f2, int deriv, hipStream_t st, hipEvent_t* ev = nullptr);
 
 // a7 (adjoint): g -> c_out on stream st.
 template <typename T>

@@ -355,6 +355,8 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
             for (int k = 0; k < nA; ++k) hp.passA_fwd.push_back(FftItem{b, 0, B.q, k});
             for (int s = 0; s < B.q; ++s)
                 for (int k = 0; k < nB; ++k) hp.passB.push_back(FftItem{b, s, 1, k});
+            for (int s = 0; s < 2 * B.q; ++s)
+                for (int k = 0; k < nB; ++k) hp.passB_fused.push_back(FftItem{b, s, 1, k});
             for (int k = 0; k < nA; ++k) hp.passA_adj.push_back(FftItem{b, 0, B.q, k});
         } else {
             const int ns = std::max(1, std::min(B.q, std::min(MAX_Q, 1 << (LOG2P - B.log2n))));
@@ -362,6 +364,9 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
                 hp.onepass_fwd.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
                 hp.onepass_adj.push_back(FftItem{b, s0, std::min(ns, B.q - s0), 0});
             }
+            const int ns2 = std::max(1, std::min(2 * B.q, std::min(MAX_Q, 1 << (LOG2P - B.log2n))));
+            for (int s0 = 0; s0 < 2 * B.q; s0 += ns2)
+                hp.onepass_fused.push_back(FftItem{b, s0, std::min(ns2, 2 * B.q - s0), 0});
         }
         hp.qs = std::max(hp.qs, B.q);
     }
@@ -448,6 +453,8 @@ static void finish(HostPlan& hp)
     group(hp.passA_fwd, hp.g_passA_fwd, 0);   // pass A instances are per grid length
     group(hp.passA_adj, hp.g_passA_adj, 0);
     group(hp.passB, hp.g_passB, 2);
+    group(hp.onepass_fused, hp.g_onepass_fused, 0);
+    group(hp.passB_fused, hp.g_passB_fused, 2);
     if (hp.cstart.empty()) hp.cstart.push_back(0);
     if (hp.clist.empty()) hp.clist.push_back(-1);
     if (hp.mask.empty()) hp.mask.push_back(0u);
@@ -457,8 +464,10 @@ static void finish(HostPlan& hp)
     const size_t S = hp.elem_bytes();
     auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
     hp.off_grid = 0;
-    hp.off_scratch = al(hp.off_grid + (size_t)hp.grid_elems * S);
-    hp.off_acc = al(hp.off_scratch + (size_t)hp.scratch_elems * S);
+    // grids and pass-A output for 2q columns per band: the size the fused
+    // forward + derivative call needs (the other calls use the first halves)
+    hp.off_scratch = al(hp.off_grid + (size_t)hp.grid_elems * 2 * S);
+    hp.off_acc = al(hp.off_scratch + (size_t)hp.scratch_elems * 2 * S);
     hp.off_U = al(hp.off_acc + (size_t)hp.N * 16);
     hp.off_phi = al(hp.off_U + (size_t)hp.M * hp.qs * S);
     hp.off_l0 = al(hp.off_phi + (size_t)hp.M * 2 * hp.mw * (S / 2));
@@ -562,6 +571,8 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
         shift_fft(out.passB, p.passB);
         shift_fft(out.onepass_adj, p.onepass_adj);
         shift_fft(out.passA_adj, p.passA_adj);
+        shift_fft(out.onepass_fused, p.onepass_fused);
+        shift_fft(out.passB_fused, p.passB_fused);
         const int32_t clo = (int32_t)out.clist.size();
         for (CellItem it : p.cells) {
             it.band += bo;

@@ -38,9 +38,13 @@ struct HostPlan {
 
     // work lists
     std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj;
+    // forward + derivative in one pass: column lists over 2q columns per band
+    // (the derivative's column s is column q + s; pass A's list serves both)
+    std::vector<FftItem> onepass_fused, passB_fused;
     std::vector<CellItem> cells;        // adjoint grid side: cell groups of the NFFT bands
     // FFT item lists are sorted by transform length; one group per length
     std::vector<LaunchGroup> g_onepass_fwd, g_passA_fwd, g_passB, g_onepass_adj, g_passA_adj;
+    std::vector<LaunchGroup> g_onepass_fused, g_passB_fused;
     std::vector<NodeItem> nodes;        // gather: NFFT bands and the constant band
     std::vector<NodeItem> nfft_nodes;   // adjoint node side: NFFT bands only
     std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands

@@ -190,6 +190,22 @@ class Plan:
         """h_k ~ sum_j g_j conj(exp(2 pi i k z_j)), k < N."""
         return self._run(self._lib.flt_adjoint, g, self.M, self.N, out, "g")
 
+    def forward_derivative(self, c, out=None, out_prime=None):
+        """(f, f') in one pass: the forward and the derivative transforms of c."""
+        import torch
+        if self.host_only:
+            raise RuntimeError("host-only plan")
+        c = self._prep(c, self.N, "c")
+        f = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out is None else \
+            self._prep(out, self.M, "out")
+        fp = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out_prime is None else \
+            self._prep(out_prime, self.M, "out_prime")
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(self._lib.flt_forward_derivative(self._ptr, ctypes.c_void_p(c.data_ptr()),
+                                                 ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(fp.data_ptr()),
+                                                 ctypes.c_void_p(stream)), "flt_forward_derivative")
+        return f, fp
+
     def profile_forward(self, c, out=None):
         """One forward with per-stage HIP-event timing; returns (f, stage_ms)
         with stage_ms for (one-pass FFTs, pass A, pass B, gather, direct bands)."""
@@ -227,25 +243,29 @@ def _make_function():
 
         Backward (PyTorch's conjugate-Wirtinger convention):
             dL/dc = C^H grad_f                      (plan.adjoint)
-            dL/dz = grad_f * conj(f'(z))            (plan.derivative)
-        ``z`` must hold the values the plan was built from."""
+            dL/dz = grad_f * conj(f'(z))            (f' from plan.forward_derivative)
+        ``z`` must hold the values the plan was built from.  When z needs a
+        gradient, the forward computes f and f' in one pass and keeps f'."""
 
         @staticmethod
         def forward(ctx, c, z, plan):
             ctx.plan = plan
-            ctx.save_for_backward(c)
             ctx.z_dtype = z.dtype
+            if ctx.needs_input_grad[1]:
+                f, fp = plan.forward_derivative(c)
+                ctx.save_for_backward(fp)
+                return f
+            ctx.save_for_backward(None)
             return plan.forward(c)
 
         @staticmethod
         def backward(ctx, grad_f):
-            (c,) = ctx.saved_tensors
+            (fp,) = ctx.saved_tensors
             plan = ctx.plan
             grad_f = grad_f.to(plan.torch_dtype).contiguous()
             gc = plan.adjoint(grad_f) if ctx.needs_input_grad[0] else None
             gz = None
             if ctx.needs_input_grad[1]:
-                fp = plan.derivative(c.detach())
                 gz = (grad_f * fp.conj()).to(ctx.z_dtype)
             return gc, gz, None
 

@@ -35,7 +35,7 @@ def run(lib, x, z, eps, dt, op, N, flags):
     z = np.ascontiguousarray(z, np.complex128)
     ct = np.complex64 if dt == 1 else np.complex128
     inp = np.ascontiguousarray(x, ct)
-    out = np.zeros(N if op == 2 else len(z), ct)
+    out = np.zeros(N if op == 2 else (2 if op == 3 else 1) * len(z), ct)   # op 3: f, then f'
     rc = lib.flt_emu_run(N, len(z), z.ctypes.data, eps, dt, flags, op, inp.ctypes.data, out.ctypes.data)
     assert rc == 0
     return out.astype(np.complex128)
@@ -64,6 +64,16 @@ def test_cpu_build_vs_oracle(emu, N, M, eps, dt, flags):
     assert np.abs(fp - oracle.derivative(c, z)).max() <= eps * np.abs(2 * np.pi * np.arange(N) * c).sum()
     h = run(emu, g, z, eps, dt, 2, N, flags)
     assert np.abs(h - oracle.adjoint(g, z, N)).max() <= eps * np.abs(g).sum()
+    # forward and derivative in one pass (2q columns per band): the bars, and the
+    # separate calls' values up to rounding
+    ffp = run(emu, c, z, eps, dt, 3, N, flags)
+    f3, fp3 = ffp[:M], ffp[M:]
+    n1, n1d = np.abs(c).sum(), np.abs(2 * np.pi * np.arange(N) * c).sum()
+    assert np.abs(f3 - oracle.forward(c, z)).max() <= eps * n1
+    assert np.abs(fp3 - oracle.derivative(c, z)).max() <= eps * n1d
+    tol = 1e-6 if dt == 1 else 1e-14
+    assert np.abs(f3 - f).max() <= tol * n1
+    assert np.abs(fp3 - fp).max() <= tol * n1d
     if dt == 2 and flags == 2:
         n1 = np.abs(c).sum()
         assert np.abs(f - O.alg2_forward(c, z, eps, "nfft")).max() <= 1e-13 * n1
@@ -88,25 +98,26 @@ def test_cpu_build_batched_equals_single_instances(emu):
     zp = np.ascontiguousarray(np.concatenate(zs))
     co = np.concatenate([[0], np.cumsum(Ns)])
     fo = np.concatenate([[0], np.cumsum(Ms)])
-    runs = [(0, op) for op in (0, 1, 2)] + [(2, 0)]    # NFFT-only: forward (its sparse bands are slow here)
+    runs = [(0, op) for op in (0, 1, 2, 3)] + [(2, 0)]    # NFFT-only: forward (its sparse bands are slow here)
     for flags, op in runs:
         x, nout = (gs, Ns) if op == 2 else (cs, Ms)
         inp = np.ascontiguousarray(np.concatenate(x), np.complex64)
-        out = np.zeros(int(nout.sum()), np.complex64)
+        out = np.zeros(int(nout.sum()) * (2 if op == 3 else 1), np.complex64)   # op 3: all f, then all f'
         rc = emu.flt_emu_run_batch(len(Ns), Ns.ctypes.data, Ms.ctypes.data, zp.ctypes.data, eps, dt, flags, op,
                                    inp.ctypes.data, out.ctypes.data)
         assert rc == 0
         oo = co if op == 2 else fo
-        for i in range(len(Ns)):
-            got = out[oo[i]:oo[i + 1]].astype(np.complex128)
-            scale = np.abs(x[i]).sum() * (1.0 if op != 1 else 2 * np.pi * Ns[i])
-            if flags == 0:
-                single = run(emu, x[i], zs[i], eps, dt, op, int(Ns[i]), flags)
-                assert np.abs(got - single).max() <= 1e-9 * scale, (op, i)
-            if op == 0:
-                ref = oracle.forward(x[i], zs[i])
-            elif op == 1:
-                ref = oracle.derivative(x[i], zs[i])
-            else:
-                ref = oracle.adjoint(x[i], zs[i], int(Ns[i]))
-            assert np.abs(got - ref).max() <= eps * scale, (op, i)
+        for part, kind in ((0, op),) if op != 3 else ((0, 0), (int(Ms.sum()), 1)):
+            for i in range(len(Ns)):
+                got = out[part + oo[i]:part + oo[i + 1]].astype(np.complex128)
+                scale = np.abs(x[i]).sum() * (1.0 if kind != 1 else 2 * np.pi * Ns[i])
+                if flags == 0:
+                    single = run(emu, x[i], zs[i], eps, dt, kind, int(Ns[i]), flags)
+                    assert np.abs(got - single).max() <= 1e-9 * scale, (op, kind, i)
+                if kind == 0:
+                    ref = oracle.forward(x[i], zs[i])
+                elif kind == 1:
+                    ref = oracle.derivative(x[i], zs[i])
+                else:
+                    ref = oracle.adjoint(x[i], zs[i], int(Ns[i]))
+                assert np.abs(got - ref).max() <= eps * scale, (op, kind, i)

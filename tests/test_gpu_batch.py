@@ -116,9 +116,12 @@ def test_graph_replays_match_eager(torch, dtype, eps):
     eager = Plan(N, z, eps, tdt)
     graph = Plan(N, z, eps, tdt, graph=True)
     f0, h0, d0 = eager.forward(c), eager.adjoint(g), eager.derivative(c)
+    e0, ep0 = eager.forward_derivative(c)
     f1 = torch.empty_like(f0)
     h1 = torch.empty_like(h0)
     d1 = torch.empty_like(d0)
+    e1 = torch.empty_like(f0)
+    ep1 = torch.empty_like(f0)
     n1c = float(c.abs().sum())
     n1g = float(g.abs().sum())
     tol = 1e-12 if dtype == "c128" else 1e-7
@@ -127,6 +130,7 @@ def test_graph_replays_match_eager(torch, dtype, eps):
         graph.forward(c, out=f1)
         graph.adjoint(g, out=h1)
         graph.derivative(c, out=d1)
+        graph.forward_derivative(c, out=e1, out_prime=ep1)
         torch.cuda.synchronize()
         x = (c * 2).sum()            # eager work between replays
         torch.cuda.synchronize()
@@ -134,6 +138,8 @@ def test_graph_replays_match_eager(torch, dtype, eps):
         assert float((f1 - f0).abs().max()) <= tol * n1c
         assert float((h1 - h0).abs().max()) <= tol * n1g
         assert float((d1 - d0).abs().max()) <= tol * n1c * 2 * np.pi * N
+        assert float((e1 - e0).abs().max()) <= tol * n1c
+        assert float((ep1 - ep0).abs().max()) <= tol * n1c * 2 * np.pi * N
     # new buffers: the plan captures again
     f2 = graph.forward(c)
     torch.cuda.synchronize()

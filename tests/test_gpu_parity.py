@@ -190,3 +190,80 @@ def test_large_workload_sampled(torch, dtype, eps, nfft_only):
     E = np.abs(f[sel] - ref).max() / np.abs(c).sum()
     _say("   sampled nodes", len(sel), "E =", E)
     assert E <= eps
+
+
+FUSED_CASES = [
+    # N, M, eps, dtype, nfft_only     (one-pass only / two-pass FFT bands; both band policies)
+    (1000, 777, 1e-8, "c128", False),
+    (9000, 1500, 1e-6, "c64", False),
+    (9000, 1500, 1e-6, "c64", True),
+    (70000, 3000, 1e-6, "c64", False),
+    (70000, 3000, 1e-12, "c128", True),
+]
+
+
+@pytest.mark.parametrize("N,M,eps,dtype,nfft_only", FUSED_CASES)
+def test_forward_derivative_one_pass(torch, N, M, eps, dtype, nfft_only):
+    """flt_forward_derivative: f and f' in one pass (2q columns per band) meet
+    the bars against the direct sums and agree with the separate calls."""
+    from paper_1606_03255_amd import Plan
+    _say("forward+derivative", N, M, eps, dtype, "nfft_only" if nfft_only else "policy")
+    rng = np.random.default_rng(N + M + 31)
+    c = inputs.coefficients(rng, N)
+    z = _nodes(rng, M, "mixed")
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        c = c.astype(np.complex64).astype(np.complex128)
+    plan = Plan(N, z, eps, tdt, nfft_only=nfft_only)
+    x = torch.from_numpy(c).to("cuda", tdt)
+    f, fp = plan.forward_derivative(x)
+    f0, fp0 = plan.forward(x), plan.derivative(x)
+    torch.cuda.synchronize()
+    f, fp, f0, fp0 = (t.cpu().numpy().astype(np.complex128) for t in (f, fp, f0, fp0))
+    plan.close()
+    n1, n1d = np.abs(c).sum(), np.abs(2 * np.pi * np.arange(N) * c).sum()
+    E = np.abs(f - oracle.forward(c, z)).max() / n1
+    Ed = np.abs(fp - oracle.derivative(c, z)).max() / n1d
+    _say("   E forward =", E, " E derivative =", Ed)
+    assert E <= eps and Ed <= eps
+    tol = 1e-6 if dtype == "c64" else 1e-13
+    assert np.abs(f - f0).max() <= tol * n1
+    assert np.abs(fp - fp0).max() <= tol * n1d
+
+
+@pytest.mark.parametrize("dtype,eps", [("c64", 1e-6), ("c128", 1e-11)])
+def test_autograd_gradients(torch, dtype, eps):
+    """fourier_laplace through autograd: dL/dc = C^H grad_f and
+    dL/dz = grad_f conj(f'(z)) for L = sum |f - t|^2 (PyTorch's conjugate
+    Wirtinger convention, grad_f = 2 (f - t)), against the direct sums applied
+    to the grad_f the backward receives."""
+    from paper_1606_03255_amd import Plan, fourier_laplace
+    rng = np.random.default_rng(5)
+    N, M = 9000, 1200
+    c = inputs.coefficients(rng, N)
+    z = _nodes(rng, M, "mixed")
+    t = inputs.coefficients(rng, M)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        c = c.astype(np.complex64).astype(np.complex128)
+    plan = Plan(N, z, eps, tdt)
+    ct = torch.from_numpy(c).to("cuda", tdt).requires_grad_(True)
+    zt = torch.from_numpy(z).to("cuda").requires_grad_(True)
+    tt = torch.from_numpy(t).to("cuda", tdt)
+    f = fourier_laplace(ct, zt, plan)
+    loss = (f - tt).abs().pow(2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    gc = ct.grad.cpu().numpy().astype(np.complex128)
+    gz = zt.grad.cpu().numpy()
+    fg = f.detach().cpu().numpy().astype(np.complex128)
+    assert np.abs(fg - oracle.forward(c, z)).max() <= eps * np.abs(c).sum()
+    gf = 2 * (fg - t.astype(np.complex64 if dtype == "c64" else np.complex128))   # the grad_f backward receives
+    ref_c = oracle.adjoint(gf, z, N)
+    ref_z = gf * np.conj(oracle.derivative(c, z))
+    Ec = np.abs(gc - ref_c).max() / np.abs(gf).sum()
+    # the bar on f' (eps times its 1-norm) carried through the product with grad_f
+    Ez = np.abs(gz - ref_z).max() / (np.abs(gf).max() * np.abs(2 * np.pi * np.arange(N) * c).sum())
+    _say("autograd", dtype, "E dL/dc =", Ec, " E dL/dz =", Ez)
+    plan.close()
+    assert Ec <= 2 * eps and Ez <= 2 * eps
