@@ -54,10 +54,12 @@ typedef struct flt_plan flt_plan;
 #define FLT_FLAG_GRAPH     (1u << 2) /* capture each operation's launch sequence into a hipGraph on its first call
                                         (and again whenever the buffers or the workspace change) and replay it */
 #define FLT_FLAG_AUTOTUNE  (1u << 3) /* choose the band policy by timing: candidate plans (the direct-sum rate of
-                                        the policy scaled by 0, 1/2, 1, 2, 4; distinct band choices only) run
+                                        the policy scaled by 0, 1/2, 1, 2, 4, 8; distinct band choices only) run
                                         forward + adjoint on the device during creation and the fastest is kept;
-                                        the choice is cached per (dtype, eps, instances, size class) for the
-                                        process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
+                                        the choice is cached per (objective, dtype, eps, instances, size class)
+                                        for the process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
+#define FLT_FLAG_TUNE_FORWARD (1u << 4) /* with FLT_FLAG_AUTOTUNE: time the forward alone (plans used for
+                                        evaluation only); without it forward + adjoint (training steps) */
 
 /* return codes */
 #define FLT_OK            0

@@ -15,6 +15,7 @@ FLT_FLAG_HOST_ONLY = 1
 FLT_FLAG_NFFT_ONLY = 2
 FLT_FLAG_GRAPH = 4
 FLT_FLAG_AUTOTUNE = 8
+FLT_FLAG_TUNE_FORWARD = 16
 
 ERRORS = {
     0: "FLT_OK", -1: "FLT_EINVAL", -2: "FLT_EDOMAIN", -3: "FLT_EPRECISION", -4: "FLT_ENOWORKSPACE",

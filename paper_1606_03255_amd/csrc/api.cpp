@@ -172,17 +172,19 @@ static int upload(flt_plan* p)
     return FLT_OK;
 }
 
-static const uint32_t KNOWN_FLAGS = FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY | FLT_FLAG_GRAPH | FLT_FLAG_AUTOTUNE;
+static const uint32_t KNOWN_FLAGS =
+    FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY | FLT_FLAG_GRAPH | FLT_FLAG_AUTOTUNE | FLT_FLAG_TUNE_FORWARD;
 
 static void release(flt_plan* p);
 static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, void* out2, hipStream_t st);
 
 // FLT_FLAG_AUTOTUNE: the band policy's direct-sum rate factor chosen by timing
-// forward + adjoint of candidate plans, cached per (dtype, eps, instances,
-// size class of sum N and sum M) for the life of the process.
+// forward + adjoint (FLT_FLAG_TUNE_FORWARD: the forward alone) of candidate
+// plans, cached per (objective, dtype, eps, instances, size class of sum N and
+// sum M) for the life of the process.
 namespace {
-const double TUNE_SCALES[] = {0.0, 0.5, 1.0, 2.0, 4.0};
-using TuneKey = std::tuple<int, double, int64_t, int, int>;
+const double TUNE_SCALES[] = {0.0, 0.5, 1.0, 2.0, 4.0, 8.0};
+using TuneKey = std::tuple<int, int, double, int64_t, int, int>;
 std::map<TuneKey, double> g_tuned;
 std::mutex g_tune_mu;
 
@@ -193,9 +195,9 @@ int size_class(int64_t v)
     return r;
 }
 
-// Mean time (ms) of forward + adjoint of an uploaded candidate, on buffers and
-// a workspace of its own; FLT_OK or an error code.
-int time_candidate(flt_plan* p, double* ms)
+// Mean time (ms) of forward + adjoint (fwd_only: the forward) of an uploaded
+// candidate, on buffers and a workspace of its own; FLT_OK or an error code.
+int time_candidate(flt_plan* p, bool fwd_only, double* ms)
 {
     const HostPlan& hp = p->hp;
     const size_t S = hp.elem_bytes();
@@ -217,11 +219,11 @@ int time_candidate(flt_plan* p, double* ms)
         p->ws_bytes = hp.ws_bytes;
         const int reps = 3;
         e = enqueue(p, 0, c, f, nullptr, st);                       // warm-up
-        if (e == hipSuccess) e = enqueue(p, 2, g, h, nullptr, st);
+        if (e == hipSuccess && !fwd_only) e = enqueue(p, 2, g, h, nullptr, st);
         if (e == hipSuccess) e = hipEventRecord(e0, st);
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
             e = enqueue(p, 0, c, f, nullptr, st);
-            if (e == hipSuccess) e = enqueue(p, 2, g, h, nullptr, st);
+            if (e == hipSuccess && !fwd_only) e = enqueue(p, 2, g, h, nullptr, st);
         }
         if (e == hipSuccess) e = hipEventRecord(e1, st);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -246,7 +248,9 @@ template <class Build> static int tuned_scale(uint32_t flags, Build&& build, dou
     HostPlan probe;
     int rc = build(probe, 1.0);
     if (rc != FLT_OK) return rc;
-    const TuneKey key{probe.dtype, probe.eps, (int64_t)probe.inst.size(), size_class(probe.N), size_class(probe.M)};
+    const bool fwd_only = (flags & FLT_FLAG_TUNE_FORWARD) != 0;
+    const TuneKey key{fwd_only ? 1 : 0, probe.dtype, probe.eps, (int64_t)probe.inst.size(), size_class(probe.N),
+                      size_class(probe.M)};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
@@ -271,7 +275,7 @@ template <class Build> static int tuned_scale(uint32_t flags, Build&& build, dou
             cand->host_only = false;
             rc = upload(cand);
             double ms = 0;
-            if (rc == FLT_OK) rc = time_candidate(cand, &ms);
+            if (rc == FLT_OK) rc = time_candidate(cand, fwd_only, &ms);
             if (rc == FLT_OK && ms < best) {
                 best = ms;
                 *scale = sc;

@@ -199,10 +199,10 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                                                                       grids.data(), acc.data(), lds.data());
                 });
             });
-        std::vector<cplx<T>> nw(DIRECT_ANG), ngv(DIRECT_ANG);
+        std::vector<cplx<T>> nw(DIRECT_ANG), ngv(DIRECT_ANG), redv(256 * ADJ_TS);
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
             body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, acc.data(), nw.data(),
-                                        ngv.data());
+                                        ngv.data(), redv.data());
         });
         for (int64_t k = 0; k < hp.N; ++k) co[k] = mk<T>((T)acc[2 * k], (T)acc[2 * k + 1]);
         return FLT_OK;

@@ -151,8 +151,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_direct_adj(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
                                                     const cplx<T>* g, double* acc)
 {
-    __shared__ cplx<T> nw[DIRECT_ANG], ng[DIRECT_ANG];
-    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, acc, nw, ng);
+    __shared__ cplx<T> nw[DIRECT_ANG], ng[DIRECT_ANG], red[256 * ADJ_TS];
+    body_direct_adj<DevCtx, T>(DevCtx(), pv, items, dlist, g, acc, nw, ng, red);
 }
 
 // Clear `n` 16-byte words (a fill kernel, so the sequence stays capturable).

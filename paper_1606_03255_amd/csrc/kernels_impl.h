@@ -1137,9 +1137,13 @@ FLT_HD void body_direct_io(const Ctx& ctx, const PlanView<T>& pv, const int32_t*
 // Direct adjoint: acc_k += sum_j g_j conj(w_j)^k over a group of up to
 // DIRECT_ANG direct nodes (their conj(w) and g in LDS), direct_atpt
 // consecutive k >= 1 per thread (k = 0 is summed over all nodes apart).
+// ADJ_TS: the sums leave in slices of that many consecutive k per thread,
+// transposed through LDS (red, GATHER_THREADS * ADJ_TS values) so that
+// consecutive lanes add into consecutive coefficients.
+constexpr int ADJ_TS = 8;
 template <class Ctx, typename T>
 FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
-                            const cplx<T>* gin, double* accall, cplx<T>* nw, cplx<T>* ng)
+                            const cplx<T>* gin, double* accall, cplx<T>* nw, cplx<T>* ng, cplx<T>* red)
 {
     constexpr int ATPT = direct_atpt((int)sizeof(T));
     const DirectItem it = items[ctx.bid()];
@@ -1151,11 +1155,11 @@ FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectI
         ng[gi] = gin[pv.perm[j]];
     }
     ctx.sync();
-    const int64_t k0 = ((int64_t)it.chunk * ctx.ntid() + ctx.tid()) * ATPT;
-    if (k0 >= N) return;
+    const int64_t kc = (int64_t)it.chunk * ctx.ntid() * ATPT;   // first k of the workgroup
+    const int64_t k0 = kc + (int64_t)ctx.tid() * ATPT;
     T ar[ATPT], ai[ATPT];
     for (int t = 0; t < ATPT; ++t) ar[t] = ai[t] = 0;
-    for (int gi = 0; gi < it.count; ++gi) {
+    for (int gi = 0; gi < (k0 < N ? it.count : 0); ++gi) {
         const int32_t j = dlist[it.first + gi];
         const cplx<T> gv = ng[gi], w = nw[gi];
         cplx<T> p = direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], -1.0);
@@ -1165,11 +1169,20 @@ FLT_HD void body_direct_adj(const Ctx& ctx, const PlanView<T>& pv, const DirectI
             p = mul(p, w);
         }
     }
-    for (int t = 0; t < ATPT; ++t) {
-        const int64_t k = k0 + t;
-        if (k >= 1 && k < N) {
-            ctx.atomic_add(acc + 2 * k, (double)ar[t]);
-            ctx.atomic_add(acc + 2 * k + 1, (double)ai[t]);
+    static_assert(ATPT % ADJ_TS == 0, "whole slices");
+    const int tid = ctx.tid(), nt = ctx.ntid();
+    for (int t0 = 0; t0 < ATPT; t0 += ADJ_TS) {
+        ctx.sync();
+        for (int u = 0; u < ADJ_TS; ++u) red[tid * ADJ_TS + u] = mk(ar[t0 + u], ai[t0 + u]);
+        ctx.sync();
+        for (int u = 0; u < ADJ_TS; ++u) {
+            const int e = u * nt + tid;                       // thread e / ADJ_TS, its term t0 + e % ADJ_TS
+            const int64_t k = kc + (int64_t)(e / ADJ_TS) * ATPT + t0 + e % ADJ_TS;
+            if (k >= 1 && k < N) {
+                const cplx<T> v = red[e];
+                ctx.atomic_add(acc + 2 * k, (double)v.x);
+                ctx.atomic_add(acc + 2 * k + 1, (double)v.y);
+            }
         }
     }
 }
@@ -1280,18 +1293,26 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         }
         ctx.sync();
     }
+    // the per-point sums leave through the LDS tile, re-read with the b
+    // sub-transforms (consecutive k) fastest: a wave's atomics then fall on
+    // runs of consecutive coefficients instead of one cache line per lane
     for (int i = 0; i < ITEMS; ++i) {
         const int p = ctx.tid() + i * FFT_THREADS;
-        if (p >= P) break;
-        const int j1 = p & ((1 << log2n1) - 1);
-        const int jj = p >> log2n1;
+        lds[lds_at(p)] = mk(accr[i], acci[i]);
+    }
+    ctx.sync();
+    for (int i = 0; i < ITEMS; ++i) {
+        const int r = ctx.tid() + i * FFT_THREADS;
+        const int jj = r & ((1 << log2b) - 1);
+        const int j1 = r >> log2b;
         const int j = j2_0 + jj + (j1 << log2n2);
         const int kp = j < (n >> 1) ? j : j - n;
         const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
+        const cplx<T> a = lds[lds_at((jj << log2n1) + j1)];
         const double d = (double)pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
-        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)accr[i]);
-        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)acci[i]);
+        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)a.x);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)a.y);
     }
 }
 

@@ -50,8 +50,9 @@ class Plan:
     every band on Algorithm 2's NFFT path; by default bands with few nodes and
     large grids are summed directly (exactly).  ``graph=True`` captures each
     operation's launch sequence into a hipGraph on first use and replays it.
-    ``autotune=True`` chooses the band policy by timing candidate plans on the
-    device (cached per size class for the process).
+    ``autotune=True`` chooses the band policy by timing forward + adjoint of
+    candidate plans on the device (cached per size class for the process);
+    ``autotune="forward"`` times the forward alone (plans for evaluation only).
 
     ``Plan.batch`` builds one plan for many independent instances; its
     transforms act on packed arrays (instance after instance).
@@ -73,7 +74,8 @@ class Plan:
         self.dtype_code = _dtype_code(dtype)
         self.host_only = bool(host_only)
         flags = ((L.FLT_FLAG_HOST_ONLY if host_only else 0) | (L.FLT_FLAG_NFFT_ONLY if nfft_only else 0)
-                 | (L.FLT_FLAG_GRAPH if graph else 0) | (L.FLT_FLAG_AUTOTUNE if autotune else 0))
+                 | (L.FLT_FLAG_GRAPH if graph else 0) | (L.FLT_FLAG_AUTOTUNE if autotune else 0)
+                 | (L.FLT_FLAG_TUNE_FORWARD if autotune == "forward" else 0))
         self._ws = None
         zp = zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         I64 = ctypes.POINTER(ctypes.c_int64)

@@ -175,7 +175,7 @@ def test_autotuned_plans(torch):
     p = Plan(N, z, 1e-6, torch.complex64, autotune=True)
     sc = p.info()["direct_scale"]
     _say("tuned direct-rate factor", sc)
-    assert sc in (0.0, 0.5, 1.0, 2.0, 4.0)
+    assert sc in (0.0, 0.5, 1.0, 2.0, 4.0, 8.0)
     f = p.forward(torch.from_numpy(c).to("cuda")).cpu().numpy().astype(np.complex128)
     ci = c.astype(np.complex128)
     assert np.abs(f - oracle.forward(ci, z)).max() <= 1e-6 * np.abs(ci).sum()
@@ -184,3 +184,11 @@ def test_autotuned_plans(torch):
     p2 = Plan(N, z2, 1e-6, torch.complex64, autotune=True)
     assert p2.info()["direct_scale"] == sc
     p2.close()
+    # tuned on the forward alone: its own choice, the same bar
+    p3 = Plan(N, z, 1e-6, torch.complex64, autotune="forward")
+    sf = p3.info()["direct_scale"]
+    _say("forward-tuned direct-rate factor", sf)
+    assert sf in (0.0, 0.5, 1.0, 2.0, 4.0, 8.0)
+    f3 = p3.forward(torch.from_numpy(c).to("cuda")).cpu().numpy().astype(np.complex128)
+    assert np.abs(f3 - oracle.forward(ci, z)).max() <= 1e-6 * np.abs(ci).sum()
+    p3.close()
