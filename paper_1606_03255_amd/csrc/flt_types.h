@@ -49,8 +49,9 @@ constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
 // direct sum: most chunks of 256 * DIRECT_TPT terms per workgroup, by working type
 constexpr int direct_cpw(int dtype_bytes) { return dtype_bytes == 4 ? 4 : 1; }
 constexpr int DIRECT_ANG = 256;           // direct adjoint: nodes per workgroup
-// direct adjoint: consecutive coefficients per thread (one anchor each), by working type
-constexpr int direct_atpt(int dtype_bytes) { return dtype_bytes == 4 ? 32 : 16; }
+// direct adjoint: consecutive coefficients per thread (one anchor each); 16 for
+// both working types (more workgroups: the sums have few nodes to spread over)
+constexpr int direct_atpt(int /*dtype_bytes*/) { return 16; }
 constexpr int SUMG_PER_THREAD = 16;       // sum of g: elements per thread
 constexpr int CELL_TARGET = 16;           // adjoint spread: contributions per thread a cell's group aims at
 

@@ -674,8 +674,14 @@ FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it
     for (int m = 0; m < tile_items<T>() / G::V; ++m) {
         const int ch = ctx.tid() + m * FFT_THREADS;
         const int p0 = (G::row(ch) << G::log2B) + G::col(ch, 0);   // multiple of V: one mask word
-        if (ADJ) bits[m] = mask[p0 >> 5] >> (p0 & 31);
-        for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, src[p0 + u]);
+        if (ADJ) {
+            // only the cells some window wrote are read (the others are zero)
+            const uint32_t b = mask[p0 >> 5] >> (p0 & 31);
+            bits[m] = b;
+            for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, ((b >> u) & 1u) ? src[p0 + u] : mk<T>(0, 0));
+        } else {
+            for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, src[p0 + u]);
+        }
     }
 }
 
