@@ -71,6 +71,7 @@ def test_error_codes():
     assert _create(10, 0, z, 1e-6, 1) == -1                               # M < 1
     assert _create(10, 2, z, 1e-6, 3) == -1                               # dtype
     assert _create(10, 2, z, 1e-6, 1, flags=1 << 7) == -1                 # flags
+    assert _create(10, 2, z, 1e-6, 1, flags=L.FLT_FLAG_HOST_ONLY | L.FLT_FLAG_AUTOTUNE | L.FLT_FLAG_TUNE_FORWARD) == 0
     assert _create(10, 2, z, 1.5, 1) == -2                                # eps not in (0,1)
     assert _create(10, 2, z, 0.0, 1) == -2
     assert _create(10, 2, np.array([0.1 - 1e-9j, 0.2]), 1e-6, 1) == -2    # Im z < 0
@@ -93,7 +94,10 @@ def test_host_only_plan_refuses_device_work():
     assert lib.flt_forward(ptr, dummy, dummy, None) == -6
     assert lib.flt_adjoint(ptr, dummy, dummy, None) == -6
     assert lib.flt_plan_set_workspace(ptr, dummy, 1 << 30) == -6
+    assert lib.flt_forward_derivative(ptr, dummy, dummy, ctypes.c_void_p(32), None) == -6
     assert lib.flt_forward(None, dummy, dummy, None) == -1
+    assert lib.flt_forward_derivative(None, dummy, dummy, ctypes.c_void_p(32), None) == -1
+    assert lib.flt_forward_derivative(ptr, None, dummy, ctypes.c_void_p(32), None) == -1
     size = ctypes.c_size_t()
     assert lib.flt_plan_workspace_size(ptr, ctypes.byref(size)) == 0 and size.value > 0
     assert lib.flt_strerror(-4) == b"workspace missing or too small"
