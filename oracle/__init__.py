@@ -13,6 +13,8 @@ Contents
              and a compensated-Horner cross-check.
 ``brute``    independent brute force: every power w^k formed on its own in
              80-bit extended precision (numpy longdouble) or with mpmath.
+``laplace``  the discrete Laplace transform of Sect. 3: its plain FP64
+             definition and Algorithm 1 step by step (Def. 3.2, Thm A.3).
 ``method``   the paper's Algorithm 2 (Sect. 4) step by step in numpy FP64,
              with the Laplace-side factorisation of Def. 3.2 / Lemma A.2 and
              the Fourier "black box" either exact (dense NDFT) or a
