@@ -172,6 +172,44 @@ int flt_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream);
  * bands) in milliseconds.  Same arguments and results as flt_forward. */
 int flt_profile_forward(flt_plan* plan, const void* c, void* f, void* stream, double* stage_ms);
 
+/* ------------------------------------------------------------------------
+ * The discrete Laplace transform (Sect. 3, Algorithm 1):
+ *
+ *     f_j = sum_{k<N} fhat_k exp(-y_j xi_k),   xi_k > 0, y_j >= 0,
+ *
+ * by the dyadic partition of Def. 3.2 (y_1 = max y_j, xi_1 = max xi_k), rank-q
+ * Chebyshev interpolation of every admissible block, cumulative sums for the
+ * blocks where the kernel is 1, and nothing for those where it is below eps.
+ * Error <= eps * sum |fhat_k| (Thm A.3).  All work after plan creation runs in
+ * HIP kernels; the arithmetic is FP64 for both dtypes (dtype sets the type of
+ * fhat and f: FLT_C64 complex64, FLT_C128 complex128).
+ * ------------------------------------------------------------------------ */
+typedef struct flt_laplace_plan flt_laplace_plan;
+
+typedef struct flt_laplace_info {
+    int64_t N, M;            /* frequencies, nodes */
+    int32_t dtype;           /* FLT_C64 or FLT_C128 */
+    int32_t q;               /* Chebyshev rank, ceil(1/2 + log4(1/eps)) */
+    int32_t levels;          /* the paper's M, ceil(log2(y_1 xi_1 / eps)) + 1 (1 if every y_j = 0) */
+    int32_t pad;
+    double eps, y1, xi1;     /* target accuracy and the interval lengths */
+} flt_laplace_info;
+
+/* Plan for N frequencies xi (host, N doubles, > 0, finite) and M nodes y
+ * (host, M doubles, >= 0, finite); both copied.  flags: 0 or
+ * FLT_FLAG_HOST_ONLY.  The plan owns a small device accumulator (a few KB), so
+ * transform calls allocate nothing; calls on one plan must not overlap.
+ * Errors: FLT_EINVAL (null, N or M < 1, dtype, flags), FLT_EDOMAIN (eps outside
+ * (0,1), xi <= 0, y < 0, non-finite values), FLT_EPRECISION (eps below 1e-6
+ * for FLT_C64, 1e-14 for FLT_C128), FLT_ERANGE, FLT_EHIP, FLT_ENOMEM. */
+int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi, int64_t M, const double* y,
+                            double eps, int dtype, uint32_t flags);
+int flt_laplace_plan_info(const flt_laplace_plan* plan, flt_laplace_info* out);
+/* f[j] ~ sum_k fhat_k exp(-y_j xi_k).  fhat: device complex[N] of the plan's
+ * dtype, in the order xi was given; f: device complex[M], overwritten. */
+int flt_laplace_forward(flt_laplace_plan* plan, const void* fhat, void* f, void* stream);
+void flt_laplace_plan_destroy(flt_laplace_plan* plan);
+
 const char* flt_strerror(int code);
 int flt_last_hip_error(void); /* hipError_t of the last failing HIP call in this thread */
 

@@ -27,6 +27,7 @@ EXPORTS = (
     "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
     "flt_forward_derivative", "flt_profile_forward", "flt_strerror", "flt_last_hip_error",
+    "flt_laplace_plan_create", "flt_laplace_plan_info", "flt_laplace_forward", "flt_laplace_plan_destroy",
 )
 
 
@@ -46,6 +47,14 @@ class FltBandInfo(ctypes.Structure):
         ("m", ctypes.c_int32), ("q", ctypes.c_int32), ("ell_lo", ctypes.c_int32), ("ell_hi", ctypes.c_int32),
         ("K", ctypes.c_int64), ("n", ctypes.c_int64), ("k0", ctypes.c_int64), ("nodes", ctypes.c_int64),
         ("passes", ctypes.c_int32), ("direct", ctypes.c_int32), ("cells", ctypes.c_int64),
+    ]
+
+
+class FltLaplaceInfo(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("M", ctypes.c_int64),
+        ("dtype", ctypes.c_int32), ("q", ctypes.c_int32), ("levels", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("y1", ctypes.c_double), ("xi1", ctypes.c_double),
     ]
 
 
@@ -86,6 +95,12 @@ def load():
     for name in ("flt_forward", "flt_derivative", "flt_adjoint"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.flt_forward_derivative.argtypes = [vp, vp, vp, vp, vp]
+    lib.flt_laplace_plan_create.argtypes = [P(vp), ctypes.c_int64, P(ctypes.c_double), ctypes.c_int64,
+                                            P(ctypes.c_double), ctypes.c_double, ctypes.c_int, ctypes.c_uint32]
+    lib.flt_laplace_plan_info.argtypes = [vp, P(FltLaplaceInfo)]
+    lib.flt_laplace_forward.argtypes = [vp, vp, vp, vp]
+    lib.flt_laplace_plan_destroy.argtypes = [vp]
+    lib.flt_laplace_plan_destroy.restype = None
     lib.flt_profile_forward.argtypes = [vp, vp, vp, vp, P(ctypes.c_double)]
     lib.flt_strerror.argtypes = [ctypes.c_int]
     lib.flt_strerror.restype = ctypes.c_char_p

@@ -32,7 +32,7 @@ def _run(cmd):
 def build_lib(jobs=3):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    srcs = ["kernels.hip", "api.cpp", "plan_host.cpp"]
+    srcs = ["kernels.hip", "laplace.hip", "api.cpp", "plan_host.cpp", "laplace_plan.cpp"]
     objs = []
     procs = []
     for s in srcs:
@@ -54,7 +54,8 @@ def build_lib(jobs=3):
 def build_emu():
     tmp = EMU + ".tmp%d" % os.getpid()
     _run(["g++", "-O2", "-g", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-I" + INC, "-I" + CSRC,
-          os.path.join(CSRC, "emu.cpp"), os.path.join(CSRC, "plan_host.cpp"), "-o", tmp])
+          os.path.join(CSRC, "emu.cpp"), os.path.join(CSRC, "plan_host.cpp"), os.path.join(CSRC, "laplace_plan.cpp"),
+          "-o", tmp])
     os.replace(tmp, EMU)
     return EMU
 

@@ -574,3 +574,116 @@ const char* flt_strerror(int code)
 int flt_last_hip_error(void) { return g_last_hip; }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// The discrete Laplace transform (Sect. 3, Algorithm 1)
+// ---------------------------------------------------------------------------
+struct flt_laplace_plan {
+    LapHost hp;
+    bool host_only = true;
+    void* dev = nullptr;      // tables, work items and the accumulator, one allocation
+    LapView V{};
+    const LapItem* items = nullptr;
+};
+
+extern "C" {
+
+int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi, int64_t M, const double* y,
+                            double eps, int dtype, uint32_t flags)
+{
+    if (!out) return FLT_EINVAL;
+    *out = nullptr;
+    if (flags & ~FLT_FLAG_HOST_ONLY) return FLT_EINVAL;
+    flt_laplace_plan* p = new (std::nothrow) flt_laplace_plan();
+    if (!p) return FLT_ENOMEM;
+    int rc;
+    try {
+        rc = build_laplace_plan(p->hp, N, xi, M, y, eps, dtype);
+    } catch (const std::bad_alloc&) {
+        rc = FLT_ENOMEM;
+    }
+    if (rc != FLT_OK) {
+        delete p;
+        return rc;
+    }
+    if (!(flags & FLT_FLAG_HOST_ONLY)) {
+        const LapHost& hp = p->hp;
+        Packer pk;
+        const size_t o_xs = pk.add(hp.xs.data(), hp.xs.size() * sizeof(double));
+        const size_t o_kp = pk.add(hp.kperm.data(), hp.kperm.size() * sizeof(int32_t));
+        const size_t o_bn = pk.add(hp.bnodes.data(), hp.bnodes.size() * sizeof(double));
+        const size_t o_yn = pk.add(hp.ynodes.data(), hp.ynodes.size() * sizeof(double));
+        const size_t o_bw = pk.add(hp.bw.data(), hp.bw.size() * sizeof(double));
+        const size_t o_lm = pk.add(hp.lm.data(), hp.lm.size() * sizeof(int32_t));
+        const size_t o_Lm = pk.add(hp.Lm.data(), hp.Lm.size() * sizeof(int32_t));
+        const size_t o_ko = pk.add(hp.koff.data(), hp.koff.size() * sizeof(int64_t));
+        const size_t o_K = pk.add(hp.K.data(), hp.K.size() * sizeof(double));
+        const size_t o_y = pk.add(hp.y.data(), hp.y.size() * sizeof(double));
+        const size_t o_bd = pk.add(hp.band.data(), hp.band.size() * sizeof(int32_t));
+        const size_t o_it = pk.add(hp.items.data(), hp.items.size() * sizeof(LapItem));
+        std::vector<double> zeros((size_t)lap_acc_doubles(hp.L, hp.q), 0.0);
+        const size_t o_acc = pk.add(zeros.data(), zeros.size() * sizeof(double));
+        hipError_t e = hipMalloc(&p->dev, pk.buf.size());
+        if (e == hipSuccess) e = hipMemcpy(p->dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (p->dev) (void)hipFree(p->dev);
+            delete p;
+            return hip_fail(e);
+        }
+        char* b = (char*)p->dev;
+        LapView& V = p->V;
+        V.q = hp.q;
+        V.L = hp.L;
+        V.xs = (const double*)(b + o_xs);
+        V.kperm = (const int32_t*)(b + o_kp);
+        V.bnodes = (const double*)(b + o_bn);
+        V.ynodes = (const double*)(b + o_yn);
+        V.bw = (const double*)(b + o_bw);
+        V.lm = (const int32_t*)(b + o_lm);
+        V.Lm = (const int32_t*)(b + o_Lm);
+        V.koff = (const int64_t*)(b + o_ko);
+        V.K = (const double*)(b + o_K);
+        V.y = (const double*)(b + o_y);
+        V.band = (const int32_t*)(b + o_bd);
+        V.acc = (double*)(b + o_acc);
+        p->items = (const LapItem*)(b + o_it);
+        p->host_only = false;
+    }
+    *out = p;
+    return FLT_OK;
+}
+
+int flt_laplace_plan_info(const flt_laplace_plan* p, flt_laplace_info* o)
+{
+    if (!p || !o) return FLT_EINVAL;
+    memset(o, 0, sizeof(*o));
+    o->N = p->hp.N;
+    o->M = p->hp.M;
+    o->dtype = p->hp.dtype;
+    o->q = p->hp.q;
+    o->levels = p->hp.L;
+    o->eps = p->hp.eps;
+    o->y1 = p->hp.y1;
+    o->xi1 = p->hp.xi1;
+    return FLT_OK;
+}
+
+int flt_laplace_forward(flt_laplace_plan* p, const void* fhat, void* f, void* stream)
+{
+    if (!p || !fhat || !f) return FLT_EINVAL;
+    if (p->host_only) return FLT_ESTATE;
+    const hipStream_t st = (hipStream_t)stream;
+    const int ni = (int)p->hp.items.size();
+    const hipError_t e = p->hp.dtype == FLT_C64 ? launch_laplace<float>(p->V, p->items, ni, p->hp.M, fhat, f, st)
+                                                : launch_laplace<double>(p->V, p->items, ni, p->hp.M, fhat, f, st);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+
+void flt_laplace_plan_destroy(flt_laplace_plan* p)
+{
+    if (!p) return;
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+}
+
+}  // extern "C"

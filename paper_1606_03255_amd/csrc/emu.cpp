@@ -16,6 +16,7 @@
 
 #include "flt.h"
 #include "kernels_impl.h"
+#include "laplace.h"
 #include "plan_host.h"
 
 namespace flt {
@@ -212,6 +213,46 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
 
 }  // namespace flt
 
+namespace flt {
+
+// The Laplace transform's kernel bodies on the CPU (same plan, same launches).
+template <typename T> static int emu_laplace(const LapHost& hp, const void* in, void* out)
+{
+    std::vector<double> acc((size_t)lap_acc_doubles(hp.L, hp.q), 1e300);   // garbage: the zero kernel must clear it
+    LapView V{};
+    V.q = hp.q;
+    V.L = hp.L;
+    V.xs = hp.xs.data();
+    V.kperm = hp.kperm.data();
+    V.bnodes = hp.bnodes.data();
+    V.ynodes = hp.ynodes.data();
+    V.bw = hp.bw.data();
+    V.lm = hp.lm.data();
+    V.Lm = hp.Lm.data();
+    V.koff = hp.koff.data();
+    V.K = hp.K.data();
+    V.y = hp.y.data();
+    V.band = hp.band.data();
+    V.acc = acc.data();
+    const int64_t n = (int64_t)acc.size();
+    run_blocks((n + LAP_THREADS - 1) / LAP_THREADS, LAP_THREADS, [&](const HostCtx& ctx) {
+        lap_body_zero(ctx, V.acc, n);
+    });
+    std::vector<double> sden(LAP_CHUNK), sf(2 * LAP_CHUNK), red(4 * LAP_THREADS);
+    std::vector<int32_t> shit(LAP_CHUNK);
+    run_blocks(hp.items.size(), LAP_THREADS, [&](const HostCtx& ctx) {
+        lap_body_moments<HostCtx, T>(ctx, V, hp.items.data(), (const cplx<T>*)in, sden.data(), shit.data(),
+                                     sf.data(), red.data());
+    });
+    run_blocks(1, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_bands(ctx, V); });
+    run_blocks((hp.M + LAP_THREADS - 1) / LAP_THREADS, LAP_THREADS, [&](const HostCtx& ctx) {
+        lap_body_nodes<HostCtx, T>(ctx, V, hp.M, (cplx<T>*)out);
+    });
+    return FLT_OK;
+}
+
+}  // namespace flt
+
 // The kernel bodies on the CPU for one call: op 0 forward, 1 derivative,
 // 2 adjoint, 3 forward and derivative in one pass (out: f, then f', 2M values).
 extern "C" int flt_emu_run(int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags, int op,
@@ -231,4 +272,14 @@ extern "C" int flt_emu_run_batch(int32_t count, const int64_t* N, const int64_t*
     int rc = flt::build_batch_plan(hp, count, N, M, z, eps, dtype, flags);
     if (rc != FLT_OK) return rc;
     return dtype == FLT_C64 ? flt::emu_run<float>(hp, op, in, out) : flt::emu_run<double>(hp, op, in, out);
+}
+
+// The Laplace transform on the CPU build (in: fhat, out: f, the plan's dtype).
+extern "C" int flt_emu_laplace(int64_t N, const double* xi, int64_t M, const double* y, double eps, int dtype,
+                               const void* in, void* out)
+{
+    flt::LapHost hp;
+    int rc = flt::build_laplace_plan(hp, N, xi, M, y, eps, dtype);
+    if (rc != FLT_OK) return rc;
+    return dtype == FLT_C64 ? flt::emu_laplace<float>(hp, in, out) : flt::emu_laplace<double>(hp, in, out);
 }

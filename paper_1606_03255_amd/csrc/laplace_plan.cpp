@@ -1,0 +1,115 @@
+// Planner of the discrete Laplace transform (Sect. 3, Def. 3.2, Algorithm 1):
+// parameters, dyadic blocks of the frequencies and bands of the nodes, the
+// Chebyshev tables and the kernel blocks K^{Y_m,Omega_l}.  Host, FP64.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "flt.h"
+#include "laplace.h"
+
+namespace flt {
+
+// Index i of the dyadic interval holding v >= 0: (v1 2^-i, v1 2^(1-i)] for
+// i < L, [0, v1 2^(1-L)] for i = L (Def. 3.2); exact compares after a guess.
+static int lap_level(double v, double v1, int L)
+{
+    if (L == 1 || v <= std::ldexp(v1, 1 - L)) return L;
+    int i = (int)std::floor(std::log2(v1 / v)) + 1;
+    i = std::max(1, std::min(L - 1, i));
+    while (i > 1 && v > std::ldexp(v1, 1 - i)) --i;
+    while (i < L - 1 && v <= std::ldexp(v1, -i)) ++i;
+    return i;
+}
+
+// Chebyshev nodes of [a, b]: centre + half-width cos((2r+1) pi / (2q)) (Sect. 2).
+static void cheb_nodes(double a, double b, int q, double* out)
+{
+    for (int r = 0; r < q; ++r) out[r] = 0.5 * (a + b) + 0.5 * (b - a) * std::cos((2 * r + 1) * M_PI / (2.0 * q));
+}
+
+int build_laplace_plan(LapHost& hp, int64_t N, const double* xi, int64_t M, const double* y, double eps,
+                       int dtype)
+{
+    if (!xi || !y || N < 1 || M < 1) return FLT_EINVAL;
+    if (dtype != FLT_C64 && dtype != FLT_C128) return FLT_EINVAL;
+    if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
+    if (eps < (dtype == FLT_C64 ? 1e-6 : 1e-14)) return FLT_EPRECISION;
+    if (N > (int64_t)INT32_MAX || M > (int64_t)INT32_MAX) return FLT_ERANGE;
+    double xi1 = 0.0, y1 = 0.0;
+    for (int64_t k = 0; k < N; ++k) {
+        if (!(xi[k] > 0.0) || !std::isfinite(xi[k])) return FLT_EDOMAIN;   // xi_k > 0 (Thm A.3)
+        xi1 = std::max(xi1, xi[k]);
+    }
+    for (int64_t j = 0; j < M; ++j) {
+        if (!(y[j] >= 0.0) || !std::isfinite(y[j])) return FLT_EDOMAIN;    // y_j >= 0
+        y1 = std::max(y1, y[j]);
+    }
+    hp = LapHost();
+    hp.N = N;
+    hp.M = M;
+    hp.dtype = dtype;
+    hp.eps = eps;
+    hp.xi1 = xi1;
+    hp.y1 = y1;
+    hp.q = (int)std::ceil(0.5 + std::log(1.0 / eps) / std::log(4.0));
+    if (hp.q > LAP_MAX_Q) return FLT_EPRECISION;
+    const int q = hp.q;
+    // levels (the paper's M); all nodes at 0: one level, every block "kernel = 1"
+    hp.L = y1 > 0.0 ? (int)std::ceil(std::log2(y1 * xi1 / eps)) + 1 : 1;
+    hp.L = std::max(hp.L, 1);
+    if (hp.L > 1000) return FLT_ERANGE;
+    const int L = hp.L;
+    hp.bw.resize(q);
+    for (int r = 0; r < q; ++r) hp.bw[r] = (r & 1 ? -1.0 : 1.0) * std::sin((2 * r + 1) * M_PI / (2.0 * q));
+    // frequencies sorted by block, then value
+    std::vector<int32_t> blk(N);
+    for (int64_t k = 0; k < N; ++k) blk[k] = lap_level(xi[k], xi1, L);
+    std::vector<int32_t> ord(N);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        return blk[a] != blk[b] ? blk[a] < blk[b] : xi[a] < xi[b];
+    });
+    hp.xs.resize(N);
+    hp.kperm.resize(N);
+    for (int64_t i = 0; i < N; ++i) {
+        hp.xs[i] = xi[ord[i]];
+        hp.kperm[i] = ord[i];
+    }
+    for (int64_t i = 0; i < N;) {   // items: chunks of one block
+        int64_t e = i;
+        while (e < N && blk[ord[e]] == blk[ord[i]] && e - i < LAP_CHUNK) ++e;
+        hp.items.push_back(LapItem{blk[ord[i]], (int32_t)(e - i), i});
+        i = e;
+    }
+    // Chebyshev nodes of the blocks l < L and bands m < L (closures of the intervals)
+    hp.bnodes.assign((size_t)std::max(L - 1, 1) * q, 0.0);
+    hp.ynodes.assign((size_t)std::max(L - 1, 1) * q, 0.0);
+    for (int l = 1; l < L; ++l) cheb_nodes(std::ldexp(xi1, -l), std::ldexp(xi1, 1 - l), q, &hp.bnodes[(size_t)(l - 1) * q]);
+    for (int m = 1; m < L; ++m) cheb_nodes(std::ldexp(y1, -m), std::ldexp(y1, 1 - m), q, &hp.ynodes[(size_t)(m - 1) * q]);
+    // l_m, L_m (Def. 3.2; natural log inside l_m) and K^{Y_m,Omega_l}[s][r] = exp(-y_s xi_r)
+    const double lg = L > 1 ? std::log2(y1 * xi1) - std::log2(std::log(1.0 / eps)) : 0.0;
+    for (int m = 1; m < L; ++m) {
+        const int lm = std::max(1, (int)std::floor(lg - m) + 1);
+        const int Lm = L - m;
+        hp.lm.push_back(lm);
+        hp.Lm.push_back(Lm);
+        hp.koff.push_back((int64_t)hp.K.size());
+        for (int l = lm; l <= Lm; ++l)
+            for (int s = 0; s < q; ++s)
+                for (int r = 0; r < q; ++r)
+                    hp.K.push_back(std::exp(-hp.ynodes[(size_t)(m - 1) * q + s] * hp.bnodes[(size_t)(l - 1) * q + r]));
+    }
+    if (hp.lm.empty()) {   // keep every table non-empty
+        hp.lm.push_back(1);
+        hp.Lm.push_back(0);
+        hp.koff.push_back(0);
+    }
+    if (hp.K.empty()) hp.K.push_back(0.0);
+    hp.y.assign(y, y + M);
+    hp.band.resize(M);
+    for (int64_t j = 0; j < M; ++j) hp.band[j] = lap_level(y[j], y1, L);
+    return FLT_OK;
+}
+
+}  // namespace flt

@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "flt_types.h"
+#include "laplace.h"
 
 namespace flt {
 
@@ -53,6 +54,11 @@ struct WsLayout {
 template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* c, void* f,
                           void* f2, int deriv, hipStream_t st, hipEvent_t* ev = nullptr);
+
+// The discrete Laplace transform: fhat -> f on stream st (laplace.hip).
+template <typename T>
+hipError_t launch_laplace(const LapView& V, const LapItem* items, int nitems, int64_t M, const void* fhat, void* f,
+                          hipStream_t st);
 
 // a7 (adjoint): g -> c_out on stream st.
 template <typename T>

@@ -24,6 +24,16 @@ def _as_host_z(z):
     return z
 
 
+def _as_host_real(v):
+    try:
+        import torch
+        if isinstance(v, torch.Tensor):
+            v = v.detach().to("cpu", torch.float64).numpy()
+    except ImportError:  # pragma: no cover
+        pass
+    return np.asarray(v, dtype=np.float64).reshape(-1)
+
+
 def _dtype_code(dtype):
     if dtype in ("c64", "complex64", L.FLT_C64):
         return L.FLT_C64
@@ -283,3 +293,81 @@ def fourier_laplace(c, z, plan):
     if _FL is None:
         _FL = _make_function()
     return _FL.apply(c, z, plan)
+
+
+class LaplacePlan:
+    """The discrete Laplace transform f_j = sum_k fhat_k exp(-y_j xi_k)
+    (xi_k > 0, y_j >= 0) by Algorithm 1, error <= eps * sum |fhat_k|.
+
+    ``xi`` and ``y`` are real (host arrays or tensors, copied); ``dtype``
+    sets the type of fhat and f (the arithmetic is FP64 either way).  The
+    plan owns its small device accumulator: calls on one plan must not
+    overlap."""
+
+    def __init__(self, xi, y, eps, dtype="complex64", device=None, host_only=False):
+        self._lib = L.load()
+        self._ptr = ctypes.c_void_p()
+        xh = np.ascontiguousarray(_as_host_real(xi))
+        yh = np.ascontiguousarray(_as_host_real(y))
+        self.N, self.M = int(xh.shape[0]), int(yh.shape[0])
+        self.dtype_code = _dtype_code(dtype)
+        self.host_only = bool(host_only)
+        D = ctypes.POINTER(ctypes.c_double)
+
+        def create():
+            L.check(self._lib.flt_laplace_plan_create(ctypes.byref(self._ptr), self.N, xh.ctypes.data_as(D), self.M,
+                                                      yh.ctypes.data_as(D), float(eps), self.dtype_code,
+                                                      L.FLT_FLAG_HOST_ONLY if host_only else 0),
+                    "flt_laplace_plan_create")
+
+        if host_only:
+            create()
+            self.device = None
+            return
+        import torch
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            create()
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex64 if self.dtype_code == L.FLT_C64 else torch.complex128
+
+    def info(self):
+        o = L.FltLaplaceInfo()
+        L.check(self._lib.flt_laplace_plan_info(self._ptr, ctypes.byref(o)), "flt_laplace_plan_info")
+        return {k: getattr(o, k) for k, _ in L.FltLaplaceInfo._fields_ if k != "pad"}
+
+    def forward(self, fhat, out=None):
+        """f_j ~ sum_k fhat_k exp(-y_j xi_k); fhat: complex[N] on the device."""
+        import torch
+        if self.host_only:
+            raise RuntimeError("host-only plan")
+        if not isinstance(fhat, torch.Tensor) or fhat.dtype != self.torch_dtype or fhat.device != self.device \
+                or fhat.numel() != self.N:
+            raise TypeError("fhat must be a %s tensor of %d elements on %s" % (self.torch_dtype, self.N, self.device))
+        fhat = fhat.contiguous()
+        if out is None:
+            out = torch.empty(self.M, dtype=self.torch_dtype, device=self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(self._lib.flt_laplace_forward(self._ptr, ctypes.c_void_p(fhat.data_ptr()),
+                                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)),
+                "flt_laplace_forward")
+        return out
+
+    def close(self):
+        if getattr(self, "_ptr", None) and self._ptr.value:
+            if self.device is not None:
+                import torch
+                torch.cuda.synchronize(self.device)
+            self._lib.flt_laplace_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

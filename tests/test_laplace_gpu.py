@@ -1,0 +1,94 @@
+"""GPU parity of the Laplace transform (Sect. 3, Algorithm 1) through the C
+ABI: against the direct sums, E <= eps relative to ||fhat||_1 (Thm A.3);
+against Algorithm 1 step by step (FP64): the same approximant up to rounding.
+The benchmark size (N = M = 2^20) is checked on sampled nodes."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import laplace as LP
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _inputs(seed, N, M, y_hi):
+    rng = np.random.default_rng(seed)
+    xi = rng.random(N) * N + 1e-3
+    y = np.concatenate([rng.random(max(M - 3, 0)) * y_hi, [0.0, y_hi, 1e-15]])[:M]
+    fhat = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return fhat, xi, y
+
+
+CASES = [
+    # N, M, eps, dtype
+    (1, 1, 1e-8, "c128"),
+    (777, 300, 1e-10, "c128"),
+    (5000, 2000, 1e-6, "c64"),
+    (65536, 2000, 1e-12, "c128"),
+    (65537, 1500, 1e-6, "c64"),
+]
+
+
+@pytest.mark.parametrize("N,M,eps,dtype", CASES)
+def test_laplace_vs_oracle(torch, N, M, eps, dtype):
+    from paper_1606_03255_amd import LaplacePlan
+    _say("laplace", N, M, eps, dtype)
+    fhat, xi, y = _inputs(N + M, N, M, 20.0 / N)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        fhat = fhat.astype(np.complex64).astype(np.complex128)
+    plan = LaplacePlan(xi, y, eps, tdt)
+    f = plan.forward(torch.from_numpy(fhat).to("cuda", tdt))
+    f2 = plan.forward(torch.from_numpy(fhat).to("cuda", tdt))   # a second call: accumulators cleared
+    torch.cuda.synchronize()
+    f, f2 = f.cpu().numpy().astype(np.complex128), f2.cpu().numpy().astype(np.complex128)
+    plan.close()
+    n1 = np.abs(fhat).sum()
+    E = np.abs(f - LP.direct(fhat, xi, y)).max() / n1
+    _say("   E =", E)
+    assert E <= eps
+    assert np.abs(f2 - f).max() <= 1e-12 * n1
+    if dtype == "c128":
+        assert np.abs(f - LP.alg1(fhat, xi, y, eps)).max() <= 1e-13 * n1
+
+
+def test_laplace_all_nodes_at_zero(torch):
+    from paper_1606_03255_amd import LaplacePlan
+    rng = np.random.default_rng(2)
+    fhat = rng.standard_normal(3000) + 1j * rng.standard_normal(3000)
+    xi = rng.random(3000) * 50 + 0.1
+    plan = LaplacePlan(xi, np.zeros(17), 1e-10, torch.complex128)
+    f = plan.forward(torch.from_numpy(fhat).to("cuda")).cpu().numpy()
+    plan.close()
+    assert np.abs(f - fhat.sum()).max() <= 1e-14 * np.abs(fhat).sum()
+
+
+@pytest.mark.parametrize("dtype,eps", [("c64", 1e-6), ("c128", 1e-12)])
+def test_laplace_benchmark_size_sampled(torch, dtype, eps):
+    from paper_1606_03255_amd import LaplacePlan
+    N = M = 1 << 20
+    fhat, xi, y = _inputs(5, N, M, 20.0 / N)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        fhat = fhat.astype(np.complex64).astype(np.complex128)
+    plan = LaplacePlan(xi, y, eps, tdt)
+    f = plan.forward(torch.from_numpy(fhat).to("cuda", tdt)).cpu().numpy().astype(np.complex128)
+    plan.close()
+    sel = np.sort(np.random.default_rng(6).choice(M, 300, replace=False))
+    sel = np.unique(np.concatenate([sel, [M - 3, M - 2, M - 1]]))
+    E = np.abs(f[sel] - LP.direct(fhat, xi, y[sel])).max() / np.abs(fhat).sum()
+    _say("laplace 2^20", dtype, "E on", len(sel), "nodes =", E)
+    assert E <= eps
