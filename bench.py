@@ -16,6 +16,9 @@ roofline   the dominant kernel's algorithmic bytes per launch over its launch
            duration (HIP events recorded between the launches on the stream
            the kernels run on), against the 8 TB/s HBM peak; for the direct
            sums (ALU-bound) their flops against the FP32 vector peak.
+laplace    the discrete Laplace transform (Algorithm 1) at N = M = 2^20: time
+           per call, node evals/s, algorithmic bytes against the HBM peak, and
+           its error on sampled nodes against the oracle's direct sums.
 direct_scale  the band-policy factor of the forward-tuned plan (the step's own
            plan reports its factor in fwd_bwd).
 cpu_baseline  the FP64 direct-sum oracle on a random sample of the nodes, on
@@ -171,6 +174,49 @@ def batched_leg(torch, dev, args, tune, log):
     return rec
 
 
+def laplace_error(sample):
+    """Part of the CPU-baseline leg: the Laplace leg's sampled nodes against
+    the oracle's direct sums, relative to ||fhat||_1 (Thm A.3's E)."""
+    import numpy as np
+
+    import oracle.laplace as OL
+    ref = OL.direct(sample["fhat"], sample["xi"], sample["y"])
+    return float(np.abs(sample["f"] - ref).max() / np.abs(sample["fhat"]).sum())
+
+
+def laplace_leg(torch, dev, args, log):
+    """The discrete Laplace transform (Algorithm 1) at N = M = 2^20: xi_k
+    uniform in (0, N], y_j uniform in [0, 20/N] (exp(-y xi) spans 1 .. e^-20),
+    complex64 coefficients, eps 1e-6.  Roofline: the algorithmic bytes of one
+    call (per frequency: sorted value 8 B, index 4 B, fhat 8 B; per node: y
+    8 B, band 4 B, f 8 B) over its time, against the HBM peak."""
+    import numpy as np
+
+    from paper_1606_03255_amd import LaplacePlan
+    N = M = 1 << 20
+    rng = np.random.default_rng(21)
+    xi = rng.random(N) * N + 1e-3
+    y = rng.random(M) * (20.0 / N)
+    fhat = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+    t = time.perf_counter()
+    plan = LaplacePlan(xi, y, 1e-6, torch.complex64, device=dev)
+    plan_ms = (time.perf_counter() - t) * 1e3
+    fh = torch.from_numpy(fhat).to(dev)
+    f = torch.empty(M, dtype=torch.complex64, device=dev)
+    ms, _ = time_steps(torch, lambda: plan.forward(fh, out=f), max(5, args.steps), args.warmup)
+    sel = np.sort(rng.choice(M, 64, replace=False))
+    sample = {"fhat": fhat.astype(np.complex128), "xi": xi, "y": y[sel], "f": f.cpu().numpy()[sel]}
+    nbytes = N * (8 + 4 + 8) + M * (8 + 4 + 8)
+    info = plan.info()
+    plan.close()
+    rec = {"N": N, "M": M, "eps": 1e-6, "dtype": "c64 in/out, f64 arithmetic", "q": info["q"],
+           "levels": info["levels"], "ms": round(ms, 4), "node_evals_per_s": M / (ms * 1e-3),
+           "bytes_per_call": nbytes, "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+           "frac_hbm": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "E": None, "plan_ms": round(plan_ms, 1)}
+    log("laplace: %.4f ms, %.3e node evals/s" % (ms, rec["node_evals_per_s"]))
+    return rec, sample
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +227,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="plans with the default band policy instead of the timed choice")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched leg")
+    ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-transform (Algorithm 1) leg")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size reference "
                          "for HBM counter readings)")
@@ -291,6 +338,9 @@ def main():
     batched = None
     if not args.no_batched:
         batched = batched_leg(torch, dev, args, tune, log)
+    laplace = lap_sample = None
+    if not args.no_laplace and not args.forward_only:
+        laplace, lap_sample = laplace_leg(torch, dev, args, log)
 
     cpu = None
     E32 = None
@@ -299,6 +349,9 @@ def main():
         cpu, E32, E64c, n_checked = cpu_baseline(w, f32, f64 if f64 is not None else f32, p32.node_bands())
         E64 = E64c if f64 is not None else None
         log("cpu baseline", cpu, "E32", E32, "E64", E64)
+        if laplace is not None:
+            laplace["E"] = laplace_error(lap_sample)
+            log("laplace E", laplace["E"])
 
     info = p32.info()
     rec = {
@@ -317,6 +370,7 @@ def main():
         "plan_ms": round(plan32_ms, 1),
         "direct_scale": info["direct_scale"],
         "batched": batched,
+        "laplace": laplace,
         "bytes_forward_model": info["bytes_forward"],
         "wall_s_timed": round(wall, 3),
     }
