@@ -611,9 +611,8 @@ int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi,
         Packer pk;
         const size_t o_xs = pk.add(hp.xs.data(), hp.xs.size() * sizeof(double));
         const size_t o_kp = pk.add(hp.kperm.data(), hp.kperm.size() * sizeof(int32_t));
-        const size_t o_bn = pk.add(hp.bnodes.data(), hp.bnodes.size() * sizeof(double));
-        const size_t o_yn = pk.add(hp.ynodes.data(), hp.ynodes.size() * sizeof(double));
-        const size_t o_bw = pk.add(hp.bw.data(), hp.bw.size() * sizeof(double));
+        const size_t o_bc = pk.add(hp.bcw.data(), hp.bcw.size() * sizeof(double));
+        const size_t o_yc = pk.add(hp.ycw.data(), hp.ycw.size() * sizeof(double));
         const size_t o_lm = pk.add(hp.lm.data(), hp.lm.size() * sizeof(int32_t));
         const size_t o_Lm = pk.add(hp.Lm.data(), hp.Lm.size() * sizeof(int32_t));
         const size_t o_ko = pk.add(hp.koff.data(), hp.koff.size() * sizeof(int64_t));
@@ -621,7 +620,8 @@ int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi,
         const size_t o_y = pk.add(hp.y.data(), hp.y.size() * sizeof(double));
         const size_t o_bd = pk.add(hp.band.data(), hp.band.size() * sizeof(int32_t));
         const size_t o_it = pk.add(hp.items.data(), hp.items.size() * sizeof(LapItem));
-        std::vector<double> zeros((size_t)lap_acc_doubles(hp.L, hp.q), 0.0);
+        const size_t o_bi = pk.add(hp.bitem.data(), hp.bitem.size() * sizeof(int32_t));
+        std::vector<double> zeros((size_t)lap_acc_doubles(hp.L, hp.q) + hp.items.size() * 2 * hp.q, 0.0);
         const size_t o_acc = pk.add(zeros.data(), zeros.size() * sizeof(double));
         hipError_t e = hipMalloc(&p->dev, pk.buf.size());
         if (e == hipSuccess) e = hipMemcpy(p->dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
@@ -636,16 +636,18 @@ int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi,
         V.L = hp.L;
         V.xs = (const double*)(b + o_xs);
         V.kperm = (const int32_t*)(b + o_kp);
-        V.bnodes = (const double*)(b + o_bn);
-        V.ynodes = (const double*)(b + o_yn);
-        V.bw = (const double*)(b + o_bw);
+        V.bcw = (const double*)(b + o_bc);
+        V.ycw = (const double*)(b + o_yc);
         V.lm = (const int32_t*)(b + o_lm);
         V.Lm = (const int32_t*)(b + o_Lm);
         V.koff = (const int64_t*)(b + o_ko);
         V.K = (const double*)(b + o_K);
         V.y = (const double*)(b + o_y);
         V.band = (const int32_t*)(b + o_bd);
+        V.bitem = (const int32_t*)(b + o_bi);
+        V.nitems = (int32_t)hp.items.size();
         V.acc = (double*)(b + o_acc);
+        V.part = V.acc + lap_acc_doubles(hp.L, hp.q);
         p->items = (const LapItem*)(b + o_it);
         p->host_only = false;
     }

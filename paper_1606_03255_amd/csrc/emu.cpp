@@ -218,36 +218,47 @@ namespace flt {
 // The Laplace transform's kernel bodies on the CPU (same plan, same launches).
 template <typename T> static int emu_laplace(const LapHost& hp, const void* in, void* out)
 {
-    std::vector<double> acc((size_t)lap_acc_doubles(hp.L, hp.q), 1e300);   // garbage: the zero kernel must clear it
+    // garbage: every call must write each accumulator and partial before reading it
+    std::vector<double> acc((size_t)lap_acc_doubles(hp.L, hp.q), 1e300);
+    std::vector<double> part(hp.items.size() * 2 * hp.q, 1e300);
     LapView V{};
     V.q = hp.q;
     V.L = hp.L;
     V.xs = hp.xs.data();
     V.kperm = hp.kperm.data();
-    V.bnodes = hp.bnodes.data();
-    V.ynodes = hp.ynodes.data();
-    V.bw = hp.bw.data();
+    V.bcw = hp.bcw.data();
+    V.ycw = hp.ycw.data();
     V.lm = hp.lm.data();
     V.Lm = hp.Lm.data();
     V.koff = hp.koff.data();
     V.K = hp.K.data();
     V.y = hp.y.data();
     V.band = hp.band.data();
+    V.bitem = hp.bitem.data();
+    V.nitems = (int32_t)hp.items.size();
+    V.part = part.data();
     V.acc = acc.data();
-    const int64_t n = (int64_t)acc.size();
-    run_blocks((n + LAP_THREADS - 1) / LAP_THREADS, LAP_THREADS, [&](const HostCtx& ctx) {
-        lap_body_zero(ctx, V.acc, n);
-    });
-    std::vector<double> sden(LAP_CHUNK), sf(2 * LAP_CHUNK), red(4 * LAP_THREADS);
-    std::vector<int32_t> shit(LAP_CHUNK);
-    run_blocks(hp.items.size(), LAP_THREADS, [&](const HostCtx& ctx) {
-        lap_body_moments<HostCtx, T>(ctx, V, hp.items.data(), (const cplx<T>*)in, sden.data(), shit.data(),
-                                     sf.data(), red.data());
-    });
-    run_blocks(1, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_bands(ctx, V); });
-    run_blocks((hp.M + LAP_THREADS - 1) / LAP_THREADS, LAP_THREADS, [&](const HostCtx& ctx) {
-        lap_body_nodes<HostCtx, T>(ctx, V, hp.M, (cplx<T>*)out);
-    });
+    std::vector<double> red(8 * LAP_THREADS), red2(LAP_THREADS), rred(LAP_THREADS), bred(4 * LAP_THREADS);
+    auto all = [&](auto qb) {
+        constexpr int QB = decltype(qb)::value;
+        run_blocks(hp.items.size(), LAP_THREADS, [&](const HostCtx& ctx) {
+            lap_body_moments<HostCtx, T, QB>(ctx, V, hp.items.data(), (const cplx<T>*)in, red.data(), red2.data());
+        });
+        run_blocks((size_t)hp.L, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_reduce(ctx, V, rred.data()); });
+        run_blocks((size_t)hp.L, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_bands<HostCtx, QB>(ctx, V, bred.data()); });
+        const int64_t per = (int64_t)LAP_THREADS * LAP_NODE_PER, ns = lap_node_stage(hp.L, hp.q);
+        std::vector<double> sb((size_t)std::max<int64_t>(ns, 1));
+        run_blocks((hp.M + per - 1) / per, LAP_THREADS, [&](const HostCtx& ctx) {
+            lap_body_nodes<HostCtx, T, QB>(ctx, V, hp.M, (cplx<T>*)out, ns > 0 ? sb.data() : nullptr);
+        });
+    };
+    switch (lap_qbucket(hp.q)) {
+    case 8: all(std::integral_constant<int, 8>()); break;
+    case 12: all(std::integral_constant<int, 12>()); break;
+    case 16: all(std::integral_constant<int, 16>()); break;
+    case 24: all(std::integral_constant<int, 24>()); break;
+    default: all(std::integral_constant<int, 32>()); break;
+    }
     return FLT_OK;
 }
 

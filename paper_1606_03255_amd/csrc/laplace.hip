@@ -11,45 +11,60 @@ struct LapCtx {
     __device__ __forceinline__ int ntid() const { return (int)blockDim.x; }
     __device__ __forceinline__ int bid() const { return (int)blockIdx.x; }
     __device__ __forceinline__ void sync() const { __syncthreads(); }
-    __device__ __forceinline__ void atomic_add(double* p, double v) const { unsafeAtomicAdd(p, v); }
 };
 
-__global__ __launch_bounds__(LAP_THREADS) void k_lap_zero(double* acc, int64_t n)
-{
-    lap_body_zero(LapCtx(), acc, n);
-}
-
-template <typename T>
+template <typename T, int QB>
 __global__ __launch_bounds__(LAP_THREADS) void k_lap_moments(LapView V, const LapItem* items, const cplx<T>* fhat)
 {
-    __shared__ double sden[LAP_CHUNK], sf[2 * LAP_CHUNK], red[4 * LAP_THREADS];
-    __shared__ int32_t shit[LAP_CHUNK];
-    lap_body_moments<LapCtx, T>(LapCtx(), V, items, fhat, sden, shit, sf, red);
+    __shared__ double red[8 * LAP_THREADS], red2[LAP_THREADS];
+    lap_body_moments<LapCtx, T, QB>(LapCtx(), V, items, fhat, red, red2);
 }
 
+__global__ __launch_bounds__(LAP_THREADS) void k_lap_reduce(LapView V)
+{
+    __shared__ double red[LAP_THREADS];
+    lap_body_reduce(LapCtx(), V, red);
+}
+
+template <int QB>
 __global__ __launch_bounds__(LAP_THREADS) void k_lap_bands(LapView V)
 {
-    lap_body_bands(LapCtx(), V);
+    __shared__ double red[4 * LAP_THREADS];
+    lap_body_bands<LapCtx, QB>(LapCtx(), V, red);
 }
 
-template <typename T>
-__global__ __launch_bounds__(LAP_THREADS) void k_lap_nodes(LapView V, int64_t M, cplx<T>* f)
+template <typename T, int QB>
+__global__ __launch_bounds__(LAP_THREADS) void k_lap_nodes(LapView V, int64_t M, cplx<T>* f, int staged)
 {
-    lap_body_nodes<LapCtx, T>(LapCtx(), V, M, f);
+    extern __shared__ double sb[];   // lap_node_stage(L, q) doubles when staged
+    lap_body_nodes<LapCtx, T, QB>(LapCtx(), V, M, f, staged ? sb : nullptr);
 }
 
-// Clear the accumulators, block moments and sums, band side, node side.
+// Item partials of the block moments, their sum per block, band side, node
+// side, at one rank bucket.  Every accumulator is written in full by each call.
+template <typename T, int QB>
+static void launch_all(const LapView& V, const LapItem* items, int nitems, int64_t M, const void* fhat, void* f,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL((k_lap_moments<T, QB>), dim3(nitems), dim3(LAP_THREADS), 0, st, V, items, (const cplx<T>*)fhat);
+    hipLaunchKernelGGL(k_lap_reduce, dim3((unsigned)V.L), dim3(LAP_THREADS), 0, st, V);
+    hipLaunchKernelGGL(k_lap_bands<QB>, dim3((unsigned)V.L), dim3(LAP_THREADS), 0, st, V);
+    const int64_t per = (int64_t)LAP_THREADS * LAP_NODE_PER, ns = lap_node_stage(V.L, V.q);
+    hipLaunchKernelGGL((k_lap_nodes<T, QB>), dim3((unsigned)((M + per - 1) / per)), dim3(LAP_THREADS),
+                       (unsigned)(ns * sizeof(double)), st, V, M, (cplx<T>*)f, ns > 0 ? 1 : 0);
+}
+
 template <typename T>
 hipError_t launch_laplace(const LapView& V, const LapItem* items, int nitems, int64_t M, const void* fhat, void* f,
                           hipStream_t st)
 {
-    const int64_t n = lap_acc_doubles(V.L, V.q);
-    hipLaunchKernelGGL(k_lap_zero, dim3((unsigned)((n + LAP_THREADS - 1) / LAP_THREADS)), dim3(LAP_THREADS), 0, st,
-                       V.acc, n);
-    hipLaunchKernelGGL(k_lap_moments<T>, dim3(nitems), dim3(LAP_THREADS), 0, st, V, items, (const cplx<T>*)fhat);
-    hipLaunchKernelGGL(k_lap_bands, dim3(1), dim3(LAP_THREADS), 0, st, V);
-    hipLaunchKernelGGL(k_lap_nodes<T>, dim3((unsigned)((M + LAP_THREADS - 1) / LAP_THREADS)), dim3(LAP_THREADS), 0,
-                       st, V, M, (cplx<T>*)f);
+    switch (lap_qbucket(V.q)) {
+    case 8: launch_all<T, 8>(V, items, nitems, M, fhat, f, st); break;
+    case 12: launch_all<T, 12>(V, items, nitems, M, fhat, f, st); break;
+    case 16: launch_all<T, 16>(V, items, nitems, M, fhat, f, st); break;
+    case 24: launch_all<T, 24>(V, items, nitems, M, fhat, f, st); break;
+    default: launch_all<T, 32>(V, items, nitems, M, fhat, f, st); break;
+    }
     return hipGetLastError();
 }
 

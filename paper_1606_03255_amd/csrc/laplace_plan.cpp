@@ -60,16 +60,17 @@ int build_laplace_plan(LapHost& hp, int64_t N, const double* xi, int64_t M, cons
     hp.L = std::max(hp.L, 1);
     if (hp.L > 1000) return FLT_ERANGE;
     const int L = hp.L;
-    hp.bw.resize(q);
-    for (int r = 0; r < q; ++r) hp.bw[r] = (r & 1 ? -1.0 : 1.0) * std::sin((2 * r + 1) * M_PI / (2.0 * q));
-    // frequencies sorted by block, then value
+    // frequencies grouped by block, caller order kept inside a block (a
+    // counting sort): neighbouring lanes then gather nearby coefficients
     std::vector<int32_t> blk(N);
-    for (int64_t k = 0; k < N; ++k) blk[k] = lap_level(xi[k], xi1, L);
+    std::vector<int64_t> first((size_t)L + 2, 0);
+    for (int64_t k = 0; k < N; ++k) {
+        blk[k] = lap_level(xi[k], xi1, L);
+        first[blk[k] + 1]++;
+    }
+    for (int l = 1; l <= L + 1; ++l) first[l] += first[l - 1];
     std::vector<int32_t> ord(N);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-        return blk[a] != blk[b] ? blk[a] < blk[b] : xi[a] < xi[b];
-    });
+    for (int64_t k = 0; k < N; ++k) ord[first[blk[k]]++] = (int32_t)k;
     hp.xs.resize(N);
     hp.kperm.resize(N);
     for (int64_t i = 0; i < N; ++i) {
@@ -82,23 +83,60 @@ int build_laplace_plan(LapHost& hp, int64_t N, const double* xi, int64_t M, cons
         hp.items.push_back(LapItem{blk[ord[i]], (int32_t)(e - i), i});
         i = e;
     }
-    // Chebyshev nodes of the blocks l < L and bands m < L (closures of the intervals)
-    hp.bnodes.assign((size_t)std::max(L - 1, 1) * q, 0.0);
-    hp.ynodes.assign((size_t)std::max(L - 1, 1) * q, 0.0);
-    for (int l = 1; l < L; ++l) cheb_nodes(std::ldexp(xi1, -l), std::ldexp(xi1, 1 - l), q, &hp.bnodes[(size_t)(l - 1) * q]);
-    for (int m = 1; m < L; ++m) cheb_nodes(std::ldexp(y1, -m), std::ldexp(y1, 1 - m), q, &hp.ynodes[(size_t)(m - 1) * q]);
-    // l_m, L_m (Def. 3.2; natural log inside l_m) and K^{Y_m,Omega_l}[s][r] = exp(-y_s xi_r)
+    if (hp.items.size() > (size_t)INT32_MAX / 2) return FLT_ERANGE;
+    hp.bitem.assign((size_t)L + 1, 0);   // items of block l: bitem[l - 1] .. bitem[l] - 1
+    for (const LapItem& it : hp.items) hp.bitem[it.blk]++;
+    for (int l = 1; l <= L; ++l) hp.bitem[l] += hp.bitem[l - 1];
+    // Chebyshev nodes, centres and inverse half-widths of the blocks l < L and
+    // bands m < L (closures of the intervals)
+    const size_t nl = (size_t)std::max(L - 1, 1);
+    std::vector<double> bnodes(nl * q, 0.0), ynodes(nl * q, 0.0);
+    hp.bcw.assign(2 * nl, 0.0);
+    hp.ycw.assign(2 * (size_t)L, 0.0);   // band L: t = 0
+    for (int l = 1; l < L; ++l) {
+        const double a = std::ldexp(xi1, -l), b = std::ldexp(xi1, 1 - l);
+        cheb_nodes(a, b, q, &bnodes[(size_t)(l - 1) * q]);
+        hp.bcw[2 * (l - 1)] = 0.5 * (a + b);
+        hp.bcw[2 * (l - 1) + 1] = 2.0 / (b - a);
+    }
+    for (int m = 1; m < L; ++m) {
+        const double a = std::ldexp(y1, -m), b = std::ldexp(y1, 1 - m);
+        cheb_nodes(a, b, q, &ynodes[(size_t)(m - 1) * q]);
+        hp.ycw[2 * (m - 1)] = 0.5 * (a + b);
+        hp.ycw[2 * (m - 1) + 1] = 2.0 / (b - a);
+    }
+    // C[p][r] = a_p T_p(tau_r) = a_p cos(p (2r+1) pi / (2q)), a_0 = 1/q, a_p = 2/q
+    std::vector<double> C((size_t)q * q);
+    for (int p = 0; p < q; ++p)
+        for (int r = 0; r < q; ++r)
+            C[(size_t)p * q + r] = (p ? 2.0 : 1.0) / q * std::cos(p * (2 * r + 1) * M_PI / (2.0 * q));
+    // l_m, L_m (Def. 3.2; natural log inside l_m) and, per (m, l), C K C^T with
+    // K^{Y_m,Omega_l}[s][r] = exp(-y_s xi_r)
     const double lg = L > 1 ? std::log2(y1 * xi1) - std::log2(std::log(1.0 / eps)) : 0.0;
+    std::vector<double> K((size_t)q * q), KC((size_t)q * q);
     for (int m = 1; m < L; ++m) {
         const int lm = std::max(1, (int)std::floor(lg - m) + 1);
         const int Lm = L - m;
         hp.lm.push_back(lm);
         hp.Lm.push_back(Lm);
         hp.koff.push_back((int64_t)hp.K.size());
-        for (int l = lm; l <= Lm; ++l)
+        for (int l = lm; l <= Lm; ++l) {
             for (int s = 0; s < q; ++s)
                 for (int r = 0; r < q; ++r)
-                    hp.K.push_back(std::exp(-hp.ynodes[(size_t)(m - 1) * q + s] * hp.bnodes[(size_t)(l - 1) * q + r]));
+                    K[(size_t)s * q + r] = std::exp(-ynodes[(size_t)(m - 1) * q + s] * bnodes[(size_t)(l - 1) * q + r]);
+            for (int s = 0; s < q; ++s)   // KC = K C^T
+                for (int p = 0; p < q; ++p) {
+                    double a = 0.0;
+                    for (int r = 0; r < q; ++r) a += K[(size_t)s * q + r] * C[(size_t)p * q + r];
+                    KC[(size_t)s * q + p] = a;
+                }
+            for (int pp = 0; pp < q; ++pp)   // C KC
+                for (int p = 0; p < q; ++p) {
+                    double a = 0.0;
+                    for (int s = 0; s < q; ++s) a += C[(size_t)pp * q + s] * KC[(size_t)s * q + p];
+                    hp.K.push_back(a);
+                }
+        }
     }
     if (hp.lm.empty()) {   // keep every table non-empty
         hp.lm.push_back(1);

@@ -83,7 +83,7 @@ def test_cpu_build_edge_cases(emu):
     xi = rng.random(50) * 10 + 0.5
     got = run(emu, fhat, xi, np.zeros(9), eps, 2)
     assert np.abs(got - fhat.sum()).max() <= 1e-14 * np.abs(fhat).sum()
-    # nodes and frequencies exactly on Chebyshev nodes (the barycentric hit path)
+    # nodes and frequencies exactly on Chebyshev nodes (the Lagrange form's removable singularities)
     N, M = 400, 60
     fhat = rng.standard_normal(N) + 1j * rng.standard_normal(N)
     xi = rng.random(N) * 100 + 1.0
@@ -101,6 +101,28 @@ def test_cpu_build_edge_cases(emu):
     # one frequency, one node
     got = run(emu, np.array([2 - 1j]), np.array([3.0]), np.array([0.25]), eps, 2)
     assert abs(got[0] - (2 - 1j) * np.exp(-0.75)) <= eps * abs(2 - 1j)
+
+
+def _wide(seed, N, M):
+    # frequencies and nodes over many decades (most products y xi far past
+    # exp underflow): q = 24 and L > 160 at eps = 1e-14, so the node kernel
+    # reads its band data from global memory (too large to stage in LDS)
+    rng = np.random.default_rng(seed)
+    xi = 10.0 ** rng.uniform(-3, 19, N)
+    y = np.concatenate([[0.0], 10.0 ** rng.uniform(-20, 17, M - 1)])
+    fhat = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return fhat, xi, y
+
+
+def test_cpu_build_wide_range(emu):
+    fhat, xi, y = _wide(3, 2000, 700)
+    eps = 1e-14
+    info = LaplacePlan(xi, y, eps, "complex128", host_only=True).info()
+    assert 2 * info["levels"] * info["q"] + 2 * info["levels"] > 8192
+    got = run(emu, fhat, xi, y, eps, 2)
+    n1 = np.abs(fhat).sum()
+    assert np.abs(got - LP.direct(fhat, xi, y)).max() <= eps * n1
+    assert np.abs(got - LP.alg1(fhat, xi, y, eps)).max() <= 1e-13 * n1
 
 
 def test_abi_argument_checks():
