@@ -285,6 +285,15 @@ template <class Ctx, typename T, int QB>
 FLT_HD void lap_body_nodes(const Ctx& ctx, const LapView& V, int64_t M, cplx<T>* f, double* sb)
 {
     const int q = V.q, L = V.L, tid = ctx.tid();
+    int m[LAP_NODE_PER];
+    double yv[LAP_NODE_PER];
+    const int64_t j0 = (int64_t)ctx.bid() * LAP_NODE_PER * ctx.ntid() + tid;
+#pragma unroll
+    for (int k = 0; k < LAP_NODE_PER; ++k) {   // clamped, unconditional loads, issued before the staging
+        const int64_t j = j0 + (int64_t)k * ctx.ntid() < M ? j0 + (int64_t)k * ctx.ntid() : M - 1;
+        m[k] = V.band[j];
+        yv[k] = V.y[j];
+    }
     const double* beta = V.acc + lap_beta(L, q, 1, 0);   // band m at 2 (m - 1) q
     const double* cw = V.ycw;
     if (sb) {   // (uniform)
@@ -294,15 +303,6 @@ FLT_HD void lap_body_nodes(const Ctx& ctx, const LapView& V, int64_t M, cplx<T>*
         ctx.sync();
         beta = sb;
         cw = sb + nb;
-    }
-    int m[LAP_NODE_PER];
-    double yv[LAP_NODE_PER];
-    const int64_t j0 = (int64_t)ctx.bid() * LAP_NODE_PER * ctx.ntid() + tid;
-#pragma unroll
-    for (int k = 0; k < LAP_NODE_PER; ++k) {   // clamped, unconditional loads
-        const int64_t j = j0 + (int64_t)k * ctx.ntid() < M ? j0 + (int64_t)k * ctx.ntid() : M - 1;
-        m[k] = V.band[j];
-        yv[k] = V.y[j];
     }
 #pragma unroll
     for (int k = 0; k < LAP_NODE_PER; ++k) {
