@@ -161,8 +161,12 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             });
             std::vector<cplx<T>> nw(DIRECT_NG);
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
-                body_direct_fwd<HostCtx, T>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, deriv || d,
-                                            dacc.data(), red.data(), nw.data());
+                if (deriv || d)
+                    body_direct_fwd<HostCtx, T, true>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, dacc.data(),
+                                                      red.data(), nw.data());
+                else
+                    body_direct_fwd<HostCtx, T, false>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, dacc.data(),
+                                                       red.data(), nw.data());
             });
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 1);

@@ -131,13 +131,13 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj_f64(PlanView<doubl
     passA_adj_kernel<double>(pv, items, scratch, acc);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_direct_fwd(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
-                                                    const cplx<T>* c, int deriv, double* dacc)
+template <typename T, bool DERIV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_direct_fwd(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
+                                                    const cplx<T>* c, double* dacc)
 {
     __shared__ double red[2 * DIRECT_NG * 256];
     __shared__ cplx<T> nw[DIRECT_NG];
-    body_direct_fwd<DevCtx, T>(DevCtx(), pv, items, dlist, c, deriv, dacc, red, nw);
+    body_direct_fwd<DevCtx, T, DERIV>(DevCtx(), pv, items, dlist, c, dacc, red, nw);
 }
 
 template <typename T>
@@ -278,8 +278,12 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
         for (int d = 0; d < cols; ++d) {   // direct bands: exact sums, of c and (cols = 2) of c'
             cplx<T>* out = d ? f2 : f;
             hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 0);
-            hipLaunchKernelGGL(k_direct_fwd<T>, dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd, L.dlist,
-                               c, deriv || d, dacc);
+            if (deriv || d)
+                hipLaunchKernelGGL((k_direct_fwd<T, true>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd,
+                                   L.dlist, c, dacc);
+            else
+                hipLaunchKernelGGL((k_direct_fwd<T, false>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv,
+                                   L.direct_fwd, L.dlist, c, dacc);
             hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 1);
         }
     }

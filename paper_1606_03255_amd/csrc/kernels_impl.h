@@ -1042,7 +1042,10 @@ FLT_HD void body_sum_g(const Ctx& ctx, const PlanView<T>& pv, const SumItem* ite
 // inner sum by Horner's scheme in T and the anchor w^{k0} formed directly;
 // adjoint, the powers by the recurrence p <- p w from the anchor.  Partial
 // sums are combined in FP64.  A forward workgroup holds DIRECT_NG nodes (their
-// w in LDS) and up to direct_cpw chunks of terms, reduced once.
+// w in LDS, then registers) and up to direct_cpw chunks of terms, reduced
+// once; a thread runs the Horner recurrences of its group's nodes side by
+// side (independent chains: all 8 in FP32, fewer in FP64), the derivative's
+// 2 pi i k factors, applied as c is loaded, only in the DERIV instance.
 // ---------------------------------------------------------------------------
 
 // w^k0 = e^{-k0 y} cis(sign 2 pi k0 x) with the phase reduced exactly in FP64
@@ -1074,43 +1077,66 @@ template <typename T> FLT_HD cplx<T> direct_w(const PlanView<T>& pv, int32_t j, 
     return mk<T>((T)(m1 * cs), (T)(m1 * sn));
 }
 
-template <class Ctx, typename T>
+template <class Ctx, typename T, bool DERIV>
 FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
-                            const cplx<T>* call, int deriv, double* dacc, double* red, cplx<T>* nw)
+                            const cplx<T>* call, double* dacc, double* red, cplx<T>* nw)
 {
     const DirectItem it = items[ctx.bid()];
     const int64_t N = pv.inst[it.inst].N;
     const cplx<T>* c = call + pv.inst[it.inst].c_off;
     const int tid = ctx.tid(), nt = ctx.ntid();
-    if (tid < it.count) nw[tid] = direct_w(pv, dlist[it.first + tid], +1.0);
+    if (tid < DIRECT_NG) nw[tid] = tid < it.count ? direct_w(pv, dlist[it.first + tid], +1.0) : mk<T>(0, 0);
     for (int r = 0; r < 2 * DIRECT_NG; ++r) red[r * nt + tid] = 0.0;   // this thread's partial sums
     ctx.sync();
+    // Horner chains side by side (registers): all 8 nodes in FP32, 4 at a time
+    // for the FP64 forward, one at a time for the FP64 derivative
+    constexpr int NC = sizeof(T) == 4 ? DIRECT_NG : DERIV ? 1 : DIRECT_NG / 2;
     for (int cc = 0; cc < it.nch; ++cc) {
         const int64_t k0 = (((int64_t)it.chunk + cc) * nt + tid) * DIRECT_TPT;
         if (k0 >= N) break;
         cplx<T> cv[DIRECT_TPT];
-        for (int t = 0; t < DIRECT_TPT; ++t) {
-            const int64_t k = k0 + t;
-            cplx<T> v = k < N ? c[k] : mk<T>(0, 0);
-            if (deriv) {
-                const T sc = (T)(6.283185307179586476925286766559 * (double)k);
+        if (k0 + DIRECT_TPT <= N) {   // unconditional loads (no per-term branch), then the tail
+            for (int t = 0; t < DIRECT_TPT; ++t) cv[t] = c[k0 + t];
+        } else {
+            for (int t = 0; t < DIRECT_TPT; ++t) cv[t] = k0 + t < N ? c[k0 + t] : mk<T>(0, 0);
+        }
+        const T sc0 = (T)(6.283185307179586476925286766559 * (double)k0);   // 2 pi k = 2 pi k0 + 2 pi t
+        for (int t = 0; t < DIRECT_TPT; ++t) {   // c_t, or 2 pi i k c_t for the derivative
+            cplx<T> v = cv[t];
+            if constexpr (DERIV) {   // (FP32: a literal per t; FP64: one product per t, no table of constants)
+                const T sc = sizeof(T) == 4 ? sc0 + (T)(6.283185307179586476925286766559 * t)
+                                            : (T)(6.283185307179586476925286766559 * (double)(k0 + t));
                 v = mk(-v.y * sc, v.x * sc);
             }
             cv[t] = v;
         }
-        for (int gi = 0; gi < DIRECT_NG; ++gi) {
-            if (gi >= it.count) break;
-            const int32_t j = dlist[it.first + gi];
-            const cplx<T> w = nw[gi];
-            T hr = cv[DIRECT_TPT - 1].x, hi = cv[DIRECT_TPT - 1].y;   // Horner: h <- h w + c_t, t descending
-            for (int t = DIRECT_TPT - 2; t >= 0; --t) {
-                const T nr = hr * w.x - hi * w.y + cv[t].x;
-                hi = hr * w.y + hi * w.x + cv[t].y;
-                hr = nr;
+        auto coef = [&](int t) -> cplx<T> { return cv[t]; };
+        for (int g0 = 0; g0 < DIRECT_NG; g0 += NC) {
+            if (g0 >= it.count) break;
+            // Horner, h <- h w + c_t for t descending, NC nodes of the group at once
+            cplx<T> w[NC];
+            T hr[NC], hi[NC];
+            const cplx<T> cl = coef(DIRECT_TPT - 1);
+            for (int g = 0; g < NC; ++g) {
+                w[g] = nw[g0 + g];
+                hr[g] = cl.x;
+                hi[g] = cl.y;
             }
-            const cplx<T> a = mul(direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], +1.0), mk(hr, hi));
-            red[(2 * gi) * nt + tid] += (double)a.x;
-            red[(2 * gi + 1) * nt + tid] += (double)a.y;
+            for (int t = DIRECT_TPT - 2; t >= 0; --t) {
+                const cplx<T> ct = coef(t);
+                for (int g = 0; g < NC; ++g) {
+                    const T nr = hr[g] * w[g].x - hi[g] * w[g].y + ct.x;
+                    hi[g] = hr[g] * w[g].y + hi[g] * w[g].x + ct.y;
+                    hr[g] = nr;
+                }
+            }
+            for (int g = 0; g < NC; ++g) {
+                if (g0 + g >= it.count) break;
+                const int32_t j = dlist[it.first + g0 + g];
+                const cplx<T> a = mul(direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], +1.0), mk(hr[g], hi[g]));
+                red[(2 * (g0 + g)) * nt + tid] += (double)a.x;
+                red[(2 * (g0 + g) + 1) * nt + tid] += (double)a.y;
+            }
         }
     }
     ctx.sync();
