@@ -96,9 +96,11 @@ def time_steps(torch, fn, steps, warmup):
     return t0.elapsed_time(t1) / steps, wall
 
 
-def traffic_for(kernel):
+def traffic_for(kernel, algorithmic_bytes):
     """HBM traffic per launch from the committed rocprofv3 counter summary, or
-    None if it was taken on different kernel sources."""
+    None if it was taken on different kernel sources or on a plan whose
+    stage moves different algorithmic bytes (the band policy is tuned at run
+    time, so two runs can pick different plans)."""
     path = os.path.join(ROOT, "profiles", "traffic_large_fp32.json")
     if not os.path.exists(path):
         return None
@@ -107,7 +109,9 @@ def traffic_for(kernel):
     if rec.get("source_hash") != kernel_source_hash():
         return None
     v = rec.get("kernels", {}).get(KERNEL_NAMES[kernel])
-    return None if v is None else v.get("bytes_per_launch")
+    if v is None or v.get("algorithmic_bytes_per_launch") != algorithmic_bytes:
+        return None
+    return v.get("bytes_per_launch")
 
 
 def cpu_baseline(w, f32, f64, plan_bands, target_s=12.0):
@@ -289,12 +293,12 @@ def main():
         flops = 8.0 * nd * N
         achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic_for(dom),
+                    "frac": round(achieved / FP32_PEAK_TFLOPS, 4), "traffic": traffic_for(dom, sb[dom]),
                     "kernel": KERNEL_NAMES[dom], "flops_per_launch": flops, "ms_per_launch": round(stage_ms[dom], 4)}
     else:
         achieved = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom), "kernel": KERNEL_NAMES[dom],
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, sb[dom]), "kernel": KERNEL_NAMES[dom],
                     "bytes_per_launch": sb[dom], "ms_per_launch": round(stage_ms[dom], 4)}
     log("stages ms", {k: round(v, 4) for k, v in stage_ms.items()})
 
