@@ -198,8 +198,11 @@ typedef struct flt_laplace_info {
 
 /* Plan for N frequencies xi (host, N doubles, > 0, finite) and M nodes y
  * (host, M doubles, >= 0, finite); both copied.  flags: 0 or
- * FLT_FLAG_HOST_ONLY.  The plan owns a small device accumulator (a few KB), so
- * transform calls allocate nothing; calls on one plan must not overlap.
+ * FLT_FLAG_HOST_ONLY.  The plan owns one device allocation: its tables (about
+ * 12 bytes per frequency and per node, plus the band-block matrices) and its
+ * scratch (per block and band accumulators, 16q bytes per 2048 frequencies of
+ * item partials), all rewritten by every call; transform calls allocate
+ * nothing, and calls on one plan must not overlap.
  * Errors: FLT_EINVAL (null, N or M < 1, dtype, flags), FLT_EDOMAIN (eps outside
  * (0,1), xi <= 0, y < 0, non-finite values), FLT_EPRECISION (eps below 1e-6
  * for FLT_C64, 1e-14 for FLT_C128), FLT_ERANGE, FLT_EHIP, FLT_ENOMEM. */
