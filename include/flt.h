@@ -55,8 +55,9 @@ typedef struct flt_plan flt_plan;
                                         (and again whenever the buffers or the workspace change) and replay it */
 #define FLT_FLAG_AUTOTUNE  (1u << 3) /* choose the band policy by timing: candidate plans (the direct-sum rate of
                                         the policy scaled by 0, 1/2, 1, 2, 4, 8; distinct band choices only) run
-                                        forward + adjoint on the device during creation; in that order, each
-                                        replaces the choice only when at least 2% faster;
+                                        forward + adjoint on the device during creation, all of them twice (the
+                                        first pass a warm-up); in that order, each replaces the choice only when
+                                        at least 5% faster;
                                         the choice is cached per (objective, dtype, eps, instances, size class)
                                         for the process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
 #define FLT_FLAG_TUNE_FORWARD (1u << 4) /* with FLT_FLAG_AUTOTUNE: time the forward alone (plans used for

@@ -180,8 +180,9 @@ static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, void* 
 
 // FLT_FLAG_AUTOTUNE: the band policy's direct-sum rate factor chosen by timing
 // forward + adjoint (FLT_FLAG_TUNE_FORWARD: the forward alone) of candidate
-// plans, factors in ascending order, each replacing the current choice only
-// when at least 2% faster; cached per (objective, dtype, eps, instances, size
+// plans (all of them timed twice, the first pass a warm-up), factors in
+// ascending order, each replacing the current choice only when at least 5%
+// faster; cached per (objective, dtype, eps, instances, size
 // class of sum N and sum M) for the life of the process.
 namespace {
 const double TUNE_SCALES[] = {0.0, 0.5, 1.0, 2.0, 4.0, 8.0};
@@ -260,12 +261,20 @@ template <class Build> static int tuned_scale(uint32_t flags, Build&& build, dou
             return FLT_OK;
         }
     }
+    // the distinct candidates (by their set of direct bands), uploaded
     std::vector<std::vector<int>> seen;
-    double best = 1e300;
-    *scale = 1.0;
+    std::vector<flt_plan*> cands;
+    std::vector<double> scales;
+    auto release_all = [&]() {
+        for (flt_plan* c : cands) release(c);
+        cands.clear();
+    };
     for (double sc : TUNE_SCALES) {
         flt_plan* cand = new (std::nothrow) flt_plan();
-        if (!cand) return FLT_ENOMEM;
+        if (!cand) {
+            release_all();
+            return FLT_ENOMEM;
+        }
         rc = build(cand->hp, sc);
         std::vector<int> sig;
         for (const BandDesc& B : cand->hp.bands) sig.push_back(B.direct);
@@ -275,19 +284,35 @@ template <class Build> static int tuned_scale(uint32_t flags, Build&& build, dou
             seen.push_back(sig);
             cand->host_only = false;
             rc = upload(cand);
-            double ms = 0;
-            if (rc == FLT_OK) rc = time_candidate(cand, fwd_only, &ms);
-            // a later (larger) factor replaces the choice only when clearly
-            // faster: candidates within timing noise keep the first, so the
-            // choice does not flip between runs
-            if (rc == FLT_OK && ms < 0.98 * best) {
-                best = ms;
-                *scale = sc;
+            if (rc == FLT_OK) {
+                cands.push_back(cand);
+                scales.push_back(sc);
+                continue;
             }
         }
         release(cand);
-        if (rc != FLT_OK) return rc;
+        if (rc != FLT_OK) {
+            release_all();
+            return rc;
+        }
     }
+    // two passes over all of them; the first only warms the device (clocks,
+    // caches), so that no candidate is timed colder than another
+    std::vector<double> ms(cands.size(), 0.0);
+    for (int pass = 0; pass < 2 && rc == FLT_OK; ++pass)
+        for (size_t i = 0; i < cands.size() && rc == FLT_OK; ++i) rc = time_candidate(cands[i], fwd_only, &ms[i]);
+    release_all();
+    if (rc != FLT_OK) return rc;
+    // a later (larger) factor replaces the choice only when clearly faster:
+    // candidates within timing noise keep the first, so the choice does not
+    // flip between runs
+    double best = 1e300;
+    *scale = 1.0;
+    for (size_t i = 0; i < ms.size(); ++i)
+        if (ms[i] < 0.95 * best) {
+            best = ms[i];
+            *scale = scales[i];
+        }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = *scale;
     return FLT_OK;
