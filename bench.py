@@ -11,11 +11,16 @@ value      node evaluations per second of the FP32 form (eps = 1e-6): M times
 fwd_bwd    forward and derivative (f and f' for dL/dz, one fused call) plus the
            adjoint (dL/dc) per step, for the FP32 form and for the plain FP64
            path (eps = 1e-11) on the same inputs; speedup = t(FP64) / t(FP32).
-           ms_separate_fp32 times the three calls made one by one.
+           ms_separate_fp32 times the three calls made one by one.  The same
+           step at N = M = 2^18 (nodes in the disk) is fwd_bwd_grad.  Every
+           output of a timed step carries its error E against the oracle.
 roofline   the dominant kernel's algorithmic bytes per launch over its launch
            duration (HIP events recorded between the launches on the stream
            the kernels run on), against the 8 TB/s HBM peak; for the direct
-           sums (ALU-bound) their flops against the FP32 vector peak.
+           sums (ALU-bound) their flops against the FP32 vector peak.  The
+           adjoint's dominant stage (roofline_adjoint) and the FP64 path's
+           forward (roofline_fp64) are reported the same way; hbm_copy_GBs is
+           a measured device-to-device copy rate beside the datasheet peak.
 laplace    the discrete Laplace transform (Algorithm 1) at N = M = 2^20: time
            per call, node evals/s, algorithmic bytes against the HBM peak, and
            its error on sampled nodes against the oracle's direct sums.
@@ -37,11 +42,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "node evals/s at N=M=2^20, err<=1e-6 vs FP64 direct; fwd+bwd speedup vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3   # MI355X vector FP32, published
+# MI355X FP32 vector peak without packed FP32 instructions (the build turns
+# them off): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
 STAGES = ("onepass_fft", "passA_fft", "passB_fft", "gather", "direct")
 KERNEL_NAMES = {"onepass_fft": "k_onepass_fwd", "passA_fft": "k_passA_fwd", "passB_fft": "k_passB",
                 "gather": "k_gather", "direct": "k_direct_fwd"}
-DIRECT_NG = 8   # nodes per direct-sum workgroup (c is read once per group)
+ADJ_STAGES = ("clear_sum_g", "node_prep", "cell_spread", "passB_fft", "passA_fft", "onepass_fft", "direct",
+              "finalize")
+ADJ_KERNEL_NAMES = {"clear_sum_g": "k_sum_g", "node_prep": "k_adj_prep", "cell_spread": "k_adj_cells",
+                    "passB_fft": "k_passB", "passA_fft": "k_passA_adj", "onepass_fft": "k_onepass_adj",
+                    "direct": "k_direct_adj", "finalize": "k_finalize_adj"}
+DIRECT_NG = 8      # nodes per direct-sum workgroup (c is read once per group)
+DIRECT_ANG = 256   # nodes per direct-adjoint workgroup (each adds into every accumulator)
 
 
 def kernel_source_hash():
@@ -80,6 +93,54 @@ def stage_bytes(plan, S):
     return b
 
 
+def adjoint_stage_bytes(plan, S):
+    """Algorithmic HBM bytes per launch of each adjoint stage.  Clearing: the
+    FP64 accumulator (16 N) written, g read once for the k = 0 sum.  Node
+    side: per node of an NFFT band its record (x, y, index: 20 B) and g in,
+    its q weighted values, 2 mw window values and cell index out.  Cell
+    spread: those read once per node, the grid written (every cell of a
+    one-pass band, the cells some window touches of a two-pass band).  Pass B:
+    those cells read, the pass-A input written in full.  Pass A and the
+    one-pass bands: the band's grid read once, and one read-modify-write of
+    the FP64 accumulator (32 B) per coefficient of the band's support.  Direct
+    bands: the accumulator read and written once per group of DIRECT_ANG
+    nodes, plus the node records.  Finalize: the accumulator read, c_out
+    written."""
+    info = plan.info()
+    mw = info["mw"]
+    N, M = plan.N, plan.M
+    b = {k: 0.0 for k in ADJ_STAGES}
+    b["clear_sum_g"] = 16.0 * N + M * S
+    b["finalize"] = 16.0 * N + N * S
+    for band in plan.bands():
+        q, n, nodes, cells = band["q"], band["n"], band["nodes"], band["cells"]
+        kmax = min(band["K"], N - 1)
+        if band["direct"]:
+            b["direct"] += -(-nodes // DIRECT_ANG) * 32.0 * N + nodes * (20 + S)
+            continue
+        per_node = q * S + 2 * mw * S / 2 + 4
+        b["node_prep"] += nodes * (20 + S + per_node)
+        b["cell_spread"] += nodes * per_node + q * (n if band["passes"] == 1 else cells) * S
+        if band["passes"] == 1:
+            b["onepass_fft"] += q * n * S + 32.0 * kmax
+        else:
+            b["passB_fft"] += q * cells * S + q * n * S
+            b["passA_fft"] += q * n * S + 32.0 * kmax
+    return b
+
+
+def roofline_of(stage_ms, sb, names, bound_note=None):
+    """The dominant stage's algorithmic bytes over its duration, against HBM."""
+    dom = max(stage_ms, key=lambda k: stage_ms[k])
+    achieved = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
+    rec = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "kernel": names[dom], "bytes_per_launch": sb[dom],
+           "ms_per_launch": round(stage_ms[dom], 4)}
+    if bound_note:
+        rec["note"] = bound_note
+    return rec
+
+
 def time_steps(torch, fn, steps, warmup):
     for _ in range(warmup):
         fn()
@@ -114,6 +175,122 @@ def traffic_for(kernel, algorithmic_bytes):
     return v.get("bytes_per_launch")
 
 
+def copy_bandwidth(torch, dev, mib=2048, reps=5):
+    """A measured device-to-device copy rate (bytes read + written per second)."""
+    src = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    ms, _ = time_steps(torch, lambda: dst.copy_(src), reps, 2)
+    del src, dst
+    return round(2.0 * (mib << 20) / (ms * 1e-3) / 1e9, 1)
+
+
+def profile_stages(plan, fn_name, x, reps, names):
+    acc = [0.0] * len(names)
+    for _ in range(reps):
+        _, ms = getattr(plan, fn_name)(x)
+        acc = [a + b for a, b in zip(acc, ms)]
+    return {k: v / reps for k, v in zip(names, acc)}
+
+
+def step_leg(torch, dev, w, eps32, eps64, args, tune, log, label, profile):
+    """The training step (fused forward + derivative, then the adjoint) in the
+    FP32 form and on the plain FP64 path, on plans tuned for that step.
+    Returns the record and the outputs (host) for the error check."""
+    import numpy as np
+
+    from paper_1606_03255_amd import Plan, inputs
+    N, M = w["N"], w["M"]
+    c32 = torch.from_numpy(np.ascontiguousarray(w["c"], np.complex64)).to(dev)
+    g32 = torch.from_numpy(inputs.adjoint_input(M)).to(dev)
+    steps = max(3, args.steps // 2)
+    out = {}
+    rec = {"N": N, "M": M, "eps_fp32": eps32, "eps_fp64": eps64}
+    for form, eps, tdt in (("fp32", eps32, torch.complex64), ("fp64", eps64, torch.complex128)):
+        t = time.perf_counter()
+        p = Plan(N, w["z"], eps, tdt, device=dev, autotune=tune)     # tuned on forward + adjoint
+        rec["plan_ms_" + form] = round((time.perf_counter() - t) * 1e3, 1)
+        c = c32.to(tdt)
+        g = g32.to(tdt)
+        f = torch.empty(M, dtype=tdt, device=dev)
+        fp = torch.empty_like(f)
+        h = torch.empty(N, dtype=tdt, device=dev)
+
+        def step():
+            p.forward_derivative(c, out=f, out_prime=fp)
+            p.adjoint(g, out=h)
+        ms, _ = time_steps(torch, step, steps, 1)
+        rec["ms_" + form] = round(ms, 4)
+        rec["direct_scale_" + form] = p.info()["direct_scale"]
+        out[form] = {"f": f.cpu().numpy(), "fp": fp.cpu().numpy(), "h": h.cpu().numpy(),
+                     "bands": p.node_bands()}
+        if form == "fp32":
+            def step_sep():
+                p.forward(c, out=f)
+                p.adjoint(g, out=h)
+                p.derivative(c, out=fp)
+            rec["ms_separate_fp32"] = round(time_steps(torch, step_sep, steps, 1)[0], 4)
+        if profile:
+            reps = max(3, min(args.steps, 10))
+            sa = profile_stages(p, "profile_adjoint", g, reps, ADJ_STAGES)
+            rec["adjoint_stages_ms_" + form] = {k: round(v, 4) for k, v in sa.items()}
+            S = 8 if form == "fp32" else 16
+            sab = adjoint_stage_bytes(p, S)
+            rec["adjoint_stage_bytes_" + form] = sab
+            rec["roofline_adjoint_" + form] = roofline_of(sa, sab, ADJ_KERNEL_NAMES)
+            if form == "fp64":
+                rec["ms_fp64_forward"] = round(time_steps(torch, lambda: p.forward(c, out=f), steps, 1)[0], 4)
+                sf = profile_stages(p, "profile_forward", c, reps, STAGES)
+                rec["forward_stages_ms_fp64"] = {k: round(v, 4) for k, v in sf.items()}
+                rec["roofline_fp64_forward"] = roofline_of(sf, stage_bytes(p, 16), KERNEL_NAMES)
+        p.close()
+        del c, g, f, fp, h
+    rec["speedup"] = round(rec["ms_fp64"] / rec["ms_fp32"], 3)
+    log("%s fwd+bwd FP32 %.3f ms, FP64 %.3f ms, speedup %.2f" % (label, rec["ms_fp32"], rec["ms_fp64"],
+                                                                 rec["speedup"]))
+    return rec, out
+
+
+def _sample_with_sparse_bands(rng, M, bands, k):
+    import numpy as np
+    idx = set(rng.choice(M, size=min(k, M), replace=False).tolist())
+    for b in np.unique(bands):
+        sel = np.nonzero(bands == b)[0]
+        if len(sel) < 64:
+            idx.update(sel.tolist())
+    return np.array(sorted(idx))
+
+
+def step_errors(w, out, rec, seed):
+    """E of every output of a timed step against the oracle: f and f' on 2000
+    random nodes plus every node of bands holding < 64 nodes (relative to
+    sum |c_k| and sum |2 pi k c_k|), the adjoint on 66 blocks of 32
+    consecutive coefficients (the first, the last and 64 random ones;
+    relative to sum |g_j|)."""
+    import numpy as np
+
+    import oracle
+    from paper_1606_03255_amd import inputs
+    N, M = w["N"], w["M"]
+    c = np.asarray(w["c"], np.complex64).astype(np.complex128)
+    g = inputs.adjoint_input(M).astype(np.complex128)
+    rng = np.random.default_rng(seed)
+    sel = _sample_with_sparse_bands(rng, M, out["fp32"]["bands"], 2000)
+    zs = w["z"][sel]
+    fr = oracle.forward(c, zs)
+    fpr = oracle.derivative(c, zs)
+    B = oracle.direct.block_size()
+    nblk = -(-N // B)
+    blocks = np.unique(np.concatenate([[0, nblk - 1], rng.choice(nblk, size=64, replace=False)]))
+    k, hr = oracle.adjoint_blocks(g, w["z"], N, blocks)
+    n1, n1d, n1g = np.abs(c).sum(), np.abs(2 * np.pi * np.arange(N) * c).sum(), np.abs(g).sum()
+    for form in ("fp32", "fp64"):
+        o = out[form]
+        rec["E_f_" + form] = float(np.abs(o["f"][sel] - fr).max() / n1)
+        rec["E_fprime_" + form] = float(np.abs(o["fp"][sel] - fpr).max() / n1d)
+        rec["E_adjoint_" + form] = float(np.abs(o["h"][k] - hr).max() / n1g)
+    rec["error_sample"] = "%d nodes, %d coefficients" % (len(sel), len(k))
+
+
 def cpu_baseline(w, f32, f64, plan_bands, target_s=12.0):
     import numpy as np
 
@@ -132,6 +309,12 @@ def cpu_baseline(w, f32, f64, plan_bands, target_s=12.0):
     t = time.perf_counter()
     ref = oracle.forward(c, z[sel])
     dt = time.perf_counter() - t
+    # the independent cross-check algorithm (compensated Horner), timed on a
+    # smaller sample of the same nodes
+    hs = sel[:max(64, S // 16)]
+    t = time.perf_counter()
+    oracle.horner(c, z[hs])
+    dth = time.perf_counter() - t
     # error check: the timed sample plus every node of bands holding < 64 nodes
     extra = []
     for bnd in np.unique(plan_bands):
@@ -144,15 +327,20 @@ def cpu_baseline(w, f32, f64, plan_bands, target_s=12.0):
     allref = np.concatenate([ref, ref_x])
     n1 = np.abs(c).sum()
     E32 = float(np.abs(f32[allsel] - allref).max() / n1)
-    E64 = float(np.abs(f64[allsel] - allref).max() / n1)
+    E64 = float(np.abs(f64[allsel] - allref).max() / n1) if f64 is not None else None
+    omp = os.environ.get("OMP_NUM_THREADS")
     return {"value": S / dt, "unit": "node evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "host_cpu_count": os.cpu_count(), "omp_num_threads": int(omp) if omp and omp.isdigit() else None,
+            "horner_value": len(hs) / dth,
             "sample": "%d of the %d nodes drawn uniformly at random (seed 12345), all N=%d coefficients; "
-                      "FP64 direct sum, %.1f s" % (S, M, len(c), dt)}, E32, E64, int(len(allsel))
+                      "FP64 direct sum, %.1f s (compensated Horner: the first %d of them, %.1f s)"
+                      % (S, M, len(c), dt, len(hs), dth)}, E32, E64, int(len(allsel))
 
 
 def batched_leg(torch, dev, args, tune, log):
     """512 independent instances (N_i, M_i log-uniform in [2^8, 2^16], FP32 form,
-    eps 1e-6) in one batched plan: forward per step, eager and graph-replayed."""
+    eps 1e-6) in one batched plan: forward per step, eager and graph-replayed.
+    Returns the record and what the error check needs."""
     import numpy as np
 
     from paper_1606_03255_amd import Plan, inputs
@@ -166,16 +354,40 @@ def batched_leg(torch, dev, args, tune, log):
     f = torch.empty(pe.M, dtype=torch.complex64, device=dev)
     steps = max(5, args.steps)
     ms_e, _ = time_steps(torch, lambda: pe.forward(c, out=f), steps, args.warmup)
+    fe = f.cpu().numpy()
     ms_g, _ = time_steps(torch, lambda: pg.forward(c, out=f), steps, args.warmup)
+    fg = f.cpu().numpy()
     M = pe.M
     rec = {"instances": int(w["count"]), "sum_N": int(pe.N), "sum_M": int(M), "eps": 1e-6,
            "ms_forward_eager": round(ms_e, 4), "ms_forward_graph": round(ms_g, 4),
            "node_evals_per_s_graph": M / (ms_g * 1e-3), "plan_ms": round(plan_ms, 1),
-           "direct_scale": pe.info()["direct_scale"]}
+           "direct_scale": pe.info()["direct_scale"], "graph_equals_eager": bool(np.array_equal(fe, fg))}
     log("batched: %d instances, forward eager %.3f ms, graph %.3f ms" % (rec["instances"], ms_e, ms_g))
+    sample = {"w": w, "f": fg, "f_off": pe.f_offsets}
     pe.close()
     pg.close()
-    return rec
+    return rec, sample
+
+
+def batched_error(sample, rec):
+    """E of the graph-replayed batched forward: 48 random nodes of each of 64
+    random instances against the oracle, each relative to that instance's
+    sum |c_k|; the worst instance is reported."""
+    import numpy as np
+
+    import oracle
+    w, f, fo = sample["w"], sample["f"], sample["f_off"]
+    rng = np.random.default_rng(4321)
+    worst = 0.0
+    insts = rng.choice(w["count"], size=64, replace=False)
+    for i in insts:
+        ci, zi = w["instances"][i]
+        ci = ci.astype(np.complex128)
+        sel = np.sort(rng.choice(len(zi), size=min(48, len(zi)), replace=False))
+        E = np.abs(f[fo[i] + sel] - oracle.forward(ci, zi[sel])).max() / np.abs(ci).sum()
+        worst = max(worst, float(E))
+    rec["E"] = worst
+    rec["error_sample"] = "48 nodes of each of 64 random instances"
 
 
 def laplace_error(sample):
@@ -232,6 +444,7 @@ def main():
                     help="plans with the default band policy instead of the timed choice")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched leg")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-transform (Algorithm 1) leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd step at N = M = 2^18")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size reference "
                          "for HBM counter readings)")
@@ -257,6 +470,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = copy_bandwidth(torch, dev)
+    log("device-to-device copy %.1f GB/s" % copy_gbs)
     w = inputs.workload("large")
     N, M = w["N"], w["M"]
     t = time.perf_counter()
@@ -267,9 +482,6 @@ def main():
     plan32_ms = (time.perf_counter() - t) * 1e3
     log("FP32 plan built in %.0f ms" % plan32_ms)
     c32 = torch.from_numpy(w["c"]).to(dev)
-    rng = np.random.default_rng(7)
-    g = (rng.standard_normal(M) + 1j * rng.standard_normal(M)) * np.sqrt(0.5)
-    g32 = torch.from_numpy(g.astype(np.complex64)).to(dev)
     f32_out = torch.empty(M, dtype=torch.complex64, device=dev)
 
     ms_fwd, wall = time_steps(torch, lambda: p32.forward(c32, out=f32_out), args.steps, args.warmup)
@@ -279,11 +491,7 @@ def main():
 
     # per-kernel durations (HIP events between the launches on the current stream)
     reps = max(3, min(args.steps, 10))
-    acc = [0.0] * 5
-    for _ in range(reps):
-        _, ms = p32.profile_forward(c32)
-        acc = [a + b for a, b in zip(acc, ms)]
-    stage_ms = {k: v / reps for k, v in zip(STAGES, acc)}
+    stage_ms = profile_stages(p32, "profile_forward", c32, reps, STAGES)
     sb = stage_bytes(p32, 8)
     dom = max(STAGES, key=lambda k: stage_ms[k])
     if dom == "direct":
@@ -298,50 +506,25 @@ def main():
     else:
         achieved = sb[dom] / (stage_ms[dom] * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, sb[dom]), "kernel": KERNEL_NAMES[dom],
-                    "bytes_per_launch": sb[dom], "ms_per_launch": round(stage_ms[dom], 4)}
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic_for(dom, sb[dom]),
+                    "kernel": KERNEL_NAMES[dom], "bytes_per_launch": sb[dom], "ms_per_launch": round(stage_ms[dom], 4),
+                    "frac_of_measured_copy": round(achieved / copy_gbs, 4)}
     log("stages ms", {k: round(v, 4) for k, v in stage_ms.items()})
 
-    fwd_bwd = None
+    fwd_bwd = fwd_bwd_grad = None
+    step_out = grad_out = None
     f64 = None
     E64 = None
     if not args.forward_only:
-        fp32_out = torch.empty_like(f32_out)
-        ps = Plan(N, w["z"], 1e-6, torch.complex64, device=dev, autotune=tune)   # tuned on forward + adjoint
-        step_scale = ps.info()["direct_scale"]
+        fwd_bwd, step_out = step_leg(torch, dev, w, 1e-6, 1e-11, args, tune, log, "N=M=2^20", True)
+        f64 = step_out["fp64"]["f"].astype(np.complex128)
+        if not args.no_grad:
+            wg = inputs.workload("grad")
+            fwd_bwd_grad, grad_out = step_leg(torch, dev, wg, 1e-6, 1e-11, args, tune, log, "N=M=2^18", False)
 
-        def step32():
-            ps.forward_derivative(c32, out=f32_out, out_prime=fp32_out)
-            ps.adjoint(g32)
-        ms32, _ = time_steps(torch, step32, max(3, args.steps // 2), 1)
-
-        def step32_separate():
-            ps.forward(c32, out=f32_out)
-            ps.adjoint(g32)
-            ps.derivative(c32)
-        ms32_sep, _ = time_steps(torch, step32_separate, max(3, args.steps // 2), 1)
-        ps.close()
-        p64 = Plan(N, w["z"], 1e-11, torch.complex128, device=dev, autotune=tune)
-        c64 = c32.to(torch.complex128)
-        g64 = g32.to(torch.complex128)
-        f64_out = torch.empty(M, dtype=torch.complex128, device=dev)
-        fp64_out = torch.empty_like(f64_out)
-
-        def step64():
-            p64.forward_derivative(c64, out=f64_out, out_prime=fp64_out)
-            p64.adjoint(g64)
-        ms64, _ = time_steps(torch, step64, max(3, args.steps // 2), 1)
-        ms64_fwd, _ = time_steps(torch, lambda: p64.forward(c64, out=f64_out), max(3, args.steps // 2), 1)
-        f64 = f64_out.cpu().numpy()
-        p64.close()
-        fwd_bwd = {"ms_fp32_form": round(ms32, 4), "ms_fp64_path": round(ms64, 4),
-                   "speedup": round(ms64 / ms32, 3), "ms_fp64_forward": round(ms64_fwd, 4),
-                   "ms_separate_fp32": round(ms32_sep, 4), "direct_scale_fp32": step_scale}
-        log("fwd+bwd FP32 %.3f ms, FP64 %.3f ms, speedup %.2f" % (ms32, ms64, ms64 / ms32))
-
-    batched = None
+    batched = bsample = None
     if not args.no_batched:
-        batched = batched_leg(torch, dev, args, tune, log)
+        batched, bsample = batched_leg(torch, dev, args, tune, log)
     laplace = lap_sample = None
     if not args.no_laplace and not args.forward_only:
         laplace, lap_sample = laplace_leg(torch, dev, args, log)
@@ -350,9 +533,14 @@ def main():
     E32 = None
     n_checked = 0
     if not args.no_cpu_baseline:
-        cpu, E32, E64c, n_checked = cpu_baseline(w, f32, f64 if f64 is not None else f32, p32.node_bands())
-        E64 = E64c if f64 is not None else None
+        cpu, E32, E64, n_checked = cpu_baseline(w, f32, f64, p32.node_bands())
         log("cpu baseline", cpu, "E32", E32, "E64", E64)
+        if fwd_bwd is not None:
+            step_errors(w, step_out, fwd_bwd, 11)
+        if fwd_bwd_grad is not None:
+            step_errors(inputs.workload("grad"), grad_out, fwd_bwd_grad, 12)
+        if batched is not None:
+            batched_error(bsample, batched)
         if laplace is not None:
             laplace["E"] = laplace_error(lap_sample)
             log("laplace E", laplace["E"])
@@ -369,8 +557,10 @@ def main():
         "cpu_baseline": cpu,
         "error": {"E_fp32_form": E32, "E_fp64_path": E64, "nodes_checked": n_checked},
         "fwd_bwd": fwd_bwd,
+        "fwd_bwd_grad": fwd_bwd_grad,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_bytes": sb,
+        "hbm_copy_GBs": copy_gbs,
         "plan_ms": round(plan32_ms, 1),
         "direct_scale": info["direct_scale"],
         "batched": batched,

@@ -174,6 +174,14 @@ int flt_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream);
  * bands) in milliseconds.  Same arguments and results as flt_forward. */
 int flt_profile_forward(flt_plan* plan, const void* c, void* f, void* stream, double* stage_ms);
 
+/* Measurement: one adjoint, as flt_profile_forward; stage_ms (host, 8 doubles)
+ * receives the durations of (clearing the FP64 accumulator and the k = 0 sum
+ * of g, node-side weights and window values, cell spread onto the grids,
+ * pass B, pass A with the transposed contraction, one-pass bands, direct-sum
+ * bands, rounding the accumulator to c_out) in milliseconds.  Same arguments
+ * and results as flt_adjoint. */
+int flt_profile_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream, double* stage_ms);
+
 /* ------------------------------------------------------------------------
  * The discrete Laplace transform (Sect. 3, Algorithm 1):
  *

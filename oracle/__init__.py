@@ -8,7 +8,8 @@ Contents
 --------
 ``direct``   plain FP64 definition of the sums (C + OpenMP, ``direct.c``):
              forward f_j = sum_k c_k w_j^k (eq. 4.1 with xi_k = k),
-             adjoint h_k = sum_j g_j conj(w_j)^k (the C^* of Sect. 4),
+             adjoint h_k = sum_j g_j conj(w_j)^k (the C^* of Sect. 4), also on
+             chosen blocks of consecutive k only,
              derivative f'_j = sum_k 2 pi i k c_k w_j^k,
              and a compensated-Horner cross-check.
 ``brute``    independent brute force: every power w^k formed on its own in
@@ -20,4 +21,4 @@ Contents
              the Fourier "black box" either exact (dense NDFT) or a
              Kaiser-Bessel NFFT.
 """
-from .direct import forward, adjoint, derivative, horner, num_threads, load  # noqa: F401
+from .direct import forward, adjoint, adjoint_blocks, derivative, horner, num_threads, load  # noqa: F401

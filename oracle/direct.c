@@ -119,6 +119,41 @@ void oracle_derivative(int64_t N, int64_t M, const double* c, const double* z, d
     free(cd);
 }
 
+/* h[k], k0 <= k < kend (kend - k0 <= BLK), of the O1 adjoint: one anchor
+ * conj(w_j)^k0 per node, the recurrence inside the block, Neumaier sums over j. */
+static void adjoint_block(int64_t k0, int64_t kend, int64_t M, const double* g, const double* z, double* hout)
+{
+    double sr[BLK], cr[BLK], si[BLK], ci[BLK];
+    for (int i = 0; i < BLK; ++i) sr[i] = cr[i] = si[i] = ci[i] = 0;
+    for (int64_t j = 0; j < M; ++j) {
+        node_t nd = polar(z + 2 * j);
+        double gr = g[2 * j], gi = g[2 * j + 1];
+        if (nd.inf) { /* conj(w)^k = [k == 0] */
+            if (k0 == 0) { neumaier(&sr[0], &cr[0], gr); neumaier(&si[0], &ci[0], gi); }
+            continue;
+        }
+        double mag = exp(-(double)k0 * nd.y);
+        if (mag == 0.0) continue;
+        double mag1 = exp(-nd.y);
+        double wr = mag1 * cos(TWO_PI * nd.x), wi = -mag1 * sin(TWO_PI * nd.x);
+        double ph = -TWO_PI * frac_kx((double)k0, nd.x);
+        double pr = mag * cos(ph), pi = mag * sin(ph);
+        for (int64_t k = k0; k < kend; ++k) {
+            int i = (int)(k - k0);
+            neumaier(&sr[i], &cr[i], gr * pr - gi * pi);
+            neumaier(&si[i], &ci[i], gr * pi + gi * pr);
+            double tr = pr * wr - pi * wi;
+            pi = pr * wi + pi * wr;
+            pr = tr;
+        }
+    }
+    for (int64_t k = k0; k < kend; ++k) {
+        int i = (int)(k - k0);
+        hout[2 * i] = sr[i] + cr[i];
+        hout[2 * i + 1] = si[i] + ci[i];
+    }
+}
+
 /* O1 adjoint: h[k] = sum_{j<M} g_j conj(w_j)^k, k < N. */
 void oracle_adjoint(int64_t N, int64_t M, const double* g, const double* z, double* h)
 {
@@ -127,37 +162,28 @@ void oracle_adjoint(int64_t N, int64_t M, const double* g, const double* z, doub
     for (int64_t b = 0; b < nblk; ++b) {
         int64_t k0 = b * BLK;
         int64_t kend = k0 + BLK < N ? k0 + BLK : N;
-        double sr[BLK], cr[BLK], si[BLK], ci[BLK];
-        for (int i = 0; i < BLK; ++i) sr[i] = cr[i] = si[i] = ci[i] = 0;
-        for (int64_t j = 0; j < M; ++j) {
-            node_t nd = polar(z + 2 * j);
-            double gr = g[2 * j], gi = g[2 * j + 1];
-            if (nd.inf) { /* conj(w)^k = [k == 0] */
-                if (k0 == 0) { neumaier(&sr[0], &cr[0], gr); neumaier(&si[0], &ci[0], gi); }
-                continue;
-            }
-            double mag = exp(-(double)k0 * nd.y);
-            if (mag == 0.0) continue;
-            double mag1 = exp(-nd.y);
-            double wr = mag1 * cos(TWO_PI * nd.x), wi = -mag1 * sin(TWO_PI * nd.x);
-            double ph = -TWO_PI * frac_kx((double)k0, nd.x);
-            double pr = mag * cos(ph), pi = mag * sin(ph);
-            for (int64_t k = k0; k < kend; ++k) {
-                int i = (int)(k - k0);
-                neumaier(&sr[i], &cr[i], gr * pr - gi * pi);
-                neumaier(&si[i], &ci[i], gr * pi + gi * pr);
-                double tr = pr * wr - pi * wi;
-                pi = pr * wi + pi * wr;
-                pr = tr;
-            }
-        }
-        for (int64_t k = k0; k < kend; ++k) {
-            int i = (int)(k - k0);
-            h[2 * k] = sr[i] + cr[i];
-            h[2 * k + 1] = si[i] + ci[i];
-        }
+        adjoint_block(k0, kend, M, g, z, h + 2 * k0);
     }
 }
+
+/* The O1 adjoint on chosen blocks of BLK consecutive coefficients only (for
+ * sizes where all N of them would take too long): block i covers
+ * k = BLK*blocks[i] .. BLK*blocks[i] + BLK - 1; h receives BLK values per
+ * block (h[BLK*i + t] for k = BLK*blocks[i] + t), entries with k >= N zero. */
+void oracle_adjoint_blocks(int64_t N, int64_t M, const double* g, const double* z, int64_t nb,
+                           const int64_t* blocks, double* h)
+{
+    memset(h, 0, sizeof(double) * 2 * BLK * (size_t)(nb > 0 ? nb : 0));
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < nb; ++i) {
+        int64_t k0 = blocks[i] * BLK;
+        if (k0 < 0 || k0 >= N) continue;
+        int64_t kend = k0 + BLK < N ? k0 + BLK : N;
+        adjoint_block(k0, kend, M, g, z, h + 2 * BLK * i);
+    }
+}
+
+int oracle_block_size(void) { return BLK; }
 
 /* ---- cross-check: complex compensated Horner on the rounded w_j ---- */
 static void two_sum(double a, double b, double* s, double* e)

@@ -42,6 +42,9 @@ def load():
             fn = getattr(lib, name)
             fn.argtypes = [i64, i64, dp, dp, dp]
             fn.restype = None
+        lib.oracle_adjoint_blocks.argtypes = [i64, i64, dp, dp, i64, ctypes.POINTER(ctypes.c_int64), dp]
+        lib.oracle_adjoint_blocks.restype = None
+        lib.oracle_block_size.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -87,6 +90,29 @@ def adjoint(g, z, N):
     h = np.empty(int(N), np.complex128)
     load().oracle_adjoint(int(N), z.shape[0], _ptr(g), _ptr(z), _ptr(h))
     return h
+
+
+def adjoint_blocks(g, z, N, blocks):
+    """The adjoint h_k = sum_j g_j conj(exp(2 pi i k z_j)) on whole blocks of
+    consecutive k only (block b: k = B b .. B b + B - 1, B = block_size(),
+    k < N), for sizes where all N coefficients would take too long.  Returns
+    (k, h_k) as two arrays, blocks in the order given."""
+    g = _c128(g)
+    z = _check_z(z)
+    blocks = np.ascontiguousarray(np.asarray(blocks, dtype=np.int64).reshape(-1))
+    B = block_size()
+    if np.any(blocks < 0) or np.any(blocks * B >= int(N)):
+        raise ValueError("block outside 0 .. ceil(N / %d) - 1" % B)
+    h = np.empty(len(blocks) * B, np.complex128)
+    load().oracle_adjoint_blocks(int(N), z.shape[0], _ptr(g), _ptr(z), len(blocks),
+                                 blocks.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(h))
+    k = (blocks[:, None] * B + np.arange(B)[None, :]).reshape(-1)
+    keep = k < int(N)
+    return k[keep], h[keep]
+
+
+def block_size():
+    return int(load().oracle_block_size())
 
 
 def horner(c, z):

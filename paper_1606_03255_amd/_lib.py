@@ -26,7 +26,7 @@ ERRORS = {
 EXPORTS = (
     "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
-    "flt_forward_derivative", "flt_profile_forward", "flt_strerror", "flt_last_hip_error",
+    "flt_forward_derivative", "flt_profile_forward", "flt_profile_adjoint", "flt_strerror", "flt_last_hip_error",
     "flt_laplace_plan_create", "flt_laplace_plan_info", "flt_laplace_forward", "flt_laplace_plan_destroy",
 )
 
@@ -102,6 +102,7 @@ def load():
     lib.flt_laplace_plan_destroy.argtypes = [vp]
     lib.flt_laplace_plan_destroy.restype = None
     lib.flt_profile_forward.argtypes = [vp, vp, vp, vp, P(ctypes.c_double)]
+    lib.flt_profile_adjoint.argtypes = [vp, vp, vp, vp, P(ctypes.c_double)]
     lib.flt_strerror.argtypes = [ctypes.c_int]
     lib.flt_strerror.restype = ctypes.c_char_p
     lib.flt_last_hip_error.argtypes = []

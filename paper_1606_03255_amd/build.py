@@ -3,6 +3,7 @@ the same kernel bodies, ``libflt_emu.so``) in-tree.
 
     python -m paper_1606_03255_amd.build            # library
     python -m paper_1606_03255_amd.build --emu      # library + CPU test build
+    python -m paper_1606_03255_amd.build --emu-asan # library + CPU test build under ASan/UBSan
 """
 import os
 import subprocess
@@ -14,6 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libflt.so")
 EMU = os.path.join(HERE, "libflt_emu.so")
+EMU_ASAN = os.path.join(HERE, "libflt_emu_asan.so")
 ARCH = os.environ.get("FLT_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = [
@@ -51,16 +53,24 @@ def build_lib(jobs=3):
     return LIB
 
 
-def build_emu():
-    tmp = EMU + ".tmp%d" % os.getpid()
-    _run(["g++", "-O2", "-g", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-I" + INC, "-I" + CSRC,
+def build_emu(sanitize=False):
+    """The CPU build of the kernel bodies (host compiler only).  sanitize=True
+    builds it with AddressSanitizer and UndefinedBehaviorSanitizer into
+    libflt_emu_asan.so; a process loading it needs libasan preloaded (see
+    tests/test_cpu_build.py)."""
+    out = EMU_ASAN if sanitize else EMU
+    tmp = out + ".tmp%d" % os.getpid()
+    extra = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-O1"] if sanitize else ["-O2"]
+    _run(["g++", "-g", "-std=c++17", "-fopenmp", "-fPIC", "-shared"] + extra + ["-I" + INC, "-I" + CSRC,
           os.path.join(CSRC, "emu.cpp"), os.path.join(CSRC, "plan_host.cpp"), os.path.join(CSRC, "laplace_plan.cpp"),
           "-o", tmp])
-    os.replace(tmp, EMU)
-    return EMU
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
     build_lib()
     if "--emu" in sys.argv:
         build_emu()
+    if "--emu-asan" in sys.argv:
+        build_emu(sanitize=True)

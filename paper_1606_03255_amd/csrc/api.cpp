@@ -559,29 +559,47 @@ int flt_forward_derivative(flt_plan* p, const void* c, void* f, void* fp, void* 
     return run(p, 3, c, f, stream, fp);
 }
 
-int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, double* stage_ms)
+// One measured call: ne HIP events recorded between the stages of the
+// operation's launch sequence on the caller's stream, waited for, and the
+// ne - 1 stage durations written to stage_ms.
+static int profile(flt_plan* p, int op, const void* in, void* out, void* stream, double* stage_ms, int ne)
 {
-    int rc = check_call(p, c, f);
+    int rc = check_call(p, in, out);
     if (rc != FLT_OK) return rc;
     if (!stage_ms) return FLT_EINVAL;
     const HostPlan& hp = p->hp;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[9] = {};
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 6 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    for (int i = 0; i < ne && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
     const WsLayout W = layout(p);
-    if (e == hipSuccess)
-        e = hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, c, f, nullptr, 0, (hipStream_t)stream, ev)
-                                : launch_forward<double>(p->lists, p->pv64, W, c, f, nullptr, 0, (hipStream_t)stream,
-                                                         ev);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
-    for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+    const hipStream_t st = (hipStream_t)stream;
+    if (e == hipSuccess) {
+        if (op == 2)
+            e = hp.dtype == FLT_C64 ? launch_adjoint<float>(p->lists, p->pv32, W, in, out, st, ev)
+                                    : launch_adjoint<double>(p->lists, p->pv64, W, in, out, st, ev);
+        else
+            e = hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, in, out, nullptr, 0, st, ev)
+                                    : launch_forward<double>(p->lists, p->pv64, W, in, out, nullptr, 0, st, ev);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[ne - 1]);
+    for (int i = 0; i + 1 < ne && e == hipSuccess; ++i) {
         float ms = 0;
         e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
         stage_ms[i] = ms;
     }
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < ne; ++i)
         if (ev[i]) (void)hipEventDestroy(ev[i]);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+
+int flt_profile_forward(flt_plan* p, const void* c, void* f, void* stream, double* stage_ms)
+{
+    return profile(p, 0, c, f, stream, stage_ms, 6);
+}
+
+int flt_profile_adjoint(flt_plan* p, const void* g, void* c_out, void* stream, double* stage_ms)
+{
+    return profile(p, 2, g, c_out, stream, stage_ms, 9);
 }
 
 const char* flt_strerror(int code)

@@ -21,6 +21,16 @@ struct DevCtx {
     __device__ __forceinline__ void atomic_add(float* p, float v) const { unsafeAtomicAdd(p, v); }
 };
 
+// Static LDS of the kernels, against gfx950's 160 KB per workgroup (the
+// compiler rejects more) and the 80 KB that lets two 512-thread workgroups
+// share a compute unit, which the FFT kernels are laid out for.
+constexpr size_t LDS_LIMIT = 160 * 1024, LDS_TWO_PER_CU = 80 * 1024;
+template <typename T> constexpr size_t lds_fft_bytes() { return sizeof(cplx<T>) * tile_alloc<T>(); }
+template <typename T> constexpr size_t lds_passA_bytes() { return lds_fft_bytes<T>() + sizeof(T) * Sizes<T>::COEF; }
+static_assert(lds_passA_bytes<float>() <= LDS_TWO_PER_CU && lds_passA_bytes<double>() <= LDS_TWO_PER_CU,
+              "an FFT tile and the staged coefficients must leave room for a second workgroup per CU");
+static_assert(lds_passA_bytes<double>() <= LDS_LIMIT, "LDS per workgroup");
+
 // One launch per FFT kind; each workgroup picks the compile-time instance of
 // its band's transform length.
 template <typename T>
@@ -177,9 +187,15 @@ static int grid_for(int64_t work, int per_block)
     return (int)g;
 }
 
+// A HIP event on the stream between stages (measurement calls only).
+static void mark(LaunchStatus& ls, hipEvent_t* ev, int i, hipStream_t st)
+{
+    if (ev) ls.note(hipEventRecord(ev[i], st));
+}
+
 template <typename T>
-static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const cplx<T>* c,
-                                     int deriv, int cols, hipStream_t st, hipEvent_t* ev)
+static void fft_forward_stages(LaunchStatus& ls, const DevLists& L, const PlanView<T>& pv, const WsLayout& W,
+                               const cplx<T>* c, int deriv, int cols, hipStream_t st, hipEvent_t* ev)
 {
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
@@ -189,31 +205,39 @@ static hipError_t fft_forward_stages(const DevLists& L, const PlanView<T>& pv, c
     const int n_one = cols == 2 ? L.n_onepass_fused : L.n_onepass_fwd;
     const FftItem* pb = cols == 2 ? L.passB_fused : L.passB;
     const int n_pb = cols == 2 ? L.n_passB_fused : L.n_passB;
-    if (ev) (void)hipEventRecord(ev[0], st);
-    if (n_one)
+    mark(ls, ev, 0, st);
+    if (n_one) {
         hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(n_one), dim3(FFT_THREADS), 0, st, pv, one, c, grids, deriv, cols);
-    if (ev) (void)hipEventRecord(ev[1], st);
-    if (L.n_passA_fwd)
+        ls.launched();
+    }
+    mark(ls, ev, 1, st);
+    if (L.n_passA_fwd) {
         hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
                            scratch, basebuf, deriv, cols);
-    if (ev) (void)hipEventRecord(ev[2], st);
-    if (n_pb)
+        ls.launched();
+    }
+    mark(ls, ev, 2, st);
+    if (n_pb) {
         hipLaunchKernelGGL((k_passB<T, +1>),
                            dim3(passB_prefetch<T, +1>() ? std::min(n_pb, L.persist_blocks) : n_pb),
                            dim3(FFT_THREADS), 0, st, pv, pb, n_pb, (const cplx<T>*)scratch, grids, cols);
-    if (ev) (void)hipEventRecord(ev[3], st);
-    return hipSuccess;
+        ls.launched();
+    }
+    mark(ls, ev, 3, st);
 }
 
 template <typename T>
-static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, cplx<T>* grids, cplx<T>* scratch,
-                                     double* acc, hipStream_t st)
+static void fft_adjoint_stages(LaunchStatus& ls, const DevLists& L, const PlanView<T>& pv, cplx<T>* grids,
+                               cplx<T>* scratch, double* acc, hipStream_t st, hipEvent_t* ev)
 {
-    if (L.n_passB)
+    if (L.n_passB) {
         hipLaunchKernelGGL((k_passB<T, -1>),
                            dim3(passB_prefetch<T, -1>() ? std::min(L.n_passB, L.persist_blocks) : L.n_passB),
                            dim3(FFT_THREADS), 0, st,
                            pv, L.passB, L.n_passB, (const cplx<T>*)grids, scratch, 1);
+        ls.launched();
+    }
+    mark(ls, ev, 4, st);
     if (L.n_passA_adj) {
         if constexpr (std::is_same<T, float>::value)
             hipLaunchKernelGGL(k_passA_adj_f32, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
@@ -221,100 +245,123 @@ static hipError_t fft_adjoint_stages(const DevLists& L, const PlanView<T>& pv, c
         else
             hipLaunchKernelGGL(k_passA_adj_f64, dim3(L.n_passA_adj), dim3(FFT_THREADS), 0, st, pv, L.passA_adj,
                                (const cplx<T>*)scratch, acc);
+        ls.launched();
     }
-    if (L.n_onepass_adj)
+    mark(ls, ev, 5, st);
+    if (L.n_onepass_adj) {
         hipLaunchKernelGGL(k_onepass_adj<T>, dim3(L.n_onepass_adj), dim3(FFT_THREADS), 0, st, pv, L.onepass_adj,
                            (const cplx<T>*)grids, acc);
-    return hipSuccess;
+        ls.launched();
+    }
+    mark(ls, ev, 6, st);
 }
 
 template <typename T, int MW>
-static void mw_forward_nodes(const DevLists& L, const PlanView<T>& pv, const cplx<T>* c, const cplx<T>* grids,
-                             cplx<T>* f, int with_c0, cplx<T>* f2, hipStream_t st)
+static void mw_forward_nodes(LaunchStatus& ls, const DevLists& L, const PlanView<T>& pv, const cplx<T>* c,
+                             const cplx<T>* grids, cplx<T>* f, int with_c0, cplx<T>* f2, hipStream_t st)
 {
     hipLaunchKernelGGL((k_gather<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, c, grids, f,
                        with_c0, f2);
+    ls.launched();
 }
 
 template <typename T, int MW>
-static void mw_adjoint_nodes(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const cplx<T>* g,
-                             cplx<T>* grids, hipStream_t st)
+static void mw_adjoint_nodes(LaunchStatus& ls, const DevLists& L, const PlanView<T>& pv, const WsLayout& W,
+                             const cplx<T>* g, cplx<T>* grids, hipStream_t st, hipEvent_t* ev)
 {
     cplx<T>* U = (cplx<T>*)(W.ws + W.off_U);
     T* Phi = (T*)(W.ws + W.off_phi);
     int32_t* L0 = (int32_t*)(W.ws + W.off_l0);
-    if (L.n_nfft_nodes)
+    if (L.n_nfft_nodes) {
         hipLaunchKernelGGL((k_adj_prep<T, MW>), dim3(L.n_nfft_nodes), dim3(GATHER_THREADS), 0, st, pv,
                            L.nfft_nodes, g, W.qs, U, Phi, L0);
-    if (L.n_cells)
+        ls.launched();
+    }
+    mark(ls, ev, 2, st);
+    if (L.n_cells) {
         hipLaunchKernelGGL((k_adj_cells<T, MW>), dim3(L.n_cells), dim3(GATHER_THREADS), 0, st, pv, L.cells, W.qs,
                            (const cplx<T>*)U, (const T*)Phi, (const int32_t*)L0, L.cstart, L.clist, grids);
+        ls.launched();
+    }
+    mark(ls, ev, 3, st);
 }
 
 template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* cv, void* fv,
                           void* f2v, int deriv, hipStream_t st, hipEvent_t* ev)
 {
+    LaunchStatus ls;
     const cplx<T>* c = (const cplx<T>*)cv;
     cplx<T>* f = (cplx<T>*)fv;
     cplx<T>* f2 = (cplx<T>*)f2v;   // non-null: the derivative too, in the same pass (2q columns per band)
     const int cols = f2 ? 2 : 1;
     if (f2) deriv = 0;
+    if (pv.mw < 2 || pv.mw > MAX_MW) return hipErrorInvalidValue;
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     double* dacc = (double*)(W.ws + W.off_dacc);
-    hipError_t e = fft_forward_stages<T>(L, pv, W, c, deriv, cols, st, ev);
-    if (e != hipSuccess) return e;
+    fft_forward_stages<T>(ls, L, pv, W, c, deriv, cols, st, ev);
     if (L.n_nodes) {
         switch (pv.mw) {
-#define G(MWV) case MWV: mw_forward_nodes<T, MWV>(L, pv, c, grids, f, !deriv, f2, st); break;
+#define G(MWV) case MWV: mw_forward_nodes<T, MWV>(ls, L, pv, c, grids, f, !deriv, f2, st); break;
             G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)
 #undef G
-            default: return hipErrorInvalidValue;
         }
     }
-    if (ev) (void)hipEventRecord(ev[4], st);
+    mark(ls, ev, 4, st);
     if (L.n_dlist) {
         const int gb = (int)((L.n_dlist + 255) / 256);
         for (int d = 0; d < cols; ++d) {   // direct bands: exact sums, of c and (cols = 2) of c'
             cplx<T>* out = d ? f2 : f;
             hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 0);
+            ls.launched();
             if (deriv || d)
                 hipLaunchKernelGGL((k_direct_fwd<T, true>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd,
                                    L.dlist, c, dacc);
             else
                 hipLaunchKernelGGL((k_direct_fwd<T, false>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv,
                                    L.direct_fwd, L.dlist, c, dacc);
+            ls.launched();
             hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 1);
+            ls.launched();
         }
     }
-    if (ev) (void)hipEventRecord(ev[5], st);
-    return hipGetLastError();
+    mark(ls, ev, 5, st);
+    return ls.first;
 }
 
 template <typename T>
 hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* gv, void* outv,
-                          hipStream_t st)
+                          hipStream_t st, hipEvent_t* ev)
 {
+    LaunchStatus ls;
     const cplx<T>* g = (const cplx<T>*)gv;
     cplx<T>* out = (cplx<T>*)outv;
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
     double* acc = (double*)(W.ws + W.off_acc);
+    if (pv.mw < 2 || pv.mw > MAX_MW) return hipErrorInvalidValue;
+    mark(ls, ev, 0, st);
     hipLaunchKernelGGL(k_zero16, dim3(grid_for(W.N, 256 * 8)), dim3(256), 0, st, (double2*)acc, W.N);
+    ls.launched();
     hipLaunchKernelGGL(k_sum_g<T>, dim3(L.n_sum), dim3(256), 0, st, pv, L.sum_items, g, acc);
+    ls.launched();
+    mark(ls, ev, 1, st);
     switch (pv.mw) {
-#define S(MWV) case MWV: mw_adjoint_nodes<T, MWV>(L, pv, W, g, grids, st); break;
+#define S(MWV) case MWV: mw_adjoint_nodes<T, MWV>(ls, L, pv, W, g, grids, st, ev); break;
         S(2) S(3) S(4) S(5) S(6) S(7) S(8) S(9) S(10)
 #undef S
-        default: return hipErrorInvalidValue;
     }
-    hipError_t e = fft_adjoint_stages<T>(L, pv, grids, scratch, acc, st);
-    if (e != hipSuccess) return e;
-    if (L.n_direct_adj)
+    fft_adjoint_stages<T>(ls, L, pv, grids, scratch, acc, st, ev);
+    if (L.n_direct_adj) {
         hipLaunchKernelGGL(k_direct_adj<T>, dim3(L.n_direct_adj), dim3(256), 0, st, pv, L.direct_adj, L.dlist, g,
                            acc);
+        ls.launched();
+    }
+    mark(ls, ev, 7, st);
     hipLaunchKernelGGL(k_finalize_adj<T>, dim3(grid_for(W.N, 256 * 4)), dim3(256), 0, st, acc, out, W.N);
-    return hipGetLastError();
+    ls.launched();
+    mark(ls, ev, 8, st);
+    return ls.first;
 }
 
 template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,
@@ -322,8 +369,8 @@ template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>
 template hipError_t launch_forward<double>(const DevLists&, const PlanView<double>&, const WsLayout&, const void*,
                                            void*, void*, int, hipStream_t, hipEvent_t*);
 template hipError_t launch_adjoint<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,
-                                          void*, hipStream_t);
+                                          void*, hipStream_t, hipEvent_t*);
 template hipError_t launch_adjoint<double>(const DevLists&, const PlanView<double>&, const WsLayout&, const void*,
-                                           void*, hipStream_t);
+                                           void*, hipStream_t, hipEvent_t*);
 
 }  // namespace flt

@@ -9,6 +9,20 @@
 
 namespace flt {
 
+// The first failure of a launch sequence.  The sequence starts by clearing
+// any error an earlier, unrelated call left behind, and the error state is
+// read right after every launch, so a later successful launch can neither
+// hide a failed one nor can a stale error be reported as this call's.
+struct LaunchStatus {
+    hipError_t first = hipSuccess;
+    LaunchStatus() { (void)hipGetLastError(); }
+    void note(hipError_t e)
+    {
+        if (first == hipSuccess && e != hipSuccess) first = e;
+    }
+    void launched() { note(hipGetLastError()); }
+};
+
 // Device copies of a plan's work lists and index tables.
 struct DevLists {
     const FftItem* onepass_fwd = nullptr;
@@ -46,6 +60,9 @@ struct WsLayout {
     int64_t N = 0, M = 0, grid_elems = 0;
 };
 
+// Every launch sequence returns the first error among its launches (and
+// event records), or hipSuccess.
+//
 // a2-a6 (forward, or derivative when deriv != 0): c -> f on stream st; with
 // f2 not null, the forward into f and the derivative into f2 in one pass (2q
 // columns per band).  If ev is not null, ev[0..5] are recorded on st before
@@ -60,9 +77,12 @@ template <typename T>
 hipError_t launch_laplace(const LapView& V, const LapItem* items, int nitems, int64_t M, const void* fhat, void* f,
                           hipStream_t st);
 
-// a7 (adjoint): g -> c_out on stream st.
+// a7 (adjoint): g -> c_out on stream st.  If ev is not null, ev[0..8] are
+// recorded before the first launch and after each stage (clearing and the
+// sum of g, node-side weights, cell spread, pass B, pass A, one-pass bands,
+// direct bands, conversion of the FP64 accumulator).
 template <typename T>
 hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* g, void* c_out,
-                          hipStream_t st);
+                          hipStream_t st, hipEvent_t* ev = nullptr);
 
 }  // namespace flt

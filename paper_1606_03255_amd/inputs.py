@@ -87,6 +87,14 @@ def workload(name, seed=None):
     raise KeyError(name)
 
 
+def adjoint_input(M, seed=7, dtype=np.complex64):
+    """Input g of the adjoint at M nodes (the gradient a backward pass would
+    receive): Re, Im ~ N(0, 1/2), i.e. g_j ~ CN(0, 1)."""
+    rng = np.random.default_rng(seed)
+    g = (rng.standard_normal(M) + 1j * rng.standard_normal(M)) * np.sqrt(0.5)
+    return g.astype(dtype)
+
+
 def batched(count=512, seed=4, lo=8, hi=16):
     """``count`` independent instances, sizes log-uniform in [2^lo, 2^hi]."""
     rng = np.random.default_rng(seed)

@@ -50,6 +50,26 @@ def _dtype_code(dtype):
     raise ValueError("dtype must be complex64 or complex128")
 
 
+def _check_tensor(t, n, name, dtype, device):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor on the plan's device" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s has dtype %s, the plan computes in %s" % (name, t.dtype, dtype))
+    if t.device != device:
+        raise ValueError("%s is on %s, the plan lives on %s" % (name, t.device, device))
+    if t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return t
+
+
+def _check_out(t, n, name, dtype, device):
+    _check_tensor(t, n, name, dtype, device)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous (the result is written through its data pointer)" % name)
+    return t
+
+
 class Plan:
     """Plan for N coefficients at the nodes z (Im z >= 0) with accuracy eps.
 
@@ -165,16 +185,14 @@ class Plan:
 
     # ------------------------------------------------------------- transforms
     def _prep(self, t, n, name):
-        import torch
-        if not isinstance(t, torch.Tensor):
-            raise TypeError("%s must be a torch tensor on the plan's device" % name)
-        if t.dtype != self.torch_dtype:
-            raise TypeError("%s has dtype %s, the plan computes in %s" % (name, t.dtype, self.torch_dtype))
-        if t.device != self.device:
-            raise ValueError("%s is on %s, the plan lives on %s" % (name, t.device, self.device))
-        if t.numel() != n:
-            raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
-        return t.contiguous()
+        """An input tensor checked against the plan (type, device, size); a
+        contiguous copy is made if needed."""
+        return _check_tensor(t, n, name, self.torch_dtype, self.device).contiguous()
+
+    def _prep_out(self, t, n, name):
+        """An output tensor: as an input, and contiguous itself (the kernels
+        write through its data pointer, so a copy would lose the result)."""
+        return _check_out(t, n, name, self.torch_dtype, self.device)
 
     def _run(self, fn, x, nin, nout, out, name):
         import torch
@@ -184,7 +202,7 @@ class Plan:
         if out is None:
             out = torch.empty(nout, dtype=self.torch_dtype, device=self.device)
         else:
-            out = self._prep(out, nout, "out")
+            out = self._prep_out(out, nout, "out")
         stream = torch.cuda.current_stream(self.device).cuda_stream
         L.check(fn(self._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                    ctypes.c_void_p(stream)), fn.__name__)
@@ -209,27 +227,43 @@ class Plan:
             raise RuntimeError("host-only plan")
         c = self._prep(c, self.N, "c")
         f = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out is None else \
-            self._prep(out, self.M, "out")
+            self._prep_out(out, self.M, "out")
         fp = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out_prime is None else \
-            self._prep(out_prime, self.M, "out_prime")
+            self._prep_out(out_prime, self.M, "out_prime")
+        if f.data_ptr() == fp.data_ptr():
+            raise ValueError("out and out_prime must be distinct tensors")
         stream = torch.cuda.current_stream(self.device).cuda_stream
         L.check(self._lib.flt_forward_derivative(self._ptr, ctypes.c_void_p(c.data_ptr()),
                                                  ctypes.c_void_p(f.data_ptr()), ctypes.c_void_p(fp.data_ptr()),
                                                  ctypes.c_void_p(stream)), "flt_forward_derivative")
         return f, fp
 
+    PROFILE_FORWARD_STAGES = ("onepass_fft", "passA_fft", "passB_fft", "gather", "direct")
+    PROFILE_ADJOINT_STAGES = ("clear_sum_g", "node_prep", "cell_spread", "passB_fft", "passA_fft", "onepass_fft",
+                              "direct", "finalize")
+
+    def _profile(self, fn, x, nin, nout, out, name, nst):
+        import torch
+        if self.host_only:
+            raise RuntimeError("host-only plan")
+        x = self._prep(x, nin, name)
+        out = torch.empty(nout, dtype=self.torch_dtype, device=self.device) if out is None else \
+            self._prep_out(out, nout, "out")
+        ms = (ctypes.c_double * nst)()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(fn(self._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                   ctypes.c_void_p(stream), ms), fn.__name__)
+        return out, list(ms)
+
     def profile_forward(self, c, out=None):
         """One forward with per-stage HIP-event timing; returns (f, stage_ms)
-        with stage_ms for (one-pass FFTs, pass A, pass B, gather, direct bands)."""
-        import torch
-        c = self._prep(c, self.N, "c")
-        out = torch.empty(self.M, dtype=self.torch_dtype, device=self.device) if out is None else out
-        ms = (ctypes.c_double * 5)()
-        stream = torch.cuda.current_stream(self.device).cuda_stream
-        L.check(self._lib.flt_profile_forward(self._ptr, ctypes.c_void_p(c.data_ptr()),
-                                              ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream), ms),
-                "flt_profile_forward")
-        return out, list(ms)
+        with stage_ms for PROFILE_FORWARD_STAGES."""
+        return self._profile(self._lib.flt_profile_forward, c, self.N, self.M, out, "c", 5)
+
+    def profile_adjoint(self, g, out=None):
+        """One adjoint with per-stage HIP-event timing; returns (c_out,
+        stage_ms) with stage_ms for PROFILE_ADJOINT_STAGES."""
+        return self._profile(self._lib.flt_profile_adjoint, g, self.M, self.N, out, "g", 8)
 
     def close(self):
         if getattr(self, "_ptr", None) and self._ptr.value:
@@ -346,12 +380,11 @@ class LaplacePlan:
         import torch
         if self.host_only:
             raise RuntimeError("host-only plan")
-        if not isinstance(fhat, torch.Tensor) or fhat.dtype != self.torch_dtype or fhat.device != self.device \
-                or fhat.numel() != self.N:
-            raise TypeError("fhat must be a %s tensor of %d elements on %s" % (self.torch_dtype, self.N, self.device))
-        fhat = fhat.contiguous()
+        fhat = _check_tensor(fhat, self.N, "fhat", self.torch_dtype, self.device).contiguous()
         if out is None:
             out = torch.empty(self.M, dtype=self.torch_dtype, device=self.device)
+        else:
+            out = _check_out(out, self.M, "out", self.torch_dtype, self.device)
         stream = torch.cuda.current_stream(self.device).cuda_stream
         L.check(self._lib.flt_laplace_forward(self._ptr, ctypes.c_void_p(fhat.data_ptr()),
                                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream)),

@@ -194,3 +194,27 @@ def test_autotune_flag_on_host_only_plans_keeps_the_default_policy():
     q = flt.Plan(3000, z, 1e-6, "complex64", host_only=True)
     assert p.info()["direct_scale"] == 1.0
     assert p.bands() == q.bands()
+
+
+def test_binding_checks_outputs():
+    """The binding rejects an output tensor that does not match the plan
+    (type, size, device) or is not contiguous, before anything reaches the
+    kernels (which write through the output's data pointer)."""
+    import torch
+
+    from paper_1606_03255_amd import plan as P
+    dev = torch.device("cpu")
+    ok = torch.zeros(6, dtype=torch.complex64)
+    assert P._check_out(ok, 6, "out", torch.complex64, dev) is ok
+    with pytest.raises(TypeError):
+        P._check_out(ok, 6, "out", torch.complex128, dev)
+    with pytest.raises(ValueError):
+        P._check_out(ok, 5, "out", torch.complex64, dev)
+    with pytest.raises(ValueError):
+        P._check_out(torch.zeros(12, dtype=torch.complex64)[::2], 6, "out", torch.complex64, dev)
+    with pytest.raises(ValueError):
+        P._check_out(ok, 6, "out", torch.complex64, torch.device("cuda", 0))
+    with pytest.raises(TypeError):
+        P._check_out(np.zeros(6, np.complex64), 6, "out", torch.complex64, dev)
+    # inputs may be strided (a contiguous copy is passed on)
+    assert P._check_tensor(torch.zeros(12, dtype=torch.complex64)[::2], 6, "c", torch.complex64, dev).numel() == 6

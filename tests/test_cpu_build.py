@@ -4,6 +4,8 @@ arithmetic, synchronisation and both band policies are checked here, before
 and apart from any GPU run.  Bars as in the GPU parity tests."""
 import ctypes
 import os
+import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -13,7 +15,9 @@ from oracle import method as O
 from paper_1606_03255_amd import inputs
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-EMU = os.path.join(os.path.dirname(HERE), "paper_1606_03255_amd", "libflt_emu.so")
+ROOT = os.path.dirname(HERE)
+# FLT_EMU_LIB selects another build of the bodies (the sanitizer run below)
+EMU = os.environ.get("FLT_EMU_LIB", os.path.join(ROOT, "paper_1606_03255_amd", "libflt_emu.so"))
 
 
 @pytest.fixture(scope="module")
@@ -121,3 +125,26 @@ def test_cpu_build_batched_equals_single_instances(emu):
                 else:
                     ref = oracle.adjoint(x[i], zs[i], int(Ns[i]))
                 assert np.abs(got - ref).max() <= eps * scale, (op, kind, i)
+
+
+@pytest.mark.skipif(os.environ.get("FLT_EMU_LIB") is not None, reason="already the sanitizer run")
+@pytest.mark.skipif(os.environ.get("FLT_ASAN") != "1",
+                    reason="about 4 minutes (2 of them the sanitizer build); run with FLT_ASAN=1")
+def test_cpu_build_under_address_sanitizer():
+    """A one-pass case (complex64, band policy on) and a two-pass case
+    (complex128, NFFT only) of the test above, forward, derivative, adjoint
+    and the fused call each, on the
+    bodies built with AddressSanitizer and UndefinedBehaviorSanitizer (every
+    buffer exactly sized): any out-of-bounds access or undefined operation
+    aborts the child run."""
+    from paper_1606_03255_amd import build
+    lib = build.build_emu(sanitize=True)
+    asan = subprocess.check_output(["g++", "-print-file-name=libasan.so"], text=True).strip()
+    env = dict(os.environ, FLT_EMU_LIB=lib, LD_PRELOAD=asan, OMP_WAIT_POLICY="passive",
+               ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(HERE, "test_cpu_build.py"), "-k", "0-300-120-1e-06-1 or 2-2100-60-1e-09-2"],
+                       cwd=ROOT, env=env, capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    assert "2 passed" in r.stdout, r.stdout[-2000:]

@@ -159,3 +159,23 @@ def test_planted_mistakes_are_caught():
     assert np.abs(oracle.forward(c, z.conjugate() * -1) - ref).max() > tol
     z_eq = np.arange(N) / N + 0j
     assert np.abs(oracle.forward(c, z_eq) - np.fft.fft(c)).max() > 1e-3
+
+
+def test_adjoint_blocks_equal_the_full_adjoint():
+    """The block entry point is the full adjoint (pinned above against mpmath
+    and the FFT) restricted to the chosen blocks: same values, the ragged
+    last block included, blocks in any order."""
+    rng = np.random.default_rng(31)
+    for N, M in ((1000, 300), (97, 40), (32, 5)):
+        z = np.concatenate([inputs.nodes_annulus(rng, M // 2), inputs.nodes_disk(rng, M - M // 2)])
+        z[0] = complex(0.3, np.inf)
+        g = _rand_c(rng, M)
+        full = oracle.adjoint(g, z, N)
+        B = oracle.direct.block_size()
+        nblk = -(-N // B)
+        blocks = np.unique(np.concatenate([[0, nblk - 1], rng.integers(0, nblk, 5)]))[::-1]
+        k, h = oracle.adjoint_blocks(g, z, N, blocks)
+        assert len(k) == len(set(k.tolist())) and k.max() == N - 1 and k.min() == 0
+        assert np.array_equal(h, full[k])
+    with pytest.raises(ValueError):
+        oracle.adjoint_blocks(g, z, N, [nblk])
