@@ -90,6 +90,7 @@ typedef struct flt_info {
     double bytes_forward;    /* algorithmic HBM bytes of one forward call */
     double flops_forward;    /* algorithmic flops of one forward call */
     double direct_scale;     /* factor on the direct-sum rate the band policy used (1, or the tuned choice) */
+    size_t forward_scratch_bytes; /* device scratch of one forward call alone (see flt_forward_noalloc) */
 } flt_info;
 
 /* One occupied band (Def. 3.2 Y_m, or Y_D). */
@@ -147,6 +148,27 @@ int flt_plan_set_workspace(flt_plan* plan, void* dev, size_t bytes);
  * c: device complex[N] of the plan's dtype; f: device complex[M], overwritten.
  * Error <= eps * sum|c_k| (Thm 4.3). */
 int flt_forward(flt_plan* plan, const void* c, void* f, void* stream);
+
+/* The most device scratch flt_forward_noalloc can use (128 MiB). */
+#define FLT_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+
+/* Forward without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and result as flt_forward, with their
+ * scratch (band grids, pass-A output, direct-sum accumulator, base slots) in
+ * one static device array of FLT_NOALLOC_MAX_BYTES that the library holds on
+ * each device it runs this call on, until the process ends.  The call
+ * allocates nothing and needs no registered workspace; its address is looked
+ * up once per device on the first call there.
+ * c: device complex[N], f: device complex[M] of the plan's dtype, as for
+ * flt_forward.  Errors: as flt_forward (no FLT_ENOWORKSPACE); FLT_ERANGE if
+ * the plan's forward needs more than FLT_NOALLOC_MAX_BYTES of scratch (its
+ * flt_info.forward_scratch_bytes), checked before any device work.  Every
+ * call on one device shares that device's array: calls that overlap in time
+ * on one device (two streams, two threads, or this and another plan) race
+ * and give wrong results; calls one after another on a stream are fine (the
+ * forward writes every scratch value it reads before reading it). */
+int flt_forward_noalloc(flt_plan* plan, const void* c, void* f, void* stream);
 
 /* Derivative: fp[j] ~ f'(z_j) = sum_{k<N} 2 pi i k c_k w_j^k, i.e. Alg. 2
  * applied to c'_k = 2 pi i k c_k; error <= eps * sum_k |2 pi k c_k|. */

@@ -16,6 +16,7 @@ FLT_FLAG_NFFT_ONLY = 2
 FLT_FLAG_GRAPH = 4
 FLT_FLAG_AUTOTUNE = 8
 FLT_FLAG_TUNE_FORWARD = 16
+FLT_NOALLOC_MAX_BYTES = 128 << 20
 
 ERRORS = {
     0: "FLT_OK", -1: "FLT_EINVAL", -2: "FLT_EDOMAIN", -3: "FLT_EPRECISION", -4: "FLT_ENOWORKSPACE",
@@ -26,7 +27,7 @@ ERRORS = {
 EXPORTS = (
     "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
-    "flt_forward_derivative", "flt_profile_forward", "flt_profile_adjoint", "flt_strerror", "flt_last_hip_error",
+    "flt_forward_derivative", "flt_forward_noalloc", "flt_profile_forward", "flt_profile_adjoint", "flt_strerror", "flt_last_hip_error",
     "flt_laplace_plan_create", "flt_laplace_plan_info", "flt_laplace_forward", "flt_laplace_plan_destroy",
 )
 
@@ -39,6 +40,7 @@ class FltInfo(ctypes.Structure):
         ("eps", ctypes.c_double), ("eps_K", ctypes.c_double), ("eps_A", ctypes.c_double),
         ("y1", ctypes.c_double), ("nodes_z0", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
         ("bytes_forward", ctypes.c_double), ("flops_forward", ctypes.c_double), ("direct_scale", ctypes.c_double),
+        ("forward_scratch_bytes", ctypes.c_size_t),
     ]
 
 
@@ -95,6 +97,7 @@ def load():
     for name in ("flt_forward", "flt_derivative", "flt_adjoint"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.flt_forward_derivative.argtypes = [vp, vp, vp, vp, vp]
+    lib.flt_forward_noalloc.argtypes = [vp, vp, vp, vp]
     lib.flt_laplace_plan_create.argtypes = [P(vp), ctypes.c_int64, P(ctypes.c_double), ctypes.c_int64,
                                             P(ctypes.c_double), ctypes.c_double, ctypes.c_int, ctypes.c_uint32]
     lib.flt_laplace_plan_info.argtypes = [vp, P(FltLaplaceInfo)]

@@ -410,6 +410,7 @@ int flt_plan_info(const flt_plan* p, flt_info* o)
     o->bytes_forward = hp.bytes_forward;
     o->flops_forward = hp.flops_forward;
     o->direct_scale = hp.direct_scale;
+    o->forward_scratch_bytes = hp.fwd_ws_bytes;
     return FLT_OK;
 }
 
@@ -551,6 +552,32 @@ static int run(flt_plan* p, int op, const void* in, void* out, void* stream, voi
 int flt_forward(flt_plan* p, const void* c, void* f, void* stream) { return run(p, 0, c, f, stream); }
 
 int flt_derivative(flt_plan* p, const void* c, void* fp, void* stream) { return run(p, 1, c, fp, stream); }
+
+int flt_forward_noalloc(flt_plan* p, const void* c, void* f, void* stream)
+{
+    if (!p || !c || !f) return FLT_EINVAL;
+    if (p->host_only) return FLT_ESTATE;
+    const HostPlan& hp = p->hp;
+    if (hp.fwd_ws_bytes > FLT_NOALLOC_MAX_BYTES) return FLT_ERANGE;
+    char* base = nullptr;
+    hipError_t e = noalloc_scratch_address(p->device, &base);
+    if (e != hipSuccess) return hip_fail(e);
+    // the forward's sections packed (one column set per band)
+    WsLayout W;
+    W.ws = base;
+    W.off_grid = 0;
+    W.off_scratch = hp.fwd_off_scratch;
+    W.off_dacc = hp.fwd_off_dacc;
+    W.off_base = hp.fwd_off_base;
+    W.qs = hp.qs;
+    W.N = hp.N;
+    W.M = hp.M;
+    W.grid_elems = hp.grid_elems;
+    const hipStream_t st = (hipStream_t)stream;
+    e = hp.dtype == FLT_C64 ? launch_forward<float>(p->lists, p->pv32, W, c, f, nullptr, 0, st)
+                            : launch_forward<double>(p->lists, p->pv64, W, c, f, nullptr, 0, st);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
 
 int flt_adjoint(flt_plan* p, const void* g, void* c_out, void* stream) { return run(p, 2, g, c_out, stream); }
 

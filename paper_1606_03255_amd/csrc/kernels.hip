@@ -5,7 +5,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
+
+#include "flt.h"
 
 #include "kernels_impl.h"
 #include "launch.h"
@@ -362,6 +366,44 @@ hipError_t launch_adjoint(const DevLists& L, const PlanView<T>& pv, const WsLayo
     ls.launched();
     mark(ls, ev, 8, st);
     return ls.first;
+}
+
+// The scratch of the forward without a workspace (flt_forward_noalloc): one
+// static array, of which every device the library runs that call on holds
+// its own copy at its own address while the library is loaded.  In host code
+// this name is only a handle for the address lookup below, never a device
+// address: kernels and copies are given the looked-up address.
+static __device__ __align__(256) char noalloc_scratch[FLT_NOALLOC_MAX_BYTES];
+
+namespace {
+std::mutex g_noalloc_mu;
+std::map<int, char*> g_noalloc_at;   // device -> address of its noalloc_scratch
+}  // namespace
+
+hipError_t noalloc_scratch_address(int device, char** out)
+{
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    const auto it = g_noalloc_at.find(device);
+    if (it != g_noalloc_at.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    // the lookup with that device current, the caller's device restored after
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(noalloc_scratch));
+    if (cur != device) {
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_at[device] = (char*)ptr;
+    *out = (char*)ptr;
+    return hipSuccess;
 }
 
 template hipError_t launch_forward<float>(const DevLists&, const PlanView<float>&, const WsLayout&, const void*,

@@ -72,6 +72,11 @@ template <typename T>
 hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayout& W, const void* c, void* f,
                           void* f2, int deriv, hipStream_t st, hipEvent_t* ev = nullptr);
 
+// Device address of the static scratch array of the forward without a
+// workspace on `device` (FLT_NOALLOC_MAX_BYTES bytes), looked up once per
+// device with it current (the caller's current device is restored).
+hipError_t noalloc_scratch_address(int device, char** out);
+
 // The discrete Laplace transform: fhat -> f on stream st (laplace.hip).
 template <typename T>
 hipError_t launch_laplace(const LapView& V, const LapItem* items, int nitems, int64_t M, const void* fhat, void* f,

@@ -474,6 +474,10 @@ static void finish(HostPlan& hp)
     hp.off_dacc = al(hp.off_l0 + (size_t)hp.M * 4);
     hp.off_base = al(hp.off_dacc + (size_t)hp.M * 16);
     hp.ws_bytes = al(hp.off_base + (size_t)hp.base_elems * S);
+    hp.fwd_off_scratch = al((size_t)hp.grid_elems * S);
+    hp.fwd_off_dacc = al(hp.fwd_off_scratch + (size_t)hp.scratch_elems * S);
+    hp.fwd_off_base = al(hp.fwd_off_dacc + (size_t)hp.M * 16);
+    hp.fwd_ws_bytes = al(hp.fwd_off_base + (size_t)hp.base_elems * S);
 }
 
 int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags,

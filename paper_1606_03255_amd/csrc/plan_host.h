@@ -61,6 +61,10 @@ struct HostPlan {
     size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
     size_t off_base = 0;
     size_t ws_bytes = 0;
+    // the forward alone (one column set per band): grids, pass-A output,
+    // direct-sum accumulator and base slots, packed; what a forward without
+    // a registered workspace needs
+    size_t fwd_off_scratch = 0, fwd_off_dacc = 0, fwd_off_base = 0, fwd_ws_bytes = 0;
 
     // algorithmic model
     double bytes_forward = 0, flops_forward = 0;

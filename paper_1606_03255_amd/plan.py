@@ -212,6 +212,12 @@ class Plan:
         """f_j ~ sum_k c_k exp(2 pi i k z_j); c: complex[N] on the device."""
         return self._run(self._lib.flt_forward, c, self.N, self.M, out, "c")
 
+    def forward_noalloc(self, c, out=None):
+        """The forward without the plan's workspace: its scratch is the
+        library's static device array (flt_forward_noalloc); calls that
+        overlap in time on one device race."""
+        return self._run(self._lib.flt_forward_noalloc, c, self.N, self.M, out, "c")
+
     def derivative(self, c, out=None):
         """f'(z_j) ~ sum_k 2 pi i k c_k exp(2 pi i k z_j)."""
         return self._run(self._lib.flt_derivative, c, self.N, self.M, out, "c")
