@@ -60,7 +60,8 @@ def build_emu(sanitize=False):
     tests/test_cpu_build.py)."""
     out = EMU_ASAN if sanitize else EMU
     tmp = out + ".tmp%d" % os.getpid()
-    extra = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-O1"] if sanitize else ["-O2"]
+    extra = (["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-O1", "-DFLT_EMU_OMP_TEAMS"] if sanitize
+             else ["-O2"])
     _run(["g++", "-g", "-std=c++17", "-fopenmp", "-fPIC", "-shared"] + extra + ["-I" + INC, "-I" + CSRC,
           os.path.join(CSRC, "emu.cpp"), os.path.join(CSRC, "plan_host.cpp"), os.path.join(CSRC, "laplace_plan.cpp"),
           "-o", tmp])

@@ -1,14 +1,24 @@
-// CPU build of the kernel bodies, for tests only: every workgroup runs as an
-// OpenMP team of FFT_THREADS / GATHER_THREADS threads with real barriers, on
-// host copies of the plan tables.  It exercises exactly the index arithmetic
-// and synchronisation of the GPU kernels, so tests can check it (optionally
-// under AddressSanitizer) before anything is launched on a GPU.  Nothing in
-// the library or its Python binding loads this file's build.
+// CPU build of the kernel bodies, for tests only: every workgroup runs its
+// FFT_THREADS / GATHER_THREADS threads with real barriers, on host copies of
+// the plan tables.  It exercises exactly the index arithmetic and
+// synchronisation of the GPU kernels, so tests can check it (optionally under
+// AddressSanitizer) before anything is launched on a GPU.  Nothing in the
+// library or its Python binding loads this file's build.
+//
+// A workgroup's threads are user-level fibers on one OS thread (ucontext):
+// each runs until its next barrier or its end, then the next one, so a
+// barrier round is complete before any thread passes it.  Built with
+// FLT_EMU_OMP_TEAMS (the sanitizer build: AddressSanitizer does not follow
+// context switches) they are an OpenMP team of OS threads instead.
 #define _GNU_SOURCE 1
 #include <math.h>
 #include <omp.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
+#ifndef FLT_EMU_OMP_TEAMS
+#include <ucontext.h>
+#endif
 
 #include <algorithm>
 #include <type_traits>
@@ -21,13 +31,51 @@
 
 namespace flt {
 
+#ifndef FLT_EMU_OMP_TEAMS
+// The fibers of the workgroup being run on this OS thread.
+struct FiberTeam {
+    static constexpr size_t STACK = 256 * 1024;
+    std::vector<ucontext_t> uc;
+    std::vector<char> stacks;
+    std::vector<uint8_t> done;
+    ucontext_t sched;
+    int nt = 0, b = 0, cur = 0;
+    const void* body = nullptr;
+    void (*call)(const void*, int t, int nt, int b) = nullptr;
+    void reserve(int n)
+    {
+        if ((int)uc.size() >= n) return;
+        uc.resize(n);
+        done.resize(n);
+        stacks.assign((size_t)n * STACK, 0);
+    }
+};
+static thread_local FiberTeam g_team;
+static void fiber_barrier()
+{
+    FiberTeam& T = g_team;
+    swapcontext(&T.uc[T.cur], &T.sched);
+}
+static void fiber_entry()
+{
+    FiberTeam& T = g_team;
+    const int t = T.cur;
+    T.call(T.body, t, T.nt, T.b);
+    T.done[t] = 1;   // returns to T.sched (uc_link)
+}
+#endif
+
 struct HostCtx {
     int t, nt, b;
     int tid() const { return t; }
     int ntid() const { return nt; }
     int bid() const { return b; }
     void sync() const {
+#ifdef FLT_EMU_OMP_TEAMS
 #pragma omp barrier
+#else
+        fiber_barrier();
+#endif
     }
     void atomic_add(double* p, double v) const {
 #pragma omp atomic
@@ -50,6 +98,7 @@ template <typename T> static std::vector<T> cast(const std::vector<double>& v)
 
 template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body)
 {
+#ifdef FLT_EMU_OMP_TEAMS
     for (size_t b = 0; b < nblocks; ++b) {
 #pragma omp parallel num_threads(nthreads)
         {
@@ -57,6 +106,37 @@ template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body
             body(ctx);
         }
     }
+#else
+    using Fn = typename std::remove_reference<F>::type;
+    FiberTeam& T = g_team;
+    T.reserve(nthreads);
+    T.nt = nthreads;
+    T.body = &body;
+    T.call = [](const void* f, int t, int nt, int b) {
+        const HostCtx ctx{t, nt, b};
+        (*(const Fn*)f)(ctx);
+    };
+    for (size_t b = 0; b < nblocks; ++b) {
+        T.b = (int)b;
+        for (int t = 0; t < nthreads; ++t) {
+            getcontext(&T.uc[t]);
+            T.uc[t].uc_stack.ss_sp = T.stacks.data() + (size_t)t * FiberTeam::STACK;
+            T.uc[t].uc_stack.ss_size = FiberTeam::STACK;
+            T.uc[t].uc_link = &T.sched;
+            makecontext(&T.uc[t], fiber_entry, 0);
+            T.done[t] = 0;
+        }
+        // barrier rounds: every live fiber runs to its next barrier (or end)
+        for (int live = nthreads; live > 0;) {
+            for (int t = 0; t < nthreads; ++t) {
+                if (T.done[t]) continue;
+                T.cur = t;
+                swapcontext(&T.sched, &T.uc[t]);
+                if (T.done[t]) --live;
+            }
+        }
+    }
+#endif
 }
 
 template <typename T, int MW>
@@ -110,10 +190,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
     std::vector<cplx<T>> lds(tile_alloc<T>());
     std::vector<T> lc(Sizes<T>::COEF);
-    int64_t base_elems = 1;
-    for (const BandDesc& B : hp.bands)
-        if (B.q > 0 && !B.direct && B.log2n2 > 0) base_elems = std::max(base_elems, B.base_off + ((int64_t)1 << B.log2n));
-    std::vector<cplx<T>> basebuf(base_elems);
+    std::vector<cplx<T>> omega(PASSA_OMEGA_MAX);
+    std::vector<cplx<T>> basebuf(std::max<int64_t>(hp.base_elems, 1));
     const int64_t nd = (int64_t)hp.dlist.size();
     auto mwsw = [&](int adjoint, const cplx<T>* c, cplx<T>* f, int with_c0, cplx<T>* f2) {
         switch (hp.mw) {
@@ -140,9 +218,14 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         for (const LaunchGroup& g : hp.g_passA_fwd)
             with_log2<LP + 1, TW2_LOG2>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
-                    body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
-                                                                    scratch.data(), basebuf.data(), deriv, cols,
-                                                                    lds.data(), lc.data());
+                    if constexpr (sizeof(T) == 4)
+                        body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
+                                                                        scratch.data(), deriv, cols, lds.data(),
+                                                                        lc.data(), omega.data());
+                    else
+                        body_passA_fwd_slot<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start,
+                                                                             c, scratch.data(), basebuf.data(), deriv,
+                                                                             cols, lds.data(), lc.data());
                 });
             });
         if (!pb.empty()) {

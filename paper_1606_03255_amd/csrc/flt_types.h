@@ -91,8 +91,8 @@ struct BandDesc {
     int64_t node_start;  // first node of the band in the sorted node arrays
     int64_t node_count;
     int64_t cs_off;      // cell-start table of the band (n + 1 entries) for the adjoint
-    int64_t base_off;    // pass A: complex offset of the band's per-point c_k / (n phi_hat) slots
     int64_t mask_off;    // two-pass bands: first 32-bit word of the cell mask (bit per grid address)
+    int64_t base_off;    // FP64 pass A: complex offset of the band's per-point c_k / (n phi_hat) slots
     int64_t cells;       // grid cells per column that some node's window reads
     int64_t c_off;       // first coefficient of the band's instance in the packed c (and adjoint output)
 };

@@ -30,7 +30,11 @@ struct DevCtx {
 // share a compute unit, which the FFT kernels are laid out for.
 constexpr size_t LDS_LIMIT = 160 * 1024, LDS_TWO_PER_CU = 80 * 1024;
 template <typename T> constexpr size_t lds_fft_bytes() { return sizeof(cplx<T>) * tile_alloc<T>(); }
-template <typename T> constexpr size_t lds_passA_bytes() { return lds_fft_bytes<T>() + sizeof(T) * Sizes<T>::COEF; }
+template <typename T> constexpr int passA_omega_alloc() { return sizeof(T) == 4 ? PASSA_OMEGA_MAX : 0; }
+template <typename T> constexpr size_t lds_passA_bytes()
+{
+    return lds_fft_bytes<T>() + sizeof(T) * Sizes<T>::COEF + sizeof(cplx<T>) * passA_omega_alloc<T>();
+}
 static_assert(lds_passA_bytes<float>() <= LDS_TWO_PER_CU && lds_passA_bytes<double>() <= LDS_TWO_PER_CU,
               "an FFT tile and the staged coefficients must leave room for a second workgroup per CU");
 static_assert(lds_passA_bytes<double>() <= LDS_LIMIT, "LDS per workgroup");
@@ -49,18 +53,34 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, 
     });
 }
 
-template <typename T>
-// four waves per SIMD (two workgroups per CU, as the LDS allows)
-__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passA_fwd(PlanView<T> pv, const FftItem* items,
-                                                              const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf,
-                                                              int deriv, int cols)
+// FP32: two waves per SIMD (one workgroup per CU): the bases, the first-stage
+// butterfly and the stage twiddles of a thread stay in registers (measured
+// faster than four waves per SIMD with spills).
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_passA_fwd_f32(
+    PlanView<float> pv, const FftItem* items, const cplx<float>* c, cplx<float>* scratch, int deriv, int cols)
 {
-    __shared__ cplx<T> lds[tile_alloc<T>()];
-    __shared__ alignas(16) T lc[Sizes<T>::COEF];
-    using RG = Log2Range<T>;
+    __shared__ cplx<float> lds[tile_alloc<float>()];
+    __shared__ alignas(16) float lc[Sizes<float>::COEF];
+    __shared__ cplx<float> omega[passA_omega_alloc<float>()];
+    using RG = Log2Range<float>;
     with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_passA_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv, cols, lds,
-                                                       lc);
+        body_passA_fwd<DevCtx, float, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, deriv, cols, lds, lc,
+                                                           omega);
+    });
+}
+
+// FP64: four waves per SIMD (two workgroups per CU, as the LDS allows); the
+// bases in the workspace slots
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passA_fwd_f64(
+    PlanView<double> pv, const FftItem* items, const cplx<double>* c, cplx<double>* scratch, cplx<double>* basebuf,
+    int deriv, int cols)
+{
+    __shared__ cplx<double> lds[tile_alloc<double>()];
+    __shared__ alignas(16) double lc[Sizes<double>::COEF];
+    using RG = Log2Range<double>;
+    with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
+        body_passA_fwd_slot<DevCtx, double, decltype(LG)::value>(DevCtx(), pv, items, c, scratch, basebuf, deriv,
+                                                                 cols, lds, lc);
     });
 }
 
@@ -203,7 +223,6 @@ static void fft_forward_stages(LaunchStatus& ls, const DevLists& L, const PlanVi
 {
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     cplx<T>* scratch = (cplx<T>*)(W.ws + W.off_scratch);
-    cplx<T>* basebuf = (cplx<T>*)(W.ws + W.off_base);
     // cols = 2: the item lists over 2q columns per band
     const FftItem* one = cols == 2 ? L.onepass_fused : L.onepass_fwd;
     const int n_one = cols == 2 ? L.n_onepass_fused : L.n_onepass_fwd;
@@ -216,8 +235,12 @@ static void fft_forward_stages(LaunchStatus& ls, const DevLists& L, const PlanVi
     }
     mark(ls, ev, 1, st);
     if (L.n_passA_fwd) {
-        hipLaunchKernelGGL(k_passA_fwd<T>, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
-                           scratch, basebuf, deriv, cols);
+        if constexpr (std::is_same<T, float>::value)
+            hipLaunchKernelGGL(k_passA_fwd_f32, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
+                               scratch, deriv, cols);
+        else
+            hipLaunchKernelGGL(k_passA_fwd_f64, dim3(L.n_passA_fwd), dim3(FFT_THREADS), 0, st, pv, L.passA_fwd, c,
+                               scratch, (cplx<T>*)(W.ws + W.off_base), deriv, cols);
         ls.launched();
     }
     mark(ls, ev, 2, st);

@@ -477,8 +477,189 @@ template <typename T, int LOG2N> struct TwoPassGeo {
     static constexpr int log2B = Sizes<T>::LOG2P - log2n2;   // pass B: sub-transforms per tile
 };
 
+// Pass A of the FP32 form and its thread geometry at compile time.  Each
+// thread's c_k / (n phi_hat(k')) values stay in registers across the q columns
+// of its band.  The first FFT stage (radix
+// R1 = 2^LR1, no twiddles) is done in registers right after the column is
+// generated: thread u holds sub-transform jj = u >> LOG2LQ and the points
+// j1 = jl + r 2^LOG2LQ, r < R1, jl = u mod 2^LOG2LQ.  A band's support
+// (k - k0 in [1 - n/4, n/4]) fills half the grid: x[j2 + n2 j1] can be
+// non-zero only for j1 <= n1/4 or j1 >= 3 n1/4, i.e. r <= R1/4 or r >= 3 R1/4
+// (LIVE), and r = R1/4 only at j2 = 0, jl = 0.
+//
+// Output twiddles e^{2 pi i j2 l1 / n} at the tile elements p = tid + i 512:
+// when the bits of i fall in l1's high part only (SEP, the larger grids), l1 =
+// l1_t + i DL and the factor is tw_t w(j2)^i, tw_t per thread, the powers
+// w(j2)^i = e^{2 pi i j2 DL i / n} for the workgroup's b values of j2 in an LDS
+// table of b * ITEMS entries; otherwise two reads of the global table per point.
+template <typename T, int LOG2N> struct PassAGeo {
+    using G = TwoPassGeo<T, LOG2N>;
+    static constexpr int ITEMS = tile_items<T>();
+    static constexpr int LR1 = next_radix_log2(G::log2n1, MaxRadix<T>::LOG2);
+    static constexpr int R1 = 1 << LR1;
+    static constexpr int LOG2LQ = G::log2n1 - LR1;
+    static constexpr int LOG2T = 9;   // log2(FFT_THREADS)
+    static constexpr bool SEP = G::log2B + G::log2b <= LOG2T;
+    static constexpr int DL = SEP ? 1 << (LOG2T - G::log2b) : 0;
+    static constexpr int OMEGA = SEP ? (1 << G::log2b) * ITEMS : 0;   // LDS table entries
+    FLT_HD static constexpr bool live(int r) { return r <= R1 / 4 || r >= 3 * R1 / 4; }
+    static_assert(ITEMS == R1, "one first-stage butterfly per thread");
+    static_assert((1 << LOG2T) == FFT_THREADS, "thread count");
+};
+// LDS entries the output-twiddle table of pass A needs at most (FP32).
+constexpr int PASSA_OMEGA_MAX = 256;
+
+// k of grid index j of band B (the band's support centred at k0), or 0 when
+// the point lies outside the support 1 <= k <= kmax.
+FLT_HD int passA_k(int j, int n, int k0, int kmax)
+{
+    const int k = (j < (n >> 1) ? j : j - n) + k0;
+    return k >= 1 && k <= kmax ? k : 0;
+}
+
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                           const cplx<T>* c, cplx<T>* scratch, int deriv, int cols,
+                           cplx<T>* lds, T* lc, cplx<T>* omega)
+{
+    static_assert(sizeof(T) == 4, "the FP32 form's pass A (FP64: body_passA_fwd_slot)");
+    using G = TwoPassGeo<T, LOG2N>;
+    using A = PassAGeo<T, LOG2N>;
+    constexpr int ITEMS = A::ITEMS, R1 = A::R1, LR1 = A::LR1, LOG2LQ = A::LOG2LQ;
+    constexpr int log2n1 = G::log2n1, log2n2 = G::log2n2, log2b = G::log2b, log2B = G::log2B;
+    constexpr int n = 1 << LOG2N;
+    const FftItem it = items[ctx.bid()];
+    const BandDesc B = pv.bands[it.band];   // a copy: the stores below cannot alias it
+    const int k0 = (int)B.k0, kmax = (int)B.kmax;
+    const int j2_0 = it.blk << log2b;
+    const int tid = ctx.tid();
+    StageTw<T, log2n1, (1 << log2b), +1> stw;   // stage twiddles in registers
+    stw.load(ctx, pv.tw_stage);
+
+    // c_k / (n phi_hat(k')) of the workgroup's points, read from c in address
+    // order (jj fastest) and transposed through the LDS tile ...
+    for (int i = 0; i < ITEMS; ++i) {
+        const int p = tid + i * FFT_THREADS;
+        const int jj = p & ((1 << log2b) - 1);
+        const int j1 = p >> log2b;
+        const int j = j2_0 + jj + (j1 << log2n2);
+        const int k = passA_k(j, n, k0, kmax);
+        lds[lds_at((jj << log2n1) + j1)] = k ? point_base(pv, B, c, j < (n >> 1) ? j : j - n, k, deriv)
+                                             : mk<T>(0, 0);
+    }
+    // ... the output-twiddle powers and the first column's coefficients
+    const int o_l1lo = tid & ((1 << log2B) - 1);
+    const int o_jj = (tid >> log2B) & ((1 << log2b) - 1);
+    const int o_l1hi = tid >> (log2B + log2b);
+    cplx<T> tw_t = mk<T>(1, 0);
+    if constexpr (A::OMEGA > 0) {
+        static_assert(A::OMEGA <= PASSA_OMEGA_MAX && A::OMEGA <= FFT_THREADS, "output twiddle table size");
+        if (tid < A::OMEGA) {
+            const int jj = tid / ITEMS, i = tid % ITEMS;
+            omega[tid] = tw_grid_at(pv, (uint32_t)(j2_0 + jj) * (uint32_t)(A::DL * i), LOG2N, +1);
+        }
+        tw_t = tw_grid_at(pv, (uint32_t)(j2_0 + o_jj) * (uint32_t)((o_l1hi << log2B) + o_l1lo), LOG2N, +1);
+    }
+    stage_coef(ctx, pv, B, 0, lc);
+    ctx.sync();
+    // ... into registers, in the first stage's layout: only the live points
+    const int jj_u = tid >> LOG2LQ;
+    const int jl = tid & ((1 << LOG2LQ) - 1);
+    const bool j2zero = j2_0 + jj_u == 0;          // the one grid row where r = R1/4 can be live
+    cplx<T> base[R1];
+    int kr[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+        base[r] = mk<T>(0, 0);
+        kr[r] = 0;
+        if (!A::live(r)) continue;
+        const int j1 = jl + (r << LOG2LQ);
+        base[r] = lds[lds_at((jj_u << log2n1) + j1)];
+        kr[r] = passA_k(j2_0 + jj_u + (j1 << log2n2), n, k0, kmax);
+    }
+    ctx.sync();
+
+    cplx<T>* const Ybase = scratch + B.scratch_off * cols;
+    const int ncol = cols * B.q;
+    for (int s = 0; s < ncol; ++s) {
+        // cols = 2: columns q .. 2q - 1 are the derivative's, the same
+        // interpolant rows times 2 pi i k
+        const bool dcol = s >= B.q;
+        // generate the live points of the column (the rest is zero), apply the
+        // first radix-R1 stage in registers, store its output
+        cplx<T> v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            v[r] = mk<T>(0, 0);
+            if (!A::live(r)) continue;
+            if (r == R1 / 4 && !j2zero) continue;
+            const int k = kr[r];
+            T w = k ? laplace_row_lds(lc, B, k) : T(0);
+            cplx<T> b = base[r];
+            if (dcol) {   // c'_k = 2 pi i k c_k
+                w *= (T)(6.283185307179586476925286766559 * (double)k);
+                b = mk(-b.y, b.x);
+            }
+            v[r] = scale(b, w);
+        }
+        dft<T, R1>(v, +1);
+        {
+            // Stockham output of a first stage: element (jj, jl R1 + r)
+            const int dp = lds_at((jj_u << log2n1) + (jl << LR1));
+#pragma unroll
+            for (int r = 0; r < R1; ++r) lds[dp + r] = v[r];
+        }
+        ctx.sync();
+        lds_fft_ct<Ctx, T, log2n1, (1 << log2b), +1, LR1>(ctx, lds, stw.next());
+        // output: Y[l1 / B][j2][l1 mod B] = X_jj[l1] e^{2 pi i j2 l1 / n}; the
+        // next column's coefficients are staged meanwhile (lc is free now)
+        if (s + 1 < ncol) stage_coef(ctx, pv, B, s + 1 >= B.q ? s + 1 - B.q : s + 1, lc);
+        cplx<T>* Y = Ybase + ((int64_t)s << LOG2N);
+        if constexpr (A::OMEGA > 0) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int l1 = (o_l1hi << log2B) + o_l1lo + i * A::DL;
+                const int l1hi = l1 >> log2B;
+                const cplx<T> wv = mul(tw_t, omega[o_jj * ITEMS + i]);
+                Y[(l1hi << (log2n2 + log2B)) + ((j2_0 + o_jj) << log2B) + o_l1lo] =
+                    mul(lds[lds_at((o_jj << log2n1) + l1)], wv);
+            }
+        } else {
+            // in groups of GO points: the group's table reads first (in flight
+            // together), then the products and stores
+            constexpr int GO = sizeof(T) == 4 ? 8 : 4;
+#pragma unroll 1
+            for (int i0 = 0; i0 < ITEMS; i0 += GO) {
+                TwPair<T> w[GO];
+                for (int u = 0; u < GO; ++u) {
+                    const int p = tid + (i0 + u) * FFT_THREADS;
+                    const int l1lo = p & ((1 << log2B) - 1);
+                    const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                    const int l1 = ((p >> (log2B + log2b)) << log2B) + l1lo;
+                    w[u] = tw_grid_fetch(pv, (uint32_t)(j2_0 + jj) * (uint32_t)l1, LOG2N);
+                }
+                for (int u = 0; u < GO; ++u) {
+                    const int p = tid + (i0 + u) * FFT_THREADS;
+                    const int l1lo = p & ((1 << log2B) - 1);
+                    const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                    const int l1hi = p >> (log2B + log2b);
+                    const int l1 = (l1hi << log2B) + l1lo;
+                    Y[(l1hi << (log2n2 + log2B)) + ((j2_0 + jj) << log2B) + l1lo] =
+                        mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_join(w[u], +1));
+                }
+            }
+        }
+        ctx.sync();
+    }
+}
+
+// Pass A of the FP64 form: the same transform as body_passA_fwd, each
+// point's c_k / (n phi_hat(k')) formed once per workgroup and kept in the
+// workgroup's own slot of the workspace (band's base_off), re-read for the
+// other columns; every thread re-reads only what it wrote.  (FP64 registers
+// would not hold a thread's bases beside its FFT values without spilling.)
+template <class Ctx, typename T, int LOG2N>
+FLT_HD void body_passA_fwd_slot(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* c, cplx<T>* scratch, cplx<T>* basebuf, int deriv, int cols,
                            cplx<T>* lds, T* lc)
 {

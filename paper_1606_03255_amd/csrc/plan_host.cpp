@@ -349,8 +349,10 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
         if (B.log2n2 > 0) {
             B.scratch_off = soff;
             soff += (int64_t)B.q * n;
-            B.base_off = boff;
-            boff += n;
+            if (dtype == FLT_C128) {   // the FP64 pass A keeps its bases in the workspace
+                B.base_off = boff;
+                boff += n;
+            }
             const int nA = 1 << (B.log2n2 - B.log2b), nB = 1 << (B.log2n1 - B.log2B);
             for (int k = 0; k < nA; ++k) hp.passA_fwd.push_back(FftItem{b, 0, B.q, k});
             for (int s = 0; s < B.q; ++s)
@@ -540,9 +542,9 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
                 B.coef_off += coef_shift;
                 B.grid_off += out.grid_elems;
                 B.scratch_off += out.scratch_elems;
-                B.base_off += out.base_elems;
                 B.cs_off += cso;
                 B.mask_off += mko;
+                B.base_off += out.base_elems;
                 auto dt = deconv_at.find(B.log2n);
                 if (dt == deconv_at.end()) {
                     const int64_t len = ((int64_t)1 << B.log2n) / 4 + 1;

@@ -57,13 +57,13 @@ struct HostPlan {
 
     // workspace layout (bytes)
     int qs = 1;                         // stride of the per-node column values (max q)
-    int64_t grid_elems = 0, scratch_elems = 0, base_elems = 0;
+    int64_t grid_elems = 0, scratch_elems = 0, base_elems = 0;   // base: FP64 plans only
     size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
     size_t off_base = 0;
     size_t ws_bytes = 0;
     // the forward alone (one column set per band): grids, pass-A output,
-    // direct-sum accumulator and base slots, packed; what a forward without
-    // a registered workspace needs
+    // direct-sum accumulator and FP64 base slots, packed; what a forward
+    // without a registered workspace needs
     size_t fwd_off_scratch = 0, fwd_off_dacc = 0, fwd_off_base = 0, fwd_ws_bytes = 0;
 
     // algorithmic model
