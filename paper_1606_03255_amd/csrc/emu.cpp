@@ -190,6 +190,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
     std::vector<cplx<T>> lds(tile_alloc<T>());
     std::vector<T> lc(Sizes<T>::COEF);
+    std::vector<cplx<T>> lds2(2 * tile_alloc<T>());   // the FP32 pass A's two tiles and coefficient buffers
+    std::vector<T> lc2(2 * Sizes<T>::COEF);
     std::vector<cplx<T>> omega(PASSA_OMEGA_MAX);
     std::vector<cplx<T>> basebuf(std::max<int64_t>(hp.base_elems, 1));
     const int64_t nd = (int64_t)hp.dlist.size();
@@ -220,8 +222,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     if constexpr (sizeof(T) == 4)
                         body_passA_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start, c,
-                                                                        scratch.data(), deriv, cols, lds.data(),
-                                                                        lc.data(), omega.data());
+                                                                        scratch.data(), deriv, cols, lds2.data(),
+                                                                        lc2.data(), omega.data());
                     else
                         body_passA_fwd_slot<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_fwd.data() + g.start,
                                                                              c, scratch.data(), basebuf.data(), deriv,

@@ -27,17 +27,22 @@ struct DevCtx {
 
 // Static LDS of the kernels, against gfx950's 160 KB per workgroup (the
 // compiler rejects more) and the 80 KB that lets two 512-thread workgroups
-// share a compute unit, which the FFT kernels are laid out for.
+// share a compute unit, which the FFT kernels other than the FP32 pass A are
+// laid out for (that one runs a workgroup per CU with two tiles).
 constexpr size_t LDS_LIMIT = 160 * 1024, LDS_TWO_PER_CU = 80 * 1024;
 template <typename T> constexpr size_t lds_fft_bytes() { return sizeof(cplx<T>) * tile_alloc<T>(); }
 template <typename T> constexpr int passA_omega_alloc() { return sizeof(T) == 4 ? PASSA_OMEGA_MAX : 0; }
-template <typename T> constexpr size_t lds_passA_bytes()
+constexpr size_t lds_passA_f32_bytes()
 {
-    return lds_fft_bytes<T>() + sizeof(T) * Sizes<T>::COEF + sizeof(cplx<T>) * passA_omega_alloc<T>();
+    return 2 * lds_fft_bytes<float>() + 2 * sizeof(float) * Sizes<float>::COEF +
+           sizeof(cplx<float>) * passA_omega_alloc<float>();
 }
-static_assert(lds_passA_bytes<float>() <= LDS_TWO_PER_CU && lds_passA_bytes<double>() <= LDS_TWO_PER_CU,
-              "an FFT tile and the staged coefficients must leave room for a second workgroup per CU");
-static_assert(lds_passA_bytes<double>() <= LDS_LIMIT, "LDS per workgroup");
+constexpr size_t lds_passA_f64_bytes() { return lds_fft_bytes<double>() + sizeof(double) * Sizes<double>::COEF; }
+static_assert(lds_passA_f32_bytes() <= LDS_LIMIT, "LDS per workgroup");
+static_assert(lds_passA_f64_bytes() <= LDS_TWO_PER_CU, "two FP64 pass-A workgroups per CU");
+static_assert(lds_fft_bytes<float>() + sizeof(float) * Sizes<float>::COEF <= LDS_TWO_PER_CU &&
+                  lds_fft_bytes<double>() + sizeof(double) * Sizes<double>::COEF <= LDS_TWO_PER_CU,
+              "a tile and a coefficient buffer leave room for a second workgroup per CU");
 
 // One launch per FFT kind; each workgroup picks the compile-time instance of
 // its band's transform length.
@@ -59,8 +64,8 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, 
 __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_passA_fwd_f32(
     PlanView<float> pv, const FftItem* items, const cplx<float>* c, cplx<float>* scratch, int deriv, int cols)
 {
-    __shared__ cplx<float> lds[tile_alloc<float>()];
-    __shared__ alignas(16) float lc[Sizes<float>::COEF];
+    __shared__ cplx<float> lds[2 * tile_alloc<float>()];
+    __shared__ alignas(16) float lc[2 * Sizes<float>::COEF];
     __shared__ cplx<float> omega[passA_omega_alloc<float>()];
     using RG = Log2Range<float>;
     with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {

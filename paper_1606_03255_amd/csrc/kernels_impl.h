@@ -282,11 +282,12 @@ template <bool REG, typename T, int LOG2L, int NSUB, int SIGN> struct TwSel { us
 template <typename T, int LOG2L, int NSUB, int SIGN> struct TwSel<false, T, LOG2L, NSUB, SIGN> { using type = TableTw<T>; };
 
 // One Stockham autosort radix-2^LR stage over NSUB contiguous transforms of
-// length 2^LOG2L in `buf`, all geometry known at compile time (in place:
-// reads, barrier, writes, barrier).  Twiddles e^{SIGN 2 pi i k r / (Ns R)}
-// from the provider tw (TableTw or StageTw).
-template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, class TW>
-FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
+// length 2^LOG2L, all geometry known at compile time, reading `src` and
+// writing `dst` (LDS).  In place (src == dst, INPLACE): reads, barrier,
+// writes, barrier; out of place: reads, writes, barrier.  Twiddles
+// e^{SIGN 2 pi i k r / (Ns R)} from the provider tw (TableTw or StageTw).
+template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, bool INPLACE, class TW>
+FLT_HD void fft_stage_io(const Ctx& ctx, const cplx<T>* src, cplx<T>* dst, const TW& tw)
 {
     constexpr int R = 1 << LR;
     constexpr int P = NSUB << LOG2L;
@@ -294,19 +295,19 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
     constexpr int LOG2LQ = LOG2L - LR;
     constexpr int NB = (NBUT + FFT_THREADS - 1) / FFT_THREADS;
     cplx<T> v[NB][R];
-    int dst[NB];
+    int dsti[NB];
     for (int i = 0; i < NB; ++i) {
         const int u = ctx.tid() + i * FFT_THREADS;
-        dst[i] = -1;
+        dsti[i] = -1;
         if ((NBUT % FFT_THREADS) == 0 || u < NBUT) {
             const int sub = u >> LOG2LQ;
             const int j = u & ((1 << LOG2LQ) - 1);
-            const int src = (sub << LOG2L) + j;
+            const int srci = (sub << LOG2L) + j;
             if constexpr (LOG2LQ >= 4) {   // strides of multiples of 16: the pad is a constant offset
-                const int sp = lds_at(src);
-                for (int r = 0; r < R; ++r) v[i][r] = buf[sp + (r << LOG2LQ) + (r << (LOG2LQ - 4))];
+                const int sp = lds_at(srci);
+                for (int r = 0; r < R; ++r) v[i][r] = src[sp + (r << LOG2LQ) + (r << (LOG2LQ - 4))];
             } else {
-                for (int r = 0; r < R; ++r) v[i][r] = buf[lds_at(src + (r << LOG2LQ))];
+                for (int r = 0; r < R; ++r) v[i][r] = src[lds_at(srci + (r << LOG2LQ))];
             }
             const int k = j & ((1 << LOG2NS) - 1);
             if constexpr (LOG2NS > 0) {
@@ -320,24 +321,30 @@ FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
                 }
             }
             dft<T, R>(v[i], SIGN);
-            dst[i] = (sub << LOG2L) + ((j >> LOG2NS) << (LOG2NS + LR)) + k;
+            dsti[i] = (sub << LOG2L) + ((j >> LOG2NS) << (LOG2NS + LR)) + k;
         }
     }
-    ctx.sync();
+    if constexpr (INPLACE) ctx.sync();
     for (int i = 0; i < NB; ++i) {
-        if (dst[i] < 0) continue;
+        if (dsti[i] < 0) continue;
         if constexpr (LOG2NS >= 4) {
-            const int dp = lds_at(dst[i]);
-            for (int r = 0; r < R; ++r) buf[dp + (r << LOG2NS) + (r << (LOG2NS - 4))] = v[i][r];
+            const int dp = lds_at(dsti[i]);
+            for (int r = 0; r < R; ++r) dst[dp + (r << LOG2NS) + (r << (LOG2NS - 4))] = v[i][r];
         } else if constexpr (LOG2NS + LR <= 4) {
             // dst = base + k with base a multiple of NS R <= 16 and k + r NS < NS R: no carry into bit 4
-            const int dp = lds_at(dst[i]);
-            for (int r = 0; r < R; ++r) buf[dp + (r << LOG2NS)] = v[i][r];
+            const int dp = lds_at(dsti[i]);
+            for (int r = 0; r < R; ++r) dst[dp + (r << LOG2NS)] = v[i][r];
         } else {
-            for (int r = 0; r < R; ++r) buf[lds_at(dst[i] + (r << LOG2NS))] = v[i][r];
+            for (int r = 0; r < R; ++r) dst[lds_at(dsti[i] + (r << LOG2NS))] = v[i][r];
         }
     }
     ctx.sync();
+}
+
+template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, class TW>
+FLT_HD void fft_stage_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
+{
+    fft_stage_io<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN, true>(ctx, buf, buf, tw);
 }
 
 // In-place DFTs X[l] = sum_j x[j] e^{SIGN 2 pi i j l / L} of NSUB transforms of
@@ -351,6 +358,21 @@ FLT_HD void lds_fft_ct(const Ctx& ctx, cplx<T>* buf, const TW& tw)
         constexpr int LR = next_radix_log2(REM, MaxRadix<T>::LOG2);
         fft_stage_ct<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN>(ctx, buf, tw);
         lds_fft_ct<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, buf, tw.next());
+    }
+}
+
+// The same DFTs from stage LOG2NS on with two LDS tiles in turn (one barrier
+// per stage): the input in a, b free; returns the tile that holds the result.
+template <class Ctx, typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS = 0, class TW>
+FLT_HD cplx<T>* lds_fft_pp(const Ctx& ctx, cplx<T>* a, cplx<T>* b, const TW& tw)
+{
+    constexpr int REM = LOG2L - LOG2NS;
+    if constexpr (REM > 0) {
+        constexpr int LR = next_radix_log2(REM, MaxRadix<T>::LOG2);
+        fft_stage_io<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN, false>(ctx, a, b, tw);
+        return lds_fft_pp<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, b, a, tw.next());
+    } else {
+        return a;
     }
 }
 
@@ -517,6 +539,11 @@ FLT_HD int passA_k(int j, int n, int k0, int kmax)
     return k >= 1 && k <= kmax ? k : 0;
 }
 
+// The FP32 pass A.  LDS: two FFT tiles (lds, lds + tile_alloc) used in turn, so that an FFT
+// stage needs one barrier and a column's output can be read from one tile
+// while the next column is generated into the other; two coefficient buffers
+// (lc, lc + COEF), the next column's staged during the current generation.
+// Three barriers per column.
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* c, cplx<T>* scratch, int deriv, int cols,
@@ -562,6 +589,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
     }
     stage_coef(ctx, pv, B, 0, lc);
     ctx.sync();
+    cplx<T>* const tile[2] = {lds, lds + tile_alloc<T>()};
     // ... into registers, in the first stage's layout: only the live points
     const int jj_u = tid >> LOG2LQ;
     const int jl = tid & ((1 << LOG2LQ) - 1);
@@ -581,10 +609,15 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
 
     cplx<T>* const Ybase = scratch + B.scratch_off * cols;
     const int ncol = cols * B.q;
+    cplx<T>* gen = tile[1];   // the tile the next column is generated into
     for (int s = 0; s < ncol; ++s) {
         // cols = 2: columns q .. 2q - 1 are the derivative's, the same
         // interpolant rows times 2 pi i k
         const bool dcol = s >= B.q;
+        const T* lcs = lc + (s & 1) * Sizes<T>::COEF;
+        // the next column's coefficients into the other buffer (last read by
+        // the column before this one, before this column's first barrier)
+        if (s + 1 < ncol) stage_coef(ctx, pv, B, s + 1 >= B.q ? s + 1 - B.q : s + 1, lc + ((s + 1) & 1) * Sizes<T>::COEF);
         // generate the live points of the column (the rest is zero), apply the
         // first radix-R1 stage in registers, store its output
         cplx<T> v[R1];
@@ -594,7 +627,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             if (!A::live(r)) continue;
             if (r == R1 / 4 && !j2zero) continue;
             const int k = kr[r];
-            T w = k ? laplace_row_lds(lc, B, k) : T(0);
+            T w = k ? laplace_row_lds(lcs, B, k) : T(0);
             cplx<T> b = base[r];
             if (dcol) {   // c'_k = 2 pi i k c_k
                 w *= (T)(6.283185307179586476925286766559 * (double)k);
@@ -607,13 +640,14 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
             // Stockham output of a first stage: element (jj, jl R1 + r)
             const int dp = lds_at((jj_u << log2n1) + (jl << LR1));
 #pragma unroll
-            for (int r = 0; r < R1; ++r) lds[dp + r] = v[r];
+            for (int r = 0; r < R1; ++r) gen[dp + r] = v[r];
         }
         ctx.sync();
-        lds_fft_ct<Ctx, T, log2n1, (1 << log2b), +1, LR1>(ctx, lds, stw.next());
-        // output: Y[l1 / B][j2][l1 mod B] = X_jj[l1] e^{2 pi i j2 l1 / n}; the
-        // next column's coefficients are staged meanwhile (lc is free now)
-        if (s + 1 < ncol) stage_coef(ctx, pv, B, s + 1 >= B.q ? s + 1 - B.q : s + 1, lc);
+        cplx<T>* const res =
+            lds_fft_pp<Ctx, T, log2n1, (1 << log2b), +1, LR1>(ctx, gen, gen == tile[0] ? tile[1] : tile[0], stw.next());
+        gen = res == tile[0] ? tile[1] : tile[0];
+        // output: Y[l1 / B][j2][l1 mod B] = X_jj[l1] e^{2 pi i j2 l1 / n}, read
+        // from res while the next column is generated into the other tile
         cplx<T>* Y = Ybase + ((int64_t)s << LOG2N);
         if constexpr (A::OMEGA > 0) {
 #pragma unroll
@@ -622,7 +656,7 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
                 const int l1hi = l1 >> log2B;
                 const cplx<T> wv = mul(tw_t, omega[o_jj * ITEMS + i]);
                 Y[(l1hi << (log2n2 + log2B)) + ((j2_0 + o_jj) << log2B) + o_l1lo] =
-                    mul(lds[lds_at((o_jj << log2n1) + l1)], wv);
+                    mul(res[lds_at((o_jj << log2n1) + l1)], wv);
             }
         } else {
             // in groups of GO points: the group's table reads first (in flight
@@ -645,11 +679,10 @@ FLT_HD void body_passA_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
                     const int l1hi = p >> (log2B + log2b);
                     const int l1 = (l1hi << log2B) + l1lo;
                     Y[(l1hi << (log2n2 + log2B)) + ((j2_0 + jj) << log2B) + l1lo] =
-                        mul(lds[lds_at((jj << log2n1) + l1)], tw_grid_join(w[u], +1));
+                        mul(res[lds_at((jj << log2n1) + l1)], tw_grid_join(w[u], +1));
                 }
             }
         }
-        ctx.sync();
     }
 }
 

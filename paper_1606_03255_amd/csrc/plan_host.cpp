@@ -434,6 +434,35 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
     return FLT_OK;
 }
 
+// Workgroups are handed to the 8 XCDs of the GPU in turn (launch slot i on XCD
+// i mod 8), each XCD with an L2 of its own.  Neighbouring pass-A items of a
+// band (consecutive j2 blocks) share the cache lines of c (and, adjoint, of the
+// accumulator) when a block holds fewer j2 than a 128-byte line holds
+// elements: g = 128 / (b S) items per line.  Within every run of 8 g slots of
+// one band, slot i takes item x g + i / 8 (x = i mod 8), so that the g items
+// sharing lines run on one XCD.
+static constexpr int NUM_XCD = 8;
+static void xcd_order(const HostPlan& hp, std::vector<FftItem>& v)
+{
+    const int S = (int)hp.elem_bytes();
+    std::vector<FftItem> out(v);
+    size_t i = 0;
+    while (i < v.size()) {
+        const BandDesc& B = hp.bands[v[i].band];
+        const int g = std::max(1, 128 / (S << B.log2b));
+        const size_t run = (size_t)NUM_XCD * g;
+        bool same = g > 1 && i + run <= v.size() && i % NUM_XCD == 0;
+        for (size_t u = 1; same && u < run; ++u) same = v[i + u].band == v[i].band && v[i + u].blk == v[i].blk + (int)u;
+        if (!same) {
+            ++i;
+            continue;
+        }
+        for (size_t u = 0; u < run; ++u) out[i + u] = v[i + (u % NUM_XCD) * g + u / NUM_XCD];
+        i += run;
+    }
+    v.swap(out);
+}
+
 // Launch groups (FFT lists sorted by transform length, one compile-time kernel
 // instance per length) and the workspace layout.
 static void finish(HostPlan& hp)
@@ -454,6 +483,8 @@ static void finish(HostPlan& hp)
     group(hp.onepass_adj, hp.g_onepass_adj, 0);
     group(hp.passA_fwd, hp.g_passA_fwd, 0);   // pass A instances are per grid length
     group(hp.passA_adj, hp.g_passA_adj, 0);
+    xcd_order(hp, hp.passA_fwd);
+    xcd_order(hp, hp.passA_adj);
     group(hp.passB, hp.g_passB, 2);
     group(hp.onepass_fused, hp.g_onepass_fused, 0);
     group(hp.passB_fused, hp.g_passB_fused, 2);
