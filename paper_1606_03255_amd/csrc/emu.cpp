@@ -278,8 +278,14 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
         for (const LaunchGroup& g : hp.g_passA_adj)
             with_log2<LP + 1, TW2_LOG2>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
-                    body_passA_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_adj.data() + g.start,
-                                                                    scratch.data(), acc.data(), lds.data(), lc.data());
+                    if constexpr (sizeof(T) == 4)
+                        body_passA_adj<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_adj.data() + g.start,
+                                                                        scratch.data(), acc.data(), lds2.data(),
+                                                                        lc2.data(), omega.data());
+                    else
+                        body_passA_adj_1tile<HostCtx, T, decltype(LG)::value>(ctx, pv, hp.passA_adj.data() + g.start,
+                                                                              scratch.data(), acc.data(), lds.data(),
+                                                                              lc.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_onepass_adj)

@@ -143,31 +143,29 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_adj(PlanView<T> pv, 
     });
 }
 
-template <typename T>
-__device__ __forceinline__ void passA_adj_kernel(const PlanView<T>& pv, const FftItem* items, const cplx<T>* scratch,
-                                                 double* acc)
-{
-    __shared__ cplx<T> lds[tile_alloc<T>()];
-    __shared__ alignas(16) T lc[Sizes<T>::COEF];
-    using RG = Log2Range<T>;
-    with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_passA_adj<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc);
-    });
-}
-
-// FP32: held to four waves per SIMD (two workgroups per CU, as the LDS
-// allows); a few of the per-point column sums then live in scratch.  FP64
-// would spill far more and keeps the compiler's own choice.
-__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_passA_adj_f32(
+// FP32: the adjoint pass A with a workgroup per CU (two waves per SIMD, two
+// LDS tiles); FP64: the one-tile variant, compiler's register choice.
+__global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_passA_adj_f32(
     PlanView<float> pv, const FftItem* items, const cplx<float>* scratch, double* acc)
 {
-    passA_adj_kernel<float>(pv, items, scratch, acc);
+    __shared__ cplx<float> lds[2 * tile_alloc<float>()];
+    __shared__ alignas(16) float lc[2 * Sizes<float>::COEF];
+    __shared__ cplx<float> omega[passA_omega_alloc<float>()];
+    using RG = Log2Range<float>;
+    with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
+        body_passA_adj<DevCtx, float, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc, omega);
+    });
 }
 
 __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj_f64(PlanView<double> pv, const FftItem* items,
                                                                   const cplx<double>* scratch, double* acc)
 {
-    passA_adj_kernel<double>(pv, items, scratch, acc);
+    __shared__ cplx<double> lds[tile_alloc<double>()];
+    __shared__ alignas(16) double lc[Sizes<double>::COEF];
+    using RG = Log2Range<double>;
+    with_log2<RG::TWO_LO, RG::TWO_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
+        body_passA_adj_1tile<DevCtx, double, decltype(LG)::value>(DevCtx(), pv, items, scratch, acc, lds, lc);
+    });
 }
 
 template <typename T, bool DERIV>

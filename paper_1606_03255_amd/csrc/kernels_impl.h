@@ -281,21 +281,25 @@ struct StageTw<T, LOG2L, NSUB, SIGN, LOG2NS, true> {
 template <bool REG, typename T, int LOG2L, int NSUB, int SIGN> struct TwSel { using type = StageTw<T, LOG2L, NSUB, SIGN>; };
 template <typename T, int LOG2L, int NSUB, int SIGN> struct TwSel<false, T, LOG2L, NSUB, SIGN> { using type = TableTw<T>; };
 
-// One Stockham autosort radix-2^LR stage over NSUB contiguous transforms of
-// length 2^LOG2L, all geometry known at compile time, reading `src` and
-// writing `dst` (LDS).  In place (src == dst, INPLACE): reads, barrier,
-// writes, barrier; out of place: reads, writes, barrier.  Twiddles
-// e^{SIGN 2 pi i k r / (Ns R)} from the provider tw (TableTw or StageTw).
-template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, bool INPLACE, class TW>
-FLT_HD void fft_stage_io(const Ctx& ctx, const cplx<T>* src, cplx<T>* dst, const TW& tw)
+// The geometry of one Stockham stage: NB butterflies of radix R per thread.
+template <int LR, int LOG2L, int NSUB> struct StageGeo {
+    static constexpr int R = 1 << LR;
+    static constexpr int NBUT = (NSUB << LOG2L) >> LR;
+    static constexpr int NB = (NBUT + FFT_THREADS - 1) / FFT_THREADS;
+};
+
+// The read and butterfly half of a stage: v[i] receives butterfly i's R
+// outputs, whose tile elements are dsti[i] + r 2^LOG2NS (dsti[i] < 0: the
+// thread has no butterfly i).
+template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, class TW>
+FLT_HD void fft_stage_compute(const Ctx& ctx, const cplx<T>* src, const TW& tw,
+                              cplx<T> (&v)[StageGeo<LR, LOG2L, NSUB>::NB][1 << LR],
+                              int (&dsti)[StageGeo<LR, LOG2L, NSUB>::NB])
 {
     constexpr int R = 1 << LR;
-    constexpr int P = NSUB << LOG2L;
-    constexpr int NBUT = P >> LR;
+    constexpr int NBUT = StageGeo<LR, LOG2L, NSUB>::NBUT;
     constexpr int LOG2LQ = LOG2L - LR;
-    constexpr int NB = (NBUT + FFT_THREADS - 1) / FFT_THREADS;
-    cplx<T> v[NB][R];
-    int dsti[NB];
+    constexpr int NB = StageGeo<LR, LOG2L, NSUB>::NB;
     for (int i = 0; i < NB; ++i) {
         const int u = ctx.tid() + i * FFT_THREADS;
         dsti[i] = -1;
@@ -324,6 +328,21 @@ FLT_HD void fft_stage_io(const Ctx& ctx, const cplx<T>* src, cplx<T>* dst, const
             dsti[i] = (sub << LOG2L) + ((j >> LOG2NS) << (LOG2NS + LR)) + k;
         }
     }
+}
+
+// One Stockham autosort radix-2^LR stage over NSUB contiguous transforms of
+// length 2^LOG2L, all geometry known at compile time, reading `src` and
+// writing `dst` (LDS).  In place (src == dst, INPLACE): reads, barrier,
+// writes, barrier; out of place: reads, writes, barrier.  Twiddles
+// e^{SIGN 2 pi i k r / (Ns R)} from the provider tw (TableTw or StageTw).
+template <class Ctx, typename T, int LR, int LOG2L, int NSUB, int LOG2NS, int SIGN, bool INPLACE, class TW>
+FLT_HD void fft_stage_io(const Ctx& ctx, const cplx<T>* src, cplx<T>* dst, const TW& tw)
+{
+    constexpr int R = 1 << LR;
+    constexpr int NB = StageGeo<LR, LOG2L, NSUB>::NB;
+    cplx<T> v[NB][R];
+    int dsti[NB];
+    fft_stage_compute<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN>(ctx, src, tw, v, dsti);
     if constexpr (INPLACE) ctx.sync();
     for (int i = 0; i < NB; ++i) {
         if (dsti[i] < 0) continue;
@@ -373,6 +392,39 @@ FLT_HD cplx<T>* lds_fft_pp(const Ctx& ctx, cplx<T>* a, cplx<T>* b, const TW& tw)
         return lds_fft_pp<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, b, a, tw.next());
     } else {
         return a;
+    }
+}
+
+// Radix (log2) of the last stage of the DFTs run from stage LOG2NS on.
+constexpr int last_stage_lr(int log2l, int log2ns, int maxr)
+{
+    int rem = log2l - log2ns;
+    for (;;) {
+        const int r = next_radix_log2(rem, maxr);
+        if (r == rem) return r;
+        rem -= r;
+    }
+}
+
+// The same DFTs from stage LOG2NS on with two LDS tiles in turn, the last
+// stage kept in registers: fin(v, dsti) receives its outputs (the butterflies
+// of fft_stage_compute at the last stage's geometry).  Returns the tile the
+// last stage read.
+template <class Ctx, typename T, int LOG2L, int NSUB, int SIGN, int LOG2NS, class TW, class FIN>
+FLT_HD cplx<T>* lds_fft_pp_last_regs(const Ctx& ctx, cplx<T>* a, cplx<T>* b, const TW& tw, FIN&& fin)
+{
+    constexpr int REM = LOG2L - LOG2NS;
+    constexpr int LR = next_radix_log2(REM, MaxRadix<T>::LOG2);
+    if constexpr (LR == REM) {
+        constexpr int NB = StageGeo<LR, LOG2L, NSUB>::NB;
+        cplx<T> v[NB][1 << LR];
+        int dsti[NB];
+        fft_stage_compute<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN>(ctx, a, tw, v, dsti);
+        fin(v, dsti);
+        return a;
+    } else {
+        fft_stage_io<Ctx, T, LR, LOG2L, NSUB, LOG2NS, SIGN, false>(ctx, a, b, tw);
+        return lds_fft_pp_last_regs<Ctx, T, LOG2L, NSUB, SIGN, LOG2NS + LR>(ctx, b, a, tw.next(), fin);
     }
 }
 
@@ -1473,9 +1525,10 @@ FLT_HD void body_onepass_adj(const Ctx& ctx, const PlanView<T>& pv, const FftIte
 
 // Adjoint pass A: for b consecutive j2, all columns s: Y[j2][l1] e^{-2 pi i j2 l1 / n},
 // inverse-sign DFT over l1 -> j1, transposed contraction over s, deconvolved
-// once and added into acc.
+// once and added into acc.  The FP64 form's (one LDS tile; the FP32 form's is
+// body_passA_adj below).
 template <class Ctx, typename T, int LOG2N>
-FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+FLT_HD void body_passA_adj_1tile(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
                            const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc)
 {
     using G = TwoPassGeo<T, LOG2N>;
@@ -1556,6 +1609,151 @@ FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem*
         const int k = kp + (int)B.k0;
         if (k < 1 || k > B.kmax) continue;
         const cplx<T> a = lds[lds_at((jj << log2n1) + j1)];
+        const double d = (double)pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
+        ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)a.x);
+        ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)a.y);
+    }
+}
+
+// Adjoint pass A of the FP32 form: the transform of body_passA_adj_1tile with
+// the LDS of a workgroup per CU (two tiles in turn, two coefficient buffers)
+// and the last DFT stage kept in registers: the transposed contraction
+// sum_s t_k[s] Ghat_s(k) runs on the thread's last-stage outputs that lie in
+// the band's support (half of them, known at compile time as in pass A), its
+// sums held in registers across the columns.  Input twiddles as pass A's
+// output twiddles (the LDS power table for the larger grids).  Three barriers
+// per column.
+template <class Ctx, typename T, int LOG2N>
+FLT_HD void body_passA_adj(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
+                           const cplx<T>* scratch, double* acc, cplx<T>* lds, T* lc, cplx<T>* omega)
+{
+    static_assert(sizeof(T) == 4, "the FP32 form's adjoint pass A (FP64: body_passA_adj_1tile)");
+    using G = TwoPassGeo<T, LOG2N>;
+    using A = PassAGeo<T, LOG2N>;
+    constexpr int ITEMS = A::ITEMS;
+    constexpr int log2n1 = G::log2n1, log2n2 = G::log2n2, log2b = G::log2b, log2B = G::log2B;
+    constexpr int n = 1 << LOG2N;
+    constexpr int NSUB = 1 << log2b;
+    constexpr int LRL = last_stage_lr(log2n1, 0, MaxRadix<T>::LOG2);   // the last stage
+    constexpr int RL = 1 << LRL;
+    constexpr int LOG2NSL = log2n1 - LRL;
+    constexpr int NBL = StageGeo<LRL, log2n1, NSUB>::NB;
+    constexpr int COEF = Sizes<T>::COEF;
+    // output r of a last-stage butterfly is sub-transform element jl + r 2^LOG2NSL:
+    // in the support only for r <= RL/4 or r >= 3 RL/4 (r = RL/4 only at jl = 0)
+    auto live = [](int r) { return r <= RL / 4 || r >= 3 * RL / 4; };
+    const FftItem it = items[ctx.bid()];
+    const BandDesc B = pv.bands[it.band];
+    const int k0 = (int)B.k0, kmax = (int)B.kmax;
+    const int j2_0 = it.blk << log2b;
+    const int tid = ctx.tid();
+    cplx<T>* const tile[2] = {lds, lds + tile_alloc<T>()};
+    StageTw<T, log2n1, NSUB, -1> stw;
+    stw.load(ctx, pv.tw_stage);
+    const int o_l1lo = tid & ((1 << log2B) - 1);
+    const int o_jj = (tid >> log2B) & ((1 << log2b) - 1);
+    const int o_l1hi = tid >> (log2B + log2b);
+    cplx<T> tw_t = mk<T>(1, 0);
+    if constexpr (A::OMEGA > 0) {
+        static_assert(A::OMEGA <= PASSA_OMEGA_MAX && A::OMEGA <= FFT_THREADS, "input twiddle table size");
+        if (tid < A::OMEGA) {
+            const int jj = tid / ITEMS, i = tid % ITEMS;
+            omega[tid] = tw_grid_at(pv, (uint32_t)(j2_0 + jj) * (uint32_t)(A::DL * i), LOG2N, -1);
+        }
+        tw_t = tw_grid_at(pv, (uint32_t)(j2_0 + o_jj) * (uint32_t)((o_l1hi << log2B) + o_l1lo), LOG2N, -1);
+    }
+    stage_coef(ctx, pv, B, 0, lc);
+    // the thread's last-stage points: k (0 outside the support), sums
+    int kr[NBL][RL];
+    cplx<T> sum[NBL][RL];
+    {
+        constexpr int LOG2LQ = log2n1 - LRL;   // = LOG2NSL
+        for (int i = 0; i < NBL; ++i)
+            for (int r = 0; r < RL; ++r) {
+                sum[i][r] = mk<T>(0, 0);
+                kr[i][r] = 0;
+                const int u = tid + i * FFT_THREADS;
+                if (!live(r) || u >= StageGeo<LRL, log2n1, NSUB>::NBUT) continue;
+                const int jj = u >> LOG2LQ, jl = u & ((1 << LOG2LQ) - 1);
+                const int j1 = jl + (r << LOG2NSL);
+                kr[i][r] = passA_k(j2_0 + jj + (j1 << log2n2), n, k0, kmax);
+            }
+    }
+    ctx.sync();
+
+    cplx<T>* ld = tile[0];   // the tile the next column is loaded into
+    for (int s = 0; s < B.q; ++s) {
+        const cplx<T>* Y = scratch + B.scratch_off + ((int64_t)s << LOG2N);
+        if constexpr (A::OMEGA > 0) {
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int l1 = (o_l1hi << log2B) + o_l1lo + i * A::DL;
+                const cplx<T> v = Y[((l1 >> log2B) << (log2n2 + log2B)) + ((j2_0 + o_jj) << log2B) + o_l1lo];
+                ld[lds_at((o_jj << log2n1) + l1)] = mul(v, mul(tw_t, omega[o_jj * ITEMS + i]));
+            }
+        } else {
+            constexpr int GI = 8;
+#pragma unroll 1
+            for (int i0 = 0; i0 < ITEMS; i0 += GI) {
+                cplx<T> v[GI];
+                TwPair<T> w[GI];
+                for (int u = 0; u < GI; ++u) {
+                    const int p = tid + (i0 + u) * FFT_THREADS;
+                    const int l1lo = p & ((1 << log2B) - 1);
+                    const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                    const int l1hi = p >> (log2B + log2b);
+                    const int l1 = (l1hi << log2B) + l1lo;
+                    v[u] = Y[(l1hi << (log2n2 + log2B)) + ((j2_0 + jj) << log2B) + l1lo];
+                    w[u] = tw_grid_fetch(pv, (uint32_t)(j2_0 + jj) * (uint32_t)l1, LOG2N);
+                }
+                for (int u = 0; u < GI; ++u) {
+                    const int p = tid + (i0 + u) * FFT_THREADS;
+                    const int l1lo = p & ((1 << log2B) - 1);
+                    const int jj = (p >> log2B) & ((1 << log2b) - 1);
+                    const int l1 = ((p >> (log2B + log2b)) << log2B) + l1lo;
+                    ld[lds_at((jj << log2n1) + l1)] = mul(v[u], tw_grid_join(w[u], -1));
+                }
+            }
+        }
+        ctx.sync();
+        // the next column's coefficients (the other buffer was last read by
+        // the previous column's contraction, before the barrier above)
+        if (s + 1 < B.q) stage_coef(ctx, pv, B, s + 1, lc + ((s + 1) & 1) * COEF);
+        const T* lcs = lc + (s & 1) * COEF;
+        cplx<T>* const other = ld == tile[0] ? tile[1] : tile[0];
+        cplx<T>* const last = lds_fft_pp_last_regs<Ctx, T, log2n1, NSUB, -1, 0>(
+            ctx, ld, other, stw, [&](cplx<T> (&v)[NBL][RL], int (&dsti)[NBL]) {
+                for (int i = 0; i < NBL; ++i)
+                    for (int r = 0; r < RL; ++r) {
+                        if (!live(r) || dsti[i] < 0) continue;
+                        const int k = kr[i][r];
+                        const T w = k ? laplace_row_lds(lcs, B, k) : T(0);   // deconvolved once, below
+                        sum[i][r].x += v[i][r].x * w;
+                        sum[i][r].y += v[i][r].y * w;
+                    }
+            });
+        ld = last == tile[0] ? tile[1] : tile[0];
+    }
+    // the sums leave through LDS (the tile the last stage did not read), re-read
+    // with the b sub-transforms (consecutive k) fastest, so that a wave's
+    // atomics fall on runs of consecutive coefficients
+    for (int i = 0; i < NBL; ++i)
+        for (int r = 0; r < RL; ++r) {
+            const int u = tid + i * FFT_THREADS;
+            if (!live(r) || u >= StageGeo<LRL, log2n1, NSUB>::NBUT) continue;
+            const int jj = u >> LOG2NSL, jl = u & ((1 << LOG2NSL) - 1);
+            ld[lds_at((jj << log2n1) + jl + (r << LOG2NSL))] = sum[i][r];
+        }
+    ctx.sync();
+    for (int i = 0; i < ITEMS; ++i) {
+        const int r = tid + i * FFT_THREADS;
+        const int jj = r & ((1 << log2b) - 1);
+        const int j1 = r >> log2b;
+        const int j = j2_0 + jj + (j1 << log2n2);
+        const int k = passA_k(j, n, k0, kmax);
+        if (!k) continue;
+        const int kp = j < (n >> 1) ? j : j - n;
+        const cplx<T> a = ld[lds_at((jj << log2n1) + j1)];
         const double d = (double)pv.deconv[B.deconv_off + (kp < 0 ? -kp : kp)];
         ctx.atomic_add(acc + 2 * (B.c_off + k), d * (double)a.x);
         ctx.atomic_add(acc + 2 * (B.c_off + k) + 1, d * (double)a.y);
