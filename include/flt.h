@@ -53,13 +53,14 @@ typedef struct flt_plan flt_plan;
                                         cost more than summing its few nodes directly is summed exactly */
 #define FLT_FLAG_GRAPH     (1u << 2) /* capture each operation's launch sequence into a hipGraph on its first call
                                         (and again whenever the buffers or the workspace change) and replay it */
-#define FLT_FLAG_AUTOTUNE  (1u << 3) /* choose the band policy by timing: candidate plans (the direct-sum rate of
-                                        the policy scaled by 0, 1/2, 1, 2, 4, 8; distinct band choices only) run
-                                        forward + adjoint on the device during creation, all of them twice (the
-                                        first pass a warm-up); in that order, each replaces the choice only when
-                                        at least 5% faster;
-                                        the choice is cached per (objective, dtype, eps, instances, size class)
-                                        for the process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
+#define FLT_FLAG_AUTOTUNE  (1u << 3) /* choose the plan's shape by timing forward + adjoint of candidates on the
+                                        device during creation, one dimension after the other: the band policy
+                                        (direct-sum rate scaled by 0, 1/2, 1, 2, 4, 8; distinct band choices
+                                        only), then workgroups per CU of the persistent pass B (2, 1, 3, 4).
+                                        All candidates are timed twice (the first pass a warm-up); in that
+                                        order each replaces the choice only when at least 5% faster.  The
+                                        choice is cached per (objective, dtype, eps, instances, size class) for
+                                        the process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
 #define FLT_FLAG_TUNE_FORWARD (1u << 4) /* with FLT_FLAG_AUTOTUNE: time the forward alone (plans used for
                                         evaluation only); without it forward + adjoint (training steps) */
 
@@ -91,6 +92,8 @@ typedef struct flt_info {
     double flops_forward;    /* algorithmic flops of one forward call */
     double direct_scale;     /* factor on the direct-sum rate the band policy used (1, or the tuned choice) */
     size_t forward_scratch_bytes; /* device scratch of one forward call alone (see flt_forward_noalloc) */
+    int32_t passB_blocks;    /* workgroups of the persistent pass B (0 for a host-only plan) */
+    int32_t pad;
 } flt_info;
 
 /* One occupied band (Def. 3.2 Y_m, or Y_D). */

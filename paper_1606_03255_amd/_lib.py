@@ -41,6 +41,8 @@ class FltInfo(ctypes.Structure):
         ("y1", ctypes.c_double), ("nodes_z0", ctypes.c_int64), ("workspace_bytes", ctypes.c_size_t),
         ("bytes_forward", ctypes.c_double), ("flops_forward", ctypes.c_double), ("direct_scale", ctypes.c_double),
         ("forward_scratch_bytes", ctypes.c_size_t),
+        ("passB_blocks", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
     ]
 
 

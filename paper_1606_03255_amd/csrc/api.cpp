@@ -103,11 +103,11 @@ static int upload(flt_plan* p)
     const size_t o_ny = pk.add(hp.ny.data(), hp.ny.size() * sizeof(double));
     const size_t o_perm = pk.add(hp.perm.data(), hp.perm.size() * sizeof(int32_t));
     const size_t o_l0 = pk.add(hp.onepass_fwd.data(), hp.onepass_fwd.size() * sizeof(FftItem));
+    const size_t o_lf0 = pk.add(hp.onepass_fused.data(), hp.onepass_fused.size() * sizeof(FftItem));
     const size_t o_l1 = pk.add(hp.passA_fwd.data(), hp.passA_fwd.size() * sizeof(FftItem));
     const size_t o_l2 = pk.add(hp.passB.data(), hp.passB.size() * sizeof(FftItem));
     const size_t o_l3 = pk.add(hp.onepass_adj.data(), hp.onepass_adj.size() * sizeof(FftItem));
     const size_t o_l4 = pk.add(hp.passA_adj.data(), hp.passA_adj.size() * sizeof(FftItem));
-    const size_t o_lf0 = pk.add(hp.onepass_fused.data(), hp.onepass_fused.size() * sizeof(FftItem));
     const size_t o_lf2 = pk.add(hp.passB_fused.data(), hp.passB_fused.size() * sizeof(FftItem));
     const size_t o_l5 = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
     const size_t o_l6 = pk.add(hp.cells.data(), hp.cells.size() * sizeof(CellItem));
@@ -132,13 +132,14 @@ static int upload(flt_plan* p)
     p->pv64 = make_view<double>(hp, base, o_bands, o_coef, o_deconv, o_ycheb, o_tws, o_twl, o_twh, o_nx, o_ny, o_perm, o_mask, o_inst);
     DevLists& L = p->lists;
     L.onepass_fwd = (const FftItem*)(base + o_l0);
+    L.onepass_fused = (const FftItem*)(base + o_lf0);
+    L.n_onepass_fwd = (int)hp.onepass_fwd.size();
+    L.n_onepass_fused = (int)hp.onepass_fused.size();
     L.passA_fwd = (const FftItem*)(base + o_l1);
     L.passB = (const FftItem*)(base + o_l2);
     L.onepass_adj = (const FftItem*)(base + o_l3);
     L.passA_adj = (const FftItem*)(base + o_l4);
-    L.onepass_fused = (const FftItem*)(base + o_lf0);
     L.passB_fused = (const FftItem*)(base + o_lf2);
-    L.n_onepass_fused = (int)hp.onepass_fused.size();
     L.n_passB_fused = (int)hp.passB_fused.size();
     L.nodes = (const NodeItem*)(base + o_l5);
     L.cells = (const CellItem*)(base + o_l6);
@@ -151,9 +152,9 @@ static int upload(flt_plan* p)
     L.sum_items = (const SumItem*)(base + o_sum);
     L.n_sum = (int)hp.sum_items.size();
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0) {
         L.persist_blocks = 2 * cus;
-    L.n_onepass_fwd = (int)hp.onepass_fwd.size();
+    }
     L.n_passA_fwd = (int)hp.passA_fwd.size();
     L.n_passB = (int)hp.passB.size();
     L.n_onepass_adj = (int)hp.onepass_adj.size();
@@ -178,16 +179,27 @@ static const uint32_t KNOWN_FLAGS =
 static void release(flt_plan* p);
 static hipError_t enqueue(flt_plan* p, int op, const void* in, void* out, void* out2, hipStream_t st);
 
-// FLT_FLAG_AUTOTUNE: the band policy's direct-sum rate factor chosen by timing
-// forward + adjoint (FLT_FLAG_TUNE_FORWARD: the forward alone) of candidate
-// plans (all of them timed twice, the first pass a warm-up), factors in
-// ascending order, each replacing the current choice only when at least 5%
-// faster; cached per (objective, dtype, eps, instances, size
-// class of sum N and sum M) for the life of the process.
+// FLT_FLAG_AUTOTUNE: a plan's shape chosen by timing forward + adjoint
+// (FLT_FLAG_TUNE_FORWARD: the forward alone) of candidates on the device, one
+// dimension after the other:
+//   1. the band policy's direct-sum rate factor (TUNE_SCALES, distinct band
+//      choices only, one plan each);
+//   2. workgroups per compute unit of the persistent pass B (TUNE_BLOCKS;
+//      launch shapes of one plan).
+// Every candidate of a step is timed twice, the first pass a warm-up; in the
+// listed order each replaces the current choice only when at least 5% faster,
+// so candidates within timing noise keep the first.  The result is cached per
+// (objective, dtype, eps, instances, size class of sum N and sum M) for the
+// life of the process.
 namespace {
 const double TUNE_SCALES[] = {0.0, 0.5, 1.0, 2.0, 4.0, 8.0};
+const int TUNE_BLOCKS[] = {2, 1, 3, 4};
+struct Tuned {
+    PlanShape shape;
+    int passB_per_cu = 2;
+};
 using TuneKey = std::tuple<int, int, double, int64_t, int, int>;
-std::map<TuneKey, double> g_tuned;
+std::map<TuneKey, Tuned> g_tuned;
 std::mutex g_tune_mu;
 
 int size_class(int64_t v)
@@ -195,6 +207,14 @@ int size_class(int64_t v)
     int r = 0;
     while (((int64_t)1 << r) < v) ++r;
     return r;
+}
+
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return 256;
+    return cus;
 }
 
 // Mean time (ms) of forward + adjoint (fwd_only: the forward) of an uploaded
@@ -243,12 +263,37 @@ int time_candidate(flt_plan* p, bool fwd_only, double* ms)
     if (st) (void)hipStreamDestroy(st);
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
+
+// Index of the first candidate that no later one beats by 5%.
+size_t pick(const std::vector<double>& ms)
+{
+    double best = 1e300;
+    size_t at = 0;
+    for (size_t i = 0; i < ms.size(); ++i)
+        if (ms[i] < 0.95 * best) {
+            best = ms[i];
+            at = i;
+        }
+    return at;
+}
 }  // namespace
 
-template <class Build> static int tuned_scale(uint32_t flags, Build&& build, double* scale)
+// Times the uploaded candidates twice (the first pass a warm-up) and returns
+// the pick, or a negative error code.
+static int time_and_pick(std::vector<flt_plan*>& cands, bool fwd_only, size_t* at)
+{
+    std::vector<double> ms(cands.size(), 0.0);
+    int rc = FLT_OK;
+    for (int pass = 0; pass < 2 && rc == FLT_OK; ++pass)
+        for (size_t i = 0; i < cands.size() && rc == FLT_OK; ++i) rc = time_candidate(cands[i], fwd_only, &ms[i]);
+    if (rc == FLT_OK) *at = pick(ms);
+    return rc;
+}
+
+template <class Build> static int tuned_shape(uint32_t flags, Build&& build, Tuned* out)
 {
     HostPlan probe;
-    int rc = build(probe, 1.0);
+    int rc = build(probe, PlanShape());
     if (rc != FLT_OK) return rc;
     const bool fwd_only = (flags & FLT_FLAG_TUNE_FORWARD) != 0;
     const TuneKey key{fwd_only ? 1 : 0, probe.dtype, probe.eps, (int64_t)probe.inst.size(), size_class(probe.N),
@@ -257,64 +302,82 @@ template <class Build> static int tuned_scale(uint32_t flags, Build&& build, dou
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            *scale = it->second;
+            *out = it->second;
             return FLT_OK;
         }
     }
-    // the distinct candidates (by their set of direct bands), uploaded
-    std::vector<std::vector<int>> seen;
+    const int cus = device_cus();
     std::vector<flt_plan*> cands;
-    std::vector<double> scales;
     auto release_all = [&]() {
         for (flt_plan* c : cands) release(c);
         cands.clear();
     };
-    for (double sc : TUNE_SCALES) {
+    // a candidate plan of the given shape, uploaded (nullptr and rc set on failure)
+    auto make = [&](const PlanShape& sh) -> flt_plan* {
         flt_plan* cand = new (std::nothrow) flt_plan();
         if (!cand) {
-            release_all();
-            return FLT_ENOMEM;
+            rc = FLT_ENOMEM;
+            return nullptr;
         }
-        rc = build(cand->hp, sc);
-        std::vector<int> sig;
-        for (const BandDesc& B : cand->hp.bands) sig.push_back(B.direct);
-        bool dup = false;
-        for (const auto& v : seen) dup = dup || v == sig;
-        if (rc == FLT_OK && !dup) {
-            seen.push_back(sig);
+        rc = build(cand->hp, sh);
+        if (rc == FLT_OK) {
             cand->host_only = false;
             rc = upload(cand);
-            if (rc == FLT_OK) {
-                cands.push_back(cand);
-                scales.push_back(sc);
-                continue;
-            }
+        }
+        if (rc != FLT_OK) {
+            release(cand);
+            return nullptr;
+        }
+        cand->lists.persist_blocks = 2 * cus;
+        return cand;
+    };
+    Tuned best;
+    size_t at = 0;
+    // 1. the band policy: distinct sets of direct bands only
+    {
+        std::vector<std::vector<int>> seen;
+        std::vector<double> scales;
+        for (double sc : TUNE_SCALES) {
+            HostPlan hp;
+            PlanShape sh;
+            sh.direct_scale = sc;
+            rc = build(hp, sh);
+            if (rc != FLT_OK) break;
+            std::vector<int> sig;
+            for (const BandDesc& B : hp.bands) sig.push_back(B.direct);
+            bool dup = false;
+            for (const auto& v : seen) dup = dup || v == sig;
+            if (dup) continue;
+            seen.push_back(sig);
+            flt_plan* cand = make(sh);
+            if (!cand) break;
+            cands.push_back(cand);
+            scales.push_back(sc);
+        }
+        if (rc == FLT_OK) rc = time_and_pick(cands, fwd_only, &at);
+        release_all();
+        if (rc != FLT_OK) return rc;
+        best.shape.direct_scale = scales[at];
+    }
+    // 2. workgroups per compute unit of the persistent pass B
+    {
+        flt_plan* cand = make(best.shape);
+        if (!cand) return rc;
+        std::vector<double> ms;
+        for (int b : TUNE_BLOCKS) {
+            cand->lists.persist_blocks = b * cus;
+            double t = 0;
+            for (int pass = 0; pass < 2 && rc == FLT_OK; ++pass) rc = time_candidate(cand, fwd_only, &t);
+            if (rc != FLT_OK) break;
+            ms.push_back(t);
         }
         release(cand);
-        if (rc != FLT_OK) {
-            release_all();
-            return rc;
-        }
+        if (rc != FLT_OK) return rc;
+        best.passB_per_cu = TUNE_BLOCKS[pick(ms)];
     }
-    // two passes over all of them; the first only warms the device (clocks,
-    // caches), so that no candidate is timed colder than another
-    std::vector<double> ms(cands.size(), 0.0);
-    for (int pass = 0; pass < 2 && rc == FLT_OK; ++pass)
-        for (size_t i = 0; i < cands.size() && rc == FLT_OK; ++i) rc = time_candidate(cands[i], fwd_only, &ms[i]);
-    release_all();
-    if (rc != FLT_OK) return rc;
-    // a later (larger) factor replaces the choice only when clearly faster:
-    // candidates within timing noise keep the first, so the choice does not
-    // flip between runs
-    double best = 1e300;
-    *scale = 1.0;
-    for (size_t i = 0; i < ms.size(); ++i)
-        if (ms[i] < 0.95 * best) {
-            best = ms[i];
-            *scale = scales[i];
-        }
+    *out = best;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[key] = *scale;
+    g_tuned[key] = best;
     return FLT_OK;
 }
 
@@ -323,11 +386,12 @@ template <class Build> static int create(flt_plan** out, uint32_t flags, Build&&
     if (!out) return FLT_EINVAL;
     *out = nullptr;
     if (flags & ~KNOWN_FLAGS) return FLT_EINVAL;
-    double scale = 1.0;
-    if ((flags & FLT_FLAG_AUTOTUNE) && !(flags & (FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY))) {
+    Tuned tuned;
+    const bool tune = (flags & FLT_FLAG_AUTOTUNE) && !(flags & (FLT_FLAG_HOST_ONLY | FLT_FLAG_NFFT_ONLY));
+    if (tune) {
         int rc;
         try {
-            rc = tuned_scale(flags, build, &scale);
+            rc = tuned_shape(flags, build, &tuned);
         } catch (const std::bad_alloc&) {
             rc = FLT_ENOMEM;
         }
@@ -337,13 +401,17 @@ template <class Build> static int create(flt_plan** out, uint32_t flags, Build&&
     if (!p) return FLT_ENOMEM;
     int rc;
     try {
-        rc = build(p->hp, scale);
+        rc = build(p->hp, tuned.shape);
     } catch (const std::bad_alloc&) {
         rc = FLT_ENOMEM;
     }
     if (rc == FLT_OK && !(flags & FLT_FLAG_HOST_ONLY)) {
         p->host_only = false;
         rc = upload(p);
+        if (rc == FLT_OK) {
+            const int cus = device_cus();
+            p->lists.persist_blocks = tuned.passB_per_cu * cus;
+        }
         if (rc == FLT_OK && (flags & FLT_FLAG_GRAPH)) {
             const hipError_t e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
             if (e != hipSuccess) rc = hip_fail(e);
@@ -371,16 +439,16 @@ extern "C" {
 
 int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
 {
-    return create(out, flags, [&](HostPlan& hp, double scale) {
-        return build_host_plan(hp, N, M, z, eps, dtype, flags, scale);
+    return create(out, flags, [&](HostPlan& hp, const PlanShape& shape) {
+        return build_host_plan(hp, N, M, z, eps, dtype, flags, shape);
     });
 }
 
 int flt_plan_create_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M, const double* z,
                           double eps, int dtype, uint32_t flags)
 {
-    return create(out, flags, [&](HostPlan& hp, double scale) {
-        return build_batch_plan(hp, count, N, M, z, eps, dtype, flags, scale);
+    return create(out, flags, [&](HostPlan& hp, const PlanShape& shape) {
+        return build_batch_plan(hp, count, N, M, z, eps, dtype, flags, shape);
     });
 }
 
@@ -411,6 +479,7 @@ int flt_plan_info(const flt_plan* p, flt_info* o)
     o->flops_forward = hp.flops_forward;
     o->direct_scale = hp.direct_scale;
     o->forward_scratch_bytes = hp.fwd_ws_bytes;
+    o->passB_blocks = p->lists.persist_blocks;
     return FLT_OK;
 }
 

@@ -144,8 +144,9 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
                      cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0, cplx<T>* f2)
 {
     if (!adjoint) {
+        std::vector<cplx<T>> stage(GATHER_STAGE<T>());
         run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-            body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0, f2);
+            body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0, f2, stage.data());
         });
         return;
     }
@@ -190,6 +191,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
     std::vector<cplx<T>> lds(tile_alloc<T>());
     std::vector<T> lc(Sizes<T>::COEF);
+    std::vector<T> lc1(onepass_coef<T>());   // the one-pass FFT's staged coefficients
     std::vector<cplx<T>> lds2(2 * tile_alloc<T>());   // the FP32 pass A's two tiles and coefficient buffers
     std::vector<T> lc2(2 * Sizes<T>::COEF);
     std::vector<cplx<T>> omega(PASSA_OMEGA_MAX);
@@ -214,7 +216,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             with_log2<4, LP>(g.log2, [&](auto LG) {
                 run_blocks(g.count, FFT_THREADS, [&](const HostCtx& ctx) {
                     body_onepass_fwd<HostCtx, T, decltype(LG)::value>(ctx, pv, one.data() + g.start, c,
-                                                                      grids.data(), deriv, cols, lds.data());
+                                                                      grids.data(), deriv, cols, lds.data(),
+                                                                      lc1.data());
                 });
             });
         for (const LaunchGroup& g : hp.g_passA_fwd)

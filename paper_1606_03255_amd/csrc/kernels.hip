@@ -43,6 +43,10 @@ static_assert(lds_passA_f64_bytes() <= LDS_TWO_PER_CU, "two FP64 pass-A workgrou
 static_assert(lds_fft_bytes<float>() + sizeof(float) * Sizes<float>::COEF <= LDS_TWO_PER_CU &&
                   lds_fft_bytes<double>() + sizeof(double) * Sizes<double>::COEF <= LDS_TWO_PER_CU,
               "a tile and a coefficient buffer leave room for a second workgroup per CU");
+static_assert(lds_fft_bytes<float>() + sizeof(float) * onepass_coef<float>() <= LDS_TWO_PER_CU &&
+                  lds_fft_bytes<double>() + sizeof(double) * onepass_coef<double>() <= LDS_TWO_PER_CU &&
+                  onepass_coef<double>() >= 2 * MAX_Q * 16,
+              "one-pass FFT: tile and staged coefficients, two workgroups per CU");
 
 // One launch per FFT kind; each workgroup picks the compile-time instance of
 // its band's transform length.
@@ -52,9 +56,10 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_onepass_fwd(PlanView<T> pv, 
                                                                 int cols)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
+    __shared__ alignas(16) T lc[onepass_coef<T>()];
     using RG = Log2Range<T>;
     with_log2<RG::ONE_LO, RG::ONE_HI>(pv.bands[items[blockIdx.x].band].log2n, [&](auto LG) {
-        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, cols, lds);
+        body_onepass_fwd<DevCtx, T, decltype(LG)::value>(DevCtx(), pv, items, c, grids, deriv, cols, lds, lc);
     });
 }
 
@@ -104,7 +109,8 @@ __global__ __launch_bounds__(GATHER_THREADS) void k_gather(PlanView<T> pv, const
                                                            const cplx<T>* grids, cplx<T>* f, int with_c0,
                                                            cplx<T>* f2)
 {
-    body_gather<DevCtx, T, MW>(DevCtx(), pv, items, c, grids, f, with_c0, f2);
+    __shared__ cplx<T> stage[GATHER_STAGE<T>()];
+    body_gather<DevCtx, T, MW>(DevCtx(), pv, items, c, grids, f, with_c0, f2, stage);
 }
 
 template <typename T, int MW>
@@ -231,7 +237,6 @@ static void fft_forward_stages(LaunchStatus& ls, const DevLists& L, const PlanVi
     const int n_one = cols == 2 ? L.n_onepass_fused : L.n_onepass_fwd;
     const FftItem* pb = cols == 2 ? L.passB_fused : L.passB;
     const int n_pb = cols == 2 ? L.n_passB_fused : L.n_passB;
-    mark(ls, ev, 0, st);
     if (n_one) {
         hipLaunchKernelGGL(k_onepass_fwd<T>, dim3(n_one), dim3(FFT_THREADS), 0, st, pv, one, c, grids, deriv, cols);
         ls.launched();
@@ -329,6 +334,7 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
     if (pv.mw < 2 || pv.mw > MAX_MW) return hipErrorInvalidValue;
     cplx<T>* grids = (cplx<T>*)(W.ws + W.off_grid);
     double* dacc = (double*)(W.ws + W.off_dacc);
+    mark(ls, ev, 0, st);
     fft_forward_stages<T>(ls, L, pv, W, c, deriv, cols, st, ev);
     if (L.n_nodes) {
         switch (pv.mw) {

@@ -511,24 +511,64 @@ FLT_HD double frac_kx(double k, double x)
 // cols = 2 (forward and derivative in one pass): the band has 2q columns,
 // column q + s being column s of the derivative transform; the band's grid
 // region is then twice as long (offsets doubled).
+// LDS beside the tile for the staged coefficients: what keeps the pair under
+// 80 KB (two workgroups per compute unit).
+template <typename T> constexpr int onepass_coef() { return (80 * 1024 - (int)sizeof(cplx<T>) * tile_alloc<T>()) / (int)sizeof(T); }
+
+// When the Chebyshev coefficients of all the workgroup's columns (every block
+// of the band, see stage_coef) fit lc together, they are staged there first;
+// otherwise the generation reads them from global memory (more passes of
+// staging, each behind a barrier, cost more than they save).
 template <class Ctx, typename T, int LOG2N>
 FLT_HD void body_onepass_fwd(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items,
-                             const cplx<T>* c, cplx<T>* grids, int deriv, int cols, cplx<T>* lds)
+                             const cplx<T>* c, cplx<T>* grids, int deriv, int cols, cplx<T>* lds, T* lc)
 {
     // columns per workgroup: a full tile, but never more than a band has (q <= MAX_Q)
     constexpr int NSUB = (tile_points<T>() >> LOG2N) < MAX_Q ? (tile_points<T>() >> LOG2N) : MAX_Q;
     constexpr int P = NSUB << LOG2N;
+    constexpr int n = 1 << LOG2N;
     const FftItem it = items[ctx.bid()];
     const BandDesc& B = pv.bands[it.band];
     StageTw<T, LOG2N, NSUB, +1> stw;
     stw.load(ctx, pv.tw_stage);
-    for (int p = ctx.tid(); p < P; p += FFT_THREADS) {
-        const int sl = p >> LOG2N;
+    auto column = [&](int sl, bool& dcol) {   // band column of tile column sl
         const int s = it.s0 + sl;
-        const bool dcol = s >= B.q;   // a derivative column (cols = 2)
-        lds[lds_at(p)] = sl < it.ns ? grid_input(pv, B, c, dcol ? s - B.q : s, p & ((1 << LOG2N) - 1),
-                                                 deriv || dcol)
-                                    : mk<T>(0, 0);
+        dcol = s >= B.q;   // a derivative column (cols = 2)
+        return dcol ? s - B.q : s;
+    };
+    const int nblk = B.ell_hi - B.ell_lo + 1;
+    const int per_col = nblk > 0 ? nblk * coef_stride(B.q, CoefVec<T>::N) : 0;
+    const int cpc = per_col == 0 ? it.ns : onepass_coef<T>() / per_col >= it.ns ? it.ns : 0;
+    // the padding columns of the tile: zeros
+    for (int p = (it.ns << LOG2N) + ctx.tid(); p < P; p += FFT_THREADS) lds[lds_at(p)] = mk<T>(0, 0);
+    if (cpc == 0) {
+        for (int p = ctx.tid(); p < (it.ns << LOG2N); p += FFT_THREADS) {
+            bool dcol;
+            const int s = column(p >> LOG2N, dcol);
+            lds[lds_at(p)] = grid_input(pv, B, c, s, p & (n - 1), deriv || dcol);
+        }
+    } else {
+        if (per_col > 0) {
+            for (int sl = 0; sl < it.ns; ++sl) {
+                bool dcol;
+                stage_coef(ctx, pv, B, column(sl, dcol), lc + sl * per_col);
+            }
+            ctx.sync();
+        }
+        for (int p = ctx.tid(); p < (it.ns << LOG2N); p += FFT_THREADS) {
+            const int sl = p >> LOG2N;
+            bool dcol;
+            column(sl, dcol);
+            const int j = p & (n - 1);
+            const int kp = j < (n >> 1) ? j : j - n;
+            const int k = kp + (int)B.k0;
+            cplx<T> v = mk<T>(0, 0);
+            if (k >= 1 && k <= B.kmax) {
+                v = point_base(pv, B, c, kp, k, deriv || dcol);
+                if (per_col > 0) v = scale(v, laplace_row_lds(lc + sl * per_col, B, k));
+            }
+            lds[lds_at(p)] = v;
+        }
     }
     ctx.sync();
     lds_fft_ct<Ctx, T, LOG2N, NSUB, +1>(ctx, lds, stw);
@@ -1035,44 +1075,107 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
 // ---------------------------------------------------------------------------
 // Window and node weights
 // ---------------------------------------------------------------------------
+// Hardware reciprocal, square root and 2^x in FP32 (about 1 ulp); the CPU
+// build uses the correctly rounded library forms.
+FLT_HD float rcp_f32(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+FLT_HD float sqrt_f32(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+FLT_HD float exp2_f32(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_exp2f(x);
+#else
+    return exp2f(x);
+#endif
+}
+
 // Kaiser-Bessel window at grid offsets u_t = delta + mw - 1 - t, t < 2 mw:
-// phi = sinh(b v) / (pi v), v = sqrt(mw^2 - u^2).
+// phi = sinh(b v) / (pi v), v = sqrt(mw^2 - u^2).  FP32: sinh(b v) =
+// (e - 1/e) / 2 with e = 2^(b log2(e) v); the cancellation for small b v only
+// touches the edge taps, whose weights are about 1e-9 of the central ones.
 template <typename T, int MW>
 FLT_HD void kb_weights(T delta, T b, T* phi)
 {
     const T inv_pi = T(0.31830988618379067153776752674503);
-    for (int t = 0; t < 2 * MW; ++t) {
-        const T u = delta + T(MW - 1 - t);
-        const T v2 = T(MW * MW) - u * u;
-        const T v = v2 > T(0) ? (T)sqrt(v2) : T(0);
-        phi[t] = v > T(0) ? (T)sinh(b * v) / v * inv_pi : b * inv_pi;
+    if constexpr (sizeof(T) == 4) {
+        const float bl2e = b * 1.4426950408889634f;
+        for (int t = 0; t < 2 * MW; ++t) {
+            const float u = delta + float(MW - 1 - t);
+            const float v2 = float(MW * MW) - u * u;
+            const float v = v2 > 0.0f ? sqrt_f32(v2) : 0.0f;
+            const float e = exp2_f32(bl2e * v);
+            phi[t] = v > 0.0f ? (e - rcp_f32(e)) * (0.5f * inv_pi) * rcp_f32(v) : b * inv_pi;
+        }
+    } else {
+        for (int t = 0; t < 2 * MW; ++t) {
+            const T u = delta + T(MW - 1 - t);
+            const T v2 = T(MW * MW) - u * u;
+            const T v = v2 > T(0) ? (T)sqrt(v2) : T(0);
+            phi[t] = v > T(0) ? (T)sinh(b * v) / v * inv_pi : b * inv_pi;
+        }
     }
 }
 
-// Barycentric weights on the band's q Chebyshev nodes (Sect. 2), FP64:
+// Barycentric weights on the band's q Chebyshev nodes (Sect. 2):
 // L_s(y) = (lambda_s / (y - y_s)) / sum_r lambda_r / (y - y_r); a node hit gives
-// the Kronecker delta.  bary_setup returns 1/sum (or 0 with *hit set).
-struct BaryY {
-    double inv;
+// the Kronecker delta.  bary_setup returns 1/sum (or 0 with hit set).  FP64
+// for the FP64 form; FP32 for the FP32 form, from the differences y - y_s
+// formed in FP64 (the second barycentric form is stable at Chebyshev nodes,
+// also for y next to a node).
+template <typename W> struct BaryY {
+    W inv;
     int hit;
 };
-FLT_HD BaryY bary_setup(const double* yc, int q, double y)
+template <typename W> FLT_HD BaryY<W> bary_setup(const double* yc, int q, double y)
 {
-    BaryY r;
+    BaryY<W> r;
     r.hit = -1;
-    double sum = 0;
+    W sum = 0;
     for (int s = 0; s < q; ++s) {
         const double d = y - yc[2 * s];
         if (d == 0.0) r.hit = s;
+        else if constexpr (sizeof(W) == 4) sum += (float)yc[2 * s + 1] * rcp_f32((float)d);
         else sum += yc[2 * s + 1] / d;
     }
-    r.inv = r.hit >= 0 ? 0.0 : 1.0 / sum;
+    if constexpr (sizeof(W) == 4) r.inv = r.hit >= 0 ? 0.0f : rcp_f32(sum);
+    else r.inv = r.hit >= 0 ? 0.0 : 1.0 / sum;
     return r;
 }
-FLT_HD double bary_at(const double* yc, const BaryY& b, int s, double y)
+template <typename W> FLT_HD W bary_at(const double* yc, const BaryY<W>& b, int s, double y)
 {
-    if (b.hit >= 0) return s == b.hit ? 1.0 : 0.0;
-    return yc[2 * s + 1] / (y - yc[2 * s]) * b.inv;
+    if (b.hit >= 0) return s == b.hit ? W(1) : W(0);
+    if constexpr (sizeof(W) == 4) return (float)yc[2 * s + 1] * rcp_f32((float)(y - yc[2 * s])) * b.inv;
+    else return yc[2 * s + 1] / (y - yc[2 * s]) * b.inv;
+}
+
+// e^{sign 2 pi i k0 x} for a band centre k0 (0 or a power of two, so k0 x and
+// its fraction are exact in FP64); the sine and cosine of the reduced phase
+// in FP64 for the FP64 form, FP32 for the FP32 form.
+template <typename T> FLT_HD void modulation(double k0, double x, double* cs, double* sn)
+{
+    double ph = k0 * x;
+    ph -= rint(ph);   // in [-1/2, 1/2]
+    if constexpr (sizeof(T) == 4) {
+        float s, c;
+        sincosf(6.2831853071795864769f * (float)ph, &s, &c);
+        *cs = c;
+        *sn = s;
+    } else {
+        sincos(6.283185307179586476925286766559 * ph, sn, cs);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1081,65 +1184,134 @@ FLT_HD double bary_at(const double* yc, const BaryY& b, int s, double y)
 // ---------------------------------------------------------------------------
 // f2 != null (cols = 2): columns q .. 2q - 1 of each band hold the derivative
 // transform's grids, whose sums go to f2 (no c_0 term: c'_0 = 0).
+//
+// A workgroup's nodes are consecutive in the band's sorted order, so their
+// windows cover one run of the grid: the cells from l0(first) - mw + 1 to
+// l0(last) + mw.  When that run is short (dense bands: many nodes per cell)
+// the workgroup loads it once per column, coalesced, into LDS (as many columns
+// at a time as GATHER_STAGE values hold) and every node reads its taps there;
+// otherwise each node loads its own taps from the grid.
+template <typename T> constexpr int GATHER_STAGE() { return 2048; }
 template <class Ctx, typename T, int MW>
-FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items,
-                        const cplx<T>* c, const cplx<T>* grids, cplx<T>* f, int with_c0, cplx<T>* f2)
+FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items, const cplx<T>* c,
+                        const cplx<T>* grids, cplx<T>* f, int with_c0, cplx<T>* f2, cplx<T>* stage)
 {
     const NodeItem it = items[ctx.bid()];
     const int i = ctx.tid();
-    if (i >= it.count) return;
-    const int64_t jj = it.start + i;
+    const bool active = i < it.count;
+    const int64_t jj = it.start + (active ? i : 0);
     const BandDesc& B = pv.bands[it.band];
-    const int32_t dst = pv.perm[jj];
     const double c0r = with_c0 ? (double)c[B.c_off].x : 0.0;
     const double c0i = with_c0 ? (double)c[B.c_off].y : 0.0;
-    if (B.q == 0) {
-        f[dst] = mk<T>((T)c0r, (T)c0i);
-        if (f2) f2[dst] = mk<T>(0, 0);
+    if (B.q == 0) {   // the constant band (the whole item)
+        if (active) {
+            const int32_t dst = pv.perm[jj];
+            f[dst] = mk<T>((T)c0r, (T)c0i);
+            if (f2) f2[dst] = mk<T>(0, 0);
+        }
         return;
     }
     const double x = pv.nx[jj], y = pv.ny[jj];
     const int log2n = B.log2n;
-    const int64_t nmask = ((int64_t)1 << log2n) - 1;
+    const int nmask = (1 << log2n) - 1;
     const double nxv = ldexp(x, log2n);
     const double fl = floor(nxv);
-    const int64_t l0 = (int64_t)fl;
+    const int l0 = (int)fl;
     T phi[2 * MW];
     kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
     const double* yc = pv.ycheb + 2 * B.ycheb_off;
-    const BaryY by = bary_setup(yc, B.q, y);
-    int64_t addr[2 * MW];
-    for (int t = 0; t < 2 * MW; ++t) addr[t] = grid_addr(B, (l0 - MW + 1 + t) & nmask);
+    const BaryY<T> by = bary_setup<T>(yc, B.q, y);
+    // grid address of cell l (one-pass bands: natural order; two-pass: pass B's
+    // output layout Y[l1 / B][l2][l1 mod B], l = l1 + n1 l2)
+    const int lb = B.log2n2 > 0 ? B.log2B : 30;
+    const int l1m = (1 << B.log2n1) - 1, bm = (1 << lb) - 1;
+    auto addr_of = [&](int l) {
+        const int l1 = l & l1m, l2 = l >> B.log2n1;
+        return B.log2n2 > 0 ? ((l1 >> lb) << (B.log2n2 + lb)) + (l2 << lb) + (l1 & bm) : l;
+    };
     const cplx<T>* g = grids + B.grid_off * (f2 ? 2 : 1);
+    const int ncol = f2 ? 2 * B.q : B.q;
+    // the workgroup's run of cells (uniform: first and last node of the item)
+    const int lf = (int)floor(ldexp(pv.nx[it.start], log2n));
+    const int ll = (int)floor(ldexp(pv.nx[it.start + it.count - 1], log2n));
+    const int span = ll - lf + 2 * MW;
     double ar = 0, ai = 0, dr = 0, di = 0;
-    for (int s = 0; s < B.q; ++s) {
-        const cplx<T>* gs = g + ((int64_t)s << log2n);
-        T fr = 0, fi = 0;
-        for (int t = 0; t < 2 * MW; ++t) {
-            const cplx<T> v = gs[addr[t]];
-            fr += v.x * phi[t];
-            fi += v.y * phi[t];
-        }
-        const double Ls = bary_at(yc, by, s, y);
-        ar += Ls * (double)fr;
-        ai += Ls * (double)fi;
-        if (f2) {
-            const cplx<T>* gd = g + ((int64_t)(s + B.q) << log2n);
-            T er = 0, ei = 0;
-            for (int t = 0; t < 2 * MW; ++t) {
-                const cplx<T> v = gd[addr[t]];
-                er += v.x * phi[t];
-                ei += v.y * phi[t];
+    if (span <= GATHER_STAGE<T>()) {
+        const int base = lf - MW + 1;
+        const int off = l0 - lf;   // in [0, span - 2 mw] (sorted nodes)
+        const int per = GATHER_STAGE<T>() / span;
+        // thread i loads stage elements e = i, i + GATHER_THREADS, ...: column
+        // cc = e / span, cell r = e mod span, stepped without divisions
+        const int cc0 = i / span, r0 = i - cc0 * span;
+        const int step_c = GATHER_THREADS / span, step_r = GATHER_THREADS - step_c * span;
+        for (int s0 = 0; s0 < ncol; s0 += per) {
+            const int nc = ncol - s0 < per ? ncol - s0 : per;
+            if (s0 > 0) ctx.sync();   // the previous columns' reads are done
+            int cc = cc0, r = r0;
+            for (int e = i; e < nc * span; e += GATHER_THREADS) {
+                stage[e] = g[((int64_t)(s0 + cc) << log2n) + addr_of((base + r) & nmask)];
+                cc += step_c;
+                r += step_r;
+                if (r >= span) {
+                    r -= span;
+                    ++cc;
+                }
             }
-            dr += Ls * (double)er;
-            di += Ls * (double)ei;
+            ctx.sync();
+            if (active) {
+                for (int cc = 0; cc < nc; ++cc) {
+                    const int s = s0 + cc;
+                    const bool dcol = s >= B.q;   // a derivative column (f2)
+                    const cplx<T>* st = stage + cc * span + off;
+                    T fr = 0, fi = 0;
+                    for (int t = 0; t < 2 * MW; ++t) {
+                        const cplx<T> v = st[t];
+                        fr += v.x * phi[t];
+                        fi += v.y * phi[t];
+                    }
+                    const double Ls = (double)bary_at<T>(yc, by, dcol ? s - B.q : s, y);
+                    if (dcol) {
+                        dr += Ls * (double)fr;
+                        di += Ls * (double)fi;
+                    } else {
+                        ar += Ls * (double)fr;
+                        ai += Ls * (double)fi;
+                    }
+                }
+            }
+        }
+    } else if (active) {
+        // offsets within a column (a grid has at most 2^22 points)
+        int addr[2 * MW];
+        for (int t = 0; t < 2 * MW; ++t) addr[t] = addr_of((l0 - MW + 1 + t) & nmask);
+        for (int s = 0; s < B.q; ++s) {
+            const cplx<T>* gs = g + ((int64_t)s << log2n);
+            T fr = 0, fi = 0;
+            for (int t = 0; t < 2 * MW; ++t) {
+                const cplx<T> v = gs[addr[t]];
+                fr += v.x * phi[t];
+                fi += v.y * phi[t];
+            }
+            const double Ls = (double)bary_at<T>(yc, by, s, y);
+            ar += Ls * (double)fr;
+            ai += Ls * (double)fi;
+            if (f2) {
+                const cplx<T>* gd = g + ((int64_t)(s + B.q) << log2n);
+                T er = 0, ei = 0;
+                for (int t = 0; t < 2 * MW; ++t) {
+                    const cplx<T> v = gd[addr[t]];
+                    er += v.x * phi[t];
+                    ei += v.y * phi[t];
+                }
+                dr += Ls * (double)er;
+                di += Ls * (double)ei;
+            }
         }
     }
-    // e^{2 pi i k0 x}: k0 is 0 or a power of two, so k0 x and its fraction are exact
-    double ph = (double)B.k0 * x;
-    ph -= floor(ph);
+    if (!active) return;
+    const int32_t dst = pv.perm[jj];
     double sn, cs;
-    sincos(6.283185307179586476925286766559 * ph, &sn, &cs);
+    modulation<T>((double)B.k0, x, &cs, &sn);   // e^{2 pi i k0 x}
     f[dst] = mk<T>((T)(c0r + ar * cs - ai * sn), (T)(c0i + ar * sn + ai * cs));
     if (f2) f2[dst] = mk<T>((T)(dr * cs - di * sn), (T)(dr * sn + di * cs));
 }
@@ -1165,16 +1337,14 @@ FLT_HD void body_adj_prep(const Ctx& ctx, const PlanView<T>& pv, const NodeItem*
     kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
     for (int t = 0; t < 2 * MW; ++t) Phi[j * (2 * MW) + t] = phi[t];
     const cplx<T> gv = gin[pv.perm[j]];
-    double ph = (double)B.k0 * x;
-    ph -= floor(ph);
     double sn, cs;
-    sincos(6.283185307179586476925286766559 * ph, &sn, &cs);
+    modulation<T>((double)B.k0, x, &cs, &sn);
     const double ur = (double)gv.x * cs + (double)gv.y * sn;   // g e^{-2 pi i k0 x}
     const double ui = (double)gv.y * cs - (double)gv.x * sn;
     const double* yc = pv.ycheb + 2 * B.ycheb_off;
-    const BaryY by = bary_setup(yc, B.q, y);
+    const BaryY<T> by = bary_setup<T>(yc, B.q, y);
     for (int s = 0; s < B.q; ++s) {
-        const double Ls = bary_at(yc, by, s, y);
+        const double Ls = (double)bary_at<T>(yc, by, s, y);
         U[j * qs + s] = mk<T>((T)(ur * Ls), (T)(ui * Ls));
     }
 }

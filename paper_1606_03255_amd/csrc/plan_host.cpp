@@ -50,8 +50,9 @@ static const double POLICY_TERMS_PER_S_C128 = 1.5e12;
 
 // One instance, everything but the launch groups and the workspace layout.
 static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags,
-                     double direct_scale)
+                     PlanShape shape)
 {
+    const double direct_scale = shape.direct_scale;
     if (!z || N < 1 || M < 1 || (dtype != FLT_C64 && dtype != FLT_C128)) return FLT_EINVAL;
     if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
     if (eps < (dtype == FLT_C64 ? 1e-6 : 1e-14)) return FLT_EPRECISION;
@@ -514,16 +515,16 @@ static void finish(HostPlan& hp)
 }
 
 int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags,
-                    double direct_scale)
+                    PlanShape shape)
 {
-    const int rc = build_one(hp, N, M, z, eps, dtype, flags, direct_scale);
+    const int rc = build_one(hp, N, M, z, eps, dtype, flags, shape);
     if (rc != FLT_OK) return rc;
     finish(hp);
     return FLT_OK;
 }
 
 int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
-                     int dtype, uint32_t flags, double direct_scale)
+                     int dtype, uint32_t flags, PlanShape shape)
 {
     if (count < 1 || !N || !M || !z) return FLT_EINVAL;
     out = HostPlan();
@@ -532,7 +533,7 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
     std::map<int, int> ycheb_at;                  // m (or -D for Y_D) -> pair offset in the merged ycheb table
     for (int32_t i = 0; i < count; ++i) {
         HostPlan p;
-        const int rc = build_one(p, N[i], M[i], z + 2 * zoff, eps, dtype, flags, direct_scale);
+        const int rc = build_one(p, N[i], M[i], z + 2 * zoff, eps, dtype, flags, shape);
         if (rc != FLT_OK) return rc;
         zoff += M[i];
         if (i == 0) {

@@ -38,7 +38,7 @@ struct HostPlan {
 
     // work lists
     std::vector<FftItem> onepass_fwd, passA_fwd, passB, onepass_adj, passA_adj;
-    // forward + derivative in one pass: column lists over 2q columns per band
+    // forward + derivative in one pass: the lists over 2q columns per band
     // (the derivative's column s is column q + s; pass A's list serves both)
     std::vector<FftItem> onepass_fused, passB_fused;
     std::vector<CellItem> cells;        // adjoint grid side: cell groups of the NFFT bands
@@ -73,8 +73,14 @@ struct HostPlan {
 };
 
 // Returns FLT_OK or a negative FLT_E* code (see flt.h).
+// Tunable shape of a plan (the autotuner's search space): the band policy's
+// direct-sum rate factor.
+struct PlanShape {
+    double direct_scale = 1.0;
+};
+
 int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double eps, int dtype,
-                    uint32_t flags = 0, double direct_scale = 1.0);
+                    uint32_t flags = 0, PlanShape shape = PlanShape());
 
 // One plan for `count` independent instances (N[i] coefficients, M[i] nodes,
 // z packed instance after instance): the members' bands, nodes and work lists
@@ -82,7 +88,7 @@ int build_host_plan(HostPlan& hp, int64_t N, int64_t M, const double* z, double 
 // packed c (and adjoint output) holds instance i at sum_{i' < i} N[i'], the
 // packed f (and adjoint input) at sum_{i' < i} M[i'].
 int build_batch_plan(HostPlan& hp, int32_t count, const int64_t* N, const int64_t* M, const double* z, double eps,
-                     int dtype, uint32_t flags = 0, double direct_scale = 1.0);
+                     int dtype, uint32_t flags = 0, PlanShape shape = PlanShape());
 
 // Modified Bessel function I_0 by its power series (host, FP64).
 double bessel_i0(double x);
