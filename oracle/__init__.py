@@ -11,7 +11,10 @@ Contents
              adjoint h_k = sum_j g_j conj(w_j)^k (the C^* of Sect. 4), also on
              chosen blocks of consecutive k only,
              derivative f'_j = sum_k 2 pi i k c_k w_j^k,
-             and a compensated-Horner cross-check.
+             and a compensated-Horner cross-check; with real exponents
+             (principal power w^xi, Re z reduced to (-1/2, 1/2]) the forward
+             f_j = sum_k c_k w_j^{xi_k} and the transposed evaluation
+             g(xi_k) = sum_j g_j w_j^{xi_k} of Sect. 4.
 ``brute``    independent brute force: every power w^k formed on its own in
              80-bit extended precision (numpy longdouble) or with mpmath.
 ``laplace``  the discrete Laplace transform of Sect. 3: its plain FP64
@@ -21,4 +24,5 @@ Contents
              the Fourier "black box" either exact (dense NDFT) or a
              Kaiser-Bessel NFFT.
 """
-from .direct import forward, adjoint, adjoint_blocks, derivative, horner, num_threads, load  # noqa: F401
+from .direct import (forward, adjoint, adjoint_blocks, derivative, horner, num_threads, load,  # noqa: F401
+                     forward_xi, transposed_xi)

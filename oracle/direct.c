@@ -26,6 +26,18 @@
  * A second, independent algorithm (complex compensated Horner, Graillat &
  * Menissier-Morain) is provided as a cross-check for moderate N.
  *
+ * Real exponents (eq. 4.1 with xi_k in [1, N]; Sect. 4, closing remarks: the
+ * transposed evaluation g(xi)):
+ *
+ *   forward_xi     f_j  = sum_k c_k w_j^{xi_k}
+ *   transposed_xi  h_k  = sum_j g_j w_j^{xi_k}
+ *
+ * with the principal power w^p = exp(p Log w), Log w = -y + 2 pi i x_p, where
+ * x_p is Re z reduced to (-1/2, 1/2] (arg w in (-pi, pi]); the paper leaves
+ * the nonpositive real axis out, the half-open interval fixes its side.  Each
+ * term is formed on its own: e^{-xi y} times cis(2 pi frac(xi x_p)), frac
+ * from the error-free product as above; sums are Neumaier-compensated.
+ *
  * Complex arrays are interleaved (re, im) doubles.  OpenMP parallelises over
  * nodes (forward, derivative, Horner) or over blocks of k (adjoint).
  */
@@ -242,4 +254,66 @@ int oracle_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------
+ * Real exponents.  x_p: Re z reduced to (-1/2, 1/2].
+ * ------------------------------------------------------------------------ */
+static double principal_x(double re)
+{
+    double x = re - floor(re);
+    if (x >= 1.0) x = 0.0;
+    return x > 0.5 ? x - 1.0 : x;
+}
+
+/* w^xi = e^{-xi y} cis(2 pi xi x_p) (0 for Im z = +inf) */
+static void principal_pow(double xi, double xp, double y, int inf, double* re, double* im)
+{
+    if (inf) { *re = 0.0; *im = 0.0; return; }
+    double mag = exp(-xi * y);
+    double ph = TWO_PI * frac_kx(xi, xp);
+    *re = mag * cos(ph);
+    *im = mag * sin(ph);
+}
+
+void oracle_forward_xi(int64_t N, const double* xi, const double* c, int64_t M, const double* z, double* f)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < M; ++j) {
+        const double im = z[2 * j + 1];
+        const int inf = isinf(im) && im > 0;
+        const double y = inf ? 0.0 : TWO_PI * im, xp = principal_x(z[2 * j]);
+        double sr = 0, cr = 0, si = 0, ci = 0;
+        for (int64_t k = 0; k < N; ++k) {
+            double pr, pi;
+            principal_pow(xi[k], xp, y, inf, &pr, &pi);
+            if (pr == 0.0 && pi == 0.0) continue;
+            const double ar = c[2 * k], ai = c[2 * k + 1];
+            neumaier(&sr, &cr, ar * pr - ai * pi);
+            neumaier(&si, &ci, ar * pi + ai * pr);
+        }
+        f[2 * j] = sr + cr;
+        f[2 * j + 1] = si + ci;
+    }
+}
+
+void oracle_transposed_xi(int64_t M, const double* z, const double* g, int64_t N, const double* xi, double* h)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < N; ++k) {
+        double sr = 0, cr = 0, si = 0, ci = 0;
+        for (int64_t j = 0; j < M; ++j) {
+            const double im = z[2 * j + 1];
+            const int inf = isinf(im) && im > 0;
+            const double y = inf ? 0.0 : TWO_PI * im, xp = principal_x(z[2 * j]);
+            double pr, pi;
+            principal_pow(xi[k], xp, y, inf, &pr, &pi);
+            if (pr == 0.0 && pi == 0.0) continue;
+            const double ar = g[2 * j], ai = g[2 * j + 1];
+            neumaier(&sr, &cr, ar * pr - ai * pi);
+            neumaier(&si, &ci, ar * pi + ai * pr);
+        }
+        h[2 * k] = sr + cr;
+        h[2 * k + 1] = si + ci;
+    }
 }

@@ -42,6 +42,10 @@ def load():
             fn = getattr(lib, name)
             fn.argtypes = [i64, i64, dp, dp, dp]
             fn.restype = None
+        lib.oracle_forward_xi.argtypes = [i64, dp, dp, i64, dp, dp]
+        lib.oracle_forward_xi.restype = None
+        lib.oracle_transposed_xi.argtypes = [i64, dp, dp, i64, dp, dp]
+        lib.oracle_transposed_xi.restype = None
         lib.oracle_adjoint_blocks.argtypes = [i64, i64, dp, dp, i64, ctypes.POINTER(ctypes.c_int64), dp]
         lib.oracle_adjoint_blocks.restype = None
         lib.oracle_block_size.restype = ctypes.c_int
@@ -109,6 +113,39 @@ def adjoint_blocks(g, z, N, blocks):
     k = (blocks[:, None] * B + np.arange(B)[None, :]).reshape(-1)
     keep = k < int(N)
     return k[keep], h[keep]
+
+
+def _xi(xi):
+    xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1))
+    if not np.all(np.isfinite(xi)):
+        raise ValueError("exponents must be finite")
+    return xi
+
+
+def forward_xi(c, xi, z):
+    """f_j = sum_k c_k w_j^{xi_k}, real exponents, principal power
+    (Re z reduced to (-1/2, 1/2]), FP64 term by term."""
+    c = _c128(c)
+    xi = _xi(xi)
+    z = _check_z(z)
+    if c.shape[0] != xi.shape[0]:
+        raise ValueError("c and xi differ in length")
+    f = np.empty(z.shape[0], np.complex128)
+    load().oracle_forward_xi(xi.shape[0], _ptr(xi), _ptr(c), z.shape[0], _ptr(z), _ptr(f))
+    return f
+
+
+def transposed_xi(g, z, xi):
+    """h_k = sum_j g_j w_j^{xi_k} (the transposed evaluation g(xi) of Sect. 4),
+    principal power, FP64 term by term."""
+    g = _c128(g)
+    z = _check_z(z)
+    xi = _xi(xi)
+    if g.shape[0] != z.shape[0]:
+        raise ValueError("g and z differ in length")
+    h = np.empty(xi.shape[0], np.complex128)
+    load().oracle_transposed_xi(z.shape[0], _ptr(z), _ptr(g), xi.shape[0], _ptr(xi), _ptr(h))
+    return h
 
 
 def block_size():

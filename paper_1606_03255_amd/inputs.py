@@ -19,6 +19,9 @@ Named workloads (N coefficients, M nodes):
   ``large``      N = M = 2^20, first M/2 annulus then M/2 disk, c64          (seed 3)
   ``batched``    512 instances, N_i, M_i = floor(2^{8 + 8U}), disk, c64      (seed 4)
   ``grad``       N = M = 2^18, disk, c64, targets t_j ~ CN(0, 1)             (seed 5)
+  ``xi``         N = M = 2^16 (``log2n`` to change), real exponents uniform in
+                 [1, N] (one ``random(N)`` draw, unsorted), then coefficients,
+                 then nodes as ``large`` (half annulus, half disk), c64    (seed 6)
 """
 import numpy as np
 
@@ -48,7 +51,13 @@ def nodes_annulus(rng, M, r0=ANNULUS_R0):
     return x + 1j * _im_from_r2m1(-U * (1.0 - r0 * r0))
 
 
-def workload(name, seed=None):
+def exponents(rng, N, lo=1.0, hi=None):
+    """N real exponents uniform in [lo, hi] (hi = N by default), unsorted."""
+    hi = float(N) if hi is None else float(hi)
+    return lo + (hi - lo) * rng.random(N)
+
+
+def workload(name, seed=None, log2n=16):
     """Return a dict with the named workload's arrays (numpy, host)."""
     if name == "small":
         rng = np.random.default_rng(1 if seed is None else seed)
@@ -84,6 +93,13 @@ def workload(name, seed=None):
         return dict(name=name, N=N, M=M, c=c, z=z, t=t, eps32=1e-6)
     if name == "batched":
         return batched(512, seed=4 if seed is None else seed)
+    if name == "xi":
+        rng = np.random.default_rng(6 if seed is None else seed)
+        N = M = 1 << int(log2n)
+        xi = exponents(rng, N)
+        c = coefficients(rng, N, np.complex64)
+        z = np.concatenate([nodes_annulus(rng, M // 2), nodes_disk(rng, M - M // 2)])
+        return dict(name=name, N=N, M=M, xi=xi, c=c, z=z, eps32=1e-6, eps64=1e-11)
     raise KeyError(name)
 
 
