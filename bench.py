@@ -24,6 +24,9 @@ roofline   the dominant kernel's algorithmic bytes per launch over its launch
 laplace    the discrete Laplace transform (Algorithm 1) at N = M = 2^20: time
            per call, node evals/s, algorithmic bytes against the HBM peak, and
            its error on sampled nodes against the oracle's direct sums.
+xi         real exponents xi_k uniform in [1, N] (eq. 4.1; the transposed
+           g(xi) of Sect. 4) at N = M = 2^20 (--xi-log2n): time per forward
+           and transposed call, evals/s, error on sampled nodes / exponents.
 direct_scale  the band-policy factor of the forward-tuned plan (the step's own
            plan reports its factor in fwd_bwd).
 cpu_baseline  the FP64 direct-sum oracle on a random sample of the nodes, on
@@ -433,6 +436,57 @@ def laplace_leg(torch, dev, args, log):
     return rec, sample
 
 
+def xi_error(sample):
+    """Part of the CPU-baseline leg: the real-exponent leg's sampled nodes and
+    exponents against the oracle's term-by-term sums, relative to the 1-norm
+    of the input."""
+    import numpy as np
+
+    import oracle
+    Ef = np.abs(sample["f"] - oracle.forward_xi(sample["c"], sample["xi"], sample["zs"])).max() / np.abs(sample["c"]).sum()
+    Eh = np.abs(sample["h"] - oracle.transposed_xi(sample["g"], sample["z"], sample["xis"])).max() / np.abs(sample["g"]).sum()
+    return float(Ef), float(Eh)
+
+
+def xi_leg(torch, dev, args, log):
+    """Real exponents (eq. 4.1 with real xi_k; the transposed g(xi) of Sect. 4)
+    at N = M = 2^args.xi_log2n: exponents uniform in [1, N], nodes as the
+    main workload (half annulus, half disk), complex64, eps 1e-6 (FP32 form):
+    time per forward and per transposed call, node evals/s, and the error of
+    both on sampled nodes / exponents."""
+    import numpy as np
+
+    from paper_1606_03255_amd import XiPlan, inputs
+    w = inputs.workload("xi", log2n=args.xi_log2n)
+    N, M = w["N"], w["M"]
+    t = time.perf_counter()
+    plan = XiPlan(w["xi"], w["z"], 1e-6, torch.complex64, device=dev)
+    plan_ms = (time.perf_counter() - t) * 1e3
+    c = torch.from_numpy(w["c"]).to(dev)
+    g_h = inputs.adjoint_input(M)
+    g = torch.from_numpy(g_h).to(dev)
+    f = torch.empty(M, dtype=torch.complex64, device=dev)
+    h = torch.empty(N, dtype=torch.complex64, device=dev)
+    ms_f, _ = time_steps(torch, lambda: plan.forward(c, out=f), max(5, args.steps), args.warmup)
+    ms_h, _ = time_steps(torch, lambda: plan.transposed(g, out=h), max(5, args.steps), args.warmup)
+    info = plan.info()
+    plan.close()
+    rng = np.random.default_rng(23)
+    sj = np.sort(rng.choice(M, 256, replace=False))
+    sk = np.sort(rng.choice(N, 128, replace=False))
+    sample = {"c": w["c"].astype(np.complex128), "xi": w["xi"], "zs": w["z"][sj], "f": f.cpu().numpy()[sj],
+              "g": g_h.astype(np.complex128), "z": w["z"], "xis": w["xi"][sk], "h": h.cpu().numpy()[sk]}
+    rec = {"N": N, "M": M, "eps": 1e-6, "dtype": "c64 (FP32 form)", "exponents": "uniform in [1, N]",
+           "ms_forward": round(ms_f, 4), "ms_transposed": round(ms_h, 4),
+           "node_evals_per_s": M / (ms_f * 1e-3), "exponent_evals_per_s": N / (ms_h * 1e-3),
+           "mw1": info["mw1"], "inner_mw": info["inner_mw"], "inner_instances": info["inner_instances"],
+           "inner_nodes": info["inner_nodes"], "inner_coefficients": info["inner_coefficients"],
+           "sigma_min": round(info["sigma_min"], 4), "eps_inner": info["eps_in"],
+           "E_forward": None, "E_transposed": None, "plan_ms": round(plan_ms, 1)}
+    log("xi: forward %.4f ms (%.3e node evals/s), transposed %.4f ms" % (ms_f, rec["node_evals_per_s"], ms_h))
+    return rec, sample
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -445,6 +499,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched leg")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-transform (Algorithm 1) leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd step at N = M = 2^18")
+    ap.add_argument("--no-xi", action="store_true", help="skip the real-exponent leg")
+    ap.add_argument("--xi-log2n", type=int, default=20, help="log2 N = log2 M of the real-exponent leg")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size reference "
                          "for HBM counter readings)")
@@ -529,6 +585,10 @@ def main():
     if not args.no_laplace and not args.forward_only:
         laplace, lap_sample = laplace_leg(torch, dev, args, log)
 
+    xi = xi_sample = None
+    if not args.no_xi and not args.forward_only:
+        xi, xi_sample = xi_leg(torch, dev, args, log)
+
     cpu = None
     E32 = None
     n_checked = 0
@@ -544,6 +604,9 @@ def main():
         if laplace is not None:
             laplace["E"] = laplace_error(lap_sample)
             log("laplace E", laplace["E"])
+        if xi is not None:
+            xi["E_forward"], xi["E_transposed"] = xi_error(xi_sample)
+            log("xi E", xi["E_forward"], xi["E_transposed"])
 
     info = p32.info()
     rec = {
@@ -565,6 +628,7 @@ def main():
         "direct_scale": info["direct_scale"],
         "batched": batched,
         "laplace": laplace,
+        "xi": xi,
         "bytes_forward_model": info["bytes_forward"],
         "wall_s_timed": round(wall, 3),
     }

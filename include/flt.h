@@ -248,6 +248,66 @@ int flt_laplace_plan_info(const flt_laplace_plan* plan, flt_laplace_info* out);
 int flt_laplace_forward(flt_laplace_plan* plan, const void* fhat, void* f, void* stream);
 void flt_laplace_plan_destroy(flt_laplace_plan* plan);
 
+/* ------------------------------------------------------------------------
+ * Real exponents (eq. 4.1 with xi_k >= 1 real; Sect. 4, closing remarks: the
+ * transposed evaluation g(xi) and the adjoint C^*):
+ *
+ *     forward     f_j = sum_k c_k w_j^{xi_k}
+ *     transposed  h_k = sum_j g_j w_j^{xi_k}          (the paper's g(xi_k))
+ *     adjoint     h_k = sum_j g_j conj(w_j^{xi_k})
+ *
+ * with w_j = exp(2 pi i z_j) and the principal power w^xi = exp(xi Log w),
+ * Log w = -y + 2 pi i x_p, x_p = Re z reduced to (-1/2, 1/2] (the paper leaves
+ * the nonpositive real axis out; this fixes its side).  Nodes with
+ * y = 2 pi Im z > ln(3 / eps) give 0 (every term is below eps / 3 there).
+ *
+ * Method: the Laplace factor as in Algorithm 2 (the integer plan's partition
+ * and Chebyshev interpolants, evaluated at real xi), the Fourier factor of
+ * each band column by an NNFFT: a Kaiser-Bessel window of half-width mw1
+ * spreads the exponents onto the integers l = sigma xi (sigma in [1.9, 2]),
+ * one batched integer plan evaluates every (band, column) sum at the nodes
+ * x_p / sigma, and a per-node division by the window's Fourier transform
+ * undoes the spread.  Error <= eps sum_k |c_k| (eps / 3 Laplace, eps / 6
+ * window, eps / 6 for the inner sums after the window's amplification).
+ * ------------------------------------------------------------------------ */
+typedef struct flt_xi_plan flt_xi_plan;
+
+typedef struct flt_xi_info {
+    int64_t N, M;                 /* exponents, nodes */
+    int32_t dtype;                /* FLT_C64 (FP32 form) or FLT_C128 */
+    int32_t q;                    /* Chebyshev rank of the Laplace factor */
+    int32_t mw1;                  /* frequency window half-width */
+    int32_t num_bands;            /* node bands with exponents in their support */
+    int32_t inner_instances;      /* inner integer sums: one per (band, column) */
+    int32_t inner_mw;             /* the inner plan's window half-width (0 for a host-only plan) */
+    double eps, eps_w, eps_in;    /* target; window share; inner plans' accuracy */
+    double sigma_min, amp;        /* smallest frequency density; inner-error amplification */
+    int64_t inner_coefficients;   /* integer frequencies over all inner sums */
+    int64_t inner_nodes;          /* nodes over all inner sums (sum of q_b M_b) */
+    size_t inner_workspace_bytes; /* the inner plan's workspace (0 for a host-only plan) */
+} flt_xi_info;
+
+/* Plan for N exponents xi (host, N doubles, finite, >= 1, any order, at most
+ * 2^29) and M nodes z (host, 2M doubles as for flt_plan_create); both copied.
+ * flags: 0 or FLT_FLAG_HOST_ONLY.  The plan owns its device memory: tables,
+ * the inner batched plan with its workspace, and buffers of
+ * inner_coefficients + inner_nodes complex values and N FP64 complex
+ * accumulators, all rewritten by every call.  Transform calls allocate
+ * nothing; calls on one plan must not overlap.  Errors: FLT_EINVAL (null,
+ * N or M < 1, dtype, flags), FLT_EDOMAIN (eps outside (0,1), xi < 1 or not
+ * finite, Im z < 0 or NaN), FLT_EPRECISION (eps below 1e-6 for FLT_C64,
+ * 1e-14 for FLT_C128, or a window wider than supported), FLT_ERANGE
+ * (N > 2^30, xi > 2^29), FLT_EHIP, FLT_ENOMEM. */
+int flt_xi_plan_create(flt_xi_plan** out, int64_t N, const double* xi, int64_t M, const double* z, double eps,
+                       int dtype, uint32_t flags);
+int flt_xi_plan_info(const flt_xi_plan* plan, flt_xi_info* out);
+/* c: device complex[N] in the order xi was given; f: device complex[M], overwritten. */
+int flt_xi_forward(flt_xi_plan* plan, const void* c, void* f, void* stream);
+/* g: device complex[M]; h: device complex[N] (order of xi), overwritten. */
+int flt_xi_transposed(flt_xi_plan* plan, const void* g, void* h, void* stream);
+int flt_xi_adjoint(flt_xi_plan* plan, const void* g, void* h, void* stream);
+void flt_xi_plan_destroy(flt_xi_plan* plan);   /* NULL: no-op */
+
 const char* flt_strerror(int code);
 int flt_last_hip_error(void); /* hipError_t of the last failing HIP call in this thread */
 

@@ -29,6 +29,8 @@ EXPORTS = (
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
     "flt_forward_derivative", "flt_forward_noalloc", "flt_profile_forward", "flt_profile_adjoint", "flt_strerror", "flt_last_hip_error",
     "flt_laplace_plan_create", "flt_laplace_plan_info", "flt_laplace_forward", "flt_laplace_plan_destroy",
+    "flt_xi_plan_create", "flt_xi_plan_info", "flt_xi_forward", "flt_xi_transposed", "flt_xi_adjoint",
+    "flt_xi_plan_destroy",
 )
 
 
@@ -59,6 +61,18 @@ class FltLaplaceInfo(ctypes.Structure):
         ("N", ctypes.c_int64), ("M", ctypes.c_int64),
         ("dtype", ctypes.c_int32), ("q", ctypes.c_int32), ("levels", ctypes.c_int32), ("pad", ctypes.c_int32),
         ("eps", ctypes.c_double), ("y1", ctypes.c_double), ("xi1", ctypes.c_double),
+    ]
+
+
+class FltXiInfo(ctypes.Structure):
+    _fields_ = [
+        ("N", ctypes.c_int64), ("M", ctypes.c_int64),
+        ("dtype", ctypes.c_int32), ("q", ctypes.c_int32), ("mw1", ctypes.c_int32), ("num_bands", ctypes.c_int32),
+        ("inner_instances", ctypes.c_int32), ("inner_mw", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("eps_w", ctypes.c_double), ("eps_in", ctypes.c_double),
+        ("sigma_min", ctypes.c_double), ("amp", ctypes.c_double),
+        ("inner_coefficients", ctypes.c_int64), ("inner_nodes", ctypes.c_int64),
+        ("inner_workspace_bytes", ctypes.c_size_t),
     ]
 
 
@@ -106,6 +120,13 @@ def load():
     lib.flt_laplace_forward.argtypes = [vp, vp, vp, vp]
     lib.flt_laplace_plan_destroy.argtypes = [vp]
     lib.flt_laplace_plan_destroy.restype = None
+    lib.flt_xi_plan_create.argtypes = [P(vp), ctypes.c_int64, P(ctypes.c_double), ctypes.c_int64,
+                                       P(ctypes.c_double), ctypes.c_double, ctypes.c_int, ctypes.c_uint32]
+    lib.flt_xi_plan_info.argtypes = [vp, P(FltXiInfo)]
+    for name in ("flt_xi_forward", "flt_xi_transposed", "flt_xi_adjoint"):
+        getattr(lib, name).argtypes = [vp, vp, vp, vp]
+    lib.flt_xi_plan_destroy.argtypes = [vp]
+    lib.flt_xi_plan_destroy.restype = None
     lib.flt_profile_forward.argtypes = [vp, vp, vp, vp, P(ctypes.c_double)]
     lib.flt_profile_adjoint.argtypes = [vp, vp, vp, vp, P(ctypes.c_double)]
     lib.flt_strerror.argtypes = [ctypes.c_int]

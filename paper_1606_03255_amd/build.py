@@ -34,7 +34,7 @@ def _run(cmd):
 def build_lib(jobs=3):
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    srcs = ["kernels.hip", "laplace.hip", "api.cpp", "plan_host.cpp", "laplace_plan.cpp"]
+    srcs = ["kernels.hip", "laplace.hip", "xi.hip", "api.cpp", "plan_host.cpp", "laplace_plan.cpp", "xi_plan.cpp"]
     objs = []
     procs = []
     for s in srcs:
@@ -64,7 +64,7 @@ def build_emu(sanitize=False):
              else ["-O2"])
     _run(["g++", "-g", "-std=c++17", "-fopenmp", "-fPIC", "-shared"] + extra + ["-I" + INC, "-I" + CSRC,
           os.path.join(CSRC, "emu.cpp"), os.path.join(CSRC, "plan_host.cpp"), os.path.join(CSRC, "laplace_plan.cpp"),
-          "-o", tmp])
+          os.path.join(CSRC, "xi_plan.cpp"), "-o", tmp])
     os.replace(tmp, out)
     return out
 

@@ -435,6 +435,16 @@ static void release(flt_plan* p)
     delete p;
 }
 
+// The real-exponent plan's inner batched integer plan: as
+// flt_plan_create_batch, with eps allowed below the dtype's floor.
+static int create_inner_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M, const double* z,
+                              double eps, int dtype)
+{
+    return create(out, 0, [&](HostPlan& hp, const PlanShape& shape) {
+        return build_batch_plan(hp, count, N, M, z, eps, dtype, PLAN_FLAG_NO_FLOOR, shape);
+    });
+}
+
 extern "C" {
 
 int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype, uint32_t flags)
@@ -830,5 +840,200 @@ void flt_laplace_plan_destroy(flt_laplace_plan* p)
     if (p->dev) (void)hipFree(p->dev);
     delete p;
 }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Real exponents (eq. 4.1 with real xi_k; the transposed g(xi) of Sect. 4)
+// ---------------------------------------------------------------------------
+struct flt_xi_plan {
+    XiHost hp;
+    bool host_only = true;
+    void* dev = nullptr;      // tables and work items
+    void* buf = nullptr;      // inner coefficients, inner node values, FP64 accumulator
+    void* ws = nullptr;       // the inner plan's workspace
+    flt_plan* inner = nullptr;
+    XiView<float> v32{};
+    XiView<double> v64{};
+    const XiItem* spread = nullptr;
+    const XiItem* gather = nullptr;
+    const NodeItem* nodes = nullptr;
+    char* cin = nullptr;
+    char* hout = nullptr;
+    double* hacc = nullptr;
+    int qmax = 1;
+};
+
+static void xi_release(flt_xi_plan* p)
+{
+    if (!p) return;
+    if (p->inner) release(p->inner);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->buf) (void)hipFree(p->buf);
+    if (p->dev) (void)hipFree(p->dev);
+    delete p;
+}
+
+template <typename T>
+static XiView<T> xi_view(const XiHost& hp, char* b, size_t o_bands, size_t o_coef, size_t o_yc, size_t o_xi,
+                         size_t o_xp, size_t o_xpos, size_t o_ny, size_t o_perm)
+{
+    XiView<T> v;
+    v.bands = (const XiBand*)(b + o_bands);
+    v.coef = (const T*)(b + o_coef);
+    v.ycheb = (const double*)(b + o_yc);
+    v.xi = (const double*)(b + o_xi);
+    v.xi_perm = (const int32_t*)(b + o_xp);
+    v.xp = (const double*)(b + o_xpos);
+    v.ny = (const double*)(b + o_ny);
+    v.perm = (const int32_t*)(b + o_perm);
+    v.mw1 = hp.mw1;
+    return v;
+}
+
+static int xi_upload(flt_xi_plan* p)
+{
+    XiHost& hp = p->hp;
+    const HostPlan& op = hp.outer;
+    const bool f32 = hp.dtype == FLT_C64;
+    int rc = create_inner_batch(&p->inner, (int32_t)hp.in_N.size(), hp.in_N.data(), hp.in_M.data(), hp.in_z.data(),
+                                hp.eps_in, hp.dtype);
+    if (rc != FLT_OK) return rc;
+    std::vector<double>().swap(hp.in_z);   // the inner plan holds its copy
+    size_t wsb = 0;
+    rc = flt_plan_workspace_size(p->inner, &wsb);
+    if (rc != FLT_OK) return rc;
+    hipError_t e = hipMalloc(&p->ws, wsb ? wsb : 256);
+    if (e != hipSuccess) return hip_fail(e);
+    rc = flt_plan_set_workspace(p->inner, p->ws, wsb);
+    if (rc != FLT_OK) return rc;
+
+    Packer pk;
+    const size_t o_bands = pk.add(hp.bands.data(), hp.bands.size() * sizeof(XiBand));
+    const size_t o_sp = pk.add(hp.spread.data(), hp.spread.size() * sizeof(XiItem));
+    const size_t o_ga = pk.add(hp.gather.data(), hp.gather.size() * sizeof(XiItem));
+    const size_t o_nd = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
+    const size_t o_coef = f32 ? pk.add_cast<float>(op.coef) : pk.add_cast<double>(op.coef);
+    const size_t o_yc = pk.add(op.ycheb.data(), op.ycheb.size() * sizeof(double));
+    const size_t o_xi = pk.add(hp.xi.data(), hp.xi.size() * sizeof(double));
+    const size_t o_xp = pk.add(hp.xi_perm.data(), hp.xi_perm.size() * sizeof(int32_t));
+    const size_t o_xpos = pk.add(hp.xp.data(), hp.xp.size() * sizeof(double));
+    const size_t o_ny = pk.add(op.ny.data(), op.ny.size() * sizeof(double));
+    const size_t o_perm = pk.add(op.perm.data(), op.perm.size() * sizeof(int32_t));
+    e = hipMalloc(&p->dev, pk.buf.size());
+    if (e == hipSuccess) e = hipMemcpy(p->dev, pk.buf.data(), pk.buf.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    char* b = (char*)p->dev;
+    p->v32 = xi_view<float>(hp, b, o_bands, o_coef, o_yc, o_xi, o_xp, o_xpos, o_ny, o_perm);
+    p->v64 = xi_view<double>(hp, b, o_bands, o_coef, o_yc, o_xi, o_xp, o_xpos, o_ny, o_perm);
+    p->spread = (const XiItem*)(b + o_sp);
+    p->gather = (const XiItem*)(b + o_ga);
+    p->nodes = (const NodeItem*)(b + o_nd);
+    for (const XiBand& X : hp.bands) p->qmax = std::max(p->qmax, (int)X.q);
+
+    const size_t S = f32 ? 8 : 16;
+    auto al = [](size_t v) { return (v + 255) & ~(size_t)255; };
+    const size_t b_cin = al(std::max<int64_t>(hp.cin_elems, 1) * S);
+    const size_t b_hout = al(std::max<int64_t>(hp.hout_elems, 1) * S);
+    e = hipMalloc(&p->buf, b_cin + b_hout + (size_t)hp.N * 16);
+    if (e != hipSuccess) return hip_fail(e);
+    p->cin = (char*)p->buf;
+    p->hout = p->cin + b_cin;
+    p->hacc = (double*)(p->hout + b_hout);
+    return FLT_OK;
+}
+
+extern "C" {
+
+int flt_xi_plan_create(flt_xi_plan** out, int64_t N, const double* xi, int64_t M, const double* z, double eps,
+                       int dtype, uint32_t flags)
+{
+    if (!out) return FLT_EINVAL;
+    *out = nullptr;
+    if (flags & ~FLT_FLAG_HOST_ONLY) return FLT_EINVAL;
+    flt_xi_plan* p = new (std::nothrow) flt_xi_plan();
+    if (!p) return FLT_ENOMEM;
+    int rc;
+    try {
+        rc = build_xi_plan(p->hp, N, xi, M, z, eps, dtype);
+        if (rc == FLT_OK && !(flags & FLT_FLAG_HOST_ONLY)) {
+            rc = xi_upload(p);
+            if (rc == FLT_OK) p->host_only = false;
+        }
+    } catch (const std::bad_alloc&) {
+        rc = FLT_ENOMEM;
+    }
+    if (rc != FLT_OK) {
+        xi_release(p);
+        return rc;
+    }
+    *out = p;
+    return FLT_OK;
+}
+
+int flt_xi_plan_info(const flt_xi_plan* p, flt_xi_info* o)
+{
+    if (!p || !o) return FLT_EINVAL;
+    const XiHost& hp = p->hp;
+    memset(o, 0, sizeof(*o));
+    o->N = hp.N;
+    o->M = hp.M;
+    o->dtype = hp.dtype;
+    o->q = hp.outer.q;
+    o->mw1 = hp.mw1;
+    int nb = 0;
+    for (const XiBand& X : hp.bands) nb += X.q > 0;
+    o->num_bands = nb;
+    o->inner_instances = (int32_t)hp.in_N.size();
+    o->eps = hp.eps;
+    o->eps_w = hp.eps_w;
+    o->eps_in = hp.eps_in;
+    o->sigma_min = hp.sig_min;
+    o->amp = hp.amp;
+    o->inner_coefficients = hp.cin_elems;
+    o->inner_nodes = hp.hout_elems;
+    if (p->inner) {
+        o->inner_mw = p->inner->hp.mw;
+        o->inner_workspace_bytes = p->inner->hp.ws_bytes;
+    }
+    return FLT_OK;
+}
+
+static int xi_run(flt_xi_plan* p, int op, const void* in, void* out, void* stream)
+{
+    if (!p || !in || !out) return FLT_EINVAL;
+    if (p->host_only) return FLT_ESTATE;
+    const hipStream_t st = (hipStream_t)stream;
+    const XiHost& hp = p->hp;
+    const bool f32 = hp.dtype == FLT_C64;
+    hipError_t e;
+    int rc;
+    if (op == 0) {
+        e = f32 ? launch_xi_spread<float>(p->v32, p->qmax, p->spread, (int)hp.spread.size(), in, p->cin, st)
+                : launch_xi_spread<double>(p->v64, p->qmax, p->spread, (int)hp.spread.size(), in, p->cin, st);
+        if (e != hipSuccess) return hip_fail(e);
+        rc = flt_forward(p->inner, p->cin, p->hout, stream);
+        if (rc != FLT_OK) return rc;
+        e = f32 ? launch_xi_combine<float>(p->v32, p->nodes, (int)hp.nodes.size(), p->hout, out, st)
+                : launch_xi_combine<double>(p->v64, p->nodes, (int)hp.nodes.size(), p->hout, out, st);
+        return e == hipSuccess ? FLT_OK : hip_fail(e);
+    }
+    const int conj = op == 2;
+    e = f32 ? launch_xi_prep<float>(p->v32, p->nodes, (int)hp.nodes.size(), in, conj, p->hout, st)
+            : launch_xi_prep<double>(p->v64, p->nodes, (int)hp.nodes.size(), in, conj, p->hout, st);
+    if (e != hipSuccess) return hip_fail(e);
+    rc = flt_adjoint(p->inner, p->hout, p->cin, stream);
+    if (rc != FLT_OK) return rc;
+    e = f32 ? launch_xi_gather<float>(p->v32, p->qmax, p->gather, (int)hp.gather.size(), p->cin, p->hacc, hp.N, conj,
+                                      out, st)
+            : launch_xi_gather<double>(p->v64, p->qmax, p->gather, (int)hp.gather.size(), p->cin, p->hacc, hp.N,
+                                       conj, out, st);
+    return e == hipSuccess ? FLT_OK : hip_fail(e);
+}
+
+int flt_xi_forward(flt_xi_plan* p, const void* c, void* f, void* stream) { return xi_run(p, 0, c, f, stream); }
+int flt_xi_transposed(flt_xi_plan* p, const void* g, void* h, void* stream) { return xi_run(p, 1, g, h, stream); }
+int flt_xi_adjoint(flt_xi_plan* p, const void* g, void* h, void* stream) { return xi_run(p, 2, g, h, stream); }
+void flt_xi_plan_destroy(flt_xi_plan* p) { xi_release(p); }
 
 }  // extern "C"

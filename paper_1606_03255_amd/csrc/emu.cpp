@@ -28,6 +28,7 @@
 #include "kernels_impl.h"
 #include "laplace.h"
 #include "plan_host.h"
+#include "xi_impl.h"
 
 namespace flt {
 
@@ -360,7 +361,73 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
     return FLT_OK;
 }
 
+// The real-exponent transform on the CPU: op 0 forward (in c, out f), 1
+// transposed, 2 adjoint (in g, out h); the inner sums by emu_run.
+template <typename T> static int emu_xi(XiHost& hp, int op, const void* in, void* out)
+{
+    HostPlan inner;
+    int rc = build_batch_plan(inner, (int32_t)hp.in_N.size(), hp.in_N.data(), hp.in_M.data(), hp.in_z.data(),
+                              hp.eps_in, hp.dtype, PLAN_FLAG_NO_FLOOR);
+    if (rc != FLT_OK) return rc;
+    const std::vector<T> coef = cast<T>(hp.outer.coef);
+    XiView<T> xv;
+    xv.bands = hp.bands.data();
+    xv.coef = coef.data();
+    xv.ycheb = hp.outer.ycheb.data();
+    xv.xi = hp.xi.data();
+    xv.xi_perm = hp.xi_perm.data();
+    xv.xp = hp.xp.data();
+    xv.ny = hp.outer.ny.data();
+    xv.perm = hp.outer.perm.data();
+    xv.mw1 = hp.mw1;
+    int qmax = 1;
+    for (const XiBand& X : hp.bands) qmax = std::max(qmax, (int)X.q);
+    std::vector<cplx<T>> cin(std::max<int64_t>(hp.cin_elems, 1)), hout(std::max<int64_t>(hp.hout_elems, 1));
+    std::vector<T> lc(XI_NBLK * 32 * 32);
+    std::vector<cplx<T>> ct(32 * 1024 / sizeof(cplx<T>));   // xi_kcap * QM for every QM
+    if (op == 0) {
+        run_blocks(hp.spread.size(), XI_THREADS, [&](const HostCtx& ctx) {
+            if (qmax <= 16) body_xi_spread<HostCtx, T, 16>(ctx, xv, hp.spread.data(), (const cplx<T>*)in, cin.data(), lc.data(), ct.data());
+            else if (qmax <= 24) body_xi_spread<HostCtx, T, 24>(ctx, xv, hp.spread.data(), (const cplx<T>*)in, cin.data(), lc.data(), ct.data());
+            else body_xi_spread<HostCtx, T, 32>(ctx, xv, hp.spread.data(), (const cplx<T>*)in, cin.data(), lc.data(), ct.data());
+        });
+        rc = emu_run<T>(inner, 0, cin.data(), hout.data());
+        if (rc != FLT_OK) return rc;
+        run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+            body_xi_combine<HostCtx, T>(ctx, xv, hp.nodes.data(), hout.data(), (cplx<T>*)out);
+        });
+        return FLT_OK;
+    }
+    const int conj = op == 2;
+    run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+        body_xi_prep<HostCtx, T>(ctx, xv, hp.nodes.data(), (const cplx<T>*)in, conj, hout.data());
+    });
+    rc = emu_run<T>(inner, 2, hout.data(), cin.data());
+    if (rc != FLT_OK) return rc;
+    std::vector<double> hacc(2 * hp.N, 0.0);
+    run_blocks(hp.gather.size(), XI_THREADS, [&](const HostCtx& ctx) {
+        if (qmax <= 16) body_xi_gather<HostCtx, T, 16>(ctx, xv, hp.gather.data(), cin.data(), hacc.data(), lc.data());
+        else if (qmax <= 24) body_xi_gather<HostCtx, T, 24>(ctx, xv, hp.gather.data(), cin.data(), hacc.data(), lc.data());
+        else body_xi_gather<HostCtx, T, 32>(ctx, xv, hp.gather.data(), cin.data(), hacc.data(), lc.data());
+    });
+    run_blocks((hp.N + XI_THREADS - 1) / XI_THREADS, XI_THREADS, [&](const HostCtx& ctx) {
+        body_xi_finalize<HostCtx, T>(ctx, xv, hp.N, hacc.data(), conj, (cplx<T>*)out);
+    });
+    return FLT_OK;
+}
+
 }  // namespace flt
+
+// The real-exponent transform on the CPU build: op 0 forward, 1 transposed,
+// 2 adjoint (see flt_xi_forward / flt_xi_transposed / flt_xi_adjoint).
+extern "C" int flt_emu_xi(int64_t N, const double* xi, int64_t M, const double* z, double eps, int dtype, int op,
+                          const void* in, void* out)
+{
+    flt::XiHost hp;
+    int rc = flt::build_xi_plan(hp, N, xi, M, z, eps, dtype);
+    if (rc != FLT_OK) return rc;
+    return dtype == FLT_C64 ? flt::emu_xi<float>(hp, op, in, out) : flt::emu_xi<double>(hp, op, in, out);
+}
 
 // The kernel bodies on the CPU for one call: op 0 forward, 1 derivative,
 // 2 adjoint, 3 forward and derivative in one pass (out: f, then f', 2M values).

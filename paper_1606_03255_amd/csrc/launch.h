@@ -6,6 +6,7 @@
 
 #include "flt_types.h"
 #include "laplace.h"
+#include "xi_plan.h"
 
 namespace flt {
 
@@ -81,6 +82,25 @@ hipError_t noalloc_scratch_address(int device, char** out);
 template <typename T>
 hipError_t launch_laplace(const LapView& V, const LapItem* items, int nitems, int64_t M, const void* fhat, void* f,
                           hipStream_t st);
+
+// Real exponents (xi.hip), on stream st: the frequency-side spread of c into
+// the inner plan's coefficients cin; the node-side combination of the inner
+// sums hin into f; the node-side weights of g for the inner transposed sums
+// (conj_in: g conjugated); the frequency-side gather of the inner transposed
+// sums vin into h through the FP64 accumulator hacc (2N doubles; conj_out: h
+// conjugated).  q: the largest band rank (selects the kernel instance).
+template <typename T>
+hipError_t launch_xi_spread(const XiView<T>& xv, int q, const XiItem* items, int nitems, const void* c, void* cin,
+                            hipStream_t st);
+template <typename T>
+hipError_t launch_xi_combine(const XiView<T>& xv, const NodeItem* items, int nitems, const void* hin, void* f,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_xi_prep(const XiView<T>& xv, const NodeItem* items, int nitems, const void* g, int conj_in,
+                          void* uin, hipStream_t st);
+template <typename T>
+hipError_t launch_xi_gather(const XiView<T>& xv, int q, const XiItem* items, int nitems, const void* vin,
+                            double* hacc, int64_t N, int conj_out, void* h, hipStream_t st);
 
 // a7 (adjoint): g -> c_out on stream st.  If ev is not null, ev[0..8] are
 // recorded before the first launch and after each stage (clearing and the

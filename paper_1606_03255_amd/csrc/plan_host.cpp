@@ -55,7 +55,7 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
     const double direct_scale = shape.direct_scale;
     if (!z || N < 1 || M < 1 || (dtype != FLT_C64 && dtype != FLT_C128)) return FLT_EINVAL;
     if (!(eps > 0.0 && eps < 1.0)) return FLT_EDOMAIN;
-    if (eps < (dtype == FLT_C64 ? 1e-6 : 1e-14)) return FLT_EPRECISION;
+    if (!(flags & PLAN_FLAG_NO_FLOOR) && eps < (dtype == FLT_C64 ? 1e-6 : 1e-14)) return FLT_EPRECISION;
     if (N - 1 > ((int64_t)1 << 21)) return FLT_ERANGE;
     if (M > (int64_t)INT32_MAX) return FLT_ERANGE;
     for (int64_t j = 0; j < M; ++j) {

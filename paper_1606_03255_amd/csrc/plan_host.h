@@ -72,6 +72,12 @@ struct HostPlan {
     size_t elem_bytes() const { return dtype == 1 ? 8 : 16; }   // complex element
 };
 
+// Planner-internal flag (never accepted from callers): accept eps below the
+// dtype's floor.  The real-exponent plan's inner integer sums need it: their
+// error is amplified by the frequency window, and FP32 sums of unit-modulus
+// terms still reach well below 1e-6 in practice.
+constexpr uint32_t PLAN_FLAG_NO_FLOOR = 1u << 30;
+
 // Returns FLT_OK or a negative FLT_E* code (see flt.h).
 // Tunable shape of a plan (the autotuner's search space): the band policy's
 // direct-sum rate factor.

@@ -410,3 +410,91 @@ class LaplacePlan:
             self.close()
         except Exception:
             pass
+
+
+class XiPlan:
+    """Real exponents: f_j = sum_k c_k w_j^{xi_k} (eq. 4.1 with real xi_k >= 1),
+    its transposed h_k = sum_j g_j w_j^{xi_k} (the g(xi) of Sect. 4) and its
+    adjoint h_k = sum_j g_j conj(w_j^{xi_k}); w_j = exp(2 pi i z_j), principal
+    power with Re z reduced to (-1/2, 1/2].  Error <= eps * sum |coefficients|.
+
+    ``xi`` (real) and ``z`` (complex, Im z >= 0) are host arrays or tensors,
+    copied.  The plan owns its device memory (tables, the inner batched
+    integer plan, its buffers): calls on one plan must not overlap."""
+
+    def __init__(self, xi, z, eps, dtype="complex64", device=None, host_only=False):
+        self._lib = L.load()
+        self._ptr = ctypes.c_void_p()
+        xh = np.ascontiguousarray(_as_host_real(xi))
+        zh = _as_host_z(z)
+        self.N, self.M = int(xh.shape[0]), int(zh.shape[0])
+        self.dtype_code = _dtype_code(dtype)
+        self.host_only = bool(host_only)
+        D = ctypes.POINTER(ctypes.c_double)
+
+        def create():
+            L.check(self._lib.flt_xi_plan_create(ctypes.byref(self._ptr), self.N, xh.ctypes.data_as(D), self.M,
+                                                 zh.ctypes.data_as(D), float(eps), self.dtype_code,
+                                                 L.FLT_FLAG_HOST_ONLY if host_only else 0),
+                    "flt_xi_plan_create")
+
+        if host_only:
+            create()
+            self.device = None
+            return
+        import torch
+        self.device = torch.device(device if device is not None else "cuda")
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            create()
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.complex64 if self.dtype_code == L.FLT_C64 else torch.complex128
+
+    def info(self):
+        o = L.FltXiInfo()
+        L.check(self._lib.flt_xi_plan_info(self._ptr, ctypes.byref(o)), "flt_xi_plan_info")
+        return {k: getattr(o, k) for k, _ in L.FltXiInfo._fields_}
+
+    def _call(self, fn, x, nin, nout, out, name):
+        import torch
+        if self.host_only:
+            raise RuntimeError("host-only plan")
+        x = _check_tensor(x, nin, "input", self.torch_dtype, self.device).contiguous()
+        if out is None:
+            out = torch.empty(nout, dtype=self.torch_dtype, device=self.device)
+        else:
+            out = _check_out(out, nout, "out", self.torch_dtype, self.device)
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        L.check(fn(self._ptr, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                   ctypes.c_void_p(stream)), name)
+        return out
+
+    def forward(self, c, out=None):
+        """f_j = sum_k c_k w_j^{xi_k}; c: complex[N] on the device, order of xi."""
+        return self._call(self._lib.flt_xi_forward, c, self.N, self.M, out, "flt_xi_forward")
+
+    def transposed(self, g, out=None):
+        """h_k = sum_j g_j w_j^{xi_k}; g: complex[M] on the device."""
+        return self._call(self._lib.flt_xi_transposed, g, self.M, self.N, out, "flt_xi_transposed")
+
+    def adjoint(self, g, out=None):
+        """h_k = sum_j g_j conj(w_j^{xi_k}); g: complex[M] on the device."""
+        return self._call(self._lib.flt_xi_adjoint, g, self.M, self.N, out, "flt_xi_adjoint")
+
+    def close(self):
+        if getattr(self, "_ptr", None) and self._ptr.value:
+            if self.device is not None:
+                import torch
+                torch.cuda.synchronize(self.device)
+            self._lib.flt_xi_plan_destroy(self._ptr)
+            self._ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

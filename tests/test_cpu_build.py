@@ -49,7 +49,7 @@ def run(lib, x, z, eps, dt, op, N, flags):
 CASES = [(300, 120, 1e-6, 1), (256, 100, 1e-10, 2), (2100, 60, 1e-9, 2), (4200, 40, 1e-6, 1), (2, 9, 1e-8, 2),
          (300, 3000, 1e-6, 1), (200, 2500, 1e-11, 2),   # these two fill low bands densely (LDS tiles)
          (70000, 40, 1e-6, 1),   # grids up to 2^18 points: pass A's output twiddles from the LDS power table
-         (300, 16000, 1e-6, 1)]   # bands of more nodes than a fused one-pass task takes
+         (300, 16000, 1e-6, 1)]   # dense bands: the gather's staged runs of cells
 
 
 @pytest.mark.parametrize("N,M,eps,dt", CASES)
