@@ -501,6 +501,9 @@ def main():
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd step at N = M = 2^18")
     ap.add_argument("--no-xi", action="store_true", help="skip the real-exponent leg")
     ap.add_argument("--xi-log2n", type=int, default=20, help="log2 N = log2 M of the real-exponent leg")
+    ap.add_argument("--only", choices=["batched", "xi", "laplace"],
+                    help="run this side leg alone and print its record instead of the benchmark line "
+                         "(for profiling one workload's kernels)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (a known-size reference "
                          "for HBM counter readings)")
@@ -526,6 +529,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        tune = not args.no_autotune
+        leg = {"batched": lambda: batched_leg(torch, dev, args, tune, log),
+               "xi": lambda: xi_leg(torch, dev, args, log),
+               "laplace": lambda: laplace_leg(torch, dev, args, log)}[args.only]
+        rec, _ = leg()
+        print(json.dumps({"only": args.only, args.only: rec}, default=float), flush=True)
+        return
     copy_gbs = copy_bandwidth(torch, dev)
     log("device-to-device copy %.1f GB/s" % copy_gbs)
     w = inputs.workload("large")
