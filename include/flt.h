@@ -221,12 +221,17 @@ int flt_profile_adjoint(flt_plan* plan, const void* g, void* c_out, void* stream
  * ------------------------------------------------------------------------ */
 typedef struct flt_laplace_plan flt_laplace_plan;
 
+/* Kernels of flt_laplace_plan_create_kernel (Thm 3.3 and its example). */
+#define FLT_KERNEL_EXP          0 /* exp(-y xi): Algorithm 1 */
+#define FLT_KERNEL_BESSEL_K_HALF 1 /* K_{1/2}(y xi) = sqrt(pi / (2 y xi)) exp(-y xi), asymptotically smooth */
+
 typedef struct flt_laplace_info {
     int64_t N, M;            /* frequencies, nodes */
     int32_t dtype;           /* FLT_C64 or FLT_C128 */
     int32_t q;               /* Chebyshev rank, ceil(1/2 + log4(1/eps)) */
-    int32_t levels;          /* the paper's M, ceil(log2(y_1 xi_1 / eps)) + 1 (1 if every y_j = 0) */
-    int32_t pad;
+    int32_t levels;          /* the paper's M: ceil(log2(y_1 xi_1 / eps)) + 1 (1 if every y_j = 0) for
+                                FLT_KERNEL_EXP, ceil(log2(y_1 xi_1 N / eps)) + 1 for general kernels */
+    int32_t kernel;          /* FLT_KERNEL_* */
     double eps, y1, xi1;     /* target accuracy and the interval lengths */
 } flt_laplace_info;
 
@@ -242,6 +247,23 @@ typedef struct flt_laplace_info {
  * for FLT_C64, 1e-14 for FLT_C128), FLT_ERANGE, FLT_EHIP, FLT_ENOMEM. */
 int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi, int64_t M, const double* y,
                             double eps, int dtype, uint32_t flags);
+/* General asymptotically smooth kernels (Thm 3.3): f_j = sum_k fhat_k kappa(y_j, xi_k) with
+ * kappa = FLT_KERNEL_BESSEL_K_HALF (the paper's example) or FLT_KERNEL_EXP (the same as
+ * flt_laplace_plan_create).  For a general kernel every frequency block l < M is interpolated in
+ * every band m < M (no blocks dropped or folded: the kernel is neither ~0 nor ~1 there), with
+ * M = ceil(log2(y_1 xi_1 N / eps)) + 1 levels; the near fields (frequencies in Omega_M for every
+ * node, every frequency for the nodes of Y_M) are summed directly.  The rank q is the smallest
+ * whose tensor Chebyshev interpolant of the kernel is within (eps / 2) max(1, max |kappa|) of it
+ * on every block, on a 33 x 33 grid per block (the per-block condition of the theorem's proof,
+ * taken from the kernel itself rather than from its asymptotic-smoothness constants; relative to
+ * the kernel's size where it exceeds 1, near the origin, where no floating-point sum is absolutely
+ * within eps).  Error <= (eps / 2) sum_k |fhat_k| max(1, kappa(y_j xi_k / 4)) (the block maximum of
+ * a kernel decreasing in y xi is at most its value at y xi / 4).
+ * FLT_KERNEL_BESSEL_K_HALF needs y_j > 0 (FLT_EDOMAIN otherwise: the kernel is singular at 0);
+ * FLT_EPRECISION if no rank up to 32 is enough.  Other arguments and errors as
+ * flt_laplace_plan_create; the forward is flt_laplace_forward. */
+int flt_laplace_plan_create_kernel(flt_laplace_plan** out, int32_t kernel, int64_t N, const double* xi, int64_t M,
+                                   const double* y, double eps, int dtype, uint32_t flags);
 int flt_laplace_plan_info(const flt_laplace_plan* plan, flt_laplace_info* out);
 /* f[j] ~ sum_k fhat_k exp(-y_j xi_k).  fhat: device complex[N] of the plan's
  * dtype, in the order xi was given; f: device complex[M], overwritten. */

@@ -5,6 +5,8 @@ Sect. 3: f = K fhat with K = (exp(-y_j xi_k)) for real frequencies xi_k > 0
 and real nodes y_j >= 0.
 
 ``direct``  the plain definition, f_j = sum_k fhat_k exp(-y_j xi_k), FP64.
+``direct_kernel``  the same sum for another kernel kappa(y_j, xi_k) (Thm 3.3):
+            "bessel_k_half", the example K_{1/2}(y xi) = sqrt(pi / (2 y xi)) e^{-y xi}.
 ``alg1``    the paper's Algorithm 1 step by step in numpy FP64 (partition of
             Def. 3.2, the approximant of Thm A.3): cumulative block sums g_m,
             block moments v = (L^Omega)^T fhat, h^{Y_m} = sum_l K^{Y_m,Omega_l} v,
@@ -32,6 +34,28 @@ def direct(fhat, xi, y, block=2048):
     out = np.zeros(len(y), np.complex128)
     for s in range(0, len(y), block):
         out[s:s + block] = np.exp(-np.outer(y[s:s + block], xi)) @ fhat
+    return out
+
+
+def bessel_k_half(x):
+    """K_{1/2}(x) = sqrt(pi / (2 x)) e^{-x} (x > 0), the closed form the paper's
+    example states for its integral definition."""
+    x = np.asarray(x, np.float64)
+    return np.sqrt(np.pi / (2.0 * x)) * np.exp(-x)
+
+
+def direct_kernel(fhat, xi, y, kernel, block=2048):
+    """f_j = sum_k fhat_k kappa(y_j, xi_k) in FP64, rows in blocks."""
+    fhat = np.asarray(fhat, np.complex128)
+    xi = np.asarray(xi, np.float64)
+    y = np.asarray(y, np.float64)
+    if kernel == "exp":
+        return direct(fhat, xi, y, block)
+    if kernel != "bessel_k_half":
+        raise ValueError(kernel)
+    out = np.zeros(len(y), np.complex128)
+    for s in range(0, len(y), block):
+        out[s:s + block] = bessel_k_half(np.outer(y[s:s + block], xi)) @ fhat
     return out
 
 

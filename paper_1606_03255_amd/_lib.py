@@ -28,7 +28,8 @@ EXPORTS = (
     "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
     "flt_forward_derivative", "flt_forward_noalloc", "flt_profile_forward", "flt_profile_adjoint", "flt_strerror", "flt_last_hip_error",
-    "flt_laplace_plan_create", "flt_laplace_plan_info", "flt_laplace_forward", "flt_laplace_plan_destroy",
+    "flt_laplace_plan_create", "flt_laplace_plan_create_kernel", "flt_laplace_plan_info", "flt_laplace_forward",
+    "flt_laplace_plan_destroy",
     "flt_xi_plan_create", "flt_xi_plan_info", "flt_xi_forward", "flt_xi_transposed", "flt_xi_adjoint",
     "flt_xi_plan_destroy",
 )
@@ -59,7 +60,7 @@ class FltBandInfo(ctypes.Structure):
 class FltLaplaceInfo(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int64), ("M", ctypes.c_int64),
-        ("dtype", ctypes.c_int32), ("q", ctypes.c_int32), ("levels", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("dtype", ctypes.c_int32), ("q", ctypes.c_int32), ("levels", ctypes.c_int32), ("kernel", ctypes.c_int32),
         ("eps", ctypes.c_double), ("y1", ctypes.c_double), ("xi1", ctypes.c_double),
     ]
 
@@ -116,6 +117,9 @@ def load():
     lib.flt_forward_noalloc.argtypes = [vp, vp, vp, vp]
     lib.flt_laplace_plan_create.argtypes = [P(vp), ctypes.c_int64, P(ctypes.c_double), ctypes.c_int64,
                                             P(ctypes.c_double), ctypes.c_double, ctypes.c_int, ctypes.c_uint32]
+    lib.flt_laplace_plan_create_kernel.argtypes = [P(vp), ctypes.c_int32, ctypes.c_int64, P(ctypes.c_double),
+                                                   ctypes.c_int64, P(ctypes.c_double), ctypes.c_double, ctypes.c_int,
+                                                   ctypes.c_uint32]
     lib.flt_laplace_plan_info.argtypes = [vp, P(FltLaplaceInfo)]
     lib.flt_laplace_forward.argtypes = [vp, vp, vp, vp]
     lib.flt_laplace_plan_destroy.argtypes = [vp]

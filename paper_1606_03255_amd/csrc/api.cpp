@@ -744,14 +744,21 @@ extern "C" {
 int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi, int64_t M, const double* y,
                             double eps, int dtype, uint32_t flags)
 {
+    return flt_laplace_plan_create_kernel(out, FLT_KERNEL_EXP, N, xi, M, y, eps, dtype, flags);
+}
+
+int flt_laplace_plan_create_kernel(flt_laplace_plan** out, int32_t kernel, int64_t N, const double* xi, int64_t M,
+                                   const double* y, double eps, int dtype, uint32_t flags)
+{
     if (!out) return FLT_EINVAL;
     *out = nullptr;
+    if (kernel != FLT_KERNEL_EXP && kernel != FLT_KERNEL_BESSEL_K_HALF) return FLT_EINVAL;
     if (flags & ~FLT_FLAG_HOST_ONLY) return FLT_EINVAL;
     flt_laplace_plan* p = new (std::nothrow) flt_laplace_plan();
     if (!p) return FLT_ENOMEM;
     int rc;
     try {
-        rc = build_laplace_plan(p->hp, N, xi, M, y, eps, dtype);
+        rc = build_laplace_plan(p->hp, N, xi, M, y, eps, dtype, kernel);
     } catch (const std::bad_alloc&) {
         rc = FLT_ENOMEM;
     }
@@ -787,6 +794,10 @@ int flt_laplace_plan_create(flt_laplace_plan** out, int64_t N, const double* xi,
         LapView& V = p->V;
         V.q = hp.q;
         V.L = hp.L;
+        V.kernel = hp.kernel;
+        V.near0 = hp.near0;
+        V.nnear = hp.nnear;
+        V.N = hp.N;
         V.xs = (const double*)(b + o_xs);
         V.kperm = (const int32_t*)(b + o_kp);
         V.bcw = (const double*)(b + o_bc);
@@ -817,6 +828,7 @@ int flt_laplace_plan_info(const flt_laplace_plan* p, flt_laplace_info* o)
     o->dtype = p->hp.dtype;
     o->q = p->hp.q;
     o->levels = p->hp.L;
+    o->kernel = p->hp.kernel;
     o->eps = p->hp.eps;
     o->y1 = p->hp.y1;
     o->xi1 = p->hp.xi1;

@@ -323,6 +323,10 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
     LapView V{};
     V.q = hp.q;
     V.L = hp.L;
+    V.kernel = hp.kernel;
+    V.near0 = hp.near0;
+    V.nnear = hp.nnear;
+    V.N = hp.N;
     V.xs = hp.xs.data();
     V.kperm = hp.kperm.data();
     V.bcw = hp.bcw.data();
@@ -348,7 +352,8 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
         const int64_t per = (int64_t)LAP_THREADS * LAP_NODE_PER, ns = lap_node_stage(hp.L, hp.q);
         std::vector<double> sb((size_t)std::max<int64_t>(ns, 1));
         run_blocks((hp.M + per - 1) / per, LAP_THREADS, [&](const HostCtx& ctx) {
-            lap_body_nodes<HostCtx, T, QB>(ctx, V, hp.M, (cplx<T>*)out, ns > 0 ? sb.data() : nullptr);
+            lap_body_nodes<HostCtx, T, QB>(ctx, V, hp.M, (cplx<T>*)out, ns > 0 ? sb.data() : nullptr,
+                                           (const cplx<T>*)in);
         });
     };
     switch (lap_qbucket(hp.q)) {
@@ -456,6 +461,16 @@ extern "C" int flt_emu_laplace(int64_t N, const double* xi, int64_t M, const dou
 {
     flt::LapHost hp;
     int rc = flt::build_laplace_plan(hp, N, xi, M, y, eps, dtype);
+    if (rc != FLT_OK) return rc;
+    return dtype == FLT_C64 ? flt::emu_laplace<float>(hp, in, out) : flt::emu_laplace<double>(hp, in, out);
+}
+
+// The same for a chosen kernel (FLT_KERNEL_*, see flt_laplace_plan_create_kernel).
+extern "C" int flt_emu_laplace_kernel(int kernel, int64_t N, const double* xi, int64_t M, const double* y,
+                                      double eps, int dtype, const void* in, void* out)
+{
+    flt::LapHost hp;
+    int rc = flt::build_laplace_plan(hp, N, xi, M, y, eps, dtype, kernel);
     if (rc != FLT_OK) return rc;
     return dtype == FLT_C64 ? flt::emu_laplace<float>(hp, in, out) : flt::emu_laplace<double>(hp, in, out);
 }

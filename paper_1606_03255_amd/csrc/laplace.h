@@ -39,8 +39,20 @@ struct LapItem {
 // The plan as the kernels read it (device or host pointers).  Levels are
 // 1..L (the paper's M): blocks Omega_l and bands Y_m, l, m < L interpolated,
 // Omega_L and Y_L the intervals at 0.
+// Kernels (Sect. 3; Thm 3.3 and its example): 0 exp(-y xi) by Algorithm 1;
+// 1 K_{1/2}(y xi) = sqrt(pi / (2 y xi)) exp(-y xi), asymptotically smooth: every
+// block l < L interpolated, the near fields Omega_L and Y_L summed directly.
+constexpr int LAP_KERNEL_EXP = 0;
+constexpr int LAP_KERNEL_K12 = 1;
+
+FLT_HD double lap_kernel_k12(double x) { return sqrt(1.5707963267948966192 / x) * exp(-x); }
+
 struct LapView {
     int32_t q, L;
+    int32_t kernel;          // LAP_KERNEL_*
+    int32_t pad;
+    int64_t near0, nnear;    // general kernels: the sorted frequencies of Omega_L (near field)
+    int64_t N;
     const double* xs;        // frequencies sorted by block
     const int32_t* kperm;    // caller index of each sorted frequency
     const double* bcw;       // 2 (l - 1): centre, 1 / half-width of Omega_l's closure
@@ -67,6 +79,8 @@ FLT_HD int64_t lap_acc_doubles(int L, int q) { return 2 * (2 * (int64_t)L * q + 
 struct LapHost {
     int64_t N = 0, M = 0;
     int dtype = 0;
+    int kernel = LAP_KERNEL_EXP;
+    int64_t near0 = 0, nnear = 0;   // general kernels: Omega_L's sorted frequencies
     double eps = 0, y1 = 0, xi1 = 0;
     int q = 0, L = 1;
     std::vector<double> xs, bcw, ycw, K, y;
@@ -77,7 +91,7 @@ struct LapHost {
 
 // Builds the plan (Def. 3.2 partition, tables); FLT_OK or an FLT_E* code.
 int build_laplace_plan(LapHost& hp, int64_t N, const double* xi, int64_t M, const double* y, double eps,
-                       int dtype);
+                       int dtype, int kernel = LAP_KERNEL_EXP);
 
 // ---------------------------------------------------------------------------
 // Kernels (bodies).  Ctx supplies tid(), ntid(), bid() and sync().
@@ -227,7 +241,9 @@ FLT_HD void lap_body_bands(const Ctx& ctx, const LapView& V, double* red)
                 }
         }
     }
-    const int g0 = m < L ? V.Lm[m - 1] + 1 : 1;   // g_{g0} = sum_{l = g0}^{L} S_l
+    // g_{g0} = sum_{l = g0}^{L} S_l (Algorithm 1's blocks where the kernel is 1;
+    // general kernels have none: their near field is summed at the nodes)
+    const int g0 = V.kernel != LAP_KERNEL_EXP ? L + 1 : m < L ? V.Lm[m - 1] + 1 : 1;
     double gr = 0.0, gi = 0.0;
     for (int l = g0 + tid; l <= L; l += LAP_THREADS) {
         gr += V.acc[lap_S(L, q, l)];
@@ -244,7 +260,7 @@ FLT_HD void lap_body_bands(const Ctx& ctx, const LapView& V, double* red)
             tr += red[2 * (tid + v)];
             ti += red[2 * (tid + v) + 1];
         }
-        if (s == 0) {
+        if (s == 0 && g0 <= L) {
             const int n = L - g0 + 1 < LAP_THREADS ? L - g0 + 1 : LAP_THREADS;
             for (int v = 0; v < n; ++v) {
                 tr += red[2 * LAP_THREADS + 2 * v];
@@ -256,7 +272,7 @@ FLT_HD void lap_body_bands(const Ctx& ctx, const LapView& V, double* red)
     }
     if (m == L && tid < q) {
         double tr = 0.0, ti = 0.0;
-        if (tid == 0) {
+        if (tid == 0 && V.kernel == LAP_KERNEL_EXP) {
             const int n = L < LAP_THREADS ? L : LAP_THREADS;
             for (int v = 0; v < n; ++v) {
                 tr += red[2 * LAP_THREADS + 2 * v];
@@ -281,8 +297,25 @@ FLT_HD int64_t lap_node_stage(int L, int q)
 // LAP_NODE_PER nodes per thread, their loads issued at once; the band data
 // read from LDS (sb, lap_node_stage doubles, staged by the workgroup) when
 // sb is set, else from global memory.
+// General kernels add the near fields directly: for a node of band m < L the
+// frequencies of Omega_L, for a node of Y_L all of them (FP64 sums).
+template <typename T>
+FLT_HD void lap_near(const LapView& V, const cplx<T>* fhat, double y, int64_t k0, int64_t k1, double* sr, double* si)
+{
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = k0; i < k1; ++i) {
+        const double w = lap_kernel_k12(y * V.xs[i]);
+        const cplx<T> v = fhat[V.kperm[i]];
+        ar += w * (double)v.x;
+        ai += w * (double)v.y;
+    }
+    *sr += ar;
+    *si += ai;
+}
+
 template <class Ctx, typename T, int QB>
-FLT_HD void lap_body_nodes(const Ctx& ctx, const LapView& V, int64_t M, cplx<T>* f, double* sb)
+FLT_HD void lap_body_nodes(const Ctx& ctx, const LapView& V, int64_t M, cplx<T>* f, double* sb,
+                           const cplx<T>* fhat)
 {
     const int q = V.q, L = V.L, tid = ctx.tid();
     int m[LAP_NODE_PER];
@@ -326,7 +359,12 @@ FLT_HD void lap_body_nodes(const Ctx& ctx, const LapView& V, int64_t M, cplx<T>*
                 b1i = ni;
             }
         const int64_t j = j0 + (int64_t)k * ctx.ntid();
-        if (j < M) f[j] = mk<T>((T)(br[0] + t * b1r - b2r), (T)(bi[0] + t * b1i - b2i));
+        double fr = br[0] + t * b1r - b2r, fi = bi[0] + t * b1i - b2i;
+        if (V.kernel != LAP_KERNEL_EXP && j < M) {
+            if (m[k] < L) lap_near(V, fhat, yv[k], V.near0, V.near0 + V.nnear, &fr, &fi);
+            else lap_near(V, fhat, yv[k], 0, V.N, &fr, &fi);
+        }
+        if (j < M) f[j] = mk<T>((T)fr, (T)fi);
     }
 }
 

@@ -35,10 +35,11 @@ __global__ __launch_bounds__(LAP_THREADS) void k_lap_bands(LapView V)
 }
 
 template <typename T, int QB>
-__global__ __launch_bounds__(LAP_THREADS) void k_lap_nodes(LapView V, int64_t M, cplx<T>* f, int staged)
+__global__ __launch_bounds__(LAP_THREADS) void k_lap_nodes(LapView V, int64_t M, cplx<T>* f, int staged,
+                                                             const cplx<T>* fhat)
 {
     extern __shared__ double sb[];   // lap_node_stage(L, q) doubles when staged
-    lap_body_nodes<LapCtx, T, QB>(LapCtx(), V, M, f, staged ? sb : nullptr);
+    lap_body_nodes<LapCtx, T, QB>(LapCtx(), V, M, f, staged ? sb : nullptr, fhat);
 }
 
 // Item partials of the block moments, their sum per block, band side, node
@@ -55,7 +56,8 @@ static void launch_all(LaunchStatus& ls, const LapView& V, const LapItem* items,
     ls.launched();
     const int64_t per = (int64_t)LAP_THREADS * LAP_NODE_PER, ns = lap_node_stage(V.L, V.q);
     hipLaunchKernelGGL((k_lap_nodes<T, QB>), dim3((unsigned)((M + per - 1) / per)), dim3(LAP_THREADS),
-                       (unsigned)(ns * sizeof(double)), st, V, M, (cplx<T>*)f, ns > 0 ? 1 : 0);
+                       (unsigned)(ns * sizeof(double)), st, V, M, (cplx<T>*)f, ns > 0 ? 1 : 0,
+                       (const cplx<T>*)fhat);
     ls.launched();
 }
 

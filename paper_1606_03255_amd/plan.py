@@ -335,16 +335,21 @@ def fourier_laplace(c, z, plan):
     return _FL.apply(c, z, plan)
 
 
+KERNELS = {"exp": 0, "bessel_k_half": 1}
+
+
 class LaplacePlan:
     """The discrete Laplace transform f_j = sum_k fhat_k exp(-y_j xi_k)
-    (xi_k > 0, y_j >= 0) by Algorithm 1, error <= eps * sum |fhat_k|.
+    (xi_k > 0, y_j >= 0) by Algorithm 1, error <= eps * sum |fhat_k|; with
+    ``kernel="bessel_k_half"`` the asymptotically smooth kernel
+    K_{1/2}(y xi) = sqrt(pi / (2 y xi)) exp(-y xi) of Thm 3.3's example (y_j > 0).
 
     ``xi`` and ``y`` are real (host arrays or tensors, copied); ``dtype``
     sets the type of fhat and f (the arithmetic is FP64 either way).  The
     plan owns its small device accumulator: calls on one plan must not
     overlap."""
 
-    def __init__(self, xi, y, eps, dtype="complex64", device=None, host_only=False):
+    def __init__(self, xi, y, eps, dtype="complex64", device=None, host_only=False, kernel="exp"):
         self._lib = L.load()
         self._ptr = ctypes.c_void_p()
         xh = np.ascontiguousarray(_as_host_real(xi))
@@ -354,11 +359,15 @@ class LaplacePlan:
         self.host_only = bool(host_only)
         D = ctypes.POINTER(ctypes.c_double)
 
+        if kernel not in KERNELS:
+            raise ValueError("kernel must be one of %s" % sorted(KERNELS))
+
         def create():
-            L.check(self._lib.flt_laplace_plan_create(ctypes.byref(self._ptr), self.N, xh.ctypes.data_as(D), self.M,
-                                                      yh.ctypes.data_as(D), float(eps), self.dtype_code,
-                                                      L.FLT_FLAG_HOST_ONLY if host_only else 0),
-                    "flt_laplace_plan_create")
+            L.check(self._lib.flt_laplace_plan_create_kernel(ctypes.byref(self._ptr), KERNELS[kernel], self.N,
+                                                             xh.ctypes.data_as(D), self.M, yh.ctypes.data_as(D),
+                                                             float(eps), self.dtype_code,
+                                                             L.FLT_FLAG_HOST_ONLY if host_only else 0),
+                    "flt_laplace_plan_create_kernel")
 
         if host_only:
             create()
@@ -379,7 +388,7 @@ class LaplacePlan:
     def info(self):
         o = L.FltLaplaceInfo()
         L.check(self._lib.flt_laplace_plan_info(self._ptr, ctypes.byref(o)), "flt_laplace_plan_info")
-        return {k: getattr(o, k) for k, _ in L.FltLaplaceInfo._fields_ if k != "pad"}
+        return {k: getattr(o, k) for k, _ in L.FltLaplaceInfo._fields_}
 
     def forward(self, fhat, out=None):
         """f_j ~ sum_k fhat_k exp(-y_j xi_k); fhat: complex[N] on the device."""

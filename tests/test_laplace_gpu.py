@@ -112,3 +112,55 @@ def test_laplace_wide_range(torch):
     n1 = np.abs(fhat).sum()
     assert np.abs(f - LP.direct(fhat, xi, y)).max() <= eps * n1
     assert np.abs(f - LP.alg1(fhat, xi, y, eps)).max() <= 1e-13 * n1
+
+
+# ---- Thm 3.3's example kernel K_{1/2}(y xi) (block-relative bar, see
+# tests/test_laplace_kernel_cpu.py)
+def _k12_bar(fhat, xi, y, eps):
+    w = np.maximum(1.0, LP.bessel_k_half(np.outer(y, xi) / 4.0))
+    return eps * (w @ np.abs(fhat))
+
+
+def _k12_inputs(seed, N, M):
+    rng = np.random.default_rng(seed)
+    xi = rng.random(N) * N + 1e-3
+    y = rng.random(M) * (20.0 / N) + 1e-9
+    if N > 4 and M > 4:
+        xi[:3] = [1e-12, 3e-11, 1e-9]
+        y[:3] = [1e-18, 4e-17, 2e-15]
+    fhat = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    return fhat, xi, y
+
+
+@pytest.mark.parametrize("N,M,eps,dtype", [(1000, 700, 1e-6, "c64"), (3000, 2000, 1e-11, "c128"),
+                                           (65537, 1500, 1e-6, "c64"), (1, 3, 1e-8, "c128")])
+def test_k12_vs_direct(torch, N, M, eps, dtype):
+    from paper_1606_03255_amd import LaplacePlan
+    _say("k12", N, M, eps, dtype)
+    fhat, xi, y = _k12_inputs(N + M, N, M)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    if dtype == "c64":
+        fhat = fhat.astype(np.complex64).astype(np.complex128)
+    plan = LaplacePlan(xi, y, eps, tdt, kernel="bessel_k_half")
+    f = plan.forward(torch.from_numpy(fhat).to("cuda", tdt)).cpu().numpy().astype(np.complex128)
+    plan.close()
+    r = np.abs(f - LP.direct_kernel(fhat, xi, y, "bessel_k_half")) / _k12_bar(fhat, xi, y, eps)
+    _say("  error / bar %.3g" % r.max())
+    assert r.max() <= 1.0
+
+
+def test_k12_benchmark_size_sampled(torch):
+    from paper_1606_03255_amd import LaplacePlan
+    N = M = 1 << 20
+    rng = np.random.default_rng(21)
+    xi = rng.random(N) * N + 1e-3
+    y = rng.random(M) * (20.0 / N) + 1e-9
+    fhat = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+    plan = LaplacePlan(xi, y, 1e-6, torch.complex64, kernel="bessel_k_half")
+    f = plan.forward(torch.from_numpy(fhat).to("cuda")).cpu().numpy().astype(np.complex128)
+    plan.close()
+    sel = np.sort(rng.choice(M, 48, replace=False))
+    fh = fhat.astype(np.complex128)
+    r = np.abs(f[sel] - LP.direct_kernel(fh, xi, y[sel], "bessel_k_half")) / _k12_bar(fh, xi, y[sel], 1e-6)
+    _say("k12 2^20 error / bar %.3g" % r.max())
+    assert r.max() <= 1.0

@@ -1,7 +1,9 @@
 """Pins of the Laplace-transform oracle (Sect. 3, Algorithm 1, Thm A.3)
 against facts other than its own formulas: a closed-form geometric sum, the
 hot path's pinned oracle at x = 0 (eq. 4.2 with Re z = 0), exact cases of the
-approximant, and the error bound of Thm A.3 against the direct sums."""
+approximant, and the error bound of Thm A.3 against the direct sums; the
+K_{1/2} kernel of Thm 3.3's example against the library's kv, its integral
+definition and mpmath."""
 import numpy as np
 import pytest
 
@@ -83,3 +85,42 @@ def test_alg1_dropping_a_part_fails():
         if m < P["M"]:
             broken[j] -= g[P["Lm"][m] + 1]
     assert np.abs(broken - ref).max() > 1e3 * eps * N
+
+
+# ---- the asymptotically smooth kernel of Thm 3.3's example
+def test_bessel_k_half_closed_form_is_the_library_kv():
+    scipy_special = pytest.importorskip("scipy.special")
+    x = np.geomspace(1e-8, 40.0, 200)
+    ref = scipy_special.kv(0.5, x)
+    assert np.allclose(LP.bessel_k_half(x), ref, rtol=1e-13, atol=0)
+
+
+def test_bessel_k_half_closed_form_is_the_integral_definition():
+    # K_eta(x) = int_0^inf exp(-x cosh t) cosh(eta t) dt, eta = 1/2 (the paper's definition)
+    integrate = pytest.importorskip("scipy.integrate")
+    for x in (0.01, 0.3, 1.0, 2.5, 7.0):
+        top = np.arccosh(750.0 / x)   # beyond it the integrand is below e^-750
+        val, err = integrate.quad(lambda t: np.exp(-x * np.cosh(t)) * np.cosh(0.5 * t), 0, top, limit=400)
+        assert abs(val - LP.bessel_k_half(x)) <= 1e-10 * val
+
+
+def test_direct_kernel_mpmath_tiny():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 30
+    rng = np.random.default_rng(41)
+    xi = rng.random(9) * 20 + 1e-3
+    y = rng.random(7) * 0.5 + 1e-4
+    fh = rng.standard_normal(9) + 1j * rng.standard_normal(9)
+    got = LP.direct_kernel(fh, xi, y, "bessel_k_half")
+    for j in range(len(y)):
+        ref = sum(mpmath.mpc(complex(fh[k])) * mpmath.besselk(0.5, mpmath.mpf(float(y[j])) * mpmath.mpf(float(xi[k])))
+                  for k in range(len(xi)))
+        assert abs(complex(ref) - got[j]) <= 1e-14 * np.abs(fh).sum() * float(LP.bessel_k_half(y[j] * xi.min()))
+
+
+def test_direct_kernel_exp_is_direct():
+    rng = np.random.default_rng(42)
+    xi = rng.random(50) * 50
+    y = rng.random(30)
+    fh = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    assert np.array_equal(LP.direct_kernel(fh, xi, y, "exp"), LP.direct(fh, xi, y))
