@@ -131,11 +131,12 @@ def test_cpu_build_batched_equals_single_instances(emu):
 
 @pytest.mark.skipif(os.environ.get("FLT_EMU_LIB") is not None, reason="already the sanitizer run")
 @pytest.mark.skipif(os.environ.get("FLT_ASAN") != "1",
-                    reason="about 4 minutes (2 of them the sanitizer build); run with FLT_ASAN=1")
+                    reason="about 8 minutes (2 of them the sanitizer build); run with FLT_ASAN=1")
 def test_cpu_build_under_address_sanitizer():
-    """A one-pass case (complex64, band policy on) and a two-pass case
-    (complex128, NFFT only) of the test above, forward, derivative, adjoint
-    and the fused call each, on the
+    """A one-pass case (complex64, band policy on), a two-pass case
+    (complex128, NFFT only) and a dense case (the gather's staged runs of
+    cells) of the test above, forward, derivative, adjoint and the fused call
+    each, a real-exponent case and the general-kernel Laplace tests, on the
     bodies built with AddressSanitizer and UndefinedBehaviorSanitizer (every
     buffer exactly sized): any out-of-bounds access or undefined operation
     aborts the child run."""
@@ -146,7 +147,9 @@ def test_cpu_build_under_address_sanitizer():
                ASAN_OPTIONS="detect_leaks=0:halt_on_error=1:abort_on_error=1",
                UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(HERE, "test_cpu_build.py"), "-k", "0-300-120-1e-06-1 or 2-2100-60-1e-09-2"],
+                        os.path.join(HERE, "test_cpu_build.py"), os.path.join(HERE, "test_cpu_xi.py"),
+                        os.path.join(HERE, "test_laplace_kernel_cpu.py"), "-k",
+                        "0-300-120-1e-06-1 or 2-2100-60-1e-09-2 or 0-300-3000-1e-06-1 or 200-300-1e-06-1 or k12"],
                        cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
-    assert "2 passed" in r.stdout, r.stdout[-2000:]
+    assert "12 passed" in r.stdout, r.stdout[-2000:]

@@ -14,7 +14,7 @@ from paper_1606_03255_amd import LaplacePlan
 from paper_1606_03255_amd import _lib as L
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-EMU = os.path.join(os.path.dirname(HERE), "paper_1606_03255_amd", "libflt_emu.so")
+EMU = os.environ.get("FLT_EMU_LIB", os.path.join(os.path.dirname(HERE), "paper_1606_03255_amd", "libflt_emu.so"))
 
 
 @pytest.fixture(scope="module")
