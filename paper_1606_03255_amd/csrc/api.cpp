@@ -109,7 +109,8 @@ static int upload(flt_plan* p)
     const size_t o_l3 = pk.add(hp.onepass_adj.data(), hp.onepass_adj.size() * sizeof(FftItem));
     const size_t o_l4 = pk.add(hp.passA_adj.data(), hp.passA_adj.size() * sizeof(FftItem));
     const size_t o_lf2 = pk.add(hp.passB_fused.data(), hp.passB_fused.size() * sizeof(FftItem));
-    const size_t o_l5 = pk.add(hp.nodes.data(), hp.nodes.size() * sizeof(NodeItem));
+    const size_t o_l5 = pk.add(hp.gather_st.data(), hp.gather_st.size() * sizeof(NodeItem));
+    const size_t o_l5b = pk.add(hp.gather_ln.data(), hp.gather_ln.size() * sizeof(NodeItem));
     const size_t o_l6 = pk.add(hp.cells.data(), hp.cells.size() * sizeof(CellItem));
     const size_t o_l7 = pk.add(hp.nfft_nodes.data(), hp.nfft_nodes.size() * sizeof(NodeItem));
     const size_t o_l8 = pk.add(hp.direct_fwd.data(), hp.direct_fwd.size() * sizeof(DirectItem));
@@ -141,7 +142,8 @@ static int upload(flt_plan* p)
     L.passA_adj = (const FftItem*)(base + o_l4);
     L.passB_fused = (const FftItem*)(base + o_lf2);
     L.n_passB_fused = (int)hp.passB_fused.size();
-    L.nodes = (const NodeItem*)(base + o_l5);
+    L.gather_st = (const NodeItem*)(base + o_l5);
+    L.gather_ln = (const NodeItem*)(base + o_l5b);
     L.cells = (const CellItem*)(base + o_l6);
     L.nfft_nodes = (const NodeItem*)(base + o_l7);
     L.direct_fwd = (const DirectItem*)(base + o_l8);
@@ -159,7 +161,8 @@ static int upload(flt_plan* p)
     L.n_passB = (int)hp.passB.size();
     L.n_onepass_adj = (int)hp.onepass_adj.size();
     L.n_passA_adj = (int)hp.passA_adj.size();
-    L.n_nodes = (int)hp.nodes.size();
+    L.n_gather_st = (int)hp.gather_st.size();
+    L.n_gather_ln = (int)hp.gather_ln.size();
     L.n_cells = (int)hp.cells.size();
     L.n_nfft_nodes = (int)hp.nfft_nodes.size();
     L.n_direct_fwd = (int)hp.direct_fwd.size();

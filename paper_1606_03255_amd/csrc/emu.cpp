@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <limits>
 #include <vector>
 
 #include "flt.h"
@@ -145,16 +146,19 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
                      cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0, cplx<T>* f2)
 {
     if (!adjoint) {
-        std::vector<cplx<T>> stage(GATHER_STAGE<T>());
-        run_blocks(hp.nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
-            body_gather<HostCtx, T, MW>(ctx, pv, hp.nodes.data(), c, grids, f, with_c0, f2, stage.data());
+        std::vector<cplx<T>> stage(GATHER_STAGE, mk<T>(std::numeric_limits<T>::quiet_NaN(), std::numeric_limits<T>::quiet_NaN()));
+        run_blocks(hp.gather_st.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+            body_gather<HostCtx, T, MW, true>(ctx, pv, hp.gather_st.data(), c, grids, f, with_c0, f2, stage.data());
+        });
+        run_blocks(hp.gather_ln.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
+            body_gather<HostCtx, T, MW, false>(ctx, pv, hp.gather_ln.data(), c, grids, f, with_c0, f2, nullptr);
         });
         return;
     }
     run_blocks(hp.nfft_nodes.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
         body_adj_prep<HostCtx, T, MW>(ctx, pv, hp.nfft_nodes.data(), c, hp.qs, U, Phi, L0);
     });
-    std::vector<T> red(2 * ADJ_RC * GATHER_THREADS);
+    std::vector<T> red(2 * ADJ_RC * GATHER_THREADS, std::numeric_limits<T>::quiet_NaN());
     run_blocks(hp.cells.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
         body_adj_cells<HostCtx, T, MW>(ctx, pv, hp.cells.data(), hp.qs, U, Phi, L0, hp.cstart.data(),
                                        hp.clist.data(), grids, red.data());
@@ -182,19 +186,23 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     pv.mw = hp.mw;
     pv.kb_b = (T)hp.kb_b;
 
-    // exactly sized buffers, so AddressSanitizer sees any out-of-range access
+    // exactly sized buffers, so AddressSanitizer sees any out-of-range access;
+    // the workspace and LDS start as NaN, as device memory holds whatever it
+    // held: a value read before the kernels write it shows in the result
     const int cols = op == 3 ? 2 : 1;   // op 3: forward and derivative, 2q columns per band
-    std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems * cols, 1));
-    std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems * cols, 1));
-    std::vector<cplx<T>> U((size_t)hp.M * hp.qs);
-    std::vector<T> Phi((size_t)hp.M * 2 * hp.mw);
+    const T qnan = std::numeric_limits<T>::quiet_NaN();
+    const cplx<T> cnan = mk<T>(qnan, qnan);
+    std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems * cols, 1), cnan);
+    std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems * cols, 1), cnan);
+    std::vector<cplx<T>> U((size_t)hp.M * hp.qs, cnan);
+    std::vector<T> Phi((size_t)hp.M * 2 * hp.mw, qnan);
     std::vector<int32_t> L0(hp.M);
     std::vector<double> dacc(2 * hp.M, 0.0), red(2 * 256 * DIRECT_NG);
-    std::vector<cplx<T>> lds(tile_alloc<T>());
-    std::vector<T> lc(Sizes<T>::COEF);
-    std::vector<T> lc1(onepass_coef<T>());   // the one-pass FFT's staged coefficients
-    std::vector<cplx<T>> lds2(2 * tile_alloc<T>());   // the FP32 pass A's two tiles and coefficient buffers
-    std::vector<T> lc2(2 * Sizes<T>::COEF);
+    std::vector<cplx<T>> lds(tile_alloc<T>(), cnan);
+    std::vector<T> lc(Sizes<T>::COEF, qnan);
+    std::vector<T> lc1(onepass_coef<T>(), qnan);   // the one-pass FFT's staged coefficients
+    std::vector<cplx<T>> lds2(2 * tile_alloc<T>(), cnan);   // the FP32 pass A's two tiles and coefficient buffers
+    std::vector<T> lc2(2 * Sizes<T>::COEF, qnan);
     std::vector<cplx<T>> omega(PASSA_OMEGA_MAX);
     std::vector<cplx<T>> basebuf(std::max<int64_t>(hp.base_elems, 1));
     const int64_t nd = (int64_t)hp.dlist.size();

@@ -23,6 +23,10 @@ namespace flt {
 template <typename T> struct alignas(2 * sizeof(T)) cplx { T x, y; };
 
 template <typename T> FLT_HD cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
+// Two adjacent complex values, aligned to their joint size: one 16-byte load
+// in FP32 (the gather's paired window reads).
+template <typename T> struct alignas(4 * sizeof(T)) cplx2 { cplx<T> a, b; };
+template <typename T> FLT_HD cplx2<T> load_pair(const cplx<T>* p) { return *reinterpret_cast<const cplx2<T>*>(p); }
 template <typename T> FLT_HD cplx<T> add(cplx<T> a, cplx<T> b) { return mk(a.x + b.x, a.y + b.y); }
 template <typename T> FLT_HD cplx<T> sub(cplx<T> a, cplx<T> b) { return mk(a.x - b.x, a.y - b.y); }
 template <typename T> FLT_HD cplx<T> mul(cplx<T> a, cplx<T> b)
@@ -42,6 +46,7 @@ constexpr int TW_STAGE_LOG2 = 13;         // stage twiddle table: e^{-2 pi i t /
 constexpr int TW2_LOG2 = 22;              // two-level table resolution 2^22 (largest grid)
 constexpr int TW2_HALF = 11;              // lo/hi tables of 2^11 entries each
 constexpr int GATHER_THREADS = 256;       // nodes per gather/spread workgroup
+constexpr int GATHER_STAGE = 2048;        // grid values a gather workgroup stages in LDS at a time
 constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
 constexpr int MAX_MW = 10;                // largest window half-width supported
 constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread and chunk (one anchor each)

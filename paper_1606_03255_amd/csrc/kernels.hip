@@ -105,12 +105,20 @@ __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
 }
 
 template <typename T, int MW>
-__global__ __launch_bounds__(GATHER_THREADS) void k_gather(PlanView<T> pv, const NodeItem* items, const cplx<T>* c,
-                                                           const cplx<T>* grids, cplx<T>* f, int with_c0,
-                                                           cplx<T>* f2)
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather_staged(PlanView<T> pv, const NodeItem* items,
+                                                                  const cplx<T>* c, const cplx<T>* grids,
+                                                                  cplx<T>* f, int with_c0, cplx<T>* f2)
 {
-    __shared__ cplx<T> stage[GATHER_STAGE<T>()];
-    body_gather<DevCtx, T, MW>(DevCtx(), pv, items, c, grids, f, with_c0, f2, stage);
+    __shared__ cplx<T> stage[GATHER_STAGE];
+    body_gather<DevCtx, T, MW, true>(DevCtx(), pv, items, c, grids, f, with_c0, f2, stage);
+}
+
+template <typename T, int MW>
+__global__ __launch_bounds__(GATHER_THREADS) void k_gather_lane(PlanView<T> pv, const NodeItem* items,
+                                                                const cplx<T>* c, const cplx<T>* grids, cplx<T>* f,
+                                                                int with_c0, cplx<T>* f2)
+{
+    body_gather<DevCtx, T, MW, false>(DevCtx(), pv, items, c, grids, f, with_c0, f2, nullptr);
 }
 
 template <typename T, int MW>
@@ -295,9 +303,16 @@ template <typename T, int MW>
 static void mw_forward_nodes(LaunchStatus& ls, const DevLists& L, const PlanView<T>& pv, const cplx<T>* c,
                              const cplx<T>* grids, cplx<T>* f, int with_c0, cplx<T>* f2, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_gather<T, MW>), dim3(L.n_nodes), dim3(GATHER_THREADS), 0, st, pv, L.nodes, c, grids, f,
-                       with_c0, f2);
-    ls.launched();
+    if (L.n_gather_st) {
+        hipLaunchKernelGGL((k_gather_staged<T, MW>), dim3(L.n_gather_st), dim3(GATHER_THREADS), 0, st, pv,
+                           L.gather_st, c, grids, f, with_c0, f2);
+        ls.launched();
+    }
+    if (L.n_gather_ln) {
+        hipLaunchKernelGGL((k_gather_lane<T, MW>), dim3(L.n_gather_ln), dim3(GATHER_THREADS), 0, st, pv,
+                           L.gather_ln, c, grids, f, with_c0, f2);
+        ls.launched();
+    }
 }
 
 template <typename T, int MW>
@@ -336,7 +351,7 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
     double* dacc = (double*)(W.ws + W.off_dacc);
     mark(ls, ev, 0, st);
     fft_forward_stages<T>(ls, L, pv, W, c, deriv, cols, st, ev);
-    if (L.n_nodes) {
+    if (L.n_gather_st + L.n_gather_ln) {
         switch (pv.mw) {
 #define G(MWV) case MWV: mw_forward_nodes<T, MWV>(ls, L, pv, c, grids, f, !deriv, f2, st); break;
             G(2) G(3) G(4) G(5) G(6) G(7) G(8) G(9) G(10)

@@ -1101,11 +1101,22 @@ FLT_HD float exp2_f32(float x)
     return exp2f(x);
 #endif
 }
+FLT_HD float rsq_f32(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rsqf(x);
+#else
+    return 1.0f / sqrtf(x);
+#endif
+}
 
 // Kaiser-Bessel window at grid offsets u_t = delta + mw - 1 - t, t < 2 mw:
 // phi = sinh(b v) / (pi v), v = sqrt(mw^2 - u^2).  FP32: sinh(b v) =
 // (e - 1/e) / 2 with e = 2^(b log2(e) v); the cancellation for small b v only
 // touches the edge taps, whose weights are about 1e-9 of the central ones.
+// The inner taps (0 < t < 2 mw - 1) have |u| <= mw - 1, so v >= sqrt(2 mw - 1)
+// and, with the integer grids' b = 3 pi / 2 and mw >= 3, 1/e^2 < 1e-9: there
+// the window is e / (2 pi v), from one reciprocal square root and one 2^x.
 template <typename T, int MW>
 FLT_HD void kb_weights(T delta, T b, T* phi)
 {
@@ -1115,9 +1126,14 @@ FLT_HD void kb_weights(T delta, T b, T* phi)
         for (int t = 0; t < 2 * MW; ++t) {
             const float u = delta + float(MW - 1 - t);
             const float v2 = float(MW * MW) - u * u;
-            const float v = v2 > 0.0f ? sqrt_f32(v2) : 0.0f;
-            const float e = exp2_f32(bl2e * v);
-            phi[t] = v > 0.0f ? (e - rcp_f32(e)) * (0.5f * inv_pi) * rcp_f32(v) : b * inv_pi;
+            if (MW >= 3 && t > 0 && t < 2 * MW - 1) {
+                const float r = rsq_f32(v2);
+                phi[t] = exp2_f32(bl2e * (v2 * r)) * (0.5f * inv_pi) * r;
+            } else {
+                const float v = v2 > 0.0f ? sqrt_f32(v2) : 0.0f;
+                const float e = exp2_f32(bl2e * v);
+                phi[t] = v > 0.0f ? (e - rcp_f32(e)) * (0.5f * inv_pi) * rcp_f32(v) : b * inv_pi;
+            }
         }
     } else {
         for (int t = 0; t < 2 * MW; ++t) {
@@ -1187,12 +1203,13 @@ template <typename T> FLT_HD void modulation(double k0, double x, double* cs, do
 //
 // A workgroup's nodes are consecutive in the band's sorted order, so their
 // windows cover one run of the grid: the cells from l0(first) - mw + 1 to
-// l0(last) + mw.  When that run is short (dense bands: many nodes per cell)
-// the workgroup loads it once per column, coalesced, into LDS (as many columns
-// at a time as GATHER_STAGE values hold) and every node reads its taps there;
-// otherwise each node loads its own taps from the grid.
-template <typename T> constexpr int GATHER_STAGE() { return 2048; }
-template <class Ctx, typename T, int MW>
+// l0(last) + mw.  The planner sorts the items by that run's length: when it is
+// short (dense bands: many nodes per cell) the workgroup loads it once per
+// column, coalesced, into LDS (as many columns at a time as GATHER_STAGE
+// values hold) and every node reads its taps there (STAGED); otherwise each
+// node loads its own taps from the grid.  The two are separate kernels, each
+// compiled for its own path.
+template <class Ctx, typename T, int MW, bool STAGED>
 FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* items, const cplx<T>* c,
                         const cplx<T>* grids, cplx<T>* f, int with_c0, cplx<T>* f2, cplx<T>* stage)
 {
@@ -1203,7 +1220,7 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     const BandDesc& B = pv.bands[it.band];
     const double c0r = with_c0 ? (double)c[B.c_off].x : 0.0;
     const double c0i = with_c0 ? (double)c[B.c_off].y : 0.0;
-    if (B.q == 0) {   // the constant band (the whole item)
+    if (!STAGED && B.q == 0) {   // the constant band (the whole item)
         if (active) {
             const int32_t dst = pv.perm[jj];
             f[dst] = mk<T>((T)c0r, (T)c0i);
@@ -1220,7 +1237,41 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     T phi[2 * MW];
     kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
     const double* yc = pv.ycheb + 2 * B.ycheb_off;
-    const BaryY<T> by = bary_setup<T>(yc, B.q, y);
+    // Barycentric weighting in the second form (Sect. 2), summed along with
+    // the columns: sum_s L_s(y) F_s = sum_s w_s F_s / sum_s w_s with
+    // w_s = lambda_s / (y - y_s); a node on a Chebyshev node y_s takes F_s.
+    // The weights are FP32 in the FP32 form (from y - y_s formed in FP64), the
+    // sums FP64.
+    T wsum = 0;
+    int hit = -1;
+    double ar = 0, ai = 0, dr = 0, di = 0, hr = 0, hi = 0, hdr = 0, hdi = 0;
+    auto accumulate = [&](int s, T fr, T fi) {
+        const bool dcol = s >= B.q;   // a derivative column (f2): weight of column s - q
+        const int sb = dcol ? s - B.q : s;
+        const double d = y - yc[2 * sb];
+        T w;
+        if constexpr (sizeof(T) == 4) w = (float)yc[2 * sb + 1] * rcp_f32((float)d);
+        else w = yc[2 * sb + 1] / d;
+        if (d == 0.0) {
+            w = 0;
+            hit = sb;
+            if (dcol) {
+                hdr = fr;
+                hdi = fi;
+            } else {
+                hr = fr;
+                hi = fi;
+            }
+        }
+        if (dcol) {
+            dr += (double)w * (double)fr;
+            di += (double)w * (double)fi;
+        } else {
+            wsum += w;
+            ar += (double)w * (double)fr;
+            ai += (double)w * (double)fi;
+        }
+    };
     // grid address of cell l (one-pass bands: natural order; two-pass: pass B's
     // output layout Y[l1 / B][l2][l1 mod B], l = l1 + n1 l2)
     const int lb = B.log2n2 > 0 ? B.log2B : 30;
@@ -1231,15 +1282,23 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
     };
     const cplx<T>* g = grids + B.grid_off * (f2 ? 2 : 1);
     const int ncol = f2 ? 2 * B.q : B.q;
-    // the workgroup's run of cells (uniform: first and last node of the item)
-    const int lf = (int)floor(ldexp(pv.nx[it.start], log2n));
-    const int ll = (int)floor(ldexp(pv.nx[it.start + it.count - 1], log2n));
-    const int span = ll - lf + 2 * MW;
-    double ar = 0, ai = 0, dr = 0, di = 0;
-    if (span <= GATHER_STAGE<T>()) {
+    if constexpr (STAGED) {
+        // the workgroup's run of cells (uniform: first and last node of the
+        // item; the planner placed the item here because it fits the stage)
+        const int lf = (int)floor(ldexp(pv.nx[it.start], log2n));
+        const int ll = (int)floor(ldexp(pv.nx[it.start + it.count - 1], log2n));
+        const int span = ll - lf + 2 * MW;
+        if (span > GATHER_STAGE) {   // not a staged item: NaN, never LDS out of bounds
+            if (active) {
+                const T nan = T(__builtin_nan(""));
+                f[pv.perm[jj]] = mk<T>(nan, nan);
+                if (f2) f2[pv.perm[jj]] = mk<T>(nan, nan);
+            }
+            return;
+        }
         const int base = lf - MW + 1;
         const int off = l0 - lf;   // in [0, span - 2 mw] (sorted nodes)
-        const int per = GATHER_STAGE<T>() / span;
+        const int per = GATHER_STAGE / span;
         // thread i loads stage elements e = i, i + GATHER_THREADS, ...: column
         // cc = e / span, cell r = e mod span, stepped without divisions
         const int cc0 = i / span, r0 = i - cc0 * span;
@@ -1260,8 +1319,6 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
             ctx.sync();
             if (active) {
                 for (int cc = 0; cc < nc; ++cc) {
-                    const int s = s0 + cc;
-                    const bool dcol = s >= B.q;   // a derivative column (f2)
                     const cplx<T>* st = stage + cc * span + off;
                     T fr = 0, fi = 0;
                     for (int t = 0; t < 2 * MW; ++t) {
@@ -1269,46 +1326,77 @@ FLT_HD void body_gather(const Ctx& ctx, const PlanView<T>& pv, const NodeItem* i
                         fr += v.x * phi[t];
                         fi += v.y * phi[t];
                     }
-                    const double Ls = (double)bary_at<T>(yc, by, dcol ? s - B.q : s, y);
-                    if (dcol) {
-                        dr += Ls * (double)fr;
-                        di += Ls * (double)fi;
-                    } else {
-                        ar += Ls * (double)fr;
-                        ai += Ls * (double)fi;
-                    }
+                    accumulate(s0 + cc, fr, fi);
                 }
             }
         }
     } else if (active) {
-        // offsets within a column (a grid has at most 2^22 points)
-        int addr[2 * MW];
-        for (int t = 0; t < 2 * MW; ++t) addr[t] = addr_of((l0 - MW + 1 + t) & nmask);
-        for (int s = 0; s < B.q; ++s) {
-            const cplx<T>* gs = g + ((int64_t)s << log2n);
-            T fr = 0, fi = 0;
-            for (int t = 0; t < 2 * MW; ++t) {
-                const cplx<T> v = gs[addr[t]];
-                fr += v.x * phi[t];
-                fi += v.y * phi[t];
+        if constexpr (sizeof(T) == 4) {
+            // FP32: the window's cells c0 .. c0 + 2 mw - 1 (c0 = l0 - mw + 1)
+            // read as mw + 1 aligned pairs from the even cell at or below c0
+            // (both layouts keep an even cell and its successor adjacent, at an
+            // even offset); the weights shift by the parity of c0, not the values.
+            // The pairs' two cells outside the window (c0 - 1 and c0 + 2 mw for
+            // odd c0; the whole last pair for even c0, which is not read) may be
+            // cells pass B never wrote: they are replaced by 0, not multiplied
+            // by a zero weight.
+            const int c0 = (l0 - MW + 1) & nmask;
+            const int par = c0 & 1, e0 = c0 - par;
+            T phi2[2 * MW + 2];
+            for (int j = 0; j < 2 * MW + 2; ++j) {
+                const T lo = j < 2 * MW ? phi[j] : T(0);
+                const T hi2 = j >= 1 && j - 1 < 2 * MW ? phi[j - 1] : T(0);
+                phi2[j] = par ? hi2 : lo;
             }
-            const double Ls = (double)bary_at<T>(yc, by, s, y);
-            ar += Ls * (double)fr;
-            ai += Ls * (double)fi;
-            if (f2) {
-                const cplx<T>* gd = g + ((int64_t)(s + B.q) << log2n);
-                T er = 0, ei = 0;
-                for (int t = 0; t < 2 * MW; ++t) {
-                    const cplx<T> v = gd[addr[t]];
-                    er += v.x * phi[t];
-                    ei += v.y * phi[t];
+            int paddr[MW + 1];
+            for (int k = 0; k <= MW; ++k) paddr[k] = addr_of((e0 + 2 * k) & nmask);
+            // two columns' loads in flight
+#pragma unroll 2
+            for (int s = 0; s < ncol; ++s) {
+                const cplx<T>* gs = g + ((int64_t)s << log2n);
+                T fr = 0, fi = 0;
+                for (int k = 0; k <= MW; ++k) {
+                    cplx2<T> v;
+                    if (k < MW || par) v = load_pair(gs + paddr[k]);
+                    else v.a = mk<T>(0, 0);
+                    if (k == 0 && par) v.a = mk<T>(0, 0);
+                    if (k == MW) v.b = mk<T>(0, 0);
+                    fr += v.a.x * phi2[2 * k] + v.b.x * phi2[2 * k + 1];
+                    fi += v.a.y * phi2[2 * k] + v.b.y * phi2[2 * k + 1];
                 }
-                dr += Ls * (double)er;
-                di += Ls * (double)ei;
+                accumulate(s, fr, fi);
+            }
+        } else {
+            // offsets within a column (a grid has at most 2^22 points)
+            int addr[2 * MW];
+            for (int t = 0; t < 2 * MW; ++t) addr[t] = addr_of((l0 - MW + 1 + t) & nmask);
+            for (int s = 0; s < ncol; ++s) {
+                const cplx<T>* gs = g + ((int64_t)s << log2n);
+                T fr = 0, fi = 0;
+                for (int t = 0; t < 2 * MW; ++t) {
+                    const cplx<T> v = gs[addr[t]];
+                    fr += v.x * phi[t];
+                    fi += v.y * phi[t];
+                }
+                accumulate(s, fr, fi);
             }
         }
     }
     if (!active) return;
+    if (hit >= 0) {
+        ar = hr;
+        ai = hi;
+        dr = hdr;
+        di = hdi;
+    } else {
+        double inv;
+        if constexpr (sizeof(T) == 4) inv = (double)rcp_f32(wsum);
+        else inv = 1.0 / wsum;
+        ar *= inv;
+        ai *= inv;
+        dr *= inv;
+        di *= inv;
+    }
     const int32_t dst = pv.perm[jj];
     double sn, cs;
     modulation<T>((double)B.k0, x, &cs, &sn);   // e^{2 pi i k0 x}

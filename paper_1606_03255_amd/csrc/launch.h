@@ -34,7 +34,8 @@ struct DevLists {
     const FftItem* onepass_fused = nullptr;   // forward + derivative: 2q columns per band
     const FftItem* passB_fused = nullptr;
     const CellItem* cells = nullptr;
-    const NodeItem* nodes = nullptr;
+    const NodeItem* gather_st = nullptr;   // gather items staged through LDS
+    const NodeItem* gather_ln = nullptr;   // gather items read per lane
     const NodeItem* nfft_nodes = nullptr;
     const DirectItem* direct_fwd = nullptr;
     const DirectItem* direct_adj = nullptr;
@@ -46,7 +47,7 @@ struct DevLists {
     int persist_blocks = 512;   // workgroups of the persistent FFT kernels (two per compute unit)
     int n_onepass_fwd = 0, n_passA_fwd = 0, n_passB = 0, n_onepass_adj = 0, n_passA_adj = 0, n_cells = 0;
     int n_onepass_fused = 0, n_passB_fused = 0;
-    int n_nodes = 0, n_nfft_nodes = 0, n_direct_fwd = 0, n_direct_adj = 0;
+    int n_gather_st = 0, n_gather_ln = 0, n_nfft_nodes = 0, n_direct_fwd = 0, n_direct_adj = 0;
     int64_t n_dlist = 0;
     // host copies of the FFT launch groups (one kernel instance per transform length)
     std::vector<LaunchGroup> g_onepass_fwd, g_passA_fwd, g_passB, g_onepass_adj, g_passA_adj;

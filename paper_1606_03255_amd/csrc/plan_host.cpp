@@ -381,8 +381,13 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
         }
         for (int64_t s = 0; s < B.node_count; s += GATHER_THREADS) {
             const NodeItem it{b, (int32_t)std::min<int64_t>(GATHER_THREADS, B.node_count - s), B.node_start + s};
-            hp.nodes.push_back(it);
             if (B.q > 0) hp.nfft_nodes.push_back(it);
+            // the cells the item's windows read, as the gather computes them
+            // (first and last sorted node)
+            const int64_t lf = (int64_t)floor(ldexp(hp.nx[it.start], B.log2n));
+            const int64_t ll = (int64_t)floor(ldexp(hp.nx[it.start + it.count - 1], B.log2n));
+            if (B.q > 0 && ll - lf + 2 * hp.mw <= GATHER_STAGE) hp.gather_st.push_back(it);
+            else hp.gather_ln.push_back(it);
         }
     }
     if (!hp.dlist.empty()) {
@@ -621,7 +626,8 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
         auto shift_nodes = [&](std::vector<NodeItem>& dst, const std::vector<NodeItem>& src) {
             for (NodeItem it : src) { it.band += bo; it.start += no; dst.push_back(it); }
         };
-        shift_nodes(out.nodes, p.nodes);
+        shift_nodes(out.gather_st, p.gather_st);
+        shift_nodes(out.gather_ln, p.gather_ln);
         shift_nodes(out.nfft_nodes, p.nfft_nodes);
         for (int32_t v : p.dlist) out.dlist.push_back((int32_t)(v + no));
         for (DirectItem it : p.direct_fwd) { it.first += (int32_t)dlo; it.inst = i; out.direct_fwd.push_back(it); }

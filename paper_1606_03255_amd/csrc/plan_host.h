@@ -45,7 +45,9 @@ struct HostPlan {
     // FFT item lists are sorted by transform length; one group per length
     std::vector<LaunchGroup> g_onepass_fwd, g_passA_fwd, g_passB, g_onepass_adj, g_passA_adj;
     std::vector<LaunchGroup> g_onepass_fused, g_passB_fused;
-    std::vector<NodeItem> nodes;        // gather: NFFT bands and the constant band
+    // gather: items whose nodes' windows cover a run of at most GATHER_STAGE
+    // cells (staged in LDS), and the rest (the constant band's included)
+    std::vector<NodeItem> gather_st, gather_ln;
     std::vector<NodeItem> nfft_nodes;   // adjoint node side: NFFT bands only
     std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands
     std::vector<DirectItem> direct_fwd, direct_adj;
