@@ -93,6 +93,13 @@ struct HostCtx {
 // takes several items of different transform lengths.
 static const int EMU_PERSIST_BLOCKS = 5;
 
+// Scratch and LDS stand-ins start as NaN (device memory and LDS hold whatever
+// they held), so a read before the kernels' own write shows in the result.
+template <typename T> static cplx<T> nan_c()
+{
+    return mk<T>(std::numeric_limits<T>::quiet_NaN(), std::numeric_limits<T>::quiet_NaN());
+}
+
 template <typename T> static std::vector<T> cast(const std::vector<double>& v)
 {
     return std::vector<T>(v.begin(), v.end());
@@ -146,7 +153,7 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
                      cplx<T>* f, int with_c0, cplx<T>* U, T* Phi, int32_t* L0, cplx<T>* f2)
 {
     if (!adjoint) {
-        std::vector<cplx<T>> stage(GATHER_STAGE, mk<T>(std::numeric_limits<T>::quiet_NaN(), std::numeric_limits<T>::quiet_NaN()));
+        std::vector<cplx<T>> stage(GATHER_STAGE, nan_c<T>());
         run_blocks(hp.gather_st.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
             body_gather<HostCtx, T, MW, true>(ctx, pv, hp.gather_st.data(), c, grids, f, with_c0, f2, stage.data());
         });
@@ -191,7 +198,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     // held: a value read before the kernels write it shows in the result
     const int cols = op == 3 ? 2 : 1;   // op 3: forward and derivative, 2q columns per band
     const T qnan = std::numeric_limits<T>::quiet_NaN();
-    const cplx<T> cnan = mk<T>(qnan, qnan);
+    const cplx<T> cnan = nan_c<T>();
     std::vector<cplx<T>> grids(std::max<int64_t>(hp.grid_elems * cols, 1), cnan);
     std::vector<cplx<T>> scratch(std::max<int64_t>(hp.scratch_elems * cols, 1), cnan);
     std::vector<cplx<T>> U((size_t)hp.M * hp.qs, cnan);
@@ -256,7 +263,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 0);
             });
-            std::vector<cplx<T>> nw(DIRECT_NG);
+            std::vector<cplx<T>> nw(DIRECT_NG, nan_c<T>());
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
                 if (deriv || d)
                     body_direct_fwd<HostCtx, T, true>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, dacc.data(),
@@ -307,7 +314,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                                                                       grids.data(), acc.data(), lds.data());
                 });
             });
-        std::vector<cplx<T>> nw(DIRECT_ANG), ngv(DIRECT_ANG), redv(256 * ADJ_TS);
+        std::vector<cplx<T>> nw(DIRECT_ANG, nan_c<T>()), ngv(DIRECT_ANG, nan_c<T>()), redv(256 * ADJ_TS, nan_c<T>());
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
             body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, acc.data(), nw.data(),
                                         ngv.data(), redv.data());
@@ -349,7 +356,9 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
     V.nitems = (int32_t)hp.items.size();
     V.part = part.data();
     V.acc = acc.data();
-    std::vector<double> red(8 * LAP_THREADS), red2(LAP_THREADS), rred(LAP_THREADS), bred(4 * LAP_THREADS);
+    const double dnan = std::numeric_limits<double>::quiet_NaN();
+    std::vector<double> red(8 * LAP_THREADS, dnan), red2(LAP_THREADS, dnan), rred(LAP_THREADS, dnan),
+        bred(4 * LAP_THREADS, dnan);
     auto all = [&](auto qb) {
         constexpr int QB = decltype(qb)::value;
         run_blocks(hp.items.size(), LAP_THREADS, [&](const HostCtx& ctx) {
@@ -358,7 +367,7 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
         run_blocks((size_t)hp.L, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_reduce(ctx, V, rred.data()); });
         run_blocks((size_t)hp.L, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_bands<HostCtx, QB>(ctx, V, bred.data()); });
         const int64_t per = (int64_t)LAP_THREADS * LAP_NODE_PER, ns = lap_node_stage(hp.L, hp.q);
-        std::vector<double> sb((size_t)std::max<int64_t>(ns, 1));
+        std::vector<double> sb((size_t)std::max<int64_t>(ns, 1), dnan);
         run_blocks((hp.M + per - 1) / per, LAP_THREADS, [&](const HostCtx& ctx) {
             lap_body_nodes<HostCtx, T, QB>(ctx, V, hp.M, (cplx<T>*)out, ns > 0 ? sb.data() : nullptr,
                                            (const cplx<T>*)in);
@@ -395,9 +404,10 @@ template <typename T> static int emu_xi(XiHost& hp, int op, const void* in, void
     xv.mw1 = hp.mw1;
     int qmax = 1;
     for (const XiBand& X : hp.bands) qmax = std::max(qmax, (int)X.q);
-    std::vector<cplx<T>> cin(std::max<int64_t>(hp.cin_elems, 1)), hout(std::max<int64_t>(hp.hout_elems, 1));
-    std::vector<T> lc(XI_NBLK * 32 * 32);
-    std::vector<cplx<T>> ct(32 * 1024 / sizeof(cplx<T>));   // xi_kcap * QM for every QM
+    std::vector<cplx<T>> cin(std::max<int64_t>(hp.cin_elems, 1), nan_c<T>()),
+        hout(std::max<int64_t>(hp.hout_elems, 1), nan_c<T>());
+    std::vector<T> lc(XI_NBLK * 32 * 32, std::numeric_limits<T>::quiet_NaN());
+    std::vector<cplx<T>> ct(32 * 1024 / sizeof(cplx<T>), nan_c<T>());   // xi_kcap * QM for every QM
     if (op == 0) {
         run_blocks(hp.spread.size(), XI_THREADS, [&](const HostCtx& ctx) {
             if (qmax <= 16) body_xi_spread<HostCtx, T, 16>(ctx, xv, hp.spread.data(), (const cplx<T>*)in, cin.data(), lc.data(), ct.data());
