@@ -57,7 +57,7 @@ template <typename T> FLT_HD void int_phase(double l, double x, double* cs, doub
     const double ph = (p - rint(p)) + e;
     if constexpr (sizeof(T) == 4) {
         float s, c;
-        sincosf(6.2831853071795864769f * (float)ph, &s, &c);
+        sincos_rev_f32((float)ph, &s, &c);
         *cs = c;
         *sn = s;
     } else {
