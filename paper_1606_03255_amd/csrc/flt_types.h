@@ -23,10 +23,13 @@ namespace flt {
 template <typename T> struct alignas(2 * sizeof(T)) cplx { T x, y; };
 
 template <typename T> FLT_HD cplx<T> mk(T a, T b) { cplx<T> r; r.x = a; r.y = b; return r; }
-// Two adjacent complex values, aligned to their joint size: one 16-byte load
-// in FP32 (the gather's paired window reads).
-template <typename T> struct alignas(4 * sizeof(T)) cplx2 { cplx<T> a, b; };
+// Two adjacent complex values at a 16-byte boundary: one 16-byte load or store
+// in FP32 (the gather's paired window reads, the adjoint's column pairs).
+template <typename T> struct alignas(16) cplx2 { cplx<T> a, b; };
 template <typename T> FLT_HD cplx2<T> load_pair(const cplx<T>* p) { return *reinterpret_cast<const cplx2<T>*>(p); }
+template <typename T> FLT_HD void store_pair(cplx<T>* p, const cplx2<T>& v) { *reinterpret_cast<cplx2<T>*>(p) = v; }
+// Two adjacent reals at their joint alignment.
+template <typename T> struct alignas(2 * sizeof(T)) RealPair { T a, b; };
 template <typename T> FLT_HD cplx<T> add(cplx<T> a, cplx<T> b) { return mk(a.x + b.x, a.y + b.y); }
 template <typename T> FLT_HD cplx<T> sub(cplx<T> a, cplx<T> b) { return mk(a.x - b.x, a.y - b.y); }
 template <typename T> FLT_HD cplx<T> mul(cplx<T> a, cplx<T> b)

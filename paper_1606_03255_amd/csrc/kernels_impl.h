@@ -965,12 +965,12 @@ template <> struct TileRegs<double> {
     FLT_HD cplx<double> get(int r) const { return mk(re[r], im[r]); }
 };
 
-// Load item `it`'s tile into the registers v; for the adjoint direction (ADJ:
-// grid -> scratch) also the mask bits of each run of V elements (bits[m] for
-// run m, bit u for its element u), applied when the tile goes to LDS.
+// Load item `it`'s tile into the registers v; in the adjoint direction (ADJ:
+// grid -> scratch) the cells outside the band's read mask (never written) as
+// zeros.
 template <class Ctx, typename T, int LOG2N2, bool ADJ>
 FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it, const cplx<T>* src_base,
-                        int cols, TileRegs<T>& v, uint32_t* bits)
+                        int cols, TileRegs<T>& v)
 {
     using G = PassBGeo<T, LOG2N2>;
     const BandDesc& B = pv.bands[it.band];
@@ -981,10 +981,23 @@ FLT_HD void passB_fetch(const Ctx& ctx, const PlanView<T>& pv, const FftItem& it
         const int ch = ctx.tid() + m * FFT_THREADS;
         const int p0 = (G::row(ch) << G::log2B) + G::col(ch, 0);   // multiple of V: one mask word
         if (ADJ) {
-            // only the cells some window wrote are read (the others are zero)
+            // FP32: runs holding a cell some window wrote are read whole, in
+            // 16-byte pairs (V even, p0 a multiple of V), and the cells no
+            // window wrote are zeroed
             const uint32_t b = mask[p0 >> 5] >> (p0 & 31);
-            bits[m] = b;
-            for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, ((b >> u) & 1u) ? src[p0 + u] : mk<T>(0, 0));
+            if constexpr (sizeof(T) == 4 && G::V >= 2) {
+                if (b & ((1u << G::V) - 1u)) {
+                    for (int u = 0; u < G::V; u += 2) {
+                        const cplx2<T> pr = load_pair(src + p0 + u);
+                        v.set(m * G::V + u, ((b >> u) & 1u) ? pr.a : mk<T>(0, 0));
+                        v.set(m * G::V + u + 1, ((b >> (u + 1)) & 1u) ? pr.b : mk<T>(0, 0));
+                    }
+                } else {
+                    for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, mk<T>(0, 0));
+                }
+            } else {
+                for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, ((b >> u) & 1u) ? src[p0 + u] : mk<T>(0, 0));
+            }
         } else {
             for (int u = 0; u < G::V; ++u) v.set(m * G::V + u, src[p0 + u]);
         }
@@ -1009,10 +1022,8 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
     constexpr bool PREFETCH = passB_prefetch<T, SIGN>();
     using G = PassBGeo<T, LOG2N2>;
     constexpr int CHUNKS = tile_points<T>() / G::V;
-    constexpr int RUNS = tile_items<T>() / G::V;
     TileRegs<T> v;
-    uint32_t bits[RUNS];
-    passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, cols, v, bits);
+    passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, cols, v);
     // with prefetch the registers hold the next tile instead of the twiddles
     typename TwSel<!PREFETCH, T, LOG2N2, (1 << G::log2B), SIGN>::type stw;
     stw.load(ctx0, pv.tw_stage);
@@ -1022,14 +1033,13 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
         const BandDesc& B = pv.bands[it.band];
         for (int r = 0; r < tile_items<T>(); ++r) {
             const int ch = G::ch(ctx.tid(), r);
-            const bool keep = !ADJ || ((bits[r / G::V] >> (r % G::V)) & 1u);
-            lds[lds_at((G::col(ch, r) << LOG2N2) + G::row(ch))] = keep ? v.get(r) : mk<T>(0, 0);
+            lds[lds_at((G::col(ch, r) << LOG2N2) + G::row(ch))] = v.get(r);
         }
         ctx.sync();
         const int nx = i + nblocks;
         const bool more = nx < nitems && pv.bands[items[nx].band].log2n2 == LOG2N2;
         if (PREFETCH && more)
-            passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, cols, v, bits);
+            passB_fetch<IterCtx<Ctx>, T, LOG2N2, ADJ>(ctx, pv, items[nx], src_base, cols, v);
         lds_fft_ct<IterCtx<Ctx>, T, LOG2N2, (1 << G::log2B), SIGN>(ctx, lds, stw);
         const int64_t blk_off = ((int64_t)it.s0 << B.log2n) + ((int64_t)it.blk << Sizes<T>::LOG2P);
         cplx<T>* dst = dst_base + (ADJ ? B.scratch_off : B.grid_off) * cols + blk_off;
@@ -1039,8 +1049,18 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
             const int lo0 = (t >> LOG2N2) * G::V;
             const int p0 = (l2 << G::log2B) + lo0;
             const uint32_t keep = ADJ ? ~0u : mask[p0 >> 5] >> (p0 & 31);
-            for (int u = 0; u < G::V; ++u)
-                if ((keep >> u) & 1u) dst[p0 + u] = lds[lds_at(((lo0 + u) << LOG2N2) + l2)];
+            constexpr uint32_t full = G::V >= 32 ? ~0u : (1u << G::V) - 1u;
+            if (sizeof(T) == 4 && G::V >= 2 && (keep & full) == full) {   // FP32, a whole run: pair stores
+                for (int u = 0; u < G::V; u += 2) {
+                    cplx2<T> pr;
+                    pr.a = lds[lds_at(((lo0 + u) << LOG2N2) + l2)];
+                    pr.b = lds[lds_at(((lo0 + u + 1) << LOG2N2) + l2)];
+                    store_pair(dst + p0 + u, pr);
+                }
+            } else {
+                for (int u = 0; u < G::V; ++u)
+                    if ((keep >> u) & 1u) dst[p0 + u] = lds[lds_at(((lo0 + u) << LOG2N2) + l2)];
+            }
         }
         ctx.sync();
         i = nx;
@@ -1438,7 +1458,12 @@ FLT_HD void body_adj_prep(const Ctx& ctx, const PlanView<T>& pv, const NodeItem*
     L0[j] = (int32_t)fl;
     T phi[2 * MW];
     kb_weights<T, MW>((T)(nxv - fl), pv.kb_b, phi);
-    for (int t = 0; t < 2 * MW; ++t) Phi[j * (2 * MW) + t] = phi[t];
+    for (int t = 0; t < 2 * MW; t += 2) {   // tap pairs (8-byte aligned in FP32, 16 in FP64)
+        RealPair<T> pr;
+        pr.a = phi[t];
+        pr.b = phi[t + 1];
+        *reinterpret_cast<RealPair<T>*>(Phi + j * (2 * MW) + t) = pr;
+    }
     const cplx<T> gv = gin[pv.perm[j]];
     double sn, cs;
     modulation<T>((double)B.k0, x, &cs, &sn);
@@ -1446,9 +1471,14 @@ FLT_HD void body_adj_prep(const Ctx& ctx, const PlanView<T>& pv, const NodeItem*
     const double ui = (double)gv.y * cs - (double)gv.x * sn;
     const double* yc = pv.ycheb + 2 * B.ycheb_off;
     const BaryY<T> by = bary_setup<T>(yc, B.q, y);
-    for (int s = 0; s < B.q; ++s) {
-        const double Ls = (double)bary_at<T>(yc, by, s, y);
-        U[j * qs + s] = mk<T>((T)(ur * Ls), (T)(ui * Ls));
+    // column pairs (the row stride qs is even; a padding column gets 0)
+    for (int s = 0; s < B.q; s += 2) {
+        const double L0s = (double)bary_at<T>(yc, by, s, y);
+        const double L1s = s + 1 < B.q ? (double)bary_at<T>(yc, by, s + 1, y) : 0.0;
+        cplx2<T> v;
+        v.a = mk<T>((T)(ur * L0s), (T)(ui * L0s));
+        v.b = mk<T>((T)(ur * L1s), (T)(ui * L1s));
+        store_pair(U + j * qs + s, v);
     }
 }
 
@@ -1504,11 +1534,15 @@ FLT_HD void body_adj_cells(const Ctx& ctx, const PlanView<T>& pv, const CellItem
                 if (t >= n) t -= n;
                 const T w = Phi[(int64_t)j * (2 * MW) + t];
                 const cplx<T>* u = U + (int64_t)j * qs + s0;
-                for (int c = 0; c < QC; ++c)
+                // column pairs, one 16-byte load each in FP32 (QC and qs even;
+                // a padding column's sum is never stored)
+                for (int c = 0; c < QC; c += 2)
                     if (s0 + c < B.q) {
-                        const cplx<T> uv = u[c];
-                        ar[c] += uv.x * w;
-                        ai[c] += uv.y * w;
+                        const cplx2<T> uv = load_pair(u + c);
+                        ar[c] += uv.a.x * w;
+                        ai[c] += uv.a.y * w;
+                        ar[c + 1] += uv.b.x * w;
+                        ai[c + 1] += uv.b.y * w;
                     }
             }
         }

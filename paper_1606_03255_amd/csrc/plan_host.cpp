@@ -507,6 +507,7 @@ static void finish(HostPlan& hp)
     // forward + derivative call needs (the other calls use the first halves)
     hp.off_scratch = al(hp.off_grid + (size_t)hp.grid_elems * 2 * S);
     hp.off_acc = al(hp.off_scratch + (size_t)hp.scratch_elems * 2 * S);
+    hp.qs = (hp.qs + 1) & ~1;   // even: the adjoint moves column values in pairs
     hp.off_U = al(hp.off_acc + (size_t)hp.N * 16);
     hp.off_phi = al(hp.off_U + (size_t)hp.M * hp.qs * S);
     hp.off_l0 = al(hp.off_phi + (size_t)hp.M * 2 * hp.mw * (S / 2));

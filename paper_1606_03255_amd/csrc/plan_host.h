@@ -58,7 +58,7 @@ struct HostPlan {
     std::vector<SumItem> sum_items;     // adjoint k = 0 sums: runs of one instance's g
 
     // workspace layout (bytes)
-    int qs = 1;                         // stride of the per-node column values (max q)
+    int qs = 1;                         // stride of the per-node column values (max q, rounded up to even)
     int64_t grid_elems = 0, scratch_elems = 0, base_elems = 0;   // base: FP64 plans only
     size_t off_grid = 0, off_scratch = 0, off_acc = 0, off_U = 0, off_phi = 0, off_l0 = 0, off_dacc = 0;
     size_t off_base = 0;
