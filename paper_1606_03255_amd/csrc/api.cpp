@@ -315,14 +315,16 @@ template <class Build> static int tuned_shape(uint32_t flags, Build&& build, Tun
         for (flt_plan* c : cands) release(c);
         cands.clear();
     };
-    // a candidate plan of the given shape, uploaded (nullptr and rc set on failure)
-    auto make = [&](const PlanShape& sh) -> flt_plan* {
+    // a candidate plan of the given shape (or of a host plan already built for
+    // it), uploaded (nullptr and rc set on failure)
+    auto make = [&](const PlanShape& sh, HostPlan* built = nullptr) -> flt_plan* {
         flt_plan* cand = new (std::nothrow) flt_plan();
         if (!cand) {
             rc = FLT_ENOMEM;
             return nullptr;
         }
-        rc = build(cand->hp, sh);
+        if (built) cand->hp = std::move(*built);
+        else rc = build(cand->hp, sh);
         if (rc == FLT_OK) {
             cand->host_only = false;
             rc = upload(cand);
@@ -352,7 +354,7 @@ template <class Build> static int tuned_shape(uint32_t flags, Build&& build, Tun
             for (const auto& v : seen) dup = dup || v == sig;
             if (dup) continue;
             seen.push_back(sig);
-            flt_plan* cand = make(sh);
+            flt_plan* cand = make(sh, &hp);
             if (!cand) break;
             cands.push_back(cand);
             scales.push_back(sc);

@@ -5,8 +5,11 @@
 #include <math.h>
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <numeric>
+#include <system_error>
+#include <thread>
 
 #include "flt.h"
 
@@ -534,120 +537,145 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
 {
     if (count < 1 || !N || !M || !z) return FLT_EINVAL;
     out = HostPlan();
-    int64_t zoff = 0;
+    std::vector<int64_t> zoff(count, 0);          // first node of each member in z
+    for (int32_t i = 1; i < count; ++i) zoff[i] = zoff[i - 1] + M[i - 1];
     std::map<int, int> deconv_at;                 // log2 n -> offset in the merged deconvolution table
     std::map<int, int> ycheb_at;                  // m (or -D for Y_D) -> pair offset in the merged ycheb table
-    for (int32_t i = 0; i < count; ++i) {
-        HostPlan p;
-        const int rc = build_one(p, N[i], M[i], z + 2 * zoff, eps, dtype, flags, shape);
-        if (rc != FLT_OK) return rc;
-        zoff += M[i];
-        if (i == 0) {
-            out.dtype = p.dtype;
-            out.eps = p.eps;
-            out.eps_K = p.eps_K;
-            out.eps_A = p.eps_A;
-            out.y1 = p.y1;
-            out.q = p.q;
-            out.mw = p.mw;
-            out.kb_b = p.kb_b;
-            out.flags = p.flags;
-            out.direct_scale = p.direct_scale;
-            out.tw_stage = p.tw_stage;
-            out.tw_lo = p.tw_lo;
-            out.tw_hi = p.tw_hi;
-        }
-        // the coefficient table depends on q, y_1 and D - n_xi only (see build_one):
-        // share it, appending when a member's table differs (never for one eps)
-        int32_t coef_shift = 0;
-        if (out.coef.empty()) out.coef = p.coef;
-        else if (p.coef.size() > out.coef.size() ||
-                 !std::equal(p.coef.begin(), p.coef.end(), out.coef.begin())) {
-            coef_shift = (int32_t)out.coef.size();
-            out.coef.insert(out.coef.end(), p.coef.begin(), p.coef.end());
-        }
-        const int32_t bo = (int32_t)out.bands.size();
-        const int64_t no = out.M;                    // sorted-node (and caller-index) offset
-        const int64_t co = out.N;                    // coefficient offset
-        const int64_t dlo = (int64_t)out.dlist.size();
-        const int64_t cso = (int64_t)out.cstart.size(), mko = (int64_t)out.mask.size();
-        for (size_t b = 0; b < p.bands.size(); ++b) {
-            BandDesc B = p.bands[b];
-            const int m = p.band_m[b];
-            B.c_off = co;
-            B.node_start += no;
-            if (B.q > 0 && !B.direct) {
-                B.coef_off += coef_shift;
-                B.grid_off += out.grid_elems;
-                B.scratch_off += out.scratch_elems;
-                B.cs_off += cso;
-                B.mask_off += mko;
-                B.base_off += out.base_elems;
-                auto dt = deconv_at.find(B.log2n);
-                if (dt == deconv_at.end()) {
-                    const int64_t len = ((int64_t)1 << B.log2n) / 4 + 1;
-                    dt = deconv_at.emplace(B.log2n, (int)out.deconv.size()).first;
-                    out.deconv.insert(out.deconv.end(), p.deconv.begin() + B.deconv_off,
-                                      p.deconv.begin() + B.deconv_off + len);
+    // The members are independent: they are planned on several host threads,
+    // CHUNK at a time (bounding the memory held at once), and merged in order.
+    const int32_t CHUNK = 64;
+    const int nth = std::max(1, std::min(16, (int)std::thread::hardware_concurrency()));
+    for (int32_t c0 = 0; c0 < count; c0 += CHUNK) {
+        const int32_t c1 = std::min(count, c0 + CHUNK);
+        std::vector<HostPlan> members(c1 - c0);
+        std::vector<int> rcs(c1 - c0, FLT_OK);
+        std::atomic<int32_t> next(c0);
+        auto work = [&]() {
+            for (int32_t i = next.fetch_add(1); i < c1; i = next.fetch_add(1)) {
+                try {
+                    rcs[i - c0] = build_one(members[i - c0], N[i], M[i], z + 2 * zoff[i], eps, dtype, flags, shape);
+                } catch (const std::bad_alloc&) {
+                    rcs[i - c0] = FLT_ENOMEM;
                 }
-                B.deconv_off = dt->second;
-                const int key = m < p.D ? m : -p.D;
-                auto yt = ycheb_at.find(key);
-                if (yt == ycheb_at.end()) {
-                    yt = ycheb_at.emplace(key, (int)(out.ycheb.size() / 2)).first;
-                    out.ycheb.insert(out.ycheb.end(), p.ycheb.begin() + 2 * B.ycheb_off,
-                                     p.ycheb.begin() + 2 * (B.ycheb_off + B.q));
-                }
-                B.ycheb_off = yt->second;
             }
-            out.bands.push_back(B);
-            out.band_m.push_back(m);
-        }
-        out.node_band.insert(out.node_band.end(), p.node_band.begin(), p.node_band.end());
-        out.nx.insert(out.nx.end(), p.nx.begin(), p.nx.end());
-        out.ny.insert(out.ny.end(), p.ny.begin(), p.ny.end());
-        for (int32_t v : p.perm) out.perm.push_back((int32_t)(v + no));
-        auto shift_fft = [&](std::vector<FftItem>& dst, const std::vector<FftItem>& src) {
-            for (FftItem it : src) { it.band += bo; dst.push_back(it); }
         };
-        shift_fft(out.onepass_fwd, p.onepass_fwd);
-        shift_fft(out.passA_fwd, p.passA_fwd);
-        shift_fft(out.passB, p.passB);
-        shift_fft(out.onepass_adj, p.onepass_adj);
-        shift_fft(out.passA_adj, p.passA_adj);
-        shift_fft(out.onepass_fused, p.onepass_fused);
-        shift_fft(out.passB_fused, p.passB_fused);
-        const int32_t clo = (int32_t)out.clist.size();
-        for (CellItem it : p.cells) {
-            it.band += bo;
-            if (it.listed) it.cell0 += clo;
-            out.cells.push_back(it);
+        std::vector<std::thread> pool;
+        try {
+            for (int t = 1; t < std::min(nth, (int)(c1 - c0)); ++t) pool.emplace_back(work);
+        } catch (const std::system_error&) {   // fewer threads: the calling one does the rest
         }
-        out.clist.insert(out.clist.end(), p.clist.begin(), p.clist.end());
-        auto shift_nodes = [&](std::vector<NodeItem>& dst, const std::vector<NodeItem>& src) {
-            for (NodeItem it : src) { it.band += bo; it.start += no; dst.push_back(it); }
-        };
-        shift_nodes(out.gather_st, p.gather_st);
-        shift_nodes(out.gather_ln, p.gather_ln);
-        shift_nodes(out.nfft_nodes, p.nfft_nodes);
-        for (int32_t v : p.dlist) out.dlist.push_back((int32_t)(v + no));
-        for (DirectItem it : p.direct_fwd) { it.first += (int32_t)dlo; it.inst = i; out.direct_fwd.push_back(it); }
-        for (DirectItem it : p.direct_adj) { it.first += (int32_t)dlo; it.inst = i; out.direct_adj.push_back(it); }
-        for (int32_t v : p.cstart) out.cstart.push_back((int32_t)(v + no));
-        out.mask.insert(out.mask.end(), p.mask.begin(), p.mask.end());
-        out.inst.push_back(InstDesc{co, p.N, no, p.M});
-        for (SumItem it : p.sum_items) { it.inst = i; it.start += no; out.sum_items.push_back(it); }
-        out.qs = std::max(out.qs, p.qs);
-        out.D = std::max(out.D, p.D);
-        out.n_xi = std::max(out.n_xi, p.n_xi);
-        out.nodes_z0 += p.nodes_z0;
-        out.grid_elems += p.grid_elems;
-        out.scratch_elems += p.scratch_elems;
-        out.base_elems += p.base_elems;
-        out.bytes_forward += p.bytes_forward;
-        out.flops_forward += p.flops_forward;
-        out.N += p.N;
-        out.M += p.M;
+        work();
+        for (std::thread& t : pool) t.join();
+        for (int32_t i = c0; i < c1; ++i) {
+            if (rcs[i - c0] != FLT_OK) return rcs[i - c0];
+            HostPlan p = std::move(members[i - c0]);
+            if (i == 0) {
+                out.dtype = p.dtype;
+                out.eps = p.eps;
+                out.eps_K = p.eps_K;
+                out.eps_A = p.eps_A;
+                out.y1 = p.y1;
+                out.q = p.q;
+                out.mw = p.mw;
+                out.kb_b = p.kb_b;
+                out.flags = p.flags;
+                out.direct_scale = p.direct_scale;
+                out.tw_stage = p.tw_stage;
+                out.tw_lo = p.tw_lo;
+                out.tw_hi = p.tw_hi;
+            }
+            // the coefficient table depends on q, y_1 and D - n_xi only (see build_one):
+            // share it, appending when a member's table differs (never for one eps)
+            int32_t coef_shift = 0;
+            if (out.coef.empty()) out.coef = p.coef;
+            else if (p.coef.size() > out.coef.size() ||
+                     !std::equal(p.coef.begin(), p.coef.end(), out.coef.begin())) {
+                coef_shift = (int32_t)out.coef.size();
+                out.coef.insert(out.coef.end(), p.coef.begin(), p.coef.end());
+            }
+            const int32_t bo = (int32_t)out.bands.size();
+            const int64_t no = out.M;                    // sorted-node (and caller-index) offset
+            const int64_t co = out.N;                    // coefficient offset
+            const int64_t dlo = (int64_t)out.dlist.size();
+            const int64_t cso = (int64_t)out.cstart.size(), mko = (int64_t)out.mask.size();
+            for (size_t b = 0; b < p.bands.size(); ++b) {
+                BandDesc B = p.bands[b];
+                const int m = p.band_m[b];
+                B.c_off = co;
+                B.node_start += no;
+                if (B.q > 0 && !B.direct) {
+                    B.coef_off += coef_shift;
+                    B.grid_off += out.grid_elems;
+                    B.scratch_off += out.scratch_elems;
+                    B.cs_off += cso;
+                    B.mask_off += mko;
+                    B.base_off += out.base_elems;
+                    auto dt = deconv_at.find(B.log2n);
+                    if (dt == deconv_at.end()) {
+                        const int64_t len = ((int64_t)1 << B.log2n) / 4 + 1;
+                        dt = deconv_at.emplace(B.log2n, (int)out.deconv.size()).first;
+                        out.deconv.insert(out.deconv.end(), p.deconv.begin() + B.deconv_off,
+                                          p.deconv.begin() + B.deconv_off + len);
+                    }
+                    B.deconv_off = dt->second;
+                    const int key = m < p.D ? m : -p.D;
+                    auto yt = ycheb_at.find(key);
+                    if (yt == ycheb_at.end()) {
+                        yt = ycheb_at.emplace(key, (int)(out.ycheb.size() / 2)).first;
+                        out.ycheb.insert(out.ycheb.end(), p.ycheb.begin() + 2 * B.ycheb_off,
+                                         p.ycheb.begin() + 2 * (B.ycheb_off + B.q));
+                    }
+                    B.ycheb_off = yt->second;
+                }
+                out.bands.push_back(B);
+                out.band_m.push_back(m);
+            }
+            out.node_band.insert(out.node_band.end(), p.node_band.begin(), p.node_band.end());
+            out.nx.insert(out.nx.end(), p.nx.begin(), p.nx.end());
+            out.ny.insert(out.ny.end(), p.ny.begin(), p.ny.end());
+            for (int32_t v : p.perm) out.perm.push_back((int32_t)(v + no));
+            auto shift_fft = [&](std::vector<FftItem>& dst, const std::vector<FftItem>& src) {
+                for (FftItem it : src) { it.band += bo; dst.push_back(it); }
+            };
+            shift_fft(out.onepass_fwd, p.onepass_fwd);
+            shift_fft(out.passA_fwd, p.passA_fwd);
+            shift_fft(out.passB, p.passB);
+            shift_fft(out.onepass_adj, p.onepass_adj);
+            shift_fft(out.passA_adj, p.passA_adj);
+            shift_fft(out.onepass_fused, p.onepass_fused);
+            shift_fft(out.passB_fused, p.passB_fused);
+            const int32_t clo = (int32_t)out.clist.size();
+            for (CellItem it : p.cells) {
+                it.band += bo;
+                if (it.listed) it.cell0 += clo;
+                out.cells.push_back(it);
+            }
+            out.clist.insert(out.clist.end(), p.clist.begin(), p.clist.end());
+            auto shift_nodes = [&](std::vector<NodeItem>& dst, const std::vector<NodeItem>& src) {
+                for (NodeItem it : src) { it.band += bo; it.start += no; dst.push_back(it); }
+            };
+            shift_nodes(out.gather_st, p.gather_st);
+            shift_nodes(out.gather_ln, p.gather_ln);
+            shift_nodes(out.nfft_nodes, p.nfft_nodes);
+            for (int32_t v : p.dlist) out.dlist.push_back((int32_t)(v + no));
+            for (DirectItem it : p.direct_fwd) { it.first += (int32_t)dlo; it.inst = i; out.direct_fwd.push_back(it); }
+            for (DirectItem it : p.direct_adj) { it.first += (int32_t)dlo; it.inst = i; out.direct_adj.push_back(it); }
+            for (int32_t v : p.cstart) out.cstart.push_back((int32_t)(v + no));
+            out.mask.insert(out.mask.end(), p.mask.begin(), p.mask.end());
+            out.inst.push_back(InstDesc{co, p.N, no, p.M});
+            for (SumItem it : p.sum_items) { it.inst = i; it.start += no; out.sum_items.push_back(it); }
+            out.qs = std::max(out.qs, p.qs);
+            out.D = std::max(out.D, p.D);
+            out.n_xi = std::max(out.n_xi, p.n_xi);
+            out.nodes_z0 += p.nodes_z0;
+            out.grid_elems += p.grid_elems;
+            out.scratch_elems += p.scratch_elems;
+            out.base_elems += p.base_elems;
+            out.bytes_forward += p.bytes_forward;
+            out.flops_forward += p.flops_forward;
+            out.N += p.N;
+            out.M += p.M;
+        }
     }
     if (out.M > (int64_t)INT32_MAX) return FLT_ERANGE;
     finish(out);
