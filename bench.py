@@ -174,10 +174,12 @@ def traffic_for(kernel, algorithmic_bytes):
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
         return None
-    v = rec.get("kernels", {}).get(KERNEL_NAMES[kernel])
-    if v is None or v.get("algorithmic_bytes_per_launch") != algorithmic_bytes:
-        return None
-    return v.get("bytes_per_launch")
+    # the default band policy's plan, then any other plan the counters were taken on
+    for plan in [rec] + rec.get("plans", []):
+        v = plan.get("kernels", {}).get(KERNEL_NAMES[kernel])
+        if v is not None and v.get("algorithmic_bytes_per_launch") == algorithmic_bytes:
+            return v.get("bytes_per_launch")
+    return None
 
 
 def copy_bandwidth(torch, dev, mib=2048, reps=5):
