@@ -105,10 +105,27 @@ template <typename T> static std::vector<T> cast(const std::vector<double>& v)
     return std::vector<T>(v.begin(), v.end());
 }
 
+// LDS stand-ins of the kernels being run: every workgroup's LDS starts with
+// whatever it held, so each is refilled with all-ones bytes (NaN in FP32 and
+// FP64) before every workgroup; a read before the workgroup's own write shows
+// in the result instead of seeing the previous workgroup's values.
+static thread_local std::vector<std::pair<void*, size_t>> g_lds;
+struct LdsReg {   // registered while in scope (registrations nest)
+    template <class V> explicit LdsReg(V& v) { g_lds.emplace_back((void*)v.data(), v.size() * sizeof(v[0])); }
+    ~LdsReg() { g_lds.pop_back(); }
+    LdsReg(const LdsReg&) = delete;
+    LdsReg& operator=(const LdsReg&) = delete;
+};
+static void lds_poison()
+{
+    for (const auto& e : g_lds) memset(e.first, 0xFF, e.second);
+}
+
 template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body)
 {
 #ifdef FLT_EMU_OMP_TEAMS
     for (size_t b = 0; b < nblocks; ++b) {
+        lds_poison();
 #pragma omp parallel num_threads(nthreads)
         {
             HostCtx ctx{omp_get_thread_num(), omp_get_num_threads(), (int)b};
@@ -126,6 +143,7 @@ template <class F> static void run_blocks(size_t nblocks, int nthreads, F&& body
         (*(const Fn*)f)(ctx);
     };
     for (size_t b = 0; b < nblocks; ++b) {
+        lds_poison();
         T.b = (int)b;
         for (int t = 0; t < nthreads; ++t) {
             getcontext(&T.uc[t]);
@@ -154,6 +172,7 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
 {
     if (!adjoint) {
         std::vector<cplx<T>> stage(GATHER_STAGE, nan_c<T>());
+        const LdsReg r_stage(stage);
         run_blocks(hp.gather_st.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
             body_gather<HostCtx, T, MW, true>(ctx, pv, hp.gather_st.data(), c, grids, f, with_c0, f2, stage.data());
         });
@@ -166,6 +185,7 @@ static void nodes_mw(const PlanView<T>& pv, const HostPlan& hp, int adjoint, con
         body_adj_prep<HostCtx, T, MW>(ctx, pv, hp.nfft_nodes.data(), c, hp.qs, U, Phi, L0);
     });
     std::vector<T> red(2 * ADJ_RC * GATHER_THREADS, std::numeric_limits<T>::quiet_NaN());
+    const LdsReg r_red(red);
     run_blocks(hp.cells.size(), GATHER_THREADS, [&](const HostCtx& ctx) {
         body_adj_cells<HostCtx, T, MW>(ctx, pv, hp.cells.data(), hp.qs, U, Phi, L0, hp.cstart.data(),
                                        hp.clist.data(), grids, red.data());
@@ -211,6 +231,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<cplx<T>> lds2(2 * tile_alloc<T>(), cnan);   // the FP32 pass A's two tiles and coefficient buffers
     std::vector<T> lc2(2 * Sizes<T>::COEF, qnan);
     std::vector<cplx<T>> omega(PASSA_OMEGA_MAX);
+    const LdsReg r_red(red), r_lds(lds), r_lc(lc), r_lc1(lc1), r_lds2(lds2), r_lc2(lc2), r_omega(omega);
     std::vector<cplx<T>> basebuf(std::max<int64_t>(hp.base_elems, 1));
     const int64_t nd = (int64_t)hp.dlist.size();
     auto mwsw = [&](int adjoint, const cplx<T>* c, cplx<T>* f, int with_c0, cplx<T>* f2) {
@@ -264,6 +285,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 0);
             });
             std::vector<cplx<T>> nw(DIRECT_NG, nan_c<T>());
+            const LdsReg r_nw(nw);
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
                 if (deriv || d)
                     body_direct_fwd<HostCtx, T, true>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, dacc.data(),
@@ -315,6 +337,7 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
                 });
             });
         std::vector<cplx<T>> nw(DIRECT_ANG, nan_c<T>()), ngv(DIRECT_ANG, nan_c<T>()), redv(256 * ADJ_TS, nan_c<T>());
+        const LdsReg r_nw(nw), r_ngv(ngv), r_redv(redv);
         run_blocks(hp.direct_adj.size(), 256, [&](const HostCtx& ctx) {
             body_direct_adj<HostCtx, T>(ctx, pv, hp.direct_adj.data(), hp.dlist.data(), g, acc.data(), nw.data(),
                                         ngv.data(), redv.data());
@@ -359,6 +382,7 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
     const double dnan = std::numeric_limits<double>::quiet_NaN();
     std::vector<double> red(8 * LAP_THREADS, dnan), red2(LAP_THREADS, dnan), rred(LAP_THREADS, dnan),
         bred(4 * LAP_THREADS, dnan);
+    const LdsReg r_red(red), r_red2(red2), r_rred(rred), r_bred(bred);
     auto all = [&](auto qb) {
         constexpr int QB = decltype(qb)::value;
         run_blocks(hp.items.size(), LAP_THREADS, [&](const HostCtx& ctx) {
@@ -368,6 +392,7 @@ template <typename T> static int emu_laplace(const LapHost& hp, const void* in, 
         run_blocks((size_t)hp.L, LAP_THREADS, [&](const HostCtx& ctx) { lap_body_bands<HostCtx, QB>(ctx, V, bred.data()); });
         const int64_t per = (int64_t)LAP_THREADS * LAP_NODE_PER, ns = lap_node_stage(hp.L, hp.q);
         std::vector<double> sb((size_t)std::max<int64_t>(ns, 1), dnan);
+        const LdsReg r_sb(sb);
         run_blocks((hp.M + per - 1) / per, LAP_THREADS, [&](const HostCtx& ctx) {
             lap_body_nodes<HostCtx, T, QB>(ctx, V, hp.M, (cplx<T>*)out, ns > 0 ? sb.data() : nullptr,
                                            (const cplx<T>*)in);
@@ -408,6 +433,7 @@ template <typename T> static int emu_xi(XiHost& hp, int op, const void* in, void
         hout(std::max<int64_t>(hp.hout_elems, 1), nan_c<T>());
     std::vector<T> lc(XI_NBLK * 32 * 32, std::numeric_limits<T>::quiet_NaN());
     std::vector<cplx<T>> ct(32 * 1024 / sizeof(cplx<T>), nan_c<T>());   // xi_kcap * QM for every QM
+    const LdsReg r_lc(lc), r_ct(ct);
     if (op == 0) {
         run_blocks(hp.spread.size(), XI_THREADS, [&](const HostCtx& ctx) {
             if (qmax <= 16) body_xi_spread<HostCtx, T, 16>(ctx, xv, hp.spread.data(), (const cplx<T>*)in, cin.data(), lc.data(), ct.data());
