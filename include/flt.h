@@ -58,7 +58,7 @@ typedef struct flt_plan flt_plan;
                                         (direct-sum rate scaled by 0, 1/2, 1, 2, 4, 8; distinct band choices
                                         only), then workgroups per CU of the persistent pass B (2, 1, 3, 4).
                                         All candidates are timed twice (the first pass a warm-up); in that
-                                        order each replaces the choice only when at least 5% faster.  The
+                                        order each replaces the choice only when at least 2% faster.  The
                                         choice is cached per (objective, dtype, eps, instances, size class) for
                                         the process.  Ignored with FLT_FLAG_NFFT_ONLY or FLT_FLAG_HOST_ONLY */
 #define FLT_FLAG_TUNE_FORWARD (1u << 4) /* with FLT_FLAG_AUTOTUNE: time the forward alone (plans used for

@@ -267,13 +267,14 @@ int time_candidate(flt_plan* p, bool fwd_only, double* ms)
     return e == hipSuccess ? FLT_OK : hip_fail(e);
 }
 
-// Index of the first candidate that no later one beats by 5%.
+// Index of the first candidate that no later one beats by 2% (the timing noise
+// of five calls, timed twice, is about 1%).
 size_t pick(const std::vector<double>& ms)
 {
     double best = 1e300;
     size_t at = 0;
     for (size_t i = 0; i < ms.size(); ++i)
-        if (ms[i] < 0.95 * best) {
+        if (ms[i] < 0.98 * best) {
             best = ms[i];
             at = i;
         }

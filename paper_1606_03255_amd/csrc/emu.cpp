@@ -231,7 +231,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
     std::vector<cplx<T>> lds2(2 * tile_alloc<T>(), cnan);   // the FP32 pass A's two tiles and coefficient buffers
     std::vector<T> lc2(2 * Sizes<T>::COEF, qnan);
     std::vector<cplx<T>> omega(PASSA_OMEGA_MAX);
-    const LdsReg r_red(red), r_lds(lds), r_lc(lc), r_lc1(lc1), r_lds2(lds2), r_lc2(lc2), r_omega(omega);
+    std::vector<cplx<T>> passb_tw(lds_tw_half<Log2Range<T>::B_HI>(), cnan);   // pass B's twiddle half table
+    const LdsReg r_red(red), r_lds(lds), r_lc(lc), r_lc1(lc1), r_lds2(lds2), r_lc2(lc2), r_omega(omega), r_pbtw(passb_tw);
     std::vector<cplx<T>> basebuf(std::max<int64_t>(hp.base_elems, 1));
     const int64_t nd = (int64_t)hp.dlist.size();
     auto mwsw = [&](int adjoint, const cplx<T>* c, cplx<T>* f, int with_c0, cplx<T>* f2) {
@@ -275,7 +276,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             const int n = (int)pb.size();
             const int nb = passB_prefetch<T, +1>() ? std::min(n, EMU_PERSIST_BLOCKS) : n;
             run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
-                body_passB<HostCtx, T, +1>(ctx, pv, pb.data(), n, nb, scratch.data(), grids.data(), cols, lds.data());
+                body_passB<HostCtx, T, +1>(ctx, pv, pb.data(), n, nb, scratch.data(), grids.data(), cols, lds.data(),
+                                           passb_tw.data());
             });
         }
         mwsw(0, c, f, !deriv, f2);
@@ -313,7 +315,8 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             const int n = (int)hp.passB.size();
             const int nb = passB_prefetch<T, -1>() ? std::min(n, EMU_PERSIST_BLOCKS) : n;
             run_blocks(nb, FFT_THREADS, [&](const HostCtx& ctx) {
-                body_passB<HostCtx, T, -1>(ctx, pv, hp.passB.data(), n, nb, grids.data(), scratch.data(), 1, lds.data());
+                body_passB<HostCtx, T, -1>(ctx, pv, hp.passB.data(), n, nb, grids.data(), scratch.data(), 1, lds.data(),
+                                           passb_tw.data());
             });
         }
         for (const LaunchGroup& g : hp.g_passA_adj)

@@ -47,6 +47,8 @@ static_assert(lds_fft_bytes<float>() + sizeof(float) * onepass_coef<float>() <= 
                   lds_fft_bytes<double>() + sizeof(double) * onepass_coef<double>() <= LDS_TWO_PER_CU &&
                   onepass_coef<double>() >= 2 * MAX_Q * 16,
               "one-pass FFT: tile and staged coefficients, two workgroups per CU");
+static_assert(lds_fft_bytes<float>() + sizeof(cplx<float>) * lds_tw_half<Log2Range<float>::B_HI>() <= LDS_TWO_PER_CU,
+              "persistent pass B: tile and twiddle half table, two workgroups per CU");
 
 // One launch per FFT kind; each workgroup picks the compile-time instance of
 // its band's transform length.
@@ -101,7 +103,9 @@ __global__ __launch_bounds__(FFT_THREADS) __attribute__((amdgpu_waves_per_eu(4, 
                                                           const cplx<T>* src, cplx<T>* dst, int cols)
 {
     __shared__ cplx<T> lds[tile_alloc<T>()];
-    body_passB<DevCtx, T, SIGN>(DevCtx(), pv, items, nitems, (int)gridDim.x, src, dst, cols, lds);
+    // the prefetching variant's twiddle half table (the longest pass-B transform)
+    __shared__ cplx<T> twl[passB_prefetch<T, SIGN>() ? lds_tw_half<Log2Range<T>::B_HI>() : 1];
+    body_passB<DevCtx, T, SIGN>(DevCtx(), pv, items, nitems, (int)gridDim.x, src, dst, cols, lds, twl);
 }
 
 template <typename T, int MW>

@@ -281,6 +281,39 @@ struct StageTw<T, LOG2L, NSUB, SIGN, LOG2NS, true> {
 template <bool REG, typename T, int LOG2L, int NSUB, int SIGN> struct TwSel { using type = StageTw<T, LOG2L, NSUB, SIGN>; };
 template <typename T, int LOG2L, int NSUB, int SIGN> struct TwSel<false, T, LOG2L, NSUB, SIGN> { using type = TableTw<T>; };
 
+// Stage twiddles of transforms of one length L = 2^LOG2L from a half table in
+// LDS, th[t] = e^{-2 pi i t / L} for t < L/2, and e^{-2 pi i t / L} = -th[t - L/2]
+// above: the persistent pass B's factors without a global gather per factor
+// (its registers hold the prefetched tile instead).
+template <int LOG2L> constexpr int lds_tw_half() { return 1 << (LOG2L - 1); }
+template <typename T, int LOG2L> struct LdsTw {
+    const cplx<T>* th;
+    template <int SIGN> FLT_HD cplx<T> at(int e) const   // e in [0, L)
+    {
+        constexpr int H = lds_tw_half<LOG2L>();
+        cplx<T> w = th[e & (H - 1)];
+        if (e & H) w = mk(-w.x, -w.y);
+        if (SIGN > 0) w.y = -w.y;
+        return w;
+    }
+    template <int LR, int LOG2NS, int SIGN>
+    FLT_HD void factors(int /*i*/, int k, cplx<T>* wa, cplx<T>* wb) const
+    {
+        constexpr int SH = LOG2L - LOG2NS - LR;   // k r < Ns R <= L: indices below L
+        constexpr int LA = LR / 2, LB = LR - LA;
+        for (int r1 = 1; r1 < (1 << LA); ++r1) wa[r1] = at<SIGN>((k * r1) << SH);
+        for (int r2 = 1; r2 < (1 << LB); ++r2) wb[r2] = at<SIGN>((k * r2) << (SH + LA));
+    }
+    // every thread writes its share of the table; a barrier must follow before use
+    template <class Ctx> FLT_HD void fill(const Ctx& ctx, const cplx<T>* tw_global, cplx<T>* lds_table)
+    {
+        th = lds_table;
+        for (int t = ctx.tid(); t < lds_tw_half<LOG2L>(); t += ctx.ntid())
+            lds_table[t] = tw_global[t << (TW_STAGE_LOG2 - LOG2L)];
+    }
+    FLT_HD const LdsTw& next() const { return *this; }
+};
+
 // The geometry of one Stockham stage: NB butterflies of radix R per thread.
 template <int LR, int LOG2L, int NSUB> struct StageGeo {
     static constexpr int R = 1 << LR;
@@ -1016,7 +1049,7 @@ template <typename T, int SIGN> constexpr bool passB_prefetch() { return sizeof(
 // index of the workgroup's first item not processed.
 template <class Ctx, typename T, int LOG2N2, int SIGN>
 FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* items, int i, int nitems, int nblocks,
-                     const cplx<T>* src_base, cplx<T>* dst_base, int cols, cplx<T>* lds)
+                     const cplx<T>* src_base, cplx<T>* dst_base, int cols, cplx<T>* lds, cplx<T>* twl)
 {
     constexpr bool ADJ = SIGN < 0;
     constexpr bool PREFETCH = passB_prefetch<T, SIGN>();
@@ -1024,9 +1057,15 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
     constexpr int CHUNKS = tile_points<T>() / G::V;
     TileRegs<T> v;
     passB_fetch<Ctx, T, LOG2N2, ADJ>(ctx0, pv, items[i], src_base, cols, v);
-    // with prefetch the registers hold the next tile instead of the twiddles
-    typename TwSel<!PREFETCH, T, LOG2N2, (1 << G::log2B), SIGN>::type stw;
-    stw.load(ctx0, pv.tw_stage);
+    // with prefetch the registers hold the next tile instead of the twiddles,
+    // which come from a half table in LDS (written here, read after the
+    // barrier that follows the first tile's store to LDS; the previous run's
+    // readers finished at its last barrier)
+    using TwP = typename std::conditional<PREFETCH, LdsTw<T, LOG2N2>,
+                                          typename TwSel<true, T, LOG2N2, (1 << G::log2B), SIGN>::type>::type;
+    TwP stw;
+    if constexpr (PREFETCH) stw.fill(ctx0, pv.tw_stage, twl);
+    else stw.load(ctx0, pv.tw_stage);
     for (;;) {
         const IterCtx<Ctx> ctx{ctx0, opaque(ctx0.tid())};
         const FftItem it = items[i];
@@ -1072,7 +1111,7 @@ FLT_HD int passB_run(const Ctx& ctx0, const PlanView<T>& pv, const FftItem* item
 // (forward: scratch -> grids, SIGN = +1; adjoint: grids -> scratch, SIGN = -1).
 template <class Ctx, typename T, int SIGN>
 FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* items, int nitems, int nblocks,
-                       const cplx<T>* src_base, cplx<T>* dst_base, int cols, cplx<T>* lds)
+                       const cplx<T>* src_base, cplx<T>* dst_base, int cols, cplx<T>* lds, cplx<T>* twl)
 {
     using RG = Log2Range<T>;
     int i = ctx.bid();
@@ -1080,14 +1119,14 @@ FLT_HD void body_passB(const Ctx& ctx, const PlanView<T>& pv, const FftItem* ite
         if (i < nitems)
             with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
                 passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nitems, src_base, dst_base,
-                                                             cols, lds);
+                                                             cols, lds, twl);
             });
         return;
     }
     while (i < nitems) {
         with_log2<RG::B_LO, RG::B_HI>(pv.bands[items[i].band].log2n2, [&](auto LG) {
             i = passB_run<Ctx, T, decltype(LG)::value, SIGN>(ctx, pv, items, i, nitems, nblocks, src_base, dst_base,
-                                                             cols, lds);
+                                                             cols, lds, twl);
         });
     }
 }
