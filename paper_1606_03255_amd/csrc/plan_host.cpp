@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <exception>
 #include <map>
 #include <numeric>
 #include <system_error>
@@ -554,7 +555,7 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
             for (int32_t i = next.fetch_add(1); i < c1; i = next.fetch_add(1)) {
                 try {
                     rcs[i - c0] = build_one(members[i - c0], N[i], M[i], z + 2 * zoff[i], eps, dtype, flags, shape);
-                } catch (const std::bad_alloc&) {
+                } catch (const std::exception&) {   // allocation failures (no exception may leave a thread)
                     rcs[i - c0] = FLT_ENOMEM;
                 }
             }
