@@ -98,6 +98,14 @@ def stage_bytes(plan, S):
     return b
 
 
+def stage_fracs(stage_ms, stage_b):
+    """Each stage's algorithmic bytes per second as a fraction of the HBM peak
+    (stages whose bound is not HBM traffic, such as the direct sums, included
+    for reference)."""
+    return {k: round(stage_b[k] / (stage_ms[k] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+            for k in stage_ms if stage_b.get(k) and stage_ms[k] > 0}
+
+
 def adjoint_stage_bytes(plan, S):
     """Algorithmic HBM bytes per launch of each adjoint stage.  Clearing: the
     FP64 accumulator (16 N) written, g read once for the k = 0 sum.  Node
@@ -243,6 +251,7 @@ def step_leg(torch, dev, w, eps32, eps64, args, tune, log, label, profile):
             S = 8 if form == "fp32" else 16
             sab = adjoint_stage_bytes(p, S)
             rec["adjoint_stage_bytes_" + form] = sab
+            rec["adjoint_stage_frac_hbm_" + form] = stage_fracs(sa, sab)
             rec["roofline_adjoint_" + form] = roofline_of(sa, sab, ADJ_KERNEL_NAMES)
             if form == "fp64":
                 rec["ms_fp64_forward"] = round(time_steps(torch, lambda: p.forward(c, out=f), steps, 1)[0], 4)
@@ -660,6 +669,7 @@ def main():
         "fwd_bwd_grad": fwd_bwd_grad,
         "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_bytes": sb,
+        "stage_frac_hbm": stage_fracs(stage_ms, sb),
         "hbm_copy_GBs": copy_gbs,
         "plan_ms": round(plan32_ms, 1),
         "direct_scale": info["direct_scale"],
