@@ -531,6 +531,9 @@ def main():
     ap.add_argument("--forward-only", action="store_true", help="skip the fwd+bwd and FP64 legs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="plans with the default band policy instead of the timed choice")
+    ap.add_argument("--direct-scale", type=float, default=None,
+                    help="the main FP32 plan's band-policy factor, fixed instead of timed (for counter "
+                         "runs that reproduce a tuned plan)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-instance batched leg")
     ap.add_argument("--no-laplace", action="store_true", help="skip the Laplace-transform (Algorithm 1) leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd step at N = M = 2^18")
@@ -580,7 +583,10 @@ def main():
     tune = not args.no_autotune
     # the value is a forward throughput: its plan's band policy is tuned on the
     # forward alone; the fwd+bwd step uses plans tuned on forward + adjoint
-    p32 = Plan(N, w["z"], 1e-6, torch.complex64, device=dev, autotune="forward" if tune else False)
+    if args.direct_scale is not None:
+        p32 = Plan(N, w["z"], 1e-6, torch.complex64, device=dev, direct_scale=args.direct_scale)
+    else:
+        p32 = Plan(N, w["z"], 1e-6, torch.complex64, device=dev, autotune="forward" if tune else False)
     plan32_ms = (time.perf_counter() - t) * 1e3
     log("FP32 plan built in %.0f ms" % plan32_ms)
     c32 = torch.from_numpy(w["c"]).to(dev)

@@ -25,7 +25,7 @@ ERRORS = {
 
 # every symbol include/flt.h declares
 EXPORTS = (
-    "flt_plan_create", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
+    "flt_plan_create", "flt_plan_create_policy", "flt_plan_create_batch", "flt_plan_destroy", "flt_plan_info", "flt_plan_band", "flt_plan_node_bands",
     "flt_plan_workspace_size", "flt_plan_set_workspace", "flt_forward", "flt_derivative", "flt_adjoint",
     "flt_forward_derivative", "flt_forward_noalloc", "flt_profile_forward", "flt_profile_adjoint", "flt_strerror", "flt_last_hip_error",
     "flt_laplace_plan_create", "flt_laplace_plan_create_kernel", "flt_laplace_plan_info", "flt_laplace_forward",
@@ -102,6 +102,8 @@ def load():
     P = ctypes.POINTER
     lib.flt_plan_create.argtypes = [P(vp), ctypes.c_int64, ctypes.c_int64, P(ctypes.c_double), ctypes.c_double,
                                     ctypes.c_int, ctypes.c_uint32]
+    lib.flt_plan_create_policy.argtypes = [P(vp), ctypes.c_int64, ctypes.c_int64, P(ctypes.c_double),
+                                           ctypes.c_double, ctypes.c_int, ctypes.c_uint32, ctypes.c_double]
     lib.flt_plan_create_batch.argtypes = [P(vp), ctypes.c_int32, P(ctypes.c_int64), P(ctypes.c_int64),
                                           P(ctypes.c_double), ctypes.c_double, ctypes.c_int, ctypes.c_uint32]
     lib.flt_plan_destroy.argtypes = [vp]

@@ -460,6 +460,18 @@ int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z, doubl
     });
 }
 
+int flt_plan_create_policy(flt_plan** out, int64_t N, int64_t M, const double* z, double eps, int dtype,
+                           uint32_t flags, double direct_scale)
+{
+    if (out) *out = nullptr;
+    if ((flags & FLT_FLAG_AUTOTUNE) || !(direct_scale >= 0.0 && direct_scale <= 1.0e300)) return FLT_EINVAL;   // NaN and inf fail too
+    return create(out, flags, [&](HostPlan& hp, const PlanShape& shape) {
+        PlanShape sh = shape;   // the default shape (no tuning), with the given factor
+        sh.direct_scale = direct_scale;
+        return build_host_plan(hp, N, M, z, eps, dtype, flags, sh);
+    });
+}
+
 int flt_plan_create_batch(flt_plan** out, int32_t count, const int64_t* N, const int64_t* M, const double* z,
                           double eps, int dtype, uint32_t flags)
 {

@@ -83,13 +83,15 @@ class Plan:
     ``autotune=True`` chooses the band policy by timing forward + adjoint of
     candidate plans on the device (cached per size class for the process);
     ``autotune="forward"`` times the forward alone (plans for evaluation only).
+    ``direct_scale=x`` builds a single plan with the band policy's factor x
+    (a tuned plan's ``info()["direct_scale"]``) without timing anything.
 
     ``Plan.batch`` builds one plan for many independent instances; its
     transforms act on packed arrays (instance after instance).
     """
 
     def __init__(self, N, z, eps, dtype="complex64", device=None, host_only=False, nfft_only=False, graph=False,
-                 autotune=False, _sizes=None):
+                 autotune=False, direct_scale=None, _sizes=None):
         self._lib = L.load()
         self._ptr = ctypes.c_void_p()
         zh = _as_host_z(z)
@@ -110,8 +112,14 @@ class Plan:
         zp = zh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         I64 = ctypes.POINTER(ctypes.c_int64)
 
+        if direct_scale is not None and (autotune or _sizes is not None):
+            raise ValueError("direct_scale fixes the band policy of a single plan: not with autotune or a batch")
+
         def create():
-            if _sizes is None:
+            if direct_scale is not None:
+                rc = self._lib.flt_plan_create_policy(ctypes.byref(self._ptr), self.N, self.M, zp, float(eps),
+                                                      self.dtype_code, flags, float(direct_scale))
+            elif _sizes is None:
                 rc = self._lib.flt_plan_create(ctypes.byref(self._ptr), self.N, self.M, zp, float(eps),
                                                self.dtype_code, flags)
             else:

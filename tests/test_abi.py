@@ -196,6 +196,37 @@ def test_autotune_flag_on_host_only_plans_keeps_the_default_policy():
     assert p.bands() == q.bands()
 
 
+def test_fixed_band_policy():
+    """flt_plan_create_policy rebuilds a plan with the given band-policy
+    factor: the factor is reported, a larger factor never makes fewer bands
+    direct (the direct-sum cost is divided by it), factor 1 equals the default
+    plan, and invalid factors or the tuning flag are refused."""
+    rng = np.random.default_rng(5)
+    z = np.concatenate([inputs.nodes_disk(rng, 3000), inputs.nodes_annulus(rng, 300)])
+    base = flt.Plan(70000, z, 1e-6, "complex64", host_only=True)
+    prev = None
+    for sc in (0.0, 0.5, 1.0, 2.0, 8.0):
+        p = flt.Plan(70000, z, 1e-6, "complex64", host_only=True, direct_scale=sc)
+        assert p.info()["direct_scale"] == sc
+        direct = [b["direct"] for b in p.bands()]
+        if prev is not None:
+            assert all(d >= e for d, e in zip(direct, prev))
+        prev = direct
+        if sc == 1.0:
+            assert p.bands() == base.bands()
+        p.close()
+    lib = L.load()
+    ptr = ctypes.c_void_p()
+    zz = np.ascontiguousarray(z.astype(np.complex128))
+    zp = zz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for sc, flags in ((-1.0, L.FLT_FLAG_HOST_ONLY), (float("nan"), L.FLT_FLAG_HOST_ONLY),
+                      (float("inf"), L.FLT_FLAG_HOST_ONLY), (1.0, L.FLT_FLAG_HOST_ONLY | L.FLT_FLAG_AUTOTUNE)):
+        assert lib.flt_plan_create_policy(ctypes.byref(ptr), 70000, len(z), zp, 1e-6, 1, flags, sc) == -1   # FLT_EINVAL
+        assert not ptr.value
+    with pytest.raises(ValueError):
+        flt.Plan(70000, z, 1e-6, "complex64", host_only=True, autotune=True, direct_scale=2.0)
+
+
 def test_binding_checks_outputs():
     """The binding rejects an output tensor that does not match the plan
     (type, size, device) or is not contiguous, before anything reaches the
