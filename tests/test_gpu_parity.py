@@ -272,3 +272,31 @@ def test_output_tensors_are_checked(torch):
         with pytest.raises((TypeError, ValueError)):
             lp.forward(fh, out=out)
     lp.close()
+
+
+@pytest.mark.parametrize("direct_scale", [0.0, 4.0])
+@pytest.mark.parametrize("dtype,eps", [("c64", 1e-6), ("c128", 1e-10)])
+def test_fixed_policy_plan_vs_direct(torch, direct_scale, dtype, eps):
+    """A plan built with a given band-policy factor (flt_plan_create_policy):
+    forward and adjoint meet the bar; factor 0 keeps every band whose direct
+    sum the policy can avoid on the NFFT path, factor 4 sends more to the
+    direct sums."""
+    from paper_1606_03255_amd import Plan
+    rng = np.random.default_rng(11)
+    N, M = 70000, 3000
+    z = _nodes(rng, M, "mixed")
+    c = inputs.coefficients(rng, N)
+    g = inputs.coefficients(rng, M)
+    if dtype == "c64":
+        c = c.astype(np.complex64).astype(np.complex128)
+        g = g.astype(np.complex64).astype(np.complex128)
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    _say("fixed policy", direct_scale, dtype, N, M)
+    plan = Plan(N, z, eps, tdt, direct_scale=direct_scale)
+    assert plan.info()["direct_scale"] == direct_scale
+    f = plan.forward(torch.from_numpy(c).to("cuda", tdt)).cpu().numpy().astype(np.complex128)
+    h = plan.adjoint(torch.from_numpy(g).to("cuda", tdt)).cpu().numpy().astype(np.complex128)
+    plan.close()
+    assert np.abs(f - oracle.forward(c, z)).max() <= eps * np.abs(c).sum()
+    k = rng.choice(N, 400, replace=False)
+    assert np.abs(h[k] - oracle.adjoint(g, z, N)[k]).max() <= eps * np.abs(g).sum()
