@@ -119,11 +119,14 @@ int flt_plan_create(flt_plan** out, int64_t N, int64_t M, const double* z,
                     double eps, int dtype, uint32_t flags);
 
 /* As flt_plan_create, with the band policy's factor on the direct-sum rate
- * given (the default policy is 1; FLT_FLAG_AUTOTUNE chooses among 0, 1/2, 1,
- * 2, 4, 8 and reports its choice in flt_info.direct_scale): rebuilds a tuned
- * plan's shape without timing, e.g. in another process.  The result is the
- * same transform to the same bar; only which bands are summed directly
- * changes.  direct_scale must be finite and >= 0, and flags may not hold
+ * given.  The band policy decides which bands of the partition (Def. 3.2) are
+ * summed directly and exactly instead of by Alg. 2's NFFT (few nodes, large
+ * grids; FLT_FLAG_NFFT_ONLY turns it off): its default factor is 1, and
+ * FLT_FLAG_AUTOTUNE chooses among 0, 1/2, 1, 2, 4, 8 and reports the choice in
+ * flt_info.direct_scale.  This call rebuilds a tuned plan's shape without
+ * timing, e.g. in another process.  The result meets the same bar (Thm 4.3;
+ * direct bands are exact); only which bands are summed directly changes.
+ * direct_scale must be finite and >= 0, and flags may not hold
  * FLT_FLAG_AUTOTUNE (FLT_EINVAL otherwise). */
 int flt_plan_create_policy(flt_plan** out, int64_t N, int64_t M, const double* z,
                            double eps, int dtype, uint32_t flags, double direct_scale);
