@@ -114,6 +114,7 @@ static int upload(flt_plan* p)
     const size_t o_l6 = pk.add(hp.cells.data(), hp.cells.size() * sizeof(CellItem));
     const size_t o_l7 = pk.add(hp.nfft_nodes.data(), hp.nfft_nodes.size() * sizeof(NodeItem));
     const size_t o_l8 = pk.add(hp.direct_fwd.data(), hp.direct_fwd.size() * sizeof(DirectItem));
+    const size_t o_l8s = pk.add(hp.direct_short.data(), hp.direct_short.size() * sizeof(DirectItem));
     const size_t o_l9 = pk.add(hp.direct_adj.data(), hp.direct_adj.size() * sizeof(DirectItem));
     const size_t o_dl = pk.add(hp.dlist.data(), hp.dlist.size() * sizeof(int32_t));
     const size_t o_cs = pk.add(hp.cstart.data(), hp.cstart.size() * sizeof(int32_t));
@@ -147,6 +148,8 @@ static int upload(flt_plan* p)
     L.cells = (const CellItem*)(base + o_l6);
     L.nfft_nodes = (const NodeItem*)(base + o_l7);
     L.direct_fwd = (const DirectItem*)(base + o_l8);
+    L.direct_short = (const DirectItem*)(base + o_l8s);
+    L.n_direct_short = (int)hp.direct_short.size();
     L.direct_adj = (const DirectItem*)(base + o_l9);
     L.dlist = (const int32_t*)(base + o_dl);
     L.cstart = (const int32_t*)(base + o_cs);

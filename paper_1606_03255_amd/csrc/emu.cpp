@@ -286,15 +286,23 @@ static int emu_run(const HostPlan& hp, int op, const void* in, void* out)
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 0);
             });
-            std::vector<cplx<T>> nw(DIRECT_NG, nan_c<T>());
+            std::vector<cplx<T>> nw(DIRECT_NG * DIRECT_GMAX, nan_c<T>());
             const LdsReg r_nw(nw);
             run_blocks(hp.direct_fwd.size(), 256, [&](const HostCtx& ctx) {
                 if (deriv || d)
-                    body_direct_fwd<HostCtx, T, true>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, dacc.data(),
-                                                      red.data(), nw.data());
+                    body_direct_fwd<HostCtx, T, true, false>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c,
+                                                             dacc.data(), red.data(), nw.data());
                 else
-                    body_direct_fwd<HostCtx, T, false>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c, dacc.data(),
-                                                       red.data(), nw.data());
+                    body_direct_fwd<HostCtx, T, false, false>(ctx, pv, hp.direct_fwd.data(), hp.dlist.data(), c,
+                                                              dacc.data(), red.data(), nw.data());
+            });
+            run_blocks(hp.direct_short.size(), 256, [&](const HostCtx& ctx) {
+                if (deriv || d)
+                    body_direct_fwd<HostCtx, T, true, true>(ctx, pv, hp.direct_short.data(), hp.dlist.data(), c,
+                                                            dacc.data(), red.data(), nw.data());
+                else
+                    body_direct_fwd<HostCtx, T, false, true>(ctx, pv, hp.direct_short.data(), hp.dlist.data(), c,
+                                                             dacc.data(), red.data(), nw.data());
             });
             run_blocks((nd + 255) / 256, 256, [&](const HostCtx& ctx) {
                 body_direct_io<HostCtx, T>(ctx, pv, hp.dlist.data(), nd, dacc.data(), o, 1);

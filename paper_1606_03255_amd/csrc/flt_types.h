@@ -53,7 +53,8 @@ constexpr int GATHER_STAGE = 2048;        // grid values a gather workgroup stag
 constexpr int MAX_Q = 32;                 // largest Chebyshev rank supported
 constexpr int MAX_MW = 10;                // largest window half-width supported
 constexpr int DIRECT_TPT = 32;            // direct sum: terms per thread and chunk (one anchor each)
-constexpr int DIRECT_NG = 8;              // direct sum: nodes per workgroup
+constexpr int DIRECT_NG = 8;              // direct sum: nodes per thread group
+constexpr int DIRECT_GMAX = 32;           // direct sum: most thread groups per workgroup (short sums)
 // direct sum: most chunks of 256 * DIRECT_TPT terms per workgroup, by working type
 constexpr int direct_cpw(int dtype_bytes) { return dtype_bytes == 4 ? 4 : 1; }
 constexpr int DIRECT_ANG = 256;           // direct adjoint: nodes per workgroup
@@ -152,9 +153,11 @@ struct CellItem {
 struct DirectItem {
     int32_t first;       // first entry of the run in the direct-node list
     int16_t count;       // nodes in the run
-    int16_t nch;         // forward: chunks of 256 * DIRECT_TPT terms, from `chunk` on
+    int16_t nch;         // forward: chunks of 2^log2tpg * DIRECT_TPT terms, from `chunk` on
     int32_t chunk;
     int32_t inst;        // instance whose coefficients the chunks cover
+    int32_t log2tpg;     // forward: threads per group of DIRECT_NG nodes (8: the whole workgroup;
+                         // fewer for short sums, the groups then splitting the workgroup)
 };
 
 // One instance of a plan (a single plan has one; a batched plan one per

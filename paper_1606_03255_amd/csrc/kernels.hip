@@ -186,13 +186,14 @@ __global__ __launch_bounds__(FFT_THREADS, 2) void k_passA_adj_f64(PlanView<doubl
     });
 }
 
-template <typename T, bool DERIV>
+template <typename T, bool DERIV, bool GROUPED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_direct_fwd(PlanView<T> pv, const DirectItem* items, const int32_t* dlist,
                                                     const cplx<T>* c, double* dacc)
 {
     __shared__ double red[2 * DIRECT_NG * 256];
-    __shared__ cplx<T> nw[DIRECT_NG];
-    body_direct_fwd<DevCtx, T, DERIV>(DevCtx(), pv, items, dlist, c, dacc, red, nw);
+    static_assert(256 / 8 == DIRECT_GMAX, "groups of at least 8 threads fill DIRECT_GMAX groups");
+    __shared__ cplx<T> nw[DIRECT_NG * DIRECT_GMAX];
+    body_direct_fwd<DevCtx, T, DERIV, GROUPED>(DevCtx(), pv, items, dlist, c, dacc, red, nw);
 }
 
 template <typename T>
@@ -369,13 +370,25 @@ hipError_t launch_forward(const DevLists& L, const PlanView<T>& pv, const WsLayo
             cplx<T>* out = d ? f2 : f;
             hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 0);
             ls.launched();
-            if (deriv || d)
-                hipLaunchKernelGGL((k_direct_fwd<T, true>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv, L.direct_fwd,
-                                   L.dlist, c, dacc);
-            else
-                hipLaunchKernelGGL((k_direct_fwd<T, false>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv,
-                                   L.direct_fwd, L.dlist, c, dacc);
-            ls.launched();
+            // long sums, then short ones (thread groups), both adding into dacc
+            if (L.n_direct_fwd) {
+                if (deriv || d)
+                    hipLaunchKernelGGL((k_direct_fwd<T, true, false>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv,
+                                       L.direct_fwd, L.dlist, c, dacc);
+                else
+                    hipLaunchKernelGGL((k_direct_fwd<T, false, false>), dim3(L.n_direct_fwd), dim3(256), 0, st, pv,
+                                       L.direct_fwd, L.dlist, c, dacc);
+                ls.launched();
+            }
+            if (L.n_direct_short) {
+                if (deriv || d)
+                    hipLaunchKernelGGL((k_direct_fwd<T, true, true>), dim3(L.n_direct_short), dim3(256), 0, st, pv,
+                                       L.direct_short, L.dlist, c, dacc);
+                else
+                    hipLaunchKernelGGL((k_direct_fwd<T, false, true>), dim3(L.n_direct_short), dim3(256), 0, st, pv,
+                                       L.direct_short, L.dlist, c, dacc);
+                ls.launched();
+            }
             hipLaunchKernelGGL(k_direct_io<T>, dim3(gb), dim3(256), 0, st, pv, L.dlist, L.n_dlist, dacc, out, 1);
             ls.launched();
         }

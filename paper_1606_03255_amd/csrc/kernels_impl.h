@@ -1690,7 +1690,7 @@ template <typename T> FLT_HD cplx<T> direct_w(const PlanView<T>& pv, int32_t j, 
     return mk<T>((T)(m1 * cs), (T)(m1 * sn));
 }
 
-template <class Ctx, typename T, bool DERIV>
+template <class Ctx, typename T, bool DERIV, bool GROUPED>
 FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectItem* items, const int32_t* dlist,
                             const cplx<T>* call, double* dacc, double* red, cplx<T>* nw)
 {
@@ -1698,14 +1698,24 @@ FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectI
     const int64_t N = pv.inst[it.inst].N;
     const cplx<T>* c = call + pv.inst[it.inst].c_off;
     const int tid = ctx.tid(), nt = ctx.ntid();
-    if (tid < DIRECT_NG) nw[tid] = tid < it.count ? direct_w(pv, dlist[it.first + tid], +1.0) : mk<T>(0, 0);
-    for (int r = 0; r < 2 * DIRECT_NG; ++r) red[r * nt + tid] = 0.0;   // this thread's partial sums
+    // thread groups of 2^lt threads, each with DIRECT_NG nodes of the run: one
+    // group spanning the workgroup for long sums; several (GROUPED) for short
+    // ones, whose terms would leave most threads idle
+    const int lt = GROUPED ? it.log2tpg : 8, tpg = 1 << lt;
+    const int ng = GROUPED ? ((nt >> lt) < DIRECT_GMAX ? (nt >> lt) : DIRECT_GMAX) : 1;   // groups
+    const int grp = GROUPED ? tid >> lt : 0, r = GROUPED ? tid & (tpg - 1) : tid;
+    const int gfirst = grp * DIRECT_NG;         // the group's first node in the run
+    for (int e = tid; e < DIRECT_NG * ng; e += nt)
+        nw[e] = e < it.count ? direct_w(pv, dlist[it.first + e], +1.0) : mk<T>(0, 0);
+    for (int q = 0; q < 2 * DIRECT_NG; ++q) red[q * nt + tid] = 0.0;   // this thread's partial sums
     ctx.sync();
+    const int gcount = it.count - gfirst;       // the group's nodes (<= 0: none)
     // Horner chains side by side (registers): all 8 nodes in FP32, 4 at a time
     // for the FP64 forward, one at a time for the FP64 derivative
     constexpr int NC = sizeof(T) == 4 ? DIRECT_NG : DERIV ? 1 : DIRECT_NG / 2;
-    for (int cc = 0; cc < it.nch; ++cc) {
-        const int64_t k0 = (((int64_t)it.chunk + cc) * nt + tid) * DIRECT_TPT;
+    for (int cc = 0; cc < it.nch && gcount > 0; ++cc) {
+        const int64_t k0 = (GROUPED ? (((int64_t)it.chunk + cc) << lt) + r : ((int64_t)it.chunk + cc) * nt + r) *
+                           DIRECT_TPT;
         if (k0 >= N) break;
         cplx<T> cv[DIRECT_TPT];
         if (k0 + DIRECT_TPT <= N) {   // unconditional loads (no per-term branch), then the tail
@@ -1725,13 +1735,13 @@ FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectI
         }
         auto coef = [&](int t) -> cplx<T> { return cv[t]; };
         for (int g0 = 0; g0 < DIRECT_NG; g0 += NC) {
-            if (g0 >= it.count) break;
+            if (g0 >= gcount) break;
             // Horner, h <- h w + c_t for t descending, NC nodes of the group at once
             cplx<T> w[NC];
             T hr[NC], hi[NC];
             const cplx<T> cl = coef(DIRECT_TPT - 1);
             for (int g = 0; g < NC; ++g) {
-                w[g] = nw[g0 + g];
+                w[g] = nw[gfirst + g0 + g];
                 hr[g] = cl.x;
                 hi[g] = cl.y;
             }
@@ -1744,8 +1754,8 @@ FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectI
                 }
             }
             for (int g = 0; g < NC; ++g) {
-                if (g0 + g >= it.count) break;
-                const int32_t j = dlist[it.first + g0 + g];
+                if (g0 + g >= gcount) break;
+                const int32_t j = dlist[it.first + gfirst + g0 + g];
                 const cplx<T> a = mul(direct_anchor<T>((double)k0, pv.nx[j], pv.ny[j], +1.0), mk(hr[g], hi[g]));
                 red[(2 * (g0 + g)) * nt + tid] += (double)a.x;
                 red[(2 * (g0 + g) + 1) * nt + tid] += (double)a.y;
@@ -1753,14 +1763,19 @@ FLT_HD void body_direct_fwd(const Ctx& ctx, const PlanView<T>& pv, const DirectI
         }
     }
     ctx.sync();
-    for (int h = nt >> 1; h > 0; h >>= 1) {
-        if (tid < h)
-            for (int r = 0; r < 2 * DIRECT_NG; ++r) red[r * nt + tid] += red[r * nt + tid + h];
+    for (int h = (GROUPED ? tpg : nt) >> 1; h > 0; h >>= 1) {   // within each group
+        if (r < h)
+            for (int q = 0; q < 2 * DIRECT_NG; ++q) red[q * nt + tid] += red[q * nt + tid + h];
         ctx.sync();
     }
-    if (tid < 2 * it.count) {
-        const int32_t j = dlist[it.first + (tid >> 1)];
-        ctx.atomic_add(dacc + 2 * (int64_t)j + (tid & 1), red[tid * nt]);
+    // the groups' sums (row q of group g2 in column g2 2^lt) to their nodes
+    for (int e = tid; e < 2 * DIRECT_NG * ng; e += nt) {
+        const int g2 = e / (2 * DIRECT_NG), q = e - g2 * (2 * DIRECT_NG);
+        const int node = g2 * DIRECT_NG + (q >> 1);
+        if (node < it.count) {
+            const int32_t j = dlist[it.first + node];
+            ctx.atomic_add(dacc + 2 * (int64_t)j + (q & 1), red[q * nt + (GROUPED ? g2 << lt : 0)]);
+        }
     }
 }
 

@@ -38,6 +38,8 @@ struct DevLists {
     const NodeItem* gather_ln = nullptr;   // gather items read per lane
     const NodeItem* nfft_nodes = nullptr;
     const DirectItem* direct_fwd = nullptr;
+    const DirectItem* direct_short = nullptr;   // forward direct sums of short instances (thread groups)
+    int n_direct_short = 0;
     const DirectItem* direct_adj = nullptr;
     const int32_t* dlist = nullptr;
     const int32_t* cstart = nullptr;

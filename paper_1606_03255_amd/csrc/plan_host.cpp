@@ -398,16 +398,29 @@ static int build_one(HostPlan& hp, int64_t N, int64_t M, const double* z, double
         const int64_t nd = (int64_t)hp.dlist.size();
         const int64_t fchunks = (N + (int64_t)256 * DIRECT_TPT - 1) / ((int64_t)256 * DIRECT_TPT);
         const int cpw = direct_cpw(dtype == FLT_C64 ? 4 : 8);
-        for (int64_t g = 0; g < nd; g += DIRECT_NG)
-            for (int64_t ch = 0; ch < fchunks; ch += cpw)
-                hp.direct_fwd.push_back(DirectItem{(int32_t)g, (int16_t)std::min<int64_t>(DIRECT_NG, nd - g),
-                                                   (int16_t)std::min<int64_t>(cpw, fchunks - ch), (int32_t)ch, 0});
+        // short sums (fewer 32-term pieces than threads): a workgroup splits into
+        // groups of 2^lt threads, one per piece, each group with its own nodes
+        const int64_t pieces = (N + DIRECT_TPT - 1) / DIRECT_TPT;
+        int lt = 3;   // at least 8 threads per group: at most 256 / 8 = DIRECT_GMAX groups
+        while (lt < 8 && ((int64_t)1 << lt) < pieces) ++lt;
+        if (lt < 8) {
+            const int64_t ng = 256 >> lt;
+            const int64_t per = DIRECT_NG * ng;
+            for (int64_t g = 0; g < nd; g += per)
+                hp.direct_short.push_back(DirectItem{(int32_t)g, (int16_t)std::min<int64_t>(per, nd - g), 1, 0, 0, lt});
+        } else {
+            for (int64_t g = 0; g < nd; g += DIRECT_NG)
+                for (int64_t ch = 0; ch < fchunks; ch += cpw)
+                    hp.direct_fwd.push_back(DirectItem{(int32_t)g, (int16_t)std::min<int64_t>(DIRECT_NG, nd - g),
+                                                       (int16_t)std::min<int64_t>(cpw, fchunks - ch), (int32_t)ch,
+                                                       0, 8});
+        }
         const int64_t aspan = (int64_t)256 * direct_atpt(dtype == FLT_C64 ? 4 : 8);   // adjoint workgroup
         const int64_t achunks = (N + aspan - 1) / aspan;
         for (int64_t g = 0; g < nd; g += DIRECT_ANG)
             for (int64_t ch = 0; ch < achunks; ++ch)
                 hp.direct_adj.push_back(DirectItem{(int32_t)g, (int16_t)std::min<int64_t>(DIRECT_ANG, nd - g), 1,
-                                                   (int32_t)ch, 0});
+                                                   (int32_t)ch, 0, 8});
     }
     hp.grid_elems = goff;
     hp.scratch_elems = soff;
@@ -660,6 +673,7 @@ int build_batch_plan(HostPlan& out, int32_t count, const int64_t* N, const int64
             shift_nodes(out.nfft_nodes, p.nfft_nodes);
             for (int32_t v : p.dlist) out.dlist.push_back((int32_t)(v + no));
             for (DirectItem it : p.direct_fwd) { it.first += (int32_t)dlo; it.inst = i; out.direct_fwd.push_back(it); }
+            for (DirectItem it : p.direct_short) { it.first += (int32_t)dlo; it.inst = i; out.direct_short.push_back(it); }
             for (DirectItem it : p.direct_adj) { it.first += (int32_t)dlo; it.inst = i; out.direct_adj.push_back(it); }
             for (int32_t v : p.cstart) out.cstart.push_back((int32_t)(v + no));
             out.mask.insert(out.mask.end(), p.mask.begin(), p.mask.end());

@@ -51,6 +51,7 @@ struct HostPlan {
     std::vector<NodeItem> nfft_nodes;   // adjoint node side: NFFT bands only
     std::vector<int32_t> dlist;         // sorted indices of the nodes of direct bands
     std::vector<DirectItem> direct_fwd, direct_adj;
+    std::vector<DirectItem> direct_short;   // the forward's short sums (log2tpg < 8)
     std::vector<int32_t> cstart;        // per NFFT band: first sorted node with cell >= c, c = 0..n
     std::vector<int32_t> clist;         // touched cells of the listed cell items (-1 pads)
     std::vector<uint32_t> mask;         // per two-pass band: bit per grid address read by some window
