@@ -1657,7 +1657,9 @@ FLT_HD void body_sum_g(const Ctx& ctx, const PlanView<T>& pv, const SumItem* ite
 // w in LDS, then registers) and up to direct_cpw chunks of terms, reduced
 // once; a thread runs the Horner recurrences of its group's nodes side by
 // side (independent chains: all 8 in FP32, fewer in FP64), the derivative's
-// 2 pi i k factors, applied as c is loaded, only in the DERIV instance.
+// 2 pi i k factors, applied as c is loaded, only in the DERIV instance.  For
+// short sums (GROUPED) the workgroup is several such groups of 2^log2tpg
+// threads, each with its own DIRECT_NG nodes and one 32-term piece per thread.
 // ---------------------------------------------------------------------------
 
 // w^k0 = e^{-k0 y} cis(sign 2 pi k0 x) with the phase reduced exactly in FP64
