@@ -2,9 +2,12 @@
 #include <hip/hip_runtime_api.h>
 #include <string.h>
 
+#include <exception>
 #include <map>
 #include <mutex>
 #include <new>
+#include <system_error>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -346,11 +349,39 @@ template <class Build> static int tuned_shape(uint32_t flags, Build&& build, Tun
     {
         std::vector<std::vector<int>> seen;
         std::vector<double> scales;
-        for (double sc : TUNE_SCALES) {
-            HostPlan hp;
+        // the host plans of every factor, built on host threads at once for a
+        // single instance (each is independent of the others; no exception may
+        // leave a thread); a batch's planner already runs its members on threads
+        constexpr int NS = (int)(sizeof(TUNE_SCALES) / sizeof(TUNE_SCALES[0]));
+        std::vector<HostPlan> hps(NS);
+        std::vector<int> rcs(NS, FLT_OK);
+        auto build_one_scale = [&](int i) {
+            try {
+                PlanShape sh;
+                sh.direct_scale = TUNE_SCALES[i];
+                rcs[i] = build(hps[i], sh);
+            } catch (const std::exception&) {
+                rcs[i] = FLT_ENOMEM;
+            }
+        };
+        {
+            std::vector<std::thread> pool;
+            int i = 0;
+            if (probe.inst.size() == 1) {
+                try {
+                    for (; i < NS; ++i) pool.emplace_back(build_one_scale, i);
+                } catch (const std::system_error&) {   // fewer threads: the rest here
+                }
+            }
+            for (; i < NS; ++i) build_one_scale(i);
+            for (std::thread& t : pool) t.join();
+        }
+        for (int si = 0; si < NS; ++si) {
+            const double sc = TUNE_SCALES[si];
+            HostPlan& hp = hps[si];
             PlanShape sh;
             sh.direct_scale = sc;
-            rc = build(hp, sh);
+            rc = rcs[si];
             if (rc != FLT_OK) break;
             std::vector<int> sig;
             for (const BandDesc& B : hp.bands) sig.push_back(B.direct);
